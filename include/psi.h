@@ -1,0 +1,171 @@
+/* psi.h -- C ABI of the MI355X (gfx950) SPaC-tree library.
+ *
+ * A SPaC-tree ("Parallel Dynamic Spatial Indexes", PPoPP'26, Sec. 4) is a
+ * spatial index over 2D/3D integer points ordered by a space-filling-curve
+ * key (Morton = SPaC-Z, Hilbert = SPaC-H). Points live in leaf blocks of at
+ * most `leaf_size` entries at build time; leaves keep no internal order
+ * (Sec. 4.2, "relaxing the key order in the leaves"); every leaf and every
+ * tree node stores the tight axis-aligned box of its points (Sec. 1, App. C).
+ *
+ * Conventions shared by every call
+ *   - Every pointer named d_* is DEVICE memory owned by the caller; it must
+ *     stay valid until the work queued on the index's stream has finished.
+ *     Host pointers are named h_* .
+ *   - Calls are asynchronous and ordered on the stream given to psi_create
+ *     (or psi_set_stream). Argument errors are returned at once. Errors that
+ *     only the device can see (coordinate out of range, an internal check)
+ *     are latched and returned by the next psi_sync / psi_size.
+ *     Update calls (insert, delete) wait once on their stream to size their
+ *     output; query calls never wait.
+ *   - Points are row-major uint32 [n][dim]. 2D coordinates must be < 2^31 and
+ *     3D coordinates < 2^21: the key has 32 (2D) or 21 (3D) bits per axis
+ *     (Sec. 3, the precision a 64-bit code allows), and 2D squared distances
+ *     must fit 64 bits.
+ *   - Boxes are uint32 [nb][2][dim]: the lo row, then the hi row; both ends
+ *     are inclusive. A box with lo > hi in any axis is empty.
+ *   - Ids are uint32 assigned by the library: psi_build numbers its points
+ *     0..n-1 in input order; each insert continues from the next unused id.
+ *     Ids are never reused.
+ *   - An index is bound to one stream and is not thread-safe.
+ */
+#ifndef PSI_H
+#define PSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSI_OK = 0,
+    PSI_E_ARG = 1,       /* bad argument (null pointer, bad size or parameter) */
+    PSI_E_RANGE = 2,     /* a coordinate exceeds the key's bits per axis */
+    PSI_E_NOMEM = 3,     /* device allocation failed */
+    PSI_E_CAPACITY = 4,  /* id space (2^32 - 1 ids) exhausted */
+    PSI_E_HIP = 5,       /* a HIP runtime call failed */
+    PSI_E_STATE = 6,     /* call not valid in the index's current state */
+    PSI_E_INTERNAL = 7   /* a device-side consistency check failed */
+} psi_status;
+
+typedef enum { PSI_MORTON = 0, PSI_HILBERT = 1 } psi_curve;
+
+/* dim: 2 or 3. curve: psi_curve. leaf_size: phi, the largest leaf a build
+ * makes (2..32); a leaf slot holds 2*phi entries so that inserts can append
+ * without moving data. fanout: children per tree node (2..32). flags: 0. */
+typedef struct {
+    uint32_t dim;
+    uint32_t curve;
+    uint32_t leaf_size;
+    uint32_t fanout;
+    uint32_t flags;
+} psi_params;
+
+typedef struct psi_index_s* psi_index;
+
+const char* psi_status_str(psi_status s);
+
+/* Create an empty index bound to `hip_stream` (a hipStream_t; NULL = the
+ * default stream). */
+psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out);
+psi_status psi_destroy(psi_index ix);
+psi_status psi_set_stream(psi_index ix, void* hip_stream);
+
+/* Build (Alg. 3): replace the contents with the n points d_pts, ids 0..n-1.
+ * Encodes each point's curve key, sorts the (key, id) pairs, cuts the sorted
+ * order into ceil(n/phi) balanced leaves and builds the node levels above.
+ * The resulting structure is canonical (a function of the point set only). */
+psi_status psi_build(psi_index ix, const uint32_t* d_pts, uint64_t n);
+
+/* Batch insert (Alg. 4): add m points; their ids are the next m unused ids
+ * in input order, written to d_new_ids (may be NULL). Each sorted run of new
+ * points is appended, unsorted, to the leaf whose key range holds it; a leaf
+ * that would exceed 2*phi entries is re-cut into balanced leaves. */
+psi_status psi_batch_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
+
+/* Batch delete (Sec. 4.2): remove the live points whose ids are listed.
+ * Unknown, already deleted and repeated ids are ignored. The number removed
+ * is written to *d_ndeleted (device uint64; may be NULL). Leaves that fall
+ * below ceil(phi/2) entries are merged with their right neighbour (the left
+ * one at the end) and re-cut. */
+psi_status psi_batch_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
+
+/* k nearest neighbours (Sec. 2.2) of nq query points, exact: row q of
+ * d_ids/d_d2 ([nq][k]) holds the k live points with the smallest (squared
+ * Euclidean distance, id), ascending; rows are padded with
+ * (0xFFFFFFFF, UINT64_MAX) when the index has fewer than k points.
+ * 1 <= k <= 128. */
+psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k,
+                   uint32_t* d_ids, uint64_t* d_d2);
+
+/* Range count (Sec. 2.2): d_counts[b] = number of live points in box b. */
+psi_status psi_range_count(psi_index ix, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts);
+
+/* Range list (Sec. 2.2): ids of the live points in box b are written to
+ * d_ids[d_offsets[b] .. d_offsets[b+1]), in an unspecified but deterministic
+ * order. d_offsets ([nb+1], device) is normally the exclusive prefix sum of
+ * psi_range_count's output; a box whose span is shorter than its count is
+ * truncated to its span. */
+psi_status psi_range_report(psi_index ix, const uint32_t* d_boxes, uint64_t nb,
+                            const uint64_t* d_offsets, uint32_t* d_ids);
+
+/* Waits for the stream; returns the first latched device error, if any. */
+psi_status psi_sync(psi_index ix);
+/* Number of live points (waits for the stream, like psi_sync). */
+psi_status psi_size(psi_index ix, uint64_t* h_n_live);
+/* Next id that an insert would assign. */
+psi_status psi_next_id(psi_index ix, uint32_t* h_next_id);
+
+/* --- inspection (tests, checkpoints) ------------------------------------ */
+
+/* All live entries in (key, id) order: d_keys [n], d_ids [n], d_pts [n][dim]
+ * (any may be NULL). Leaves are sorted on the fly; the index is unchanged. */
+psi_status psi_export(psi_index ix, uint64_t* d_keys, uint32_t* d_ids, uint32_t* d_pts);
+
+/* Tree shape: number of leaves, height h (levels 0..h, level h = leaves) and
+ * the node count of each level in h_level_sizes[0..h] (at most 64 levels). */
+psi_status psi_shape(psi_index ix, uint64_t* h_n_leaves, uint32_t* h_height, uint64_t* h_level_sizes);
+
+/* Leaves and nodes. Leaf j: pivot (key, id) -- a lower bound of its entries
+ * that is strictly above every entry of leaf j-1 --, entry count, and tight
+ * box [L][dim]. Nodes of all levels, root first and leaves last, with their
+ * boxes [nodes][dim] and counts. Any pointer may be NULL. */
+psi_status psi_export_structure(psi_index ix, uint64_t* d_piv_key, uint32_t* d_piv_id,
+                                uint32_t* d_leaf_cnt, uint32_t* d_leaf_lo, uint32_t* d_leaf_hi,
+                                uint32_t* d_node_lo, uint32_t* d_node_hi, uint64_t* d_node_cnt);
+
+/* Raw leaf contents in leaf order, entries in their stored (unsorted) order:
+ * d_ids [n], d_pts [n][dim]. Leaf j's entries start at the exclusive prefix
+ * sum of the leaf counts. */
+psi_status psi_export_leaves(psi_index ix, uint32_t* d_ids, uint32_t* d_pts);
+
+/* --- single steps of the path (parity tests, micro-benchmarks) ------------ */
+
+/* Curve keys of n points (Sec. 2.2): d_keys[i] = key of d_pts[i]. */
+psi_status psi_encode(uint32_t dim, uint32_t curve, const uint32_t* d_pts, uint64_t n,
+                      uint64_t* d_keys, void* hip_stream);
+
+/* Stable sort of n (key, id) pairs by (key, id) (Alg. 3 sorts pairs, not
+ * points). Inputs are left unchanged; outputs go to d_keys_out/d_ids_out.
+ * Temporary device memory is allocated and freed inside the call, which
+ * therefore waits on the stream before returning. */
+psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_t n,
+                          uint64_t* d_keys_out, uint32_t* d_ids_out, void* hip_stream);
+
+/* --- kernel timing ------------------------------------------------------ */
+
+/* When enabled, every kernel launch of the index is bracketed by HIP events
+ * on its stream. psi_prof_get waits for the stream and returns, for the
+ * named kernel family ("radix_pass", "encode_hist", "leaf_fill",
+ * "leaf_meta", "nodes", "knn", "range_count", "range_report", "route",
+ * "update", ...), the summed device time in ms, the launch count, and
+ * the algorithmic bytes those launches move. psi_prof_reset clears them. */
+psi_status psi_prof_enable(psi_index ix, int on);
+psi_status psi_prof_reset(psi_index ix);
+psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches,
+                        uint64_t* h_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSI_H */

@@ -60,6 +60,8 @@ def lib():
             "ora_knn_fullsort": (None, [P, P, u64, u32, P, P]),
             "ora_range_count": (None, [P, P, u64, P, i32]),
             "ora_range_report": (None, [P, P, u64, P, P, i32]),
+            "ora_knn_points": (None, [i32, P, u64, P, u64, u32, P, P, i32]),
+            "ora_range_count_points": (None, [i32, P, u64, P, u64, P, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -99,6 +101,26 @@ def sort_pairs(keys, ids):
     i = _c(ids, np.uint32).copy()
     lib().ora_sort_pairs(k.size, _p(k), _p(i))
     return k, i
+
+
+def knn_points(pts, q, k: int, threads: int = 0):
+    """Brute-force kNN over raw points (ids = row numbers)."""
+    p = _c(pts, np.uint32)
+    dim = p.shape[1]
+    qq = _c(q, np.uint32).reshape(-1, dim)
+    ids = np.empty((qq.shape[0], k), dtype=np.uint32)
+    d2 = np.empty((qq.shape[0], k), dtype=np.uint64)
+    lib().ora_knn_points(dim, _p(p), p.shape[0], _p(qq), qq.shape[0], k, _p(ids), _p(d2), threads)
+    return ids, d2
+
+
+def range_count_points(pts, boxes, threads: int = 0):
+    p = _c(pts, np.uint32)
+    dim = p.shape[1]
+    b = _c(boxes, np.uint32).reshape(-1, 2, dim)
+    out = np.empty(b.shape[0], dtype=np.uint64)
+    lib().ora_range_count_points(dim, _p(p), p.shape[0], _p(b), b.shape[0], _p(out), threads)
+    return out
 
 
 class RefIndex:

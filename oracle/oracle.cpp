@@ -421,4 +421,36 @@ void ora_range_report(void* h, const uint32_t* boxes, uint64_t nb, const uint64_
     });
 }
 
+// Brute-force kNN over a plain point array whose ids are 0..n-1 (used to
+// check sampled queries against very large inputs without building a set).
+void ora_knn_points(int dim, const uint32_t* pts, uint64_t n, const uint32_t* q, uint64_t nq, uint32_t k,
+                    uint32_t* out_ids, uint64_t* out_d2, int threads) {
+    parallel_for(nq, threads, [&](uint64_t qi) {
+        const uint32_t* qq = q + qi * dim;
+        std::priority_queue<std::pair<uint64_t, uint32_t>> best;
+        for (uint64_t i = 0; i < n; ++i) {
+            std::pair<uint64_t, uint32_t> c{sq_dist(dim, pts + i * dim, qq), (uint32_t)i};
+            if (best.size() < k) best.push(c);
+            else if (k > 0 && c < best.top()) { best.pop(); best.push(c); }
+        }
+        std::vector<std::pair<uint64_t, uint32_t>> r;
+        while (!best.empty()) { r.push_back(best.top()); best.pop(); }
+        std::reverse(r.begin(), r.end());
+        for (uint32_t j = 0; j < k; ++j) {
+            out_ids[qi * k + j] = j < r.size() ? r[j].second : kPadId;
+            out_d2[qi * k + j] = j < r.size() ? r[j].first : kPadD2;
+        }
+    });
+}
+
+// Brute-force range count over a plain point array.
+void ora_range_count_points(int dim, const uint32_t* pts, uint64_t n, const uint32_t* boxes, uint64_t nb,
+                            uint64_t* counts, int threads) {
+    parallel_for(nb, threads, [&](uint64_t b) {
+        uint64_t c = 0;
+        for (uint64_t i = 0; i < n; ++i) c += in_box(dim, pts + i * dim, boxes + b * 2 * dim);
+        counts[b] = c;
+    });
+}
+
 }  // extern "C"

@@ -1,0 +1,407 @@
+"""MI355X (gfx950) SPaC-tree spatial index: Python binding of libpsi.so.
+
+The binding only marshals arguments: every step of build, update and query
+runs in the HIP kernels of libpsi.so. Device memory and streams come from
+PyTorch (tensors on a ROCm device, `torch.cuda.current_stream()`). There is
+no CPU fallback: if libpsi.so is missing or no GPU is present, calls raise.
+
+Functions named psi_* mirror the C ABI in include/psi.h one to one; `Index`
+is a small convenience wrapper that allocates the output tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsi.so")
+
+MORTON, HILBERT = 0, 1
+PAD_ID = 0xFFFFFFFF
+PAD_D2 = 0xFFFFFFFFFFFFFFFF
+
+STATUS = {0: "PSI_OK", 1: "PSI_E_ARG", 2: "PSI_E_RANGE", 3: "PSI_E_NOMEM", 4: "PSI_E_CAPACITY",
+          5: "PSI_E_HIP", 6: "PSI_E_STATE", 7: "PSI_E_INTERNAL"}
+
+# exported symbols of include/psi.h with (restype, argtypes)
+_P, _u64, _u32, _i = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+SIGNATURES = {
+    "psi_status_str": (C.c_char_p, [_i]),
+    "psi_create": (_i, [_P, _P, _P]),
+    "psi_destroy": (_i, [_P]),
+    "psi_set_stream": (_i, [_P, _P]),
+    "psi_build": (_i, [_P, _P, _u64]),
+    "psi_batch_insert": (_i, [_P, _P, _u64, _P]),
+    "psi_batch_delete": (_i, [_P, _P, _u64, _P]),
+    "psi_knn": (_i, [_P, _P, _u64, _u32, _P, _P]),
+    "psi_range_count": (_i, [_P, _P, _u64, _P]),
+    "psi_range_report": (_i, [_P, _P, _u64, _P, _P]),
+    "psi_sync": (_i, [_P]),
+    "psi_size": (_i, [_P, _P]),
+    "psi_next_id": (_i, [_P, _P]),
+    "psi_export": (_i, [_P, _P, _P, _P]),
+    "psi_shape": (_i, [_P, _P, _P, _P]),
+    "psi_export_structure": (_i, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "psi_export_leaves": (_i, [_P, _P, _P]),
+    "psi_encode": (_i, [_u32, _u32, _P, _u64, _P, _P]),
+    "psi_sort_pairs": (_i, [_P, _P, _u64, _P, _P, _P]),
+    "psi_prof_enable": (_i, [_P, _i]),
+    "psi_prof_reset": (_i, [_P]),
+    "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
+}
+
+
+class PsiError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class psi_params(C.Structure):
+    _fields_ = [("dim", C.c_uint32), ("curve", C.c_uint32), ("leaf_size", C.c_uint32),
+                ("fanout", C.c_uint32), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpsi.so (built by paper_2601_05347_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_2601_05347_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise PsiError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _as_u32(x, dev):
+    """host array or tensor -> contiguous int32 device tensor holding u32 bits"""
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        if x.dtype not in (torch.int32, torch.uint32):
+            raise ValueError("expected 32-bit integer tensor")
+        t = x.to(dev).contiguous()
+        return t.view(torch.int32) if t.dtype == torch.uint32 else t
+    a = np.ascontiguousarray(x, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).to(dev)
+
+
+def _as_u64(x, dev):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        t = x.to(dev).contiguous()
+        return t.view(torch.int64) if t.dtype == torch.uint64 else t
+    a = np.ascontiguousarray(x, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(dev)
+
+
+def to_u32(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def to_u64(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------ C ABI mirrors
+
+def psi_status_str(code: int) -> str:
+    return lib().psi_status_str(code).decode()
+
+
+def psi_create(dim: int, curve: int, leaf_size: int = 32, fanout: int = 8, flags: int = 0, stream=None):
+    h = C.c_void_p()
+    prm = psi_params(dim, curve, leaf_size, fanout, flags)
+    _check(lib().psi_create(C.byref(prm), _stream_ptr(stream), C.byref(h)), "psi_create")
+    return h
+
+
+def psi_destroy(h):
+    _check(lib().psi_destroy(h), "psi_destroy")
+
+
+def psi_set_stream(h, stream=None):
+    _check(lib().psi_set_stream(h, _stream_ptr(stream)), "psi_set_stream")
+
+
+def psi_build(h, pts, n: int):
+    _check(lib().psi_build(h, _dev_ptr(pts), n), "psi_build")
+
+
+def psi_batch_insert(h, pts, m: int, new_ids=None):
+    _check(lib().psi_batch_insert(h, _dev_ptr(pts), m, _dev_ptr(new_ids)), "psi_batch_insert")
+
+
+def psi_batch_delete(h, ids, m: int, ndeleted=None):
+    _check(lib().psi_batch_delete(h, _dev_ptr(ids), m, _dev_ptr(ndeleted)), "psi_batch_delete")
+
+
+def psi_knn(h, q, nq: int, k: int, ids, d2):
+    _check(lib().psi_knn(h, _dev_ptr(q), nq, k, _dev_ptr(ids), _dev_ptr(d2)), "psi_knn")
+
+
+def psi_range_count(h, boxes, nb: int, counts):
+    _check(lib().psi_range_count(h, _dev_ptr(boxes), nb, _dev_ptr(counts)), "psi_range_count")
+
+
+def psi_range_report(h, boxes, nb: int, offsets, ids):
+    _check(lib().psi_range_report(h, _dev_ptr(boxes), nb, _dev_ptr(offsets), _dev_ptr(ids)),
+           "psi_range_report")
+
+
+def psi_sync(h):
+    _check(lib().psi_sync(h), "psi_sync")
+
+
+def psi_size(h) -> int:
+    v = C.c_uint64()
+    _check(lib().psi_size(h, C.byref(v)), "psi_size")
+    return v.value
+
+
+def psi_next_id(h) -> int:
+    v = C.c_uint32()
+    _check(lib().psi_next_id(h, C.byref(v)), "psi_next_id")
+    return v.value
+
+
+def psi_export(h, keys, ids, pts):
+    _check(lib().psi_export(h, _dev_ptr(keys), _dev_ptr(ids), _dev_ptr(pts)), "psi_export")
+
+
+def psi_shape(h):
+    L = C.c_uint64()
+    hh = C.c_uint32()
+    sizes = (C.c_uint64 * 64)()
+    _check(lib().psi_shape(h, C.byref(L), C.byref(hh), sizes), "psi_shape")
+    return L.value, hh.value, [sizes[i] for i in range(hh.value + 1)] if L.value else []
+
+
+def psi_export_structure(h, piv_key, piv_id, leaf_cnt, leaf_lo, leaf_hi, node_lo, node_hi, node_cnt):
+    _check(lib().psi_export_structure(h, *[_dev_ptr(t) for t in (piv_key, piv_id, leaf_cnt, leaf_lo, leaf_hi,
+                                                                  node_lo, node_hi, node_cnt)]),
+           "psi_export_structure")
+
+
+def psi_export_leaves(h, ids, pts):
+    _check(lib().psi_export_leaves(h, _dev_ptr(ids), _dev_ptr(pts)), "psi_export_leaves")
+
+
+def psi_encode(dim: int, curve: int, pts, n: int, keys, stream=None):
+    _check(lib().psi_encode(dim, curve, _dev_ptr(pts), n, _dev_ptr(keys), _stream_ptr(stream)), "psi_encode")
+
+
+def psi_sort_pairs(keys, ids, n: int, keys_out, ids_out, stream=None):
+    _check(lib().psi_sort_pairs(_dev_ptr(keys), _dev_ptr(ids), n, _dev_ptr(keys_out), _dev_ptr(ids_out),
+                                _stream_ptr(stream)), "psi_sort_pairs")
+
+
+def psi_prof_enable(h, on: bool):
+    _check(lib().psi_prof_enable(h, 1 if on else 0), "psi_prof_enable")
+
+
+def psi_prof_reset(h):
+    _check(lib().psi_prof_reset(h), "psi_prof_reset")
+
+
+def psi_prof_get(h, family: str):
+    ms = C.c_double()
+    n = C.c_uint64()
+    b = C.c_uint64()
+    _check(lib().psi_prof_get(h, family.encode(), C.byref(ms), C.byref(n), C.byref(b)), "psi_prof_get")
+    return ms.value, n.value, b.value
+
+
+# ------------------------------------------------------------ convenience
+
+class Index:
+    """A SPaC-tree on the current ROCm device, bound to one stream."""
+
+    def __init__(self, dim: int, curve: int, leaf_size: int = 32, fanout: int = 8, device="cuda", stream=None):
+        torch = _torch()
+        self.dim, self.curve, self.leaf_size, self.fanout = dim, curve, leaf_size, fanout
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = psi_create(dim, curve, leaf_size, fanout, 0, self.stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            psi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pts(self, pts):
+        t = _as_u32(pts, self.device)
+        return t.reshape(-1, self.dim).contiguous()
+
+    def build(self, pts):
+        t = self._pts(pts)
+        psi_build(self._h, t, t.shape[0])
+        return self
+
+    def batch_insert(self, pts):
+        torch = _torch()
+        t = self._pts(pts)
+        ids = torch.empty(t.shape[0], dtype=torch.int32, device=self.device)
+        psi_batch_insert(self._h, t, t.shape[0], ids)
+        return ids
+
+    def batch_delete(self, ids) -> int:
+        torch = _torch()
+        t = _as_u32(ids, self.device).reshape(-1)
+        nd = torch.zeros(1, dtype=torch.int64, device=self.device)
+        psi_batch_delete(self._h, t, t.numel(), nd)
+        return nd
+
+    def knn(self, q, k: int):
+        torch = _torch()
+        t = self._pts(q)
+        nq = t.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        psi_knn(self._h, t, nq, k, ids, d2)
+        return ids, d2
+
+    def range_count(self, boxes):
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = torch.empty(b.shape[0], dtype=torch.int64, device=self.device)
+        psi_range_count(self._h, b, b.shape[0], cnt)
+        return cnt
+
+    def range_report(self, boxes, counts=None):
+        """Returns (offsets[nb+1], ids). Counts are computed if not given."""
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = self.range_count(b) if counts is None else counts
+        off = torch.zeros(b.shape[0] + 1, dtype=torch.int64, device=self.device)
+        torch.cumsum(cnt, 0, out=off[1:])
+        total = int(off[-1].item())
+        ids = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
+        psi_range_report(self._h, b, b.shape[0], off, ids)
+        return off, ids[:total]
+
+    def sync(self):
+        psi_sync(self._h)
+
+    def size(self) -> int:
+        return psi_size(self._h)
+
+    def next_id(self) -> int:
+        return psi_next_id(self._h)
+
+    def export(self):
+        """Live entries in (key, id) order as numpy (keys u64, ids u32, pts u32[n, dim])."""
+        torch = _torch()
+        n = self.size()
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        i = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        p = torch.empty((max(n, 1), self.dim), dtype=torch.int32, device=self.device)
+        psi_export(self._h, k, i, p)
+        self.sync()
+        return to_u64(k[:n]), to_u32(i[:n]), to_u32(p[:n])
+
+    def shape(self):
+        return psi_shape(self._h)
+
+    def structure(self) -> dict:
+        torch = _torch()
+        L, h, sizes = self.shape()
+        nn = int(sum(sizes)) if L else 0
+        D, dev = self.dim, self.device
+        t = dict(piv_key=torch.empty(max(L, 1), dtype=torch.int64, device=dev),
+                 piv_id=torch.empty(max(L, 1), dtype=torch.int32, device=dev),
+                 leaf_cnt=torch.empty(max(L, 1), dtype=torch.int32, device=dev),
+                 leaf_lo=torch.empty((max(L, 1), D), dtype=torch.int32, device=dev),
+                 leaf_hi=torch.empty((max(L, 1), D), dtype=torch.int32, device=dev),
+                 node_lo=torch.empty((max(nn, 1), D), dtype=torch.int32, device=dev),
+                 node_hi=torch.empty((max(nn, 1), D), dtype=torch.int32, device=dev),
+                 node_cnt=torch.empty(max(nn, 1), dtype=torch.int64, device=dev))
+        psi_export_structure(self._h, t["piv_key"], t["piv_id"], t["leaf_cnt"], t["leaf_lo"], t["leaf_hi"],
+                             t["node_lo"], t["node_hi"], t["node_cnt"])
+        self.sync()
+        out = dict(n_leaves=L, height=h, level_sizes=np.array(sizes, dtype=np.int64))
+        for name, ten in t.items():
+            cut = ten[:L] if name.startswith(("piv", "leaf")) else ten[:nn]
+            out[name] = to_u64(cut) if ten.dtype == torch.int64 else to_u32(cut)
+        return out
+
+    def leaves(self):
+        """Raw leaf contents (stored order) and per-leaf counts."""
+        torch = _torch()
+        n = self.size()
+        i = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        p = torch.empty((max(n, 1), self.dim), dtype=torch.int32, device=self.device)
+        psi_export_leaves(self._h, i, p)
+        self.sync()
+        return to_u32(i[:n]), to_u32(p[:n])
+
+    # timing
+    def prof_enable(self, on=True):
+        psi_prof_enable(self._h, on)
+
+    def prof_reset(self):
+        psi_prof_reset(self._h)
+
+    def prof_get(self, family: str):
+        return psi_prof_get(self._h, family)
+
+
+def encode(pts, dim: int, curve: int):
+    """Curve keys of points on the GPU (returns an int64 tensor of u64 bits)."""
+    torch = _torch()
+    t = _as_u32(pts, "cuda").reshape(-1, dim).contiguous()
+    keys = torch.empty(t.shape[0], dtype=torch.int64, device=t.device)
+    psi_encode(dim, curve, t, t.shape[0], keys)
+    return keys
+
+
+def sort_pairs(keys, ids):
+    """Stable sort of (key, id) pairs on the GPU; returns (keys, ids) tensors."""
+    torch = _torch()
+    k = _as_u64(keys, "cuda").reshape(-1)
+    i = _as_u32(ids, "cuda").reshape(-1)
+    ko = torch.empty_like(k)
+    io = torch.empty_like(i)
+    psi_sort_pairs(k, i, k.numel(), ko, io)
+    return ko, io

@@ -1,0 +1,281 @@
+// Leaf and node construction from sorted (key, id) pairs, and exports.
+//
+// Alg. 3 (BuildSorted) cuts the sorted sequence into leaves of at most phi
+// points, fetches each leaf's points by id and gives every node the box of
+// its children. Here the cut is bottom-up: L = ceil(n/phi) balanced chunks,
+// one 32-lane group per leaf. A key is a bijection of its grid point, so the
+// point is decoded from the key instead of gathered by id: the fill reads the
+// sorted pairs once, in order, and never touches the input coordinates again.
+#include "psi_kern.h"
+
+namespace psi {
+
+namespace {
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+// 32-lane group reductions (xor offsets below 32 stay inside the half-wave).
+__device__ __forceinline__ uint32_t half_min(uint32_t v) {
+    for (int o = 16; o >= 1; o >>= 1) v = min(v, shfl_u32(v, (int)(lane_id() ^ o)));
+    return v;
+}
+__device__ __forceinline__ uint32_t half_max(uint32_t v) {
+    for (int o = 16; o >= 1; o >>= 1) v = max(v, shfl_u32(v, (int)(lane_id() ^ o)));
+    return v;
+}
+
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict__ sk,
+                                                      const uint32_t* __restrict__ sid, uint64_t n, uint64_t L,
+                                                      uint32_t C, uint32_t* __restrict__ slots,
+                                                      uint64_t* __restrict__ piv_key, uint32_t* __restrict__ piv_id,
+                                                      NodeRec* __restrict__ leafrec) {
+    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;  // leaf of this half-wave
+    const uint32_t t = threadIdx.x & 31;
+    if (j >= L) return;  // whole half-waves leave together
+    const uint64_t b = j * n / L, e = (j + 1) * n / L;
+    const uint32_t cnt = (uint32_t)(e - b);
+    const bool on = t < cnt;
+    uint32_t p[D];
+    uint64_t key = 0;
+    uint32_t id = 0;
+    if (on) {
+        key = sk[b + t];
+        id = sid[b + t];
+        sfc_point<D, CURVE>(key, p);
+        uint32_t* s = slots + j * (uint64_t)(D + 1) * C;
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d * C + t] = p[d];
+        s[D * C + t] = id;
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = 0;
+    }
+    NodeRec r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r.lo[d] = 0xFFFFFFFFu;
+        r.hi[d] = 0u;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        r.lo[d] = half_min(on ? p[d] : 0xFFFFFFFFu);
+        r.hi[d] = half_max(on ? p[d] : 0u);
+    }
+    if (t == 0) {
+        r.cnt = cnt;
+        r.slot = (uint32_t)j;
+        if (D == 2) { r.lo[2] = 0; r.hi[2] = 0; }
+        leafrec[j] = r;
+        piv_key[j] = key;
+        piv_id[j] = id;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ child, uint64_t n_child,
+                                                    NodeRec* __restrict__ parent, uint64_t n_parent, uint32_t B) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_parent) return;
+    NodeRec r;
+    for (int d = 0; d < 3; ++d) {
+        r.lo[d] = 0xFFFFFFFFu;
+        r.hi[d] = 0u;
+    }
+    uint32_t cnt = 0;
+    const uint64_t c0 = i * B, c1 = min<uint64_t>(c0 + B, n_child);
+    for (uint64_t c = c0; c < c1; ++c) {
+        const NodeRec x = child[c];
+        if (x.cnt == 0) continue;
+        cnt += x.cnt;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            r.lo[d] = min(r.lo[d], x.lo[d]);
+            r.hi[d] = max(r.hi[d], x.hi[d]);
+        }
+    }
+    r.cnt = cnt;
+    r.slot = 0xFFFFFFFFu;
+    if (D == 2 && cnt) { r.lo[2] = 0; r.hi[2] = 0; }
+    parent[i] = r;
+}
+
+__global__ void k_leaf_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t* __restrict__ cnt) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < L) cnt[j] = leaf[j].cnt;
+}
+
+__global__ void k_widen(const uint32_t* __restrict__ in, uint64_t n, uint64_t* __restrict__ out) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) out[j] = in[j];
+}
+
+// One wave per leaf: entries sorted by (key, id) inside the leaf by rank.
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_export_sorted(TreeView t, const uint64_t* __restrict__ off,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                       uint32_t* __restrict__ pts) {
+    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = lane_id();
+    if (j >= t.L) return;
+    const NodeRec r = t.leaf[j];
+    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * t.C;
+    for (uint32_t c0 = 0; c0 < r.cnt; c0 += 64) {
+        const uint32_t e = c0 + lane;
+        const bool on = e < r.cnt;
+        uint32_t p[D];
+        uint32_t id = 0;
+        uint64_t key = 0;
+        if (on) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) p[d] = s[d * t.C + e];
+            id = s[D * t.C + e];
+            key = sfc_key<D, CURVE>(p);
+        }
+        // rank against every entry of the leaf
+        uint32_t rank = 0;
+        for (uint32_t f0 = 0; f0 < r.cnt; f0 += 64) {
+            uint32_t q[D];
+            uint32_t fid = 0;
+            uint64_t fkey = 0;
+            const uint32_t f = f0 + lane;
+            if (f < r.cnt) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) q[d] = s[d * t.C + f];
+                fid = s[D * t.C + f];
+                fkey = sfc_key<D, CURVE>(q);
+            }
+            const uint32_t lim = min(64u, r.cnt - f0);
+            for (uint32_t x = 0; x < lim; ++x) {
+                const uint64_t ok = shfl_u64(fkey, (int)x);
+                const uint32_t oi = shfl_u32(fid, (int)x);
+                rank += pair_less(ok, oi, key, id) ? 1u : 0u;
+            }
+        }
+        if (on) {
+            const uint64_t o = off[j] + rank;
+            if (keys) keys[o] = key;
+            if (ids) ids[o] = id;
+            if (pts) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) pts[o * D + d] = p[d];
+            }
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_export_raw(TreeView t, const uint64_t* __restrict__ off,
+                                                    uint32_t* __restrict__ ids, uint32_t* __restrict__ pts) {
+    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = lane_id();
+    if (j >= t.L) return;
+    const NodeRec r = t.leaf[j];
+    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * t.C;
+    for (uint32_t e = lane; e < r.cnt; e += 64) {
+        const uint64_t o = off[j] + e;
+        if (ids) ids[o] = s[D * t.C + e];
+        if (pts) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) pts[o * D + d] = s[d * t.C + e];
+        }
+    }
+}
+
+template <int D>
+__global__ void k_export_structure(TreeView t, uint64_t n_inner, const uint64_t* __restrict__ pk_src,
+                                   const uint32_t* __restrict__ pi_src, uint64_t* __restrict__ piv_key,
+                                   uint32_t* __restrict__ piv_id, uint32_t* __restrict__ leaf_cnt,
+                                   uint32_t* __restrict__ leaf_lo, uint32_t* __restrict__ leaf_hi,
+                                   uint32_t* __restrict__ node_lo, uint32_t* __restrict__ node_hi,
+                                   uint64_t* __restrict__ node_cnt) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inner + t.L) return;
+    const bool is_leaf = i >= n_inner;
+    const NodeRec r = is_leaf ? t.leaf[i - n_inner] : t.inner[i];
+    if (node_cnt) node_cnt[i] = r.cnt;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (node_lo) node_lo[i * D + d] = r.lo[d];
+        if (node_hi) node_hi[i * D + d] = r.hi[d];
+    }
+    if (is_leaf) {
+        const uint64_t j = i - n_inner;
+        if (piv_key) piv_key[j] = pk_src[j];
+        if (piv_id) piv_id[j] = pi_src[j];
+        if (leaf_cnt) leaf_cnt[j] = r.cnt;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (leaf_lo) leaf_lo[j * D + d] = r.lo[d];
+            if (leaf_hi) leaf_hi[j * D + d] = r.hi[d];
+        }
+    }
+}
+
+}  // namespace
+
+void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
+                         uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
+                         uint32_t* piv_id, NodeRec* leafrec) {
+    if (L == 0) return;
+    const unsigned g = blocks_for(L, 256 / 32);
+#define PSI_BL(D, CV) hipLaunchKernelGGL((k_build_leaves<D, CV>), dim3(g), dim3(256), 0, st, sk, sid, n, L, C, slots, piv_key, piv_id, leafrec)
+    if (dim == 2 && curve == 0) PSI_BL(2, 0);
+    if (dim == 2 && curve == 1) PSI_BL(2, 1);
+    if (dim == 3 && curve == 0) PSI_BL(3, 0);
+    if (dim == 3 && curve == 1) PSI_BL(3, 1);
+#undef PSI_BL
+}
+
+void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
+                       uint64_t n_parent, uint32_t B) {
+    if (n_parent == 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_node_level<2>, dim3(blocks_for(n_parent, 256)), dim3(256), 0, st, child, n_child, parent, n_parent, B);
+    else
+        hipLaunchKernelGGL(k_node_level<3>, dim3(blocks_for(n_parent, 256)), dim3(256), 0, st, child, n_child, parent, n_parent, B);
+}
+
+void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp) {
+    // tmp: at least 2*L + scan_tmp_words(L) + 2 u32 words (as u64 storage)
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(tmp);
+    uint32_t* ex = cnt + L;
+    uint32_t* sc = ex + L + 1;
+    if (L) hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(L, 256)), dim3(256), 0, st, leaf, L, cnt);
+    launch_scan_u32(st, cnt, ex, L, ex + L, sc);
+    hipLaunchKernelGGL(k_widen, dim3(blocks_for(L + 1, 256)), dim3(256), 0, st, ex, L + 1, off);
+}
+
+void launch_export_sorted(hipStream_t st, int dim, int curve, const TreeView& t, const uint64_t* off,
+                          uint64_t* keys, uint32_t* ids, uint32_t* pts) {
+    if (t.L == 0) return;
+    const unsigned g = blocks_for(t.L, 256 / 64);
+#define PSI_EX(D, CV) hipLaunchKernelGGL((k_export_sorted<D, CV>), dim3(g), dim3(256), 0, st, t, off, keys, ids, pts)
+    if (dim == 2 && curve == 0) PSI_EX(2, 0);
+    if (dim == 2 && curve == 1) PSI_EX(2, 1);
+    if (dim == 3 && curve == 0) PSI_EX(3, 0);
+    if (dim == 3 && curve == 1) PSI_EX(3, 1);
+#undef PSI_EX
+}
+
+void launch_export_raw(hipStream_t st, int dim, const TreeView& t, const uint64_t* off, uint32_t* ids,
+                       uint32_t* pts) {
+    if (t.L == 0) return;
+    const unsigned g = blocks_for(t.L, 256 / 64);
+    if (dim == 2) hipLaunchKernelGGL(k_export_raw<2>, dim3(g), dim3(256), 0, st, t, off, ids, pts);
+    else hipLaunchKernelGGL(k_export_raw<3>, dim3(g), dim3(256), 0, st, t, off, ids, pts);
+}
+
+void launch_export_structure(hipStream_t st, int dim, const TreeView& t, uint64_t n_inner,
+                             const uint64_t* piv_key_src, const uint32_t* piv_id_src, uint64_t* piv_key,
+                             uint32_t* piv_id, uint32_t* leaf_cnt, uint32_t* leaf_lo, uint32_t* leaf_hi,
+                             uint32_t* node_lo, uint32_t* node_hi, uint64_t* node_cnt) {
+    const uint64_t tot = n_inner + t.L;
+    if (tot == 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_export_structure<2>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, t, n_inner, piv_key_src, piv_id_src, piv_key, piv_id, leaf_cnt, leaf_lo, leaf_hi, node_lo, node_hi, node_cnt);
+    else
+        hipLaunchKernelGGL(k_export_structure<3>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, t, n_inner, piv_key_src, piv_id_src, piv_key, piv_id, leaf_cnt, leaf_lo, leaf_hi, node_lo, node_hi, node_cnt);
+}
+
+}  // namespace psi

@@ -1,0 +1,482 @@
+// kNN and range queries over the SPaC-tree (Sec. 2.2 definitions; the
+// traversal follows App. C: visit subtrees in increasing distance from the
+// query to their boxes and prune a box farther than the current k-th
+// neighbour; leaves are scanned in full because their order is relaxed).
+//
+// Traversals keep no stack. The tree is implicit (node i of a level has
+// children B i .. B i + B - 1), so after finishing a node the next node is
+// found again from the parent: kNN re-scores the siblings and moves to the
+// nearest one not yet visited, range queries walk siblings in index order.
+//
+// Exactness: a subtree is skipped only when its box distance is strictly
+// greater than the k-th distance, so an equal-distance point with a smaller
+// id can still enter the result.
+#include "psi_kern.h"
+
+namespace psi {
+
+namespace {
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+template <int D>
+__device__ __forceinline__ uint64_t box_dist(const uint32_t* q, const NodeRec& r) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t a = q[d] < r.lo[d] ? r.lo[d] - q[d] : 0u;
+        const uint32_t b = q[d] > r.hi[d] ? q[d] - r.hi[d] : 0u;
+        const uint64_t x = a | b;
+        s += x * x;
+    }
+    return r.cnt ? s : PAD_D2;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t pt_dist(const uint32_t* q, const uint32_t* p) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint64_t x = q[d] > p[d] ? q[d] - p[d] : p[d] - q[d];
+        s += x * x;
+    }
+    return s;
+}
+
+__device__ __forceinline__ NodeRec fetch(const TreeView& t, const LevelInfo* lv, uint32_t l, uint64_t i) {
+    return l == t.h ? t.leaf[i] : t.inner[lv[l].off + i];
+}
+
+// Insert (d, id) into an ascending list of K pairs held in registers.
+template <int K>
+__device__ __forceinline__ void topk_insert(uint64_t (&bd)[K], uint32_t (&bi)[K], uint64_t d, uint32_t id) {
+#pragma unroll
+    for (int j = K - 1; j > 0; --j) {
+        const bool shift = pair_less(d, id, bd[j - 1], bi[j - 1]);
+        const bool here = !shift && pair_less(d, id, bd[j], bi[j]);
+        bd[j] = shift ? bd[j - 1] : (here ? d : bd[j]);
+        bi[j] = shift ? bi[j - 1] : (here ? id : bi[j]);
+    }
+    if (pair_less(d, id, bd[0], bi[0])) {
+        bd[0] = d;
+        bi[0] = id;
+    }
+}
+
+// ------------------------------------------------------- kNN, lane per query
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_knn_lane(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
+                                                  uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
+    __shared__ LevelInfo s_lv[64];
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    __syncthreads();
+    const uint64_t qi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    uint32_t q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+    uint64_t bd[K];
+    uint32_t bi[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        bd[j] = PAD_D2;
+        bi[j] = PAD_ID;
+    }
+    if (t.L > 0) {
+        const uint32_t C = t.C;
+        uint32_t l = 0;
+        uint64_t i = 0;
+        bool down = true;
+        for (;;) {
+            if (down) {
+                if (l == t.h) {
+                    const NodeRec r = t.leaf[i];
+                    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
+                    for (uint32_t e = 0; e < r.cnt; e += 4) {
+                        uint4 X[D];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e);
+                        const uint4 I = *reinterpret_cast<const uint4*>(s + D * C + e);
+                        const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
+                                                   {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
+                                                   {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
+                                                   {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
+                        const uint32_t is[4] = {I.x, I.y, I.z, I.w};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (e + u < r.cnt) {
+                                const uint64_t dd = pt_dist<D>(q, xs[u]);
+                                if (pair_less(dd, is[u], bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, is[u]);
+                            }
+                        }
+                    }
+                    down = false;
+                    continue;
+                }
+                const uint64_t c0 = i * t.B, c1 = min<uint64_t>(c0 + t.B, s_lv[l + 1].n);
+                uint64_t best = PAD_D2, bc = c0;
+                for (uint64_t c = c0; c < c1; ++c) {
+                    const uint64_t dd = box_dist<D>(q, fetch(t, s_lv, l + 1, c));
+                    if (dd < best) {
+                        best = dd;
+                        bc = c;
+                    }
+                }
+                if (best != PAD_D2 && best <= bd[K - 1]) {
+                    ++l;
+                    i = bc;
+                } else {
+                    down = false;
+                }
+            } else {
+                if (l == 0) break;
+                const uint64_t p = i / t.B, s0 = p * t.B, s1 = min<uint64_t>(s0 + t.B, s_lv[l].n);
+                const uint64_t dcur = box_dist<D>(q, fetch(t, s_lv, l, i));
+                uint64_t best = PAD_D2, bs = 0;
+                bool found = false;
+                for (uint64_t s = s0; s < s1; ++s) {
+                    if (s == i) continue;
+                    const uint64_t dd = box_dist<D>(q, fetch(t, s_lv, l, s));
+                    const bool after = dd > dcur || (dd == dcur && s > i);
+                    if (after && (!found || dd < best)) {
+                        best = dd;
+                        bs = s;
+                        found = true;
+                    }
+                }
+                if (found && best != PAD_D2 && best <= bd[K - 1]) {
+                    i = bs;
+                    down = true;
+                } else {
+                    --l;
+                    i = p;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        out_ids[qi * K + j] = bi[j];
+        out_d2[qi * K + j] = bd[j];
+    }
+}
+
+// ------------------------------------------------------- kNN, wave per query
+// The k best pairs live in LDS, ascending. A leaf is scanned one entry per
+// lane; the entries that beat the current k-th pair are ranked among
+// themselves, and both lists are merged by rank (merge by binary search).
+constexpr int KW_WAVES = 4;
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t x = shfl_u64(v, (int)(lane_id() ^ o));
+        v = x < v ? x : v;
+    }
+    return v;
+}
+
+// Among lanes with `on`, the pair (d, idx) that is smallest; returns false if none.
+__device__ __forceinline__ bool wave_argmin(bool on, uint64_t d, uint64_t& best_d, uint32_t& best_lane) {
+    const uint64_t m = wave_min_u64(on ? d : PAD_D2);
+    const uint64_t who = ballot(on && d == m);
+    if (who == 0) return false;
+    best_d = m;
+    best_lane = (uint32_t)__builtin_ctzll(who);
+    return true;
+}
+
+template <int D, int KMAX>
+__global__ __launch_bounds__(256) void k_knn_wave(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
+                                                  uint32_t k, uint32_t* __restrict__ out_ids,
+                                                  uint64_t* __restrict__ out_d2) {
+    __shared__ LevelInfo s_lv[64];
+    __shared__ uint64_t s_d[KW_WAVES][2][KMAX];
+    __shared__ uint32_t s_i[KW_WAVES][2][KMAX];
+    __shared__ uint64_t s_cd[KW_WAVES][64];
+    __shared__ uint32_t s_ci[KW_WAVES][64];
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    const uint64_t qi = (uint64_t)blockIdx.x * KW_WAVES + w;
+    if (qi >= nq) return;
+    uint32_t q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+    int cur = 0;
+    for (uint32_t x = lane; x < KMAX; x += 64) {
+        s_d[w][0][x] = PAD_D2;
+        s_i[w][0][x] = PAD_ID;
+    }
+    const uint32_t C = t.C;
+    if (t.L > 0) {
+        uint32_t l = 0;
+        uint64_t i = 0;
+        bool down = true;
+        for (;;) {
+            const uint64_t kth_d = s_d[w][cur][k - 1];
+            if (down) {
+                if (l == t.h) {
+                    const NodeRec r = t.leaf[i];
+                    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
+                    const uint32_t kth_i = s_i[w][cur][k - 1];
+                    for (uint32_t e0 = 0; e0 < r.cnt; e0 += 64) {
+                        const uint32_t e = e0 + lane;
+                        uint64_t dd = PAD_D2;
+                        uint32_t id = PAD_ID;
+                        bool cand = false;
+                        if (e < r.cnt) {
+                            uint32_t p[D];
+#pragma unroll
+                            for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+                            id = s[D * C + e];
+                            dd = pt_dist<D>(q, p);
+                            cand = pair_less(dd, id, s_d[w][cur][k - 1], s_i[w][cur][k - 1]);
+                        }
+                        (void)kth_i;
+                        const uint64_t cm = ballot(cand);
+                        if (cm == 0) continue;
+                        const uint32_t nc = (uint32_t)__popcll(cm);
+                        const uint32_t slot = count_below(cm);
+                        if (cand) {
+                            s_cd[w][slot] = dd;
+                            s_ci[w][slot] = id;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        // rank of each candidate among the candidates
+                        uint32_t rank = 0;
+                        if (cand) {
+                            for (uint32_t x = 0; x < nc; ++x) rank += pair_less(s_cd[w][x], s_ci[w][x], dd, id) ? 1u : 0u;
+                        }
+                        // position of each candidate in the merged list
+                        uint32_t cpos = 0;
+                        if (cand) {
+                            uint32_t lo = 0, hi = k;  // count list entries < (dd, id)
+                            while (lo < hi) {
+                                const uint32_t mid = (lo + hi) >> 1;
+                                if (pair_less(s_d[w][cur][mid], s_i[w][cur][mid], dd, id)) lo = mid + 1;
+                                else hi = mid;
+                            }
+                            cpos = rank + lo;
+                        }
+                        // sorted candidates, for the list side of the merge
+                        // (written after every lane has read the unsorted copy)
+                        __builtin_amdgcn_wave_barrier();
+                        if (cand) {
+                            s_cd[w][rank] = dd;
+                            s_ci[w][rank] = id;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        const int nxt = cur ^ 1;
+                        for (uint32_t x = lane; x < k; x += 64) {
+                            const uint64_t ld = s_d[w][cur][x];
+                            const uint32_t li = s_i[w][cur][x];
+                            uint32_t lo = 0, hi = nc;  // candidates smaller than list entry x
+                            while (lo < hi) {
+                                const uint32_t mid = (lo + hi) >> 1;
+                                if (pair_less(s_cd[w][mid], s_ci[w][mid], ld, li)) lo = mid + 1;
+                                else hi = mid;
+                            }
+                            const uint32_t pos = x + lo;
+                            if (pos < k) {
+                                s_d[w][nxt][pos] = ld;
+                                s_i[w][nxt][pos] = li;
+                            }
+                        }
+                        if (cand && cpos < k) {
+                            s_d[w][nxt][cpos] = dd;
+                            s_i[w][nxt][cpos] = id;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        cur = nxt;
+                    }
+                    down = false;
+                    continue;
+                }
+                const uint64_t c0 = i * t.B, c1 = min<uint64_t>(c0 + t.B, s_lv[l + 1].n);
+                const uint64_t c = c0 + lane;
+                const bool on = c < c1;
+                const uint64_t dd = on ? box_dist<D>(q, fetch(t, s_lv, l + 1, c)) : PAD_D2;
+                uint64_t best;
+                uint32_t bl;
+                if (wave_argmin(on && dd != PAD_D2, dd, best, bl) && best <= kth_d) {
+                    ++l;
+                    i = c0 + bl;
+                } else {
+                    down = false;
+                }
+            } else {
+                if (l == 0) break;
+                const uint64_t p = i / t.B, s0 = p * t.B, s1 = min<uint64_t>(s0 + t.B, s_lv[l].n);
+                const uint64_t s = s0 + lane;
+                const bool on = s < s1;
+                const uint64_t dd = on ? box_dist<D>(q, fetch(t, s_lv, l, s)) : PAD_D2;
+                const uint64_t dcur = shfl_u64(dd, (int)(i - s0));
+                const bool after = on && dd != PAD_D2 && (dd > dcur || (dd == dcur && s > i));
+                uint64_t best;
+                uint32_t bl;
+                if (wave_argmin(after, dd, best, bl) && best <= kth_d) {
+                    i = s0 + bl;
+                    down = true;
+                } else {
+                    --l;
+                    i = p;
+                }
+            }
+        }
+    }
+    for (uint32_t x = lane; x < k; x += 64) {
+        out_ids[qi * k + x] = s_i[w][cur][x];
+        out_d2[qi * k + x] = s_d[w][cur][x];
+    }
+}
+
+// ------------------------------------------------------------ range queries
+template <int D>
+__device__ __forceinline__ int box_relation(const NodeRec& r, const uint32_t* lo, const uint32_t* hi) {
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (r.hi[d] < lo[d] || r.lo[d] > hi[d]) return 0;  // disjoint
+        inside = inside && lo[d] <= r.lo[d] && r.hi[d] <= hi[d];
+    }
+    return inside ? 2 : 1;
+}
+
+template <int D>
+__device__ __forceinline__ bool in_box(const uint32_t* p, const uint32_t* lo, const uint32_t* hi) {
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) in = in && lo[d] <= p[d] && p[d] <= hi[d];
+    return in;
+}
+
+// REPORT = false: count; REPORT = true: write ids to out[0 .. lim).
+template <int D, bool REPORT>
+__global__ __launch_bounds__(256) void k_range(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
+                                               uint64_t* __restrict__ counts, const uint64_t* __restrict__ offsets,
+                                               uint32_t* __restrict__ out_ids) {
+    __shared__ LevelInfo s_lv[64];
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    __syncthreads();
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    uint32_t lo[D], hi[D];
+    bool empty = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = boxes[b * 2 * D + d];
+        hi[d] = boxes[b * 2 * D + D + d];
+        empty = empty || lo[d] > hi[d];
+    }
+    uint64_t cnt = 0;
+    uint64_t o = 0, lim = 0;
+    uint32_t* out = nullptr;
+    if (REPORT) {
+        o = offsets[b];
+        lim = offsets[b + 1];
+        out = out_ids;
+    }
+    const uint32_t C = t.C;
+    if (!empty && t.L > 0) {
+        uint32_t l = 0;
+        uint64_t i = 0;
+        for (;;) {
+            const NodeRec r = fetch(t, s_lv, l, i);
+            const int rel = r.cnt ? box_relation<D>(r, lo, hi) : 0;
+            bool descend = false;
+            if (rel == 2) {
+                if (!REPORT) {
+                    cnt += r.cnt;
+                } else {
+                    const uint64_t span = s_lv[l].span;
+                    const uint64_t j1 = min<uint64_t>((i + 1) * span, t.L);
+                    for (uint64_t j = i * span; j < j1; ++j) {
+                        const NodeRec lf = t.leaf[j];
+                        const uint32_t* s = t.slots + (uint64_t)lf.slot * (D + 1) * C + D * C;
+                        for (uint32_t e = 0; e < lf.cnt && o < lim; ++e) out[o++] = s[e];
+                    }
+                }
+            } else if (rel == 1) {
+                if (l == t.h) {
+                    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
+                    for (uint32_t e = 0; e < r.cnt; ++e) {
+                        uint32_t p[D];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+                        if (in_box<D>(p, lo, hi)) {
+                            if (!REPORT) ++cnt;
+                            else if (o < lim) out[o++] = s[D * C + e];
+                        }
+                    }
+                } else {
+                    descend = true;
+                }
+            }
+            if (descend) {
+                ++l;
+                i *= t.B;
+                continue;
+            }
+            bool done = false;
+            for (;;) {
+                if (l == 0) {
+                    done = true;
+                    break;
+                }
+                if ((i + 1) % t.B != 0 && i + 1 < s_lv[l].n) {
+                    ++i;
+                    break;
+                }
+                --l;
+                i /= t.B;
+            }
+            if (done) break;
+        }
+    }
+    if (!REPORT) counts[b] = cnt;
+}
+
+}  // namespace
+
+void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, uint64_t nq, uint32_t k,
+                uint32_t* ids, uint64_t* d2) {
+    if (nq == 0) return;
+    const unsigned gl = blocks_for(nq, 256);
+    const unsigned gw = blocks_for(nq, KW_WAVES);
+#define PSI_KL(D, K) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, ids, d2)
+#define PSI_KL_ALL(D)                                                                                    \
+    switch (k) {                                                                                         \
+        case 1: PSI_KL(D, 1); break;   case 2: PSI_KL(D, 2); break;   case 3: PSI_KL(D, 3); break;       \
+        case 4: PSI_KL(D, 4); break;   case 5: PSI_KL(D, 5); break;   case 6: PSI_KL(D, 6); break;       \
+        case 7: PSI_KL(D, 7); break;   case 8: PSI_KL(D, 8); break;   case 9: PSI_KL(D, 9); break;       \
+        case 10: PSI_KL(D, 10); break; case 11: PSI_KL(D, 11); break; case 12: PSI_KL(D, 12); break;     \
+        case 13: PSI_KL(D, 13); break; case 14: PSI_KL(D, 14); break; case 15: PSI_KL(D, 15); break;     \
+        case 16: PSI_KL(D, 16); break;                                                                   \
+        default:                                                                                         \
+            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
+            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
+            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
+    }
+    if (dim == 2) { PSI_KL_ALL(2) } else { PSI_KL_ALL(3) }
+#undef PSI_KL_ALL
+#undef PSI_KL
+}
+
+void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                        uint64_t* counts) {
+    if (nb == 0) return;
+    const unsigned g = blocks_for(nb, 256);
+    if (dim == 2) hipLaunchKernelGGL((k_range<2, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, counts, nullptr, nullptr);
+    else hipLaunchKernelGGL((k_range<3, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, counts, nullptr, nullptr);
+}
+
+void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                         const uint64_t* offsets, uint32_t* ids) {
+    if (nb == 0) return;
+    const unsigned g = blocks_for(nb, 256);
+    if (dim == 2) hipLaunchKernelGGL((k_range<2, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, nullptr, offsets, ids);
+    else hipLaunchKernelGGL((k_range<3, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, nullptr, offsets, ids);
+}
+
+}  // namespace psi

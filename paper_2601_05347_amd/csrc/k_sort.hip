@@ -1,0 +1,377 @@
+// Curve encoding and the LSD radix sort of (key, id) pairs.
+//
+// Alg. 3 sorts only (code, id) pairs and computes each code when its point is
+// first touched. Here the first touch is the histogram kernel: it reads the
+// coordinates once, writes the keys (which double as the id -> key table used
+// by deletes) and counts the digits of all eight passes. Each pass is then one
+// read and one write of the pairs: a tile ranks its pairs with wave ballots,
+// learns its global offset by a decoupled look-back over earlier tiles, stages
+// the pairs in LDS in digit order and writes them out in digit runs.
+#include "psi_kern.h"
+
+namespace psi {
+
+namespace {
+
+constexpr int WAVES = SORT_WG / 64;
+constexpr uint32_t FLAG_AGG = 1u, FLAG_INC = 2u;
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+__device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint32_t flag, uint32_t v) {
+    return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | v;
+}
+
+// Inclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_incl_scan256(uint32_t v, uint32_t* s_wsum) {
+    const uint32_t lane = lane_id();
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = shfl_u32(v, (int)lane - o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    if (lane == 63) s_wsum[w] = v;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int i = 0; i < w; ++i) add += s_wsum[i];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(256) void k_hist_pairs(const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ ids, uint32_t id_base,
+                                                    uint64_t n, PassList pl, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[MAX_PASSES][RADIX];
+    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t k = keys[i];
+        const uint32_t id = ids ? ids[i] : id_base + (uint32_t)i;
+        for (int p = 0; p < pl.n; ++p) {
+            const uint32_t dg = (pl.src[p] ? (uint64_t)id >> pl.shift[p] : k >> pl.shift[p]) & (RADIX - 1);
+            atomicAdd(&h[p][dg], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < pl.n * RADIX; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+template <int D, int CURVE, bool HIST>
+__global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict__ pts, uint64_t n,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ err) {
+    __shared__ uint32_t h[HIST ? 8 : 1][RADIX];
+    if (HIST) {
+        for (int i = threadIdx.x; i < 8 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
+        __syncthreads();
+    }
+    bool bad = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t p[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = pts[i * D + d];
+        bad |= !coord_ok<D>(p);
+        const uint64_t k = sfc_key<D, CURVE>(p);
+        keys[i] = k;
+        if (HIST) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) atomicAdd(&h[b][(k >> (8 * b)) & 255u], 1u);
+        }
+    }
+    if (bad) atomicOr(err, ERR_RANGE);
+    if (HIST) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 8 * RADIX; i += blockDim.x) {
+            const uint32_t v = (&h[0][0])[i];
+            if (v) atomicAdd(&hist[i], v);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ off) {
+    __shared__ uint32_t s_w[WAVES];
+    const uint32_t v = hist[blockIdx.x * RADIX + threadIdx.x];
+    const uint32_t inc = block_incl_scan256(v, s_w);
+    off[blockIdx.x * RADIX + threadIdx.x] = inc - v;
+}
+
+template <bool IMPLICIT_ID, bool DIGIT_ID>
+__global__ __launch_bounds__(SORT_WG) void k_onesweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin, uint32_t id_base,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n, uint32_t shift,
+    const uint32_t* __restrict__ dig_off, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
+    uint32_t epoch, uint32_t* __restrict__ err) {
+    __shared__ uint64_t s_key[SORT_TILE];
+    __shared__ uint32_t s_id[SORT_TILE];
+    __shared__ uint32_t s_wcnt[WAVES][RADIX];  // running counts per wave, then wave prefixes
+    __shared__ uint32_t s_loc[RADIX];          // first local slot of each digit
+    __shared__ uint32_t s_base[RADIX];         // global destination of local slot 0 of each digit
+    __shared__ uint32_t s_wsum[WAVES];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const uint32_t lane = lane_id();
+    for (int i = tid; i < WAVES * RADIX; i += SORT_WG) (&s_wcnt[0][0])[i] = 0;
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= gridDim.x) {  // counter not reset: never index past the status array
+        if (tid == 0) atomicOr(err, ERR_SPIN);
+        return;
+    }
+    const uint64_t wbase = (uint64_t)tile * SORT_TILE + (uint64_t)w * (SORT_IPT * 64);
+
+    uint64_t k[SORT_IPT];
+    uint32_t id[SORT_IPT];
+    uint32_t rk[SORT_IPT];
+#pragma unroll
+    for (int i = 0; i < SORT_IPT; ++i) {
+        const uint64_t pos = wbase + (uint64_t)i * 64 + lane;
+        const bool ok = pos < n;
+        k[i] = ok ? kin[pos] : 0ull;
+        id[i] = ok ? (IMPLICIT_ID ? id_base + (uint32_t)pos : iin[pos]) : 0u;
+    }
+    // Rank inside the wave, item by item (stable: item order = position order).
+#pragma unroll
+    for (int i = 0; i < SORT_IPT; ++i) {
+        const bool ok = wbase + (uint64_t)i * 64 + lane < n;
+        const uint32_t dg = (DIGIT_ID ? (uint64_t)id[i] >> shift : k[i] >> shift) & (RADIX - 1);
+        uint64_t peers = ballot(ok);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = count_below(peers);
+        const uint32_t base = s_wcnt[w][dg];
+        if (ok && below == 0) s_wcnt[w][dg] = base + (uint32_t)__popcll(peers);
+        rk[i] = base + below;
+    }
+    __syncthreads();
+
+    // Thread tid owns digit tid.
+    const uint32_t d = tid;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+        const uint32_t c = s_wcnt[x][d];
+        s_wcnt[x][d] = tot;
+        tot += c;
+    }
+    uint64_t* my = status + (uint64_t)tile * RADIX + d;
+    __hip_atomic_store(my, pack_status(epoch, tile == 0 ? FLAG_INC : FLAG_AGG, tot), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t loc = block_incl_scan256(tot, s_wsum) - tot;
+    s_loc[d] = loc;
+
+    uint32_t excl = 0;
+    if (tile > 0) {
+        int64_t t = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (t >= 0) {
+            const uint64_t s = __hip_atomic_load(status + (uint64_t)t * RADIX + d, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t fl = (uint32_t)(s >> 32) & 3u;
+            if ((uint32_t)(s >> 34) != epoch || fl == 0) {
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(err, ERR_SPIN);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += (uint32_t)s;
+            if (fl == FLAG_INC) break;
+            --t;
+        }
+        __hip_atomic_store(my, pack_status(epoch, FLAG_INC, excl + tot), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_base[d] = dig_off[d] + excl - loc;
+    __syncthreads();
+
+    // Stage in LDS in (digit, position) order.
+#pragma unroll
+    for (int i = 0; i < SORT_IPT; ++i) {
+        const bool ok = wbase + (uint64_t)i * 64 + lane < n;
+        if (ok) {
+            const uint32_t dg = (DIGIT_ID ? (uint64_t)id[i] >> shift : k[i] >> shift) & (RADIX - 1);
+            const uint32_t lp = s_loc[dg] + s_wcnt[w][dg] + rk[i];
+            s_key[lp] = k[i];
+            s_id[lp] = id[i];
+        }
+    }
+    __syncthreads();
+
+    const uint64_t tstart = (uint64_t)tile * SORT_TILE;
+    const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)SORT_TILE, n - tstart);
+    for (uint32_t j = tid; j < nvalid; j += SORT_WG) {
+        const uint64_t kk = s_key[j];
+        const uint32_t ii = s_id[j];
+        const uint32_t dg = (DIGIT_ID ? (uint64_t)ii >> shift : kk >> shift) & (RADIX - 1);
+        const uint64_t dst = (uint64_t)s_base[dg] + j;
+        if (dst < n) {
+            kout[dst] = kk;
+            iout[dst] = ii;
+        } else {
+            atomicOr(err, ERR_CAPACITY);
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_iota_u32(uint32_t* p, uint64_t n, uint32_t base) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = base + (uint32_t)i;
+}
+
+// ---- exclusive scan (reduce, scan of tile sums, downsweep) ----
+constexpr int SCAN_WG = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_WG * SCAN_IPT;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
+                                                     uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_w[WAVES];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_IPT; ++i) {
+        const uint64_t p = base + (uint64_t)i * SCAN_WG + threadIdx.x;
+        if (p < n) v += in[p];
+    }
+    v = wave_sum_u32(v);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < WAVES; ++i) t += s_w[i];
+        sums[blockIdx.x] = t;
+    }
+}
+
+// Single block: exclusive scan of m tile sums in place; total -> *total.
+__global__ __launch_bounds__(256) void k_scan_sums(uint32_t* __restrict__ sums, uint64_t m,
+                                                   uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_w[WAVES];
+    __shared__ uint32_t s_tot;
+    uint32_t carry = 0;
+    for (uint64_t b = 0; b < m; b += SCAN_WG) {
+        const uint64_t p = b + threadIdx.x;
+        const uint32_t v = p < m ? sums[p] : 0u;
+        const uint32_t inc = block_incl_scan256(v, s_w);
+        if (p < m) sums[p] = carry + inc - v;
+        if (threadIdx.x == SCAN_WG - 1) s_tot = inc;
+        __syncthreads();
+        carry += s_tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, uint64_t n,
+                                                   const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_w[WAVES];
+    // blocked layout: thread t owns items [t*IPT, t*IPT+IPT) of the tile
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_IPT;
+    uint32_t v[SCAN_IPT];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_IPT; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0u;
+        s += v[i];
+    }
+    const uint32_t inc = block_incl_scan256(s, s_w);
+    uint32_t run = sums[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_IPT; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids, uint32_t id_base,
+                       uint64_t n, const PassList& pl, uint32_t* hist) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 16);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_hist_pairs, dim3(g), dim3(256), 0, st, keys, ids, id_base, n, pl, hist);
+}
+
+void launch_encode_hist(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                        uint32_t* hist, uint32_t* err) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 16);
+    if (g > 4096) g = 4096;
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
+}
+
+void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                   uint32_t* err) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 4);
+    if (g > 8192) g = 8192;
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+}
+
+void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint32_t* off) {
+    hipLaunchKernelGGL(k_digit_offsets, dim3(npass), dim3(256), 0, st, hist, off);
+}
+
+void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
+                     const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
+                     uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
+                     uint32_t epoch, uint32_t* err) {
+    if (n == 0) return;
+    const unsigned g = blocks_for(n, SORT_TILE);
+    if (implicit_ids && !digit_from_id)
+        hipLaunchKernelGGL((k_onesweep<true, false>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
+    else if (implicit_ids && digit_from_id)
+        hipLaunchKernelGGL((k_onesweep<true, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
+    else if (digit_from_id)
+        hipLaunchKernelGGL((k_onesweep<false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
+    else
+        hipLaunchKernelGGL((k_onesweep<false, false>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
+}
+
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
+    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+}
+void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base) {
+    if (n) hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, base);
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                     uint32_t* tmp) {
+    if (n == 0) {
+        if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, (uint64_t)1, 0u);
+        return;
+    }
+    const uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_WG), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_WG), 0, st, tmp, tiles, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(SCAN_WG), 0, st, in, n, tmp, out);
+}
+
+}  // namespace psi

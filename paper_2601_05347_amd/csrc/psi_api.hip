@@ -1,0 +1,416 @@
+// C ABI of the library: index lifetime, build, queries, inspection, timing.
+#include <cstring>
+#include <new>
+
+#include "psi_index.h"
+
+using namespace psi;
+
+namespace psi {
+
+psi_status hip_ok(hipError_t e) {
+    if (e == hipSuccess) return PSI_OK;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? PSI_E_NOMEM : PSI_E_HIP;
+}
+
+static psi_status last_launch() { return hip_ok(hipGetLastError()); }
+
+psi_status readback(psi_index ix, const void* dev, size_t bytes) {
+    psi_status s = hip_ok(hipMemcpyAsync(ix->pinned, dev, bytes, hipMemcpyDeviceToHost, ix->st));
+    if (s != PSI_OK) return s;
+    return hip_ok(hipStreamSynchronize(ix->st));
+}
+
+// Stable LSD sort of (key, id) pairs; the result lands in sorter.k/i[*which].
+// Passes: optionally the four id bytes first (so equal keys end up in id
+// order whatever the input order), then the eight key bytes.
+psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
+                      bool id_digits, bool hist_ready, int* which) {
+    Sorter& S = ix->sorter;
+    PassList pl{};
+    pl.n = 0;
+    if (id_digits)
+        for (int b = 0; b < 4; ++b) { pl.src[pl.n] = 1; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
+    for (int b = 0; b < 8; ++b) { pl.src[pl.n] = 0; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
+    psi_status s;
+    if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    if ((s = S.off.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    if ((s = S.ctr.ensure(MAX_PASSES * 4)) != PSI_OK) return s;
+    for (int b = 0; b < 2; ++b) {
+        if ((s = S.k[b].ensure(n * 8)) != PSI_OK) return s;
+        if ((s = S.i[b].ensure(n * 4)) != PSI_OK) return s;
+    }
+    const uint64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if (tiles * RADIX > S.status_words) {
+        if ((s = S.status.ensure(tiles * RADIX * 8)) != PSI_OK) return s;
+        S.status_words = S.status.bytes / 8;
+        launch_fill_u32(ix->st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
+    }
+    if (!hist_ready) {
+        launch_fill_u32(ix->st, S.hist.as<uint32_t>(), (uint64_t)pl.n * RADIX, 0u);
+        ProfScope ps(ix, "hist", n * 12);
+        launch_hist_pairs(ix->st, kin, iin, id_base, n, pl, S.hist.as<uint32_t>());
+    } else if (id_digits) {
+        return PSI_E_INTERNAL;
+    }
+    launch_digit_offsets(ix->st, pl.n, S.hist.as<uint32_t>(), S.off.as<uint32_t>());
+    launch_fill_u32(ix->st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);
+    const uint64_t* ksrc = kin;
+    const uint32_t* isrc = iin;
+    for (int p = 0; p < pl.n; ++p) {
+        const int dst = p & 1;
+        if (++S.epoch >= (1u << 30)) {
+            S.epoch = 1;
+            launch_fill_u32(ix->st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
+        }
+        {
+            ProfScope ps(ix, "radix_pass", n * 24);
+            launch_onesweep(ix->st, p == 0 && iin == nullptr, pl.src[p] == 1, ksrc, isrc, id_base,
+                            S.k[dst].as<uint64_t>(), S.i[dst].as<uint32_t>(), n, pl.shift[p],
+                            S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(),
+                            S.ctr.as<uint32_t>() + p, S.epoch, ix->err.as<uint32_t>());
+        }
+        ksrc = S.k[dst].as<uint64_t>();
+        isrc = S.i[dst].as<uint32_t>();
+    }
+    *which = (pl.n - 1) & 1;
+    return last_launch();
+}
+
+// Node levels over the current directory: shape on the host, unions on the
+// device, from the level just above the leaves up to the root.
+psi_status build_nodes(psi_index ix) {
+    ix->lv.clear();
+    ix->n_inner = 0;
+    ix->h = 0;
+    if (ix->L == 0) return PSI_OK;
+    std::vector<uint64_t> sizes;  // leaves first, root last
+    uint64_t n = ix->L;
+    sizes.push_back(n);
+    while (n > 1) {
+        n = (n + ix->B - 1) / ix->B;
+        sizes.push_back(n);
+    }
+    const uint32_t h = (uint32_t)sizes.size() - 1;
+    if (h + 1 > (uint32_t)MAX_LEVELS) return PSI_E_INTERNAL;
+    ix->h = h;
+    ix->lv.resize(h + 1);
+    uint64_t off = 0, span = 1;
+    for (uint32_t l = 0; l <= h; ++l) {
+        ix->lv[l].n = sizes[h - l];
+        ix->lv[l].off = l < h ? off : 0;
+        if (l < h) off += sizes[h - l];
+    }
+    for (int l = (int)h; l >= 0; --l) {
+        ix->lv[l].span = span;
+        span *= ix->B;
+    }
+    ix->n_inner = off;
+    psi_status s = ix->inner.ensure(std::max<uint64_t>(off, 1) * sizeof(NodeRec));
+    if (s != PSI_OK) return s;
+    NodeRec* inner = ix->inner.as<NodeRec>();
+    const NodeRec* leaf = ix->leaf[ix->cur].as<NodeRec>();
+    ProfScope ps(ix, "nodes", off * 32 + ix->L * 32);
+    for (int l = (int)h - 1; l >= 0; --l) {
+        const NodeRec* child = (l + 1 == (int)h) ? leaf : inner + ix->lv[l + 1].off;
+        launch_node_level(ix->st, ix->D, child, ix->lv[l + 1].n, inner + ix->lv[l].off, ix->lv[l].n, ix->B);
+    }
+    return last_launch();
+}
+
+// Fresh build of n points whose ids are id_base .. id_base + n - 1 (Alg. 3).
+psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base) {
+    psi_status s;
+    const uint64_t idn = (uint64_t)id_base + n;
+    if ((s = ix->idkey.grow_keep(idn * 8, (uint64_t)id_base * 8, ix->st)) != PSI_OK) return s;
+    ix->L = 0;
+    ix->slot_top = 0;
+    ix->n_free = 0;
+    if (n == 0) {
+        ix->n_live = 0;
+        return build_nodes(ix);
+    }
+    Sorter& S = ix->sorter;
+    if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    launch_fill_u32(ix->st, S.hist.as<uint32_t>(), 8 * RADIX, 0u);
+    uint64_t* keys = ix->idkey.as<uint64_t>() + id_base;
+    {
+        ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
+        launch_encode_hist(ix->st, ix->D, ix->curve, d_pts, n, keys, S.hist.as<uint32_t>(), ix->err.as<uint32_t>());
+    }
+    int w = 0;
+    if ((s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w)) != PSI_OK) return s;
+    const uint64_t L = (n + ix->phi - 1) / ix->phi;
+    const int c = ix->cur;
+    if ((s = ix->slots.ensure(L * ix->slot_words() * 4)) != PSI_OK) return s;
+    if ((s = ix->leaf[c].ensure(L * sizeof(NodeRec))) != PSI_OK) return s;
+    if ((s = ix->pkey[c].ensure(L * 8)) != PSI_OK) return s;
+    if ((s = ix->pid[c].ensure(L * 4)) != PSI_OK) return s;
+    {
+        ProfScope ps(ix, "leaf_fill", n * (12 + 4 * (uint64_t)(ix->D + 1)) + L * 44);
+        launch_build_leaves(ix->st, ix->D, ix->curve, S.k[w].as<uint64_t>(), S.i[w].as<uint32_t>(), n, L, ix->C,
+                            ix->slots.as<uint32_t>(), ix->pkey[c].as<uint64_t>(), ix->pid[c].as<uint32_t>(),
+                            ix->leaf[c].as<NodeRec>());
+    }
+    ix->L = L;
+    ix->slot_top = L;
+    ix->n_live = n;
+    if ((s = last_launch()) != PSI_OK) return s;
+    return build_nodes(ix);
+}
+
+}  // namespace psi
+
+psi::TreeView psi_index_s::view() const {
+    psi::TreeView t{};
+    t.inner = inner.as<psi::NodeRec>();
+    t.leaf = leaf[cur].as<psi::NodeRec>();
+    t.slots = slots.as<uint32_t>();
+    t.h = h;
+    t.B = B;
+    t.C = C;
+    t.L = L;
+    for (size_t l = 0; l < lv.size() && l < (size_t)psi::MAX_LEVELS; ++l) t.lv[l] = lv[l];
+    return t;
+}
+
+extern "C" {
+
+const char* psi_status_str(psi_status s) {
+    switch (s) {
+        case PSI_OK: return "ok";
+        case PSI_E_ARG: return "invalid argument";
+        case PSI_E_RANGE: return "coordinate out of range";
+        case PSI_E_NOMEM: return "out of device memory";
+        case PSI_E_CAPACITY: return "id space exhausted";
+        case PSI_E_HIP: return "HIP runtime error";
+        case PSI_E_STATE: return "invalid state";
+        case PSI_E_INTERNAL: return "internal consistency check failed";
+    }
+    return "unknown status";
+}
+
+psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out) {
+    if (!prm || !out) return PSI_E_ARG;
+    *out = nullptr;
+    if ((prm->dim != 2 && prm->dim != 3) || prm->curve > 1 || prm->leaf_size < 2 || prm->leaf_size > 32 ||
+        prm->fanout < 2 || prm->fanout > 32 || prm->flags != 0)
+        return PSI_E_ARG;
+    psi_index ix = new (std::nothrow) psi_index_s;
+    if (!ix) return PSI_E_NOMEM;
+    ix->D = (int)prm->dim;
+    ix->curve = (int)prm->curve;
+    ix->phi = prm->leaf_size;
+    ix->C = (2 * prm->leaf_size + 3) & ~3u;
+    ix->B = prm->fanout;
+    ix->st = static_cast<hipStream_t>(hip_stream);
+    psi_status s = ix->err.ensure(64);
+    if (s == PSI_OK) s = hip_ok(hipHostMalloc(&ix->pinned, 4096, hipHostMallocDefault));
+    if (s == PSI_OK) s = hip_ok(hipMemsetAsync(ix->err.p, 0, 64, ix->st));
+    if (s == PSI_OK) s = hip_ok(hipStreamSynchronize(ix->st));
+    if (s != PSI_OK) {
+        if (ix->pinned) (void)hipHostFree(ix->pinned);
+        delete ix;
+        return s;
+    }
+    *out = ix;
+    return PSI_OK;
+}
+
+psi_status psi_destroy(psi_index ix) {
+    if (!ix) return PSI_E_ARG;
+    (void)hipStreamSynchronize(ix->st);
+    if (ix->pinned) (void)hipHostFree(ix->pinned);
+    delete ix;
+    return PSI_OK;
+}
+
+psi_status psi_set_stream(psi_index ix, void* hip_stream) {
+    if (!ix) return PSI_E_ARG;
+    psi_status s = hip_ok(hipStreamSynchronize(ix->st));
+    ix->st = static_cast<hipStream_t>(hip_stream);
+    return s;
+}
+
+psi_status psi_build(psi_index ix, const uint32_t* d_pts, uint64_t n) {
+    if (!ix || (n && !d_pts)) return PSI_E_ARG;
+    if (n > 0xFFFFFFFFull) return PSI_E_CAPACITY;
+    ix->next_id = 0;
+    psi_status s = do_build(ix, d_pts, n, 0);
+    if (s == PSI_OK) ix->next_id = (uint32_t)n;
+    return s;
+}
+
+psi_status psi_batch_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids) {
+    if (!ix || (m && !d_pts)) return PSI_E_ARG;
+    if ((uint64_t)ix->next_id + m > 0xFFFFFFFFull) return PSI_E_CAPACITY;
+    if (m == 0) return PSI_OK;
+    return do_insert(ix, d_pts, m, d_new_ids);
+}
+
+psi_status psi_batch_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
+    if (!ix || (m && !d_ids)) return PSI_E_ARG;
+    if (m > 0xFFFFFFFFull) return PSI_E_ARG;
+    return do_delete(ix, d_ids, m, d_ndeleted);
+}
+
+psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids, uint64_t* d_d2) {
+    if (!ix || k == 0 || k > 128 || (nq && (!d_q || !d_ids || !d_d2))) return PSI_E_ARG;
+    if (nq == 0) return PSI_OK;
+    ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
+    launch_knn(ix->st, ix->D, ix->view(), d_q, nq, k, d_ids, d_d2);
+    return last_launch();
+}
+
+psi_status psi_range_count(psi_index ix, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts) {
+    if (!ix || (nb && (!d_boxes || !d_counts))) return PSI_E_ARG;
+    if (nb == 0) return PSI_OK;
+    ProfScope ps(ix, "range_count", nb * (8ull * ix->D + 8));
+    launch_range_count(ix->st, ix->D, ix->view(), d_boxes, nb, d_counts);
+    return last_launch();
+}
+
+psi_status psi_range_report(psi_index ix, const uint32_t* d_boxes, uint64_t nb, const uint64_t* d_offsets,
+                            uint32_t* d_ids) {
+    if (!ix || (nb && (!d_boxes || !d_offsets))) return PSI_E_ARG;
+    if (nb == 0) return PSI_OK;
+    ProfScope ps(ix, "range_report", nb * (8ull * ix->D + 16));
+    launch_range_report(ix->st, ix->D, ix->view(), d_boxes, nb, d_offsets, d_ids);
+    return last_launch();
+}
+
+psi_status psi_sync(psi_index ix) {
+    if (!ix) return PSI_E_ARG;
+    psi_status s = readback(ix, ix->err.p, 4);
+    if (s != PSI_OK) return s;
+    uint32_t e = 0;
+    std::memcpy(&e, ix->pinned, 4);
+    if (e) {
+        (void)hipMemsetAsync(ix->err.p, 0, 4, ix->st);
+        (void)hipStreamSynchronize(ix->st);
+        if (e & ERR_RANGE) return PSI_E_RANGE;
+        return PSI_E_INTERNAL;
+    }
+    return PSI_OK;
+}
+
+psi_status psi_size(psi_index ix, uint64_t* h_n_live) {
+    if (!ix || !h_n_live) return PSI_E_ARG;
+    psi_status s = psi_sync(ix);
+    *h_n_live = ix->n_live;
+    return s;
+}
+
+psi_status psi_next_id(psi_index ix, uint32_t* h_next_id) {
+    if (!ix || !h_next_id) return PSI_E_ARG;
+    *h_next_id = ix->next_id;
+    return PSI_OK;
+}
+
+psi_status psi_export(psi_index ix, uint64_t* d_keys, uint32_t* d_ids, uint32_t* d_pts) {
+    if (!ix) return PSI_E_ARG;
+    if (ix->L == 0) return PSI_OK;
+    psi_status s;
+    if ((s = ix->scr.a.ensure((ix->L + 1) * 8)) != PSI_OK) return s;
+    if ((s = ix->scr.b.ensure((2 * ix->L + scan_tmp_words(ix->L) + 4) * 8)) != PSI_OK) return s;
+    launch_leaf_offsets(ix->st, ix->leaf[ix->cur].as<NodeRec>(), ix->L, ix->scr.a.as<uint64_t>(), ix->scr.b.as<uint64_t>());
+    launch_export_sorted(ix->st, ix->D, ix->curve, ix->view(), ix->scr.a.as<uint64_t>(), d_keys, d_ids, d_pts);
+    return last_launch();
+}
+
+psi_status psi_export_leaves(psi_index ix, uint32_t* d_ids, uint32_t* d_pts) {
+    if (!ix) return PSI_E_ARG;
+    if (ix->L == 0) return PSI_OK;
+    psi_status s;
+    if ((s = ix->scr.a.ensure((ix->L + 1) * 8)) != PSI_OK) return s;
+    if ((s = ix->scr.b.ensure((2 * ix->L + scan_tmp_words(ix->L) + 4) * 8)) != PSI_OK) return s;
+    launch_leaf_offsets(ix->st, ix->leaf[ix->cur].as<NodeRec>(), ix->L, ix->scr.a.as<uint64_t>(), ix->scr.b.as<uint64_t>());
+    launch_export_raw(ix->st, ix->D, ix->view(), ix->scr.a.as<uint64_t>(), d_ids, d_pts);
+    return last_launch();
+}
+
+psi_status psi_shape(psi_index ix, uint64_t* h_n_leaves, uint32_t* h_height, uint64_t* h_level_sizes) {
+    if (!ix || !h_n_leaves || !h_height) return PSI_E_ARG;
+    *h_n_leaves = ix->L;
+    *h_height = ix->h;
+    if (h_level_sizes)
+        for (uint32_t l = 0; l < ix->lv.size(); ++l) h_level_sizes[l] = ix->lv[l].n;
+    return PSI_OK;
+}
+
+psi_status psi_export_structure(psi_index ix, uint64_t* d_piv_key, uint32_t* d_piv_id, uint32_t* d_leaf_cnt,
+                                uint32_t* d_leaf_lo, uint32_t* d_leaf_hi, uint32_t* d_node_lo, uint32_t* d_node_hi,
+                                uint64_t* d_node_cnt) {
+    if (!ix) return PSI_E_ARG;
+    launch_export_structure(ix->st, ix->D, ix->view(), ix->n_inner, ix->pkey[ix->cur].as<uint64_t>(),
+                            ix->pid[ix->cur].as<uint32_t>(), d_piv_key, d_piv_id, d_leaf_cnt, d_leaf_lo, d_leaf_hi,
+                            d_node_lo, d_node_hi, d_node_cnt);
+    return last_launch();
+}
+
+psi_status psi_encode(uint32_t dim, uint32_t curve, const uint32_t* d_pts, uint64_t n, uint64_t* d_keys,
+                      void* hip_stream) {
+    if ((dim != 2 && dim != 3) || curve > 1 || (n && (!d_pts || !d_keys))) return PSI_E_ARG;
+    if (n == 0) return PSI_OK;
+    Buf err;
+    psi_status s = err.ensure(4);
+    if (s != PSI_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    launch_fill_u32(st, err.as<uint32_t>(), 1, 0u);
+    launch_encode(st, (int)dim, (int)curve, d_pts, n, d_keys, err.as<uint32_t>());
+    uint32_t e = 0;
+    if ((s = hip_ok(hipMemcpyAsync(&e, err.p, 4, hipMemcpyDeviceToHost, st))) != PSI_OK) return s;
+    if ((s = hip_ok(hipStreamSynchronize(st))) != PSI_OK) return s;
+    return e ? PSI_E_RANGE : PSI_OK;
+}
+
+psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_t n, uint64_t* d_keys_out,
+                          uint32_t* d_ids_out, void* hip_stream) {
+    if (n && (!d_keys || !d_ids || !d_keys_out || !d_ids_out)) return PSI_E_ARG;
+    if (n > 0xFFFFFFFFull) return PSI_E_ARG;
+    if (n == 0) return PSI_OK;
+    psi_params prm{2, 0, 32, 8, 0};
+    psi_index ix = nullptr;
+    psi_status s = psi_create(&prm, hip_stream, &ix);
+    if (s != PSI_OK) return s;
+    int w = 0;
+    s = sort_pairs(ix, d_keys, d_ids, 0, n, true, false, &w);
+    if (s == PSI_OK) s = hip_ok(hipMemcpyAsync(d_keys_out, ix->sorter.k[w].p, n * 8, hipMemcpyDeviceToDevice, ix->st));
+    if (s == PSI_OK) s = hip_ok(hipMemcpyAsync(d_ids_out, ix->sorter.i[w].p, n * 4, hipMemcpyDeviceToDevice, ix->st));
+    psi_status e = psi_sync(ix);
+    if (s == PSI_OK) s = e;
+    psi_destroy(ix);
+    return s;
+}
+
+psi_status psi_prof_enable(psi_index ix, int on) {
+    if (!ix) return PSI_E_ARG;
+    ix->prof.on = on != 0;
+    return PSI_OK;
+}
+
+psi_status psi_prof_reset(psi_index ix) {
+    if (!ix) return PSI_E_ARG;
+    (void)hipStreamSynchronize(ix->st);
+    ix->prof.resolve();
+    for (auto& kv : ix->prof.fam) {
+        kv.second.ms = 0;
+        kv.second.launches = 0;
+        kv.second.bytes = 0;
+    }
+    return PSI_OK;
+}
+
+psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches, uint64_t* h_bytes) {
+    if (!ix || !family) return PSI_E_ARG;
+    psi_status s = hip_ok(hipStreamSynchronize(ix->st));
+    ix->prof.resolve();
+    auto it = ix->prof.fam.find(family);
+    if (h_ms) *h_ms = it == ix->prof.fam.end() ? 0.0 : it->second.ms;
+    if (h_launches) *h_launches = it == ix->prof.fam.end() ? 0 : it->second.launches;
+    if (h_bytes) *h_bytes = it == ix->prof.fam.end() ? 0 : it->second.bytes;
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Host-callable launchers of the gfx950 kernels (one translation unit per
+// kernel family). All launches are asynchronous on the given stream.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psi_dev.h"
+
+namespace psi {
+
+// ------------------------------------------------------------- radix sort
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 256;
+constexpr int SORT_WG = 256;
+constexpr int SORT_IPT = 16;
+constexpr int SORT_TILE = SORT_WG * SORT_IPT;  // 4096 pairs per tile
+constexpr int MAX_PASSES = 12;
+
+// One LSD pass: which word supplies the digit (0 = key, 1 = id) and where.
+struct PassList {
+    int n;
+    uint8_t src[MAX_PASSES];
+    uint8_t shift[MAX_PASSES];
+};
+
+// Histograms of every pass's digit over the input pairs; ids == nullptr means
+// id = id_base + position. hist must be zeroed ([pl.n][256] u32).
+void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids, uint32_t id_base,
+                       uint64_t n, const PassList& pl, uint32_t* hist);
+// Curve keys of points (AoS) -> keys[i]; histograms of the 8 key digits
+// (hist zeroed, [8][256]); coordinates out of range set ERR_RANGE.
+void launch_encode_hist(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                        uint32_t* hist, uint32_t* err);
+// Curve keys only.
+void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                   uint32_t* err);
+// Exclusive scan of every pass's 256 counts: off[p][d].
+void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint32_t* off);
+// One stable scatter pass (decoupled look-back over tiles taken in launch
+// order). status holds n_tiles*256 words tagged with `epoch`; tile_ctr must
+// be zero.
+void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
+                     const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
+                     uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
+                     uint32_t epoch, uint32_t* err);
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
+void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
+
+// ------------------------------------------------------------------ scans
+// Exclusive prefix sums; `total` (device, may be null) receives the sum.
+// tmp needs scan_tmp_words(n) words.
+uint64_t scan_tmp_words(uint64_t n);
+void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                     uint32_t* tmp);
+
+// ------------------------------------------------------------------ build
+// Fill leaves from sorted pairs: leaf j takes sorted positions
+// [floor(j n / L), floor((j+1) n / L)), its points decoded from the keys;
+// writes slot j, the pivot and the leaf record. Requires n / L <= 32.
+void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
+                         uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
+                         uint32_t* piv_id, NodeRec* leafrec);
+// One node level: parent i = union of children [B i, B i + B) one level down.
+void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
+                       uint64_t n_parent, uint32_t B);
+
+// ---------------------------------------------------------------- queries
+struct TreeView {
+    const NodeRec* inner;   // levels 0..h-1
+    const NodeRec* leaf;    // level h (the directory)
+    const uint32_t* slots;
+    uint32_t h;
+    uint32_t B;
+    uint32_t C;
+    uint64_t L;
+    LevelInfo lv[MAX_LEVELS];  // levels 0..h (passed by value with every launch)
+};
+void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, uint64_t nq, uint32_t k,
+                uint32_t* ids, uint64_t* d2);
+void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                        uint64_t* counts);
+void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                         const uint64_t* offsets, uint32_t* ids);
+
+// ----------------------------------------------------------------- export
+// Prefix sums of leaf counts -> entry offsets (u64, L+1 entries).
+void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp);
+void launch_export_sorted(hipStream_t st, int dim, int curve, const TreeView& t, const uint64_t* off,
+                          uint64_t* keys, uint32_t* ids, uint32_t* pts);
+void launch_export_raw(hipStream_t st, int dim, const TreeView& t, const uint64_t* off, uint32_t* ids,
+                       uint32_t* pts);
+void launch_export_structure(hipStream_t st, int dim, const TreeView& t, uint64_t n_inner,
+                             const uint64_t* piv_key_src, const uint32_t* piv_id_src, uint64_t* piv_key,
+                             uint32_t* piv_id, uint32_t* leaf_cnt, uint32_t* leaf_lo, uint32_t* leaf_hi,
+                             uint32_t* node_lo, uint32_t* node_hi, uint64_t* node_cnt);
+
+}  // namespace psi
