@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPaC-tree hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  build(n) -> batch_insert(m) -> batch_delete(m existing ids)
+  -> kNN(nq queries, k) -> range_count(nb boxes) -> range_report(nb boxes).
+Default workload: 3D SPaC-H (Hilbert), n = 1e8 points with 21-bit coordinates
+(uniform), m = 1e6, 1e7 kNN queries with k = 10, 1e6 boxes with sides
+log-uniform in 2^8..2^18. Inputs are resident in HBM before timing starts.
+
+`value` is the build & batch-update throughput in Mpoints/s:
+(n + m + m) / (t_build + t_insert + t_delete). kNN queries/s and range
+boxes/s of the same steps are reported under `phases`.
+
+Prints ONE JSON line. `--gpus N` with N > 1 is refused: this build runs on one
+GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoints/s build & batch-update, kNN queries/s (1e8 pts, 3D); p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # the metric's configuration: 3D, 1e8 points, 21-bit coordinates
+    "3d-1e8": dict(dim=3, bits=21, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
+    # 2D, 1e8 points in [0, 2^30)^2
+    "2d-1e8": dict(dim=2, bits=30, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
+    # small configuration (seconds on the oracle)
+    "2d-1e6": dict(dim=2, bits=30, n=1_000_000, m=100_000, nq=10_000, k=10, nb=10_000),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="3d-1e8", choices=sorted(WORKLOADS))
+    ap.add_argument("--dist", default="uniform", choices=["uniform", "varden"])
+    ap.add_argument("--curve", default="hilbert", choices=["hilbert", "morton"])
+    ap.add_argument("--leaf", type=int, default=32)
+    ap.add_argument("--fanout", type=int, default=8)
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--ops", default="build,insert,delete,knn,range")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=16_000_000, help="points in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, args):
+    """The oracle timed on a bounded sample of the same workload (one core)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    dim, bits = cfg["dim"], cfg["bits"]
+    n = min(args.cpu_sample, cfg["n"])
+    m = max(1, n // 100)
+    data, ins, _ = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=m, n_query=0)
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, args.seed)
+    ref = oracle.RefIndex(dim, 1 if args.curve == "hilbert" else 0, args.leaf, args.fanout)
+    t0 = time.perf_counter()
+    ref.build(data)
+    ref.batch_insert(ins)
+    ref.batch_delete(dels)
+    dt = time.perf_counter() - t0
+    return {"value": round((n + 2 * m) / dt / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"build {n} + insert {m} + delete {m} {dim}D {args.dist} {args.curve} points, "
+                      f"single-threaded std::sort/std::merge oracle, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+
+    cfg = dict(WORKLOADS[args.workload])
+    if args.n:
+        cfg["n"] = args.n
+    if args.k:
+        cfg["k"] = args.k
+    dim, bits, n, m, nq, k, nb = (cfg[x] for x in ("dim", "bits", "n", "m", "nq", "k", "nb"))
+    curve = psi.HILBERT if args.curve == "hilbert" else psi.MORTON
+    ops = set(args.ops.split(","))
+    dev = torch.device("cuda:0")
+
+    t_gen = time.perf_counter()
+    data, ins, q = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=m, n_query=nq)
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, args.seed)
+    centres = q[:nb] if len(q) >= nb else synth.uniform(nb, dim, bits, args.seed, synth.P_AUX)
+    boxes = synth.boxes(centres, bits, args.seed)
+    log(f"inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    d_data = torch.from_numpy(data.view(np.int32)).to(dev)
+    d_ins = torch.from_numpy(ins.view(np.int32)).to(dev)
+    d_dels = torch.from_numpy(dels.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(q.view(np.int32)).to(dev)
+    d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
+    del data, ins, q
+    stream = torch.cuda.current_stream(dev)
+    ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev, stream=stream)
+    h = ix._h
+    new_ids = torch.empty(m, dtype=torch.int32, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    k_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    k_d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    r_cnt = torch.empty(nb, dtype=torch.int64, device=dev)
+    r_off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+    r_ids = None
+
+    phases = ["build", "insert", "delete", "knn", "range_count", "range_report"]
+
+    def step(ev):
+        nonlocal r_ids
+        ev["build"][0].record(stream)
+        if "build" in ops:
+            psi.psi_build(h, d_data, n)
+        ev["build"][1].record(stream)
+        ev["insert"][0].record(stream)
+        if "insert" in ops:
+            psi.psi_batch_insert(h, d_ins, m, new_ids)
+        ev["insert"][1].record(stream)
+        ev["delete"][0].record(stream)
+        if "delete" in ops:
+            psi.psi_batch_delete(h, d_dels, m, nd)
+        ev["delete"][1].record(stream)
+        ev["knn"][0].record(stream)
+        if "knn" in ops:
+            psi.psi_knn(h, d_q, nq, k, k_ids, k_d2)
+        ev["knn"][1].record(stream)
+        ev["range_count"][0].record(stream)
+        if "range" in ops:
+            psi.psi_range_count(h, d_boxes, nb, r_cnt)
+        ev["range_count"][1].record(stream)
+        ev["range_report"][0].record(stream)
+        if "range" in ops:
+            torch.cumsum(r_cnt, 0, out=r_off[1:])
+            if r_ids is None:  # sized once, from the first (untimed) step
+                r_ids = torch.empty(max(1, int(r_off[-1].item())), dtype=torch.int32, device=dev)
+            psi.psi_range_report(h, d_boxes, nb, r_off, r_ids)
+        ev["range_report"][1].record(stream)
+
+    def events():
+        return {p: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for p in phases}
+
+    for _ in range(max(args.warmup, 1 if "range" in ops else 0)):
+        step(events())
+    ix.sync()
+    log("warmup done")
+    ix.prof_enable(True)
+    ix.prof_reset()
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e = events()
+        step(e)
+        evs.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ix.sync()
+    log(f"{args.steps} timed steps done in {wall:.2f} s")
+    ms = {p: float(np.mean([e[p][0].elapsed_time(e[p][1]) for e in evs])) for p in phases}
+    upd_ms = ms["build"] + ms["insert"] + ms["delete"]
+    upd_pts = (n if "build" in ops else 0) + (m if "insert" in ops else 0) + (m if "delete" in ops else 0)
+    value = upd_pts / (upd_ms / 1e3) / 1e6 if upd_ms > 0 else 0.0
+
+    # dominant kernel family and its roofline
+    fams = ["radix_pass", "encode_hist", "leaf_fill", "nodes", "hist", "knn", "range_count", "range_report",
+            "update"]
+    prof = {f: ix.prof_get(f) for f in fams}
+    mem_fams = [f for f in fams if f not in ("knn", "range_count", "range_report") and prof[f][1] > 0]
+    dom = max(mem_fams, key=lambda f: prof[f][0]) if mem_fams else None
+    roof = None
+    if dom:
+        tms, launches, byt = prof[dom]
+        avg_s = tms / launches / 1e3
+        achieved = byt / launches / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": byt // launches, "avg_launch_ms": round(tms / launches, 4)}
+    kernel_ms = {f: round(prof[f][0] / args.steps, 3) for f in fams if prof[f][1]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {args.dist} SPaC-{'H' if curve else 'Z'}", "n": n, "dim": dim,
+                   "coord_bits": bits, "insert": m, "delete": m, "queries": nq, "k": k, "boxes": nb,
+                   "leaf_size": args.leaf, "fanout": args.fanout, "ops": sorted(ops)},
+        "phases": {
+            **{f"{p}_ms": round(v, 3) for p, v in ms.items()},
+            "build_mpts_s": round(n / ms["build"] / 1e3, 1) if ms["build"] > 0 else None,
+            "insert_mpts_s": round(m / ms["insert"] / 1e3, 1) if ms["insert"] > 0 and "insert" in ops else None,
+            "delete_mpts_s": round(m / ms["delete"] / 1e3, 1) if ms["delete"] > 0 and "delete" in ops else None,
+            "knn_queries_s": round(nq / ms["knn"] * 1e3, 0) if ms["knn"] > 0 and "knn" in ops else None,
+            "range_count_boxes_s": round(nb / ms["range_count"] * 1e3, 0) if "range" in ops else None,
+            "range_report_boxes_s": round(nb / ms["range_report"] * 1e3, 0) if "range" in ops else None,
+            "range_report_ids": int(r_off[-1].item()) if "range" in ops else None,
+        },
+        "kernel_ms_per_step": kernel_ms,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("timing the oracle on a CPU sample ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

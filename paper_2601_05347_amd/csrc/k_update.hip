@@ -1,0 +1,727 @@
+// Batch insert and delete kernels (Alg. 4 and Sec. 4.2).
+//
+// Updates work leaf by leaf on the sorted batch. Each batch entry is routed to
+// the leaf whose pivot range holds its (key, id); entries of one leaf form a
+// contiguous run of the sorted batch.
+//  * insert: a run that fits the leaf's slot (2 phi entries) is appended
+//    without sorting (the SPaC-tree's relaxed leaf order, Alg. 4). A leaf
+//    that would overflow is merged with its run in (key, id) order and re-cut
+//    into ceil(t / phi) balanced leaves, in fresh slots (the paper's local
+//    rebuild of an overflowing leaf; App. C).
+//  * delete: matching entries are removed from their leaf in place; the
+//    leaf's box is recomputed exactly. Leaves that fall below ceil(phi/2)
+//    entries are regrouped with the following leaves up to the next leaf that
+//    is still full enough (the last group also takes the trailing under-full
+//    leaves) and re-cut the same way; this keeps the leaf-size invariant that
+//    Alg. 4's Node() restores by flattening or redistributing.
+// Counters shared between kernels live in a small device array:
+//   ctr[0] valid batch entries, [1] runs, [2] new leaf count, [3] slots to
+//   allocate, [4] output chunks, [5] slots freed, [6] groups, [7] 1 + index
+//   of the last full-enough leaf.
+#include "psi_kern.h"
+#include "psi_update.h"
+
+namespace psi {
+
+namespace {
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+// largest r in [0, R) with off[r] <= x (off ascending, off[0] == 0)
+__device__ __forceinline__ uint32_t find_owner(const uint32_t* off, uint32_t R, uint64_t x) {
+    uint32_t lo = 0, hi = R;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_route(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi, uint64_t n,
+                        const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ pk,
+                        const uint32_t* __restrict__ pi, uint64_t L, uint32_t* __restrict__ leaf_of) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ne = n_dev ? *n_dev : n;
+    if (e >= ne) return;
+    const uint64_t k = bk[e];
+    const uint32_t i = bi[e];
+    uint64_t lo = 0, hi = L;  // first pivot greater than (k, i)
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (!pair_less(k, i, pk[mid], pi[mid])) lo = mid + 1;
+        else hi = mid;
+    }
+    leaf_of[e] = lo == 0 ? 0u : (uint32_t)(lo - 1);
+}
+
+__global__ void k_run_flags(const uint32_t* __restrict__ leaf_of, uint64_t n, const uint32_t* __restrict__ n_dev,
+                            uint32_t* __restrict__ flag) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t ne = n_dev ? *n_dev : n;
+    flag[e] = e < ne && (e == 0 || leaf_of[e] != leaf_of[e - 1]) ? 1u : 0u;
+}
+
+__global__ void k_run_write(const uint32_t* __restrict__ leaf_of, const uint32_t* __restrict__ flag,
+                            const uint32_t* __restrict__ ridx, uint64_t n, uint32_t* __restrict__ run_leaf,
+                            uint32_t* __restrict__ run_beg) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n || !flag[e]) return;
+    run_leaf[ridx[e]] = leaf_of[e];
+    run_beg[ridx[e]] = (uint32_t)e;
+}
+
+__device__ __forceinline__ uint32_t run_end(const uint32_t* run_beg, uint32_t r, uint32_t R, uint32_t n) {
+    return r + 1 < R ? run_beg[r + 1] : n;
+}
+
+__global__ void k_ins_plan(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
+                           const uint32_t* __restrict__ ctr, uint64_t m, const NodeRec* __restrict__ leaf,
+                           uint32_t C, uint32_t phi, uint32_t* __restrict__ pieces, uint32_t* __restrict__ rpieces,
+                           uint32_t* __restrict__ rchunks, uint32_t* __restrict__ rsplit) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const uint32_t R = ctr[1];
+    if (r >= R) {
+        rpieces[r] = rchunks[r] = rsplit[r] = 0u;
+        return;
+    }
+    const uint32_t j = run_leaf[r];
+    const uint32_t len = run_end(run_beg, (uint32_t)r, R, (uint32_t)m) - run_beg[r];
+    const uint32_t t = leaf[j].cnt + len;
+    if (t <= C) {
+        rpieces[r] = rchunks[r] = rsplit[r] = 0u;
+    } else {
+        const uint32_t P = (t + phi - 1) / phi;
+        pieces[j] = P;
+        rpieces[r] = P;
+        rchunks[r] = (t + UPD_CHUNK - 1) / UPD_CHUNK;
+        rsplit[r] = 1u;
+    }
+}
+
+__global__ void k_alloc(uint32_t* __restrict__ slot_alloc, uint64_t A, const uint32_t* __restrict__ free_stack,
+                        uint64_t n_free, uint64_t slot_top, Caps cap) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= A) return;
+    const uint64_t v = a < n_free ? free_stack[n_free - 1 - a] : slot_top + (a - n_free);
+    if (v >= cap.slots) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        slot_alloc[a] = 0;  // never used: the update is reported as failed
+        return;
+    }
+    slot_alloc[a] = (uint32_t)v;
+}
+
+__global__ void k_dir_copy(const NodeRec* __restrict__ src, const uint64_t* __restrict__ spk,
+                           const uint32_t* __restrict__ spi, const uint32_t* __restrict__ pieces,
+                           const uint32_t* __restrict__ newpos, uint64_t L, NodeRec* __restrict__ dst,
+                           uint64_t* __restrict__ dpk, uint32_t* __restrict__ dpi, Caps cap) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= L || pieces[j] != 1u) return;
+    const uint32_t q = newpos[j];
+    if (q >= cap.leaves) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    dst[q] = src[j];
+    dpk[q] = spk[j];
+    dpi[q] = spi[j];
+}
+
+template <int D, int CURVE>
+__global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi,
+                             const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
+                             const uint32_t* __restrict__ ctr, uint64_t m, const uint32_t* __restrict__ rsplit,
+                             const uint32_t* __restrict__ newpos, NodeRec* __restrict__ dleaf,
+                             uint64_t* __restrict__ dpk, uint32_t* __restrict__ dpi, uint32_t* __restrict__ slots,
+                             uint32_t C, uint32_t* __restrict__ err, Caps cap) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t R = ctr[1];
+    if (r >= R || rsplit[r]) return;
+    const uint32_t j = run_leaf[r];
+    const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, (uint32_t)m);
+    const uint32_t q = newpos[j];
+    if (q >= cap.leaves) {
+        atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    NodeRec rec = dleaf[q];
+    if (rec.cnt + (end - beg) > C || rec.slot >= cap.slots) {
+        atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+    for (uint32_t e = beg; e < end; ++e) {
+        uint32_t p[D];
+        sfc_point<D, CURVE>(bk[e], p);
+        const uint32_t o = rec.cnt + (e - beg);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s[d * C + o] = p[d];
+            rec.lo[d] = min(rec.lo[d], p[d]);
+            rec.hi[d] = max(rec.hi[d], p[d]);
+        }
+        s[D * C + o] = bi[e];
+    }
+    rec.cnt += end - beg;
+    dleaf[q] = rec;
+    if (j == 0 && pair_less(bk[beg], bi[beg], dpk[q], dpi[q])) {
+        dpk[q] = bk[beg];
+        dpi[q] = bi[beg];
+    }
+}
+
+// Merge of a leaf (sorted in LDS) with its sorted run, cut into P balanced
+// pieces written to fresh slots. One block handles UPD_CHUNK outputs.
+template <int D, int CURVE>
+__global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
+    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi, const uint32_t* __restrict__ run_leaf,
+    const uint32_t* __restrict__ run_beg, const uint32_t* __restrict__ ctr, uint64_t m,
+    const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ piece_off,
+    const uint32_t* __restrict__ newpos, const uint32_t* __restrict__ slot_alloc,
+    const NodeRec* __restrict__ sleaf, NodeRec* __restrict__ dleaf, uint64_t* __restrict__ dpk,
+    uint32_t* __restrict__ dpi, uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C,
+    uint32_t phi, Caps cap) {
+    __shared__ uint64_t s_uk[64], s_ak[64];
+    __shared__ uint32_t s_ui[64], s_ai[64];
+    __shared__ uint32_t s_ap[D][64];
+    const uint32_t R = ctr[1];
+    const uint32_t c = blockIdx.x;
+    const uint32_t r = find_owner(chunk_off, R, c);
+    const uint32_t j = run_leaf[r];
+    const uint32_t beg = run_beg[r], end = run_end(run_beg, r, R, (uint32_t)m);
+    const uint32_t b = end - beg;
+    const NodeRec rec = sleaf[j];
+    const uint32_t a = rec.cnt;
+    if (a > 64 || a > C || rec.slot >= cap.slots) {  // uniform over the block
+        if (threadIdx.x == 0) atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    const uint32_t t = a + b;
+    const uint32_t P = (t + phi - 1) / phi;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+    uint32_t p[D];
+    uint64_t key = 0;
+    uint32_t id = 0;
+    if (tid < a) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s[d * C + tid];
+        id = s[D * C + tid];
+        key = sfc_key<D, CURVE>(p);
+        s_uk[tid] = key;
+        s_ui[tid] = id;
+    }
+    __syncthreads();
+    if (tid < a) {
+        uint32_t rank = 0;
+        for (uint32_t x = 0; x < a; ++x) rank += pair_less(s_uk[x], s_ui[x], key, id) ? 1u : 0u;
+        s_ak[rank] = key;
+        s_ai[rank] = id;
+#pragma unroll
+        for (int d = 0; d < D; ++d) s_ap[d][rank] = p[d];
+    }
+    __syncthreads();
+    const uint64_t k = (uint64_t)(c - chunk_off[r]) * UPD_CHUNK + tid;
+    if (k >= t) return;
+    // merge path: i = number of leaf entries among the first k outputs
+    uint32_t lo = k > b ? (uint32_t)(k - b) : 0u, hi = (uint32_t)min<uint64_t>(k, a);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        const uint64_t kb = k - mid;  // index into the run
+        const bool take = kb >= b || pair_less(s_ak[mid - 1], s_ai[mid - 1], bk[beg + kb], bi[beg + kb]);
+        if (take) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t i = lo;
+    const uint64_t kb = k - i;
+    bool from_a = i < a && (kb >= b || pair_less(s_ak[i], s_ai[i], bk[beg + kb], bi[beg + kb]));
+    if (from_a) {
+        key = s_ak[i];
+        id = s_ai[i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s_ap[d][i];
+    } else {
+        key = bk[beg + kb];
+        id = bi[beg + kb];
+        sfc_point<D, CURVE>(key, p);
+    }
+    const uint32_t pc = (uint32_t)(((k + 1) * P - 1) / t);
+    const uint32_t p0 = (uint32_t)((uint64_t)pc * t / P), p1 = (uint32_t)((uint64_t)(pc + 1) * t / P);
+    const uint32_t off = (uint32_t)k - p0;
+    const uint64_t ai = (uint64_t)piece_off[r] + pc;
+    const uint64_t qq = (uint64_t)newpos[j] + pc;
+    if (ai >= cap.alloc || qq >= cap.leaves || rec.slot >= cap.slots) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    const uint32_t slot = slot_alloc[ai];
+    if (slot >= cap.slots || off >= C) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    uint32_t* o = slots + (uint64_t)slot * (D + 1) * C;
+#pragma unroll
+    for (int d = 0; d < D; ++d) o[d * C + off] = p[d];
+    o[D * C + off] = id;
+    if (off == 0) {
+        const uint32_t q = (uint32_t)qq;
+        dpk[q] = key;
+        dpi[q] = id;
+        NodeRec nr;
+        for (int d = 0; d < 3; ++d) {
+            nr.lo[d] = 0xFFFFFFFFu;
+            nr.hi[d] = 0u;
+        }
+        nr.cnt = p1 - p0;
+        nr.slot = slot;
+        dleaf[q] = nr;
+        piece_pos[ai] = q;
+    }
+}
+
+// Exact boxes of freshly cut pieces (half-wave per piece; pieces hold <= 32).
+template <int D>
+__global__ __launch_bounds__(256) void k_piece_meta(const uint32_t* __restrict__ piece_pos, uint64_t A,
+                                                    NodeRec* __restrict__ leaf, const uint32_t* __restrict__ slots,
+                                                    uint32_t C, Caps cap) {
+    const uint64_t a = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    const uint32_t t = threadIdx.x & 31;
+    if (a >= A) return;
+    const uint32_t q = piece_pos[a];
+    if (q >= cap.leaves) return;
+    NodeRec rec = leaf[q];
+    if (rec.slot >= cap.slots || rec.cnt > C) return;
+    const uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+        for (uint32_t e = t; e < rec.cnt; e += 32) {
+            const uint32_t v = s[d * C + e];
+            lo = min(lo, v);
+            hi = max(hi, v);
+        }
+        for (int o = 16; o >= 1; o >>= 1) {
+            lo = min(lo, shfl_u32(lo, (int)(lane_id() ^ o)));
+            hi = max(hi, shfl_u32(hi, (int)(lane_id() ^ o)));
+        }
+        rec.lo[d] = lo;
+        rec.hi[d] = hi;
+    }
+    if (D == 2) {
+        rec.lo[2] = 0;
+        rec.hi[2] = 0;
+    }
+    if (t == 0) leaf[q] = rec;
+}
+
+__global__ void k_ins_free(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ ctr, uint64_t m,
+                           const uint32_t* __restrict__ rsplit, const uint32_t* __restrict__ free_off,
+                           const NodeRec* __restrict__ sleaf, uint32_t* __restrict__ free_stack, uint64_t base, Caps cap) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ctr[1] || !rsplit[r]) return;
+    const uint64_t x = base + free_off[r];
+    if (x >= cap.frees) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    free_stack[x] = sleaf[run_leaf[r]].slot;
+}
+
+// ------------------------------------------------------------------ delete
+__global__ void k_del_gather(const uint32_t* __restrict__ ids, uint64_t m, const uint64_t* __restrict__ idkey,
+                             uint32_t next_id, uint64_t* __restrict__ dk, uint32_t* __restrict__ di) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t id = ids[e];
+    const uint64_t key = id < next_id ? idkey[id] : DEAD_KEY;
+    dk[e] = key;
+    di[e] = key == DEAD_KEY ? PAD_ID : id;
+}
+
+__global__ void k_del_valid(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ si, uint64_t m,
+                            uint32_t* __restrict__ flag) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const bool dup = e > 0 && sk[e] == sk[e - 1] && si[e] == si[e - 1];
+    flag[e] = sk[e] != DEAD_KEY && !dup ? 1u : 0u;
+}
+
+__global__ void k_del_compact(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ si,
+                              const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, uint64_t m,
+                              uint64_t* __restrict__ ck, uint32_t* __restrict__ ci) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m || !flag[e]) return;
+    ck[pos[e]] = sk[e];
+    ci[pos[e]] = si[e];
+}
+
+__global__ void k_del_kill(const uint32_t* __restrict__ ci, const uint32_t* __restrict__ ctr, uint64_t m,
+                           uint64_t* __restrict__ idkey, uint64_t* __restrict__ ndel) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0 && ndel) *ndel = ctr[0];
+    if (e >= m || e >= ctr[0]) return;
+    idkey[ci[e]] = DEAD_KEY;
+}
+
+template <int D>
+__global__ void k_del_remove(const uint32_t* __restrict__ ci, const uint32_t* __restrict__ run_leaf,
+                             const uint32_t* __restrict__ run_beg, const uint32_t* __restrict__ ctr, uint64_t m,
+                             NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots, uint32_t C,
+                             uint32_t* __restrict__ err, Caps cap) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t R = ctr[1];
+    if (r >= R) return;
+    const uint32_t V = ctr[0];
+    const uint32_t j = run_leaf[r];
+    const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, V);
+    NodeRec rec = leaf[j];
+    if (rec.slot >= cap.slots || rec.cnt > C) {
+        atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+    uint32_t w = 0, removed = 0;
+    uint32_t lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = 0xFFFFFFFFu;
+        hi[d] = 0u;
+    }
+    for (uint32_t e = 0; e < rec.cnt; ++e) {
+        const uint32_t id = s[D * C + e];
+        bool del = false;
+        for (uint32_t x = beg; x < end; ++x) del = del || ci[x] == id;
+        if (del) {
+            ++removed;
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const uint32_t v = s[d * C + e];
+            if (w != e) s[d * C + w] = v;
+            lo[d] = min(lo[d], v);
+            hi[d] = max(hi[d], v);
+        }
+        if (w != e) s[D * C + w] = id;
+        ++w;
+    }
+    if (removed != end - beg) atomicOr(err, ERR_DELETE);
+    rec.cnt = w;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        rec.lo[d] = lo[d];
+        rec.hi[d] = hi[d];
+    }
+    leaf[j] = rec;
+}
+
+__global__ void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half, uint32_t* __restrict__ cnt,
+                             uint32_t* __restrict__ ctr) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= L) return;
+    const uint32_t c = leaf[j].cnt;
+    cnt[j] = c;
+    if (c >= half) atomicMax(&ctr[7], (uint32_t)(j + 1));
+}
+
+__global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t L, uint32_t half,
+                             const uint32_t* __restrict__ ctr, uint32_t* __restrict__ start) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= L) return;
+    start[j] = (j == 0 || (cnt[j - 1] >= half && j < ctr[7])) ? 1u : 0u;
+}
+
+__global__ void k_del_groups(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx, uint64_t L,
+                             uint32_t* __restrict__ grp_first) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < L && start[j]) grp_first[gidx[j]] = (uint32_t)j;
+}
+
+__global__ void k_del_gplan(const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr, uint64_t L,
+                            const uint32_t* __restrict__ cum, uint32_t phi, uint32_t* __restrict__ gpieces,
+                            uint32_t* __restrict__ gchunks, uint32_t* __restrict__ galloc,
+                            uint32_t* __restrict__ gfree, uint32_t* __restrict__ gchanged) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= L) return;
+    const uint32_t G = ctr[6];
+    if (g >= G) {
+        gpieces[g] = gchunks[g] = galloc[g] = gfree[g] = gchanged[g] = 0u;
+        return;
+    }
+    const uint32_t f = grp_first[g];
+    const uint32_t e = g + 1 < G ? grp_first[g + 1] : (uint32_t)L;
+    const uint32_t t = cum[e] - cum[f];
+    const bool changed = (e - f) > 1 || t == 0;
+    const uint32_t P = changed ? (t + phi - 1) / phi : 1u;
+    gpieces[g] = P;
+    gchunks[g] = changed ? (t + UPD_CHUNK - 1) / UPD_CHUNK : 0u;
+    galloc[g] = changed ? P : 0u;
+    gfree[g] = changed ? e - f : 0u;
+    gchanged[g] = changed ? 1u : 0u;
+}
+
+__global__ void k_del_gcopy(const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr,
+                            const uint32_t* __restrict__ gchanged, const uint32_t* __restrict__ gpos,
+                            const NodeRec* __restrict__ src, const uint64_t* __restrict__ spk,
+                            const uint32_t* __restrict__ spi, NodeRec* __restrict__ dst, uint64_t* __restrict__ dpk,
+                            uint32_t* __restrict__ dpi, Caps cap) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ctr[6] || gchanged[g]) return;
+    const uint32_t j = grp_first[g], q = gpos[g];
+    if (q >= cap.leaves) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    dst[q] = src[j];
+    dpk[q] = spk[j];
+    dpi[q] = spi[j];
+}
+
+// Sort the entries of every leaf of a changed group in place, by (key, id).
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_sort_leaves(const uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ gidx,
+                                                     const uint32_t* __restrict__ gchanged, uint64_t L,
+                                                     const NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
+                                                     uint32_t C) {
+    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = lane_id();
+    if (j >= L) return;
+    const uint32_t g = gidx[j] + start[j] - 1u;
+    if (!gchanged[g]) return;
+    const NodeRec rec = leaf[j];
+    if (rec.cnt <= 1 || rec.cnt > 64 || rec.cnt > C) return;
+    uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+    const bool on = lane < rec.cnt;
+    uint32_t p[D];
+    uint32_t id = PAD_ID;
+    uint64_t key = ~0ull;
+    if (on) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s[d * C + lane];
+        id = s[D * C + lane];
+        key = sfc_key<D, CURVE>(p);
+    }
+    uint32_t rank = 0;
+    for (uint32_t x = 0; x < rec.cnt; ++x) {
+        const uint64_t ok = shfl_u64(key, (int)x);
+        const uint32_t oi = shfl_u32(id, (int)x);
+        rank += pair_less(ok, oi, key, id) ? 1u : 0u;
+    }
+    if (on) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d * C + rank] = p[d];
+        s[D * C + rank] = id;
+    }
+}
+
+// Concatenate the (sorted) leaves of a changed group and cut into P pieces.
+template <int D, int CURVE>
+__global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
+    const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr, uint64_t L,
+    const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ alloc_off,
+    const uint32_t* __restrict__ gpos, const uint32_t* __restrict__ cum, const uint32_t* __restrict__ slot_alloc,
+    const NodeRec* __restrict__ sleaf, NodeRec* __restrict__ dleaf, uint64_t* __restrict__ dpk,
+    uint32_t* __restrict__ dpi, uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C,
+    uint32_t phi, Caps cap) {
+    const uint32_t G = ctr[6];
+    const uint32_t c = blockIdx.x;
+    const uint32_t g = find_owner(chunk_off, G, c);
+    const uint32_t f = grp_first[g];
+    const uint32_t e = g + 1 < G ? grp_first[g + 1] : (uint32_t)L;
+    const uint32_t t = cum[e] - cum[f];
+    const uint32_t P = (t + phi - 1) / phi;
+    const uint64_t k = (uint64_t)(c - chunk_off[g]) * UPD_CHUNK + threadIdx.x;
+    if (k >= t) return;
+    const uint32_t gp = cum[f] + (uint32_t)k;
+    uint32_t lo = f, hi = e;  // source leaf: last s in [f, e) with cum[s] <= gp
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cum[mid] <= gp) lo = mid;
+        else hi = mid;
+    }
+    const NodeRec src = sleaf[lo];
+    const uint32_t so = gp - cum[lo];
+    if (src.slot >= cap.slots || so >= C) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    const uint32_t* s = slots + (uint64_t)src.slot * (D + 1) * C;
+    uint32_t p[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) p[d] = s[d * C + so];
+    const uint32_t id = s[D * C + so];
+    const uint32_t pc = (uint32_t)(((k + 1) * P - 1) / t);
+    const uint32_t p0 = (uint32_t)((uint64_t)pc * t / P), p1 = (uint32_t)((uint64_t)(pc + 1) * t / P);
+    const uint32_t off = (uint32_t)k - p0;
+    const uint64_t ai = (uint64_t)alloc_off[g] + pc;
+    const uint64_t qq = (uint64_t)gpos[g] + pc;
+    if (ai >= cap.alloc || qq >= cap.leaves) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    const uint32_t slot = slot_alloc[ai];
+    if (slot >= cap.slots || off >= C) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    uint32_t* o = slots + (uint64_t)slot * (D + 1) * C;
+#pragma unroll
+    for (int d = 0; d < D; ++d) o[d * C + off] = p[d];
+    o[D * C + off] = id;
+    if (off == 0) {
+        const uint32_t q = (uint32_t)qq;
+        dpk[q] = sfc_key<D, CURVE>(p);
+        dpi[q] = id;
+        NodeRec nr;
+        for (int d = 0; d < 3; ++d) {
+            nr.lo[d] = 0xFFFFFFFFu;
+            nr.hi[d] = 0u;
+        }
+        nr.cnt = p1 - p0;
+        nr.slot = slot;
+        dleaf[q] = nr;
+        piece_pos[ai] = q;
+    }
+}
+
+__global__ void k_del_free(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx,
+                           const uint32_t* __restrict__ gchanged, const uint32_t* __restrict__ grp_first,
+                           const uint32_t* __restrict__ free_off, uint64_t L, const NodeRec* __restrict__ sleaf,
+                           uint32_t* __restrict__ free_stack, uint64_t base, Caps cap) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= L) return;
+    const uint32_t g = gidx[j] + start[j] - 1u;
+    if (!gchanged[g]) return;
+    const uint64_t x = base + free_off[g] + (j - grp_first[g]);
+    if (x >= cap.frees) {
+        atomicOr(cap.err, ERR_CAPACITY);
+        return;
+    }
+    free_stack[x] = sleaf[j].slot;
+}
+
+}  // namespace
+
+#define PSI_DC(F, ...)                                                    \
+    do {                                                                   \
+        if (dim == 2 && curve == 0) hipLaunchKernelGGL((F<2, 0>), __VA_ARGS__); \
+        else if (dim == 2) hipLaunchKernelGGL((F<2, 1>), __VA_ARGS__);          \
+        else if (curve == 0) hipLaunchKernelGGL((F<3, 0>), __VA_ARGS__);        \
+        else hipLaunchKernelGGL((F<3, 1>), __VA_ARGS__);                        \
+    } while (0)
+#define PSI_D(F, ...)                                                     \
+    do {                                                                   \
+        if (dim == 2) hipLaunchKernelGGL((F<2>), __VA_ARGS__);            \
+        else hipLaunchKernelGGL((F<3>), __VA_ARGS__);                     \
+    } while (0)
+
+void upd_route(hipStream_t st, const uint64_t* bk, const uint32_t* bi, uint64_t n, const uint32_t* n_dev,
+               const uint64_t* pk, const uint32_t* pi, uint64_t L, uint32_t* leaf_of) {
+    if (n) hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, st, bk, bi, n, n_dev, pk, pi, L, leaf_of);
+}
+void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_t* n_dev, uint32_t* flag,
+              uint32_t* ridx, uint32_t* run_leaf, uint32_t* run_beg, uint32_t* R_dev, uint32_t* tmp) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(n, 256)), dim3(256), 0, st, leaf_of, n, n_dev, flag);
+    launch_scan_u32(st, flag, ridx, n, R_dev, tmp);
+    hipLaunchKernelGGL(k_run_write, dim3(blocks_for(n, 256)), dim3(256), 0, st, leaf_of, flag, ridx, n, run_leaf, run_beg);
+}
+void upd_ins_plan(hipStream_t st, const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
+                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* pieces, uint32_t* rpieces,
+                  uint32_t* rchunks, uint32_t* rsplit) {
+    hipLaunchKernelGGL(k_ins_plan, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, run_beg, ctr, m, leaf, C, phi, pieces, rpieces, rchunks, rsplit);
+}
+void upd_alloc(hipStream_t st, uint32_t* slot_alloc, uint64_t A, const uint32_t* free_stack, uint64_t n_free,
+               uint64_t slot_top, Caps cap) {
+    if (A) hipLaunchKernelGGL(k_alloc, dim3(blocks_for(A, 256)), dim3(256), 0, st, slot_alloc, A, free_stack, n_free, slot_top, cap);
+}
+void upd_dir_copy(hipStream_t st, const NodeRec* src, const uint64_t* spk, const uint32_t* spi, const uint32_t* pieces,
+                  const uint32_t* newpos, uint64_t L, NodeRec* dst, uint64_t* dpk, uint32_t* dpi, Caps cap) {
+    if (L) hipLaunchKernelGGL(k_dir_copy, dim3(blocks_for(L, 256)), dim3(256), 0, st, src, spk, spi, pieces, newpos, L, dst, dpk, dpi, cap);
+}
+void upd_ins_append(hipStream_t st, int dim, int curve, const uint64_t* bk, const uint32_t* bi,
+                    const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
+                    const uint32_t* rsplit, const uint32_t* newpos, NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi,
+                    uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
+    PSI_DC(k_ins_append, dim3(blocks_for(m, 256)), dim3(256), 0, st, bk, bi, run_leaf, run_beg, ctr, m, rsplit, newpos, dleaf, dpk, dpi, slots, C, err, cap);
+}
+void upd_ins_split(hipStream_t st, int dim, int curve, uint64_t nchunks, const uint64_t* bk, const uint32_t* bi,
+                   const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
+                   const uint32_t* chunk_off, const uint32_t* piece_off, const uint32_t* newpos,
+                   const uint32_t* slot_alloc, const NodeRec* sleaf, NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi,
+                   uint32_t* piece_pos, uint32_t* slots, uint32_t C, uint32_t phi, Caps cap) {
+    if (nchunks)
+        PSI_DC(k_ins_split, dim3((unsigned)nchunks), dim3(UPD_CHUNK), 0, st, bk, bi, run_leaf, run_beg, ctr, m, chunk_off, piece_off, newpos, slot_alloc, sleaf, dleaf, dpk, dpi, piece_pos, slots, C, phi, cap);
+}
+void upd_piece_meta(hipStream_t st, int dim, const uint32_t* piece_pos, uint64_t A, NodeRec* leaf,
+                    const uint32_t* slots, uint32_t C, Caps cap) {
+    if (A) PSI_D(k_piece_meta, dim3(blocks_for(A, 8)), dim3(256), 0, st, piece_pos, A, leaf, slots, C, cap);
+}
+void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rsplit,
+                  const uint32_t* free_off, const NodeRec* sleaf, uint32_t* free_stack, uint64_t base, Caps cap) {
+    hipLaunchKernelGGL(k_ins_free, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, free_off, sleaf, free_stack, base, cap);
+}
+
+void upd_del_gather(hipStream_t st, const uint32_t* ids, uint64_t m, const uint64_t* idkey, uint32_t next_id,
+                    uint64_t* dk, uint32_t* di) {
+    hipLaunchKernelGGL(k_del_gather, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, next_id, dk, di);
+}
+void upd_del_compact(hipStream_t st, const uint64_t* sk, const uint32_t* si, uint64_t m, uint32_t* flag,
+                     uint32_t* pos, uint32_t* V_dev, uint64_t* ck, uint32_t* ci, uint32_t* tmp) {
+    hipLaunchKernelGGL(k_del_valid, dim3(blocks_for(m, 256)), dim3(256), 0, st, sk, si, m, flag);
+    launch_scan_u32(st, flag, pos, m, V_dev, tmp);
+    hipLaunchKernelGGL(k_del_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, sk, si, flag, pos, m, ck, ci);
+}
+void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint64_t m, uint64_t* idkey,
+                  uint64_t* ndel) {
+    hipLaunchKernelGGL(k_del_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, ctr, m, idkey, ndel);
+}
+void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
+                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
+    PSI_D(k_del_remove, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
+}
+void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
+                  uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,
+                  uint32_t* gchunks, uint32_t* galloc, uint32_t* gfree, uint32_t* gchanged, uint32_t* gpos,
+                  uint32_t* chunk_off, uint32_t* alloc_off, uint32_t* free_off, uint32_t* tmp) {
+    const uint32_t half = (phi + 1) / 2;
+    const unsigned g = blocks_for(L, 256);
+    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, cnt, ctr);
+    launch_scan_u32(st, cnt, cum, L, cum + L, tmp);
+    hipLaunchKernelGGL(k_del_starts, dim3(g), dim3(256), 0, st, cnt, L, half, ctr, start);
+    launch_scan_u32(st, start, gidx, L, ctr + 6, tmp);
+    hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, L, grp_first);
+    hipLaunchKernelGGL(k_del_gplan, dim3(g), dim3(256), 0, st, grp_first, ctr, L, cum, phi, gpieces, gchunks, galloc, gfree, gchanged);
+    launch_scan_u32(st, gpieces, gpos, L, ctr + 2, tmp);
+    launch_scan_u32(st, galloc, alloc_off, L, ctr + 3, tmp);
+    launch_scan_u32(st, gchunks, chunk_off, L, ctr + 4, tmp);
+    launch_scan_u32(st, gfree, free_off, L, ctr + 5, tmp);
+}
+void upd_del_gcopy(hipStream_t st, const uint32_t* grp_first, const uint32_t* ctr, uint64_t L,
+                   const uint32_t* gchanged, const uint32_t* gpos, const NodeRec* src, const uint64_t* spk,
+                   const uint32_t* spi, NodeRec* dst, uint64_t* dpk, uint32_t* dpi, Caps cap) {
+    hipLaunchKernelGGL(k_del_gcopy, dim3(blocks_for(L, 256)), dim3(256), 0, st, grp_first, ctr, gchanged, gpos, src, spk, spi, dst, dpk, dpi, cap);
+}
+void upd_sort_leaves(hipStream_t st, int dim, int curve, const uint32_t* start, const uint32_t* gidx,
+                     const uint32_t* gchanged, uint64_t L, const NodeRec* leaf, uint32_t* slots, uint32_t C) {
+    PSI_DC(k_sort_leaves, dim3(blocks_for(L, 4)), dim3(256), 0, st, start, gidx, gchanged, L, leaf, slots, C);
+}
+void upd_del_regroup(hipStream_t st, int dim, int curve, uint64_t nchunks, const uint32_t* grp_first,
+                     const uint32_t* ctr, uint64_t L, const uint32_t* chunk_off, const uint32_t* alloc_off,
+                     const uint32_t* gpos, const uint32_t* cum, const uint32_t* slot_alloc, const NodeRec* sleaf,
+                     NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi, uint32_t* piece_pos, uint32_t* slots, uint32_t C,
+                     uint32_t phi, Caps cap) {
+    if (nchunks)
+        PSI_DC(k_del_regroup, dim3((unsigned)nchunks), dim3(UPD_CHUNK), 0, st, grp_first, ctr, L, chunk_off, alloc_off, gpos, cum, slot_alloc, sleaf, dleaf, dpk, dpi, piece_pos, slots, C, phi, cap);
+}
+void upd_del_free(hipStream_t st, const uint32_t* start, const uint32_t* gidx, const uint32_t* gchanged,
+                  const uint32_t* grp_first, const uint32_t* free_off, uint64_t L, const NodeRec* sleaf,
+                  uint32_t* free_stack, uint64_t base, Caps cap) {
+    hipLaunchKernelGGL(k_del_free, dim3(blocks_for(L, 256)), dim3(256), 0, st, start, gidx, gchanged, grp_first, free_off, L, sleaf, free_stack, base, cap);
+}
+
+}  // namespace psi
