@@ -50,9 +50,22 @@ typedef enum {
 
 typedef enum { PSI_MORTON = 0, PSI_HILBERT = 1 } psi_curve;
 
+/* psi_params.flags bits. By default a query batch of 4096 or more queries
+ * (or boxes) is processed in curve-key order of its points (box centres) so
+ * that neighbouring queries share tree nodes; results are the same either
+ * way. PSI_FLAG_INPUT_ORDER processes batches in input order.
+ * kNN with k <= 16 runs one query per lane. By default each search is
+ * seeded with the leaves around the query's own curve key and then walks the
+ * tree in fixed child order, pruning by the k-th distance;
+ * PSI_FLAG_KNN_NEAREST_FIRST instead descends to the nearest child first and
+ * re-scores siblings on the way back (App. C's visiting order). Both return
+ * the same exact result. */
+enum { PSI_FLAG_INPUT_ORDER = 1, PSI_FLAG_KNN_NEAREST_FIRST = 2 };
+
 /* dim: 2 or 3. curve: psi_curve. leaf_size: phi, the largest leaf a build
  * makes (2..32); a leaf slot holds 2*phi entries so that inserts can append
- * without moving data. fanout: children per tree node (2..32). flags: 0. */
+ * without moving data. fanout: children per tree node (2..32). flags: a
+ * combination of PSI_FLAG_* bits. */
 typedef struct {
     uint32_t dim;
     uint32_t curve;
@@ -94,7 +107,8 @@ psi_status psi_batch_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uin
  * d_ids/d_d2 ([nq][k]) holds the k live points with the smallest (squared
  * Euclidean distance, id), ascending; rows are padded with
  * (0xFFFFFFFF, UINT64_MAX) when the index has fewer than k points.
- * 1 <= k <= 128. */
+ * 1 <= k <= 128. Query coordinates obey the same limits as points (a query
+ * out of range latches PSI_E_RANGE). */
 psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k,
                    uint32_t* d_ids, uint64_t* d_d2);
 

@@ -19,6 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsi.so")
 
 MORTON, HILBERT = 0, 1
+FLAG_INPUT_ORDER = 1
+FLAG_KNN_NEAREST_FIRST = 2
 PAD_ID = 0xFFFFFFFF
 PAD_D2 = 0xFFFFFFFFFFFFFFFF
 
@@ -252,12 +254,13 @@ def psi_prof_get(h, family: str):
 class Index:
     """A SPaC-tree on the current ROCm device, bound to one stream."""
 
-    def __init__(self, dim: int, curve: int, leaf_size: int = 32, fanout: int = 8, device="cuda", stream=None):
+    def __init__(self, dim: int, curve: int, leaf_size: int = 32, fanout: int = 8, device="cuda", stream=None,
+                 flags: int = 0):
         torch = _torch()
         self.dim, self.curve, self.leaf_size, self.fanout = dim, curve, leaf_size, fanout
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self._h = psi_create(dim, curve, leaf_size, fanout, 0, self.stream)
+        self._h = psi_create(dim, curve, leaf_size, fanout, flags, self.stream)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -66,12 +66,14 @@ __device__ __forceinline__ void topk_insert(uint64_t (&bd)[K], uint32_t (&bi)[K]
 // ------------------------------------------------------- kNN, lane per query
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_knn_lane(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
+                                                  const uint32_t* __restrict__ order,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
-    __shared__ LevelInfo s_lv[64];
+    __shared__ LevelInfo s_lv[MAX_LEVELS];
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
     __syncthreads();
-    const uint64_t qi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi >= nq) return;
+    const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tq >= nq) return;
+    const uint64_t qi = order ? order[tq] : tq;
     uint32_t q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
@@ -161,6 +163,111 @@ __global__ __launch_bounds__(256) void k_knn_lane(TreeView t, const uint32_t* __
     }
 }
 
+// ---------------------------------------- kNN, lane per query, seeded search
+// The query's own curve key locates the leaf whose key range holds it (a
+// binary search over the leaf pivots); that leaf and its two neighbours in
+// curve order seed the k best with nearby points. The tree is then walked
+// depth first in fixed child order, skipping every box farther than the
+// current k-th distance and the seed leaves already scanned. A good seed
+// radius makes this visit little more than the leaves the final k-th
+// distance ball touches, without re-scoring siblings.
+template <int D, int K>
+__device__ __forceinline__ void scan_leaf(const TreeView& t, const NodeRec& r, const uint32_t* q, uint64_t (&bd)[K],
+                                          uint32_t (&bi)[K]) {
+    const uint32_t C = t.C;
+    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
+    for (uint32_t e = 0; e < r.cnt; e += 4) {
+        uint4 X[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e);
+        const uint4 I = *reinterpret_cast<const uint4*>(s + D * C + e);
+        const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
+                                   {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
+                                   {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
+                                   {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
+        const uint32_t is[4] = {I.x, I.y, I.z, I.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (e + u < r.cnt) {
+                const uint64_t dd = pt_dist<D>(q, xs[u]);
+                if (pair_less(dd, is[u], bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, is[u]);
+            }
+        }
+    }
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __restrict__ qp,
+                                                  const uint64_t* __restrict__ qkeys, uint64_t nq,
+                                                  const uint32_t* __restrict__ order,
+                                                  uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
+    __shared__ LevelInfo s_lv[MAX_LEVELS];
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    __syncthreads();
+    const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tq >= nq) return;
+    const uint64_t qi = order ? order[tq] : tq;
+    uint32_t q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+    uint64_t bd[K];
+    uint32_t bi[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        bd[j] = PAD_D2;
+        bi[j] = PAD_ID;
+    }
+    if (t.L > 0) {
+        const uint64_t key = qkeys[qi];
+        uint32_t lo = 0, hi = (uint32_t)t.L;  // first pivot key above the query's key
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (t.pkey[mid] <= key) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t j = lo ? lo - 1 : 0u;
+        const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, (uint32_t)t.L - 1);
+        for (uint32_t x = ja; x <= jb; ++x) scan_leaf<D, K>(t, t.leaf[x], q, bd, bi);
+        const uint32_t B = t.B, h = t.h;
+        uint32_t l = 0, i = 0;
+        for (;;) {
+            const NodeRec r = l == h ? t.leaf[i] : t.inner[s_lv[l].off + i];
+            bool descend = false;
+            if (r.cnt && box_dist<D>(q, r) <= bd[K - 1]) {
+                if (l == h) {
+                    if (i < ja || i > jb) scan_leaf<D, K>(t, r, q, bd, bi);
+                } else {
+                    descend = true;
+                }
+            }
+            if (descend) {
+                ++l;
+                i *= B;
+                continue;
+            }
+            bool done = false;
+            for (;;) {
+                if (l == 0) {
+                    done = true;
+                    break;
+                }
+                if ((i + 1) % B != 0 && i + 1 < s_lv[l].n) {
+                    ++i;
+                    break;
+                }
+                --l;
+                i /= B;
+            }
+            if (done) break;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        out_ids[qi * K + j] = bi[j];
+        out_d2[qi * K + j] = bd[j];
+    }
+}
+
 // ------------------------------------------------------- kNN, wave per query
 // The k best pairs live in LDS, ascending. A leaf is scanned one entry per
 // lane; the entries that beat the current k-th pair are ranked among
@@ -187,9 +294,9 @@ __device__ __forceinline__ bool wave_argmin(bool on, uint64_t d, uint64_t& best_
 
 template <int D, int KMAX>
 __global__ __launch_bounds__(256) void k_knn_wave(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
-                                                  uint32_t k, uint32_t* __restrict__ out_ids,
-                                                  uint64_t* __restrict__ out_d2) {
-    __shared__ LevelInfo s_lv[64];
+                                                  const uint32_t* __restrict__ order, uint32_t k,
+                                                  uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
+    __shared__ LevelInfo s_lv[MAX_LEVELS];
     __shared__ uint64_t s_d[KW_WAVES][2][KMAX];
     __shared__ uint32_t s_i[KW_WAVES][2][KMAX];
     __shared__ uint64_t s_cd[KW_WAVES][64];
@@ -198,8 +305,9 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView t, const uint32_t* __
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
-    const uint64_t qi = (uint64_t)blockIdx.x * KW_WAVES + w;
-    if (qi >= nq) return;
+    const uint64_t tq = (uint64_t)blockIdx.x * KW_WAVES + w;
+    if (tq >= nq) return;
+    const uint64_t qi = order ? order[tq] : tq;
     uint32_t q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
@@ -356,7 +464,7 @@ template <int D, bool REPORT>
 __global__ __launch_bounds__(256) void k_range(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
                                                uint64_t* __restrict__ counts, const uint64_t* __restrict__ offsets,
                                                uint32_t* __restrict__ out_ids) {
-    __shared__ LevelInfo s_lv[64];
+    __shared__ LevelInfo s_lv[MAX_LEVELS];
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
     __syncthreads();
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -437,14 +545,172 @@ __global__ __launch_bounds__(256) void k_range(TreeView t, const uint32_t* __res
     if (!REPORT) counts[b] = cnt;
 }
 
+// ------------------------------------------------- range queries, wave per box
+// One wave per box. Expanding a node tests all its children at once (one
+// lane per child); children that straddle the box are remembered in a
+// per-level mask (a stack of masks in LDS) and expanded depth first. Leaves
+// that straddle the box are scanned one entry per lane; whole subtrees inside
+// the box add their counts, or, for reports, are copied one leaf per lane.
+constexpr int RW_WAVES = 4;
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
+    const uint32_t lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = shfl_u32(x, (int)lane - o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    *total = shfl_u32(x, 63);
+    return x - v;
+}
+
+template <int D, bool REPORT>
+__global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
+                                                    const uint32_t* __restrict__ order,
+                                                    uint64_t* __restrict__ counts,
+                                                    const uint64_t* __restrict__ offsets,
+                                                    uint32_t* __restrict__ out) {
+    __shared__ LevelInfo s_lv[MAX_LEVELS];
+    __shared__ uint64_t s_mask[RW_WAVES][MAX_LEVELS];
+    __shared__ uint64_t s_base[RW_WAVES][MAX_LEVELS];
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = lane_id();
+    const uint64_t bx = (uint64_t)blockIdx.x * RW_WAVES + w;
+    if (bx >= nb) return;
+    const uint64_t b = order ? order[bx] : bx;
+    uint32_t lo[D], hi[D];
+    bool empty = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = boxes[b * 2 * D + d];
+        hi[d] = boxes[b * 2 * D + D + d];
+        empty = empty || lo[d] > hi[d];
+    }
+    uint64_t cnt = 0;
+    uint64_t o = 0, lim = 0;
+    if (REPORT) {
+        o = offsets[b];
+        lim = offsets[b + 1];
+    }
+    const uint32_t C = t.C, B = t.B, h = t.h;
+
+    // Visit nc children starting at c0 on level l (lane c owns child c0 + c).
+    auto visit = [&](uint32_t l, uint64_t c0, uint32_t nc) {
+        const bool on = lane < nc;
+        NodeRec r = {};
+        int rel = 0;
+        if (on) {
+            r = fetch(t, s_lv, l, c0 + lane);
+            rel = r.cnt ? box_relation<D>(r, lo, hi) : 0;
+        }
+        const uint64_t inside = ballot(rel == 2);
+        const uint64_t partial = ballot(rel == 1);
+        if (l < h) {
+            s_mask[w][l] = partial;
+            s_base[w][l] = c0;
+            if (!REPORT) {
+                uint32_t tot;
+                (void)wave_excl_scan(rel == 2 ? r.cnt : 0u, &tot);
+                cnt += tot;
+            } else {
+                uint64_t m = inside;
+                while (m) {  // copy every leaf under each inside child, one leaf per lane
+                    const uint32_t c = (uint32_t)__builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint64_t span = s_lv[l].span;
+                    const uint64_t j0 = (c0 + c) * span, j1 = min<uint64_t>(j0 + span, t.L);
+                    for (uint64_t jb = j0; jb < j1; jb += 64) {
+                        const uint64_t j = jb + lane;
+                        const NodeRec lf = j < j1 ? t.leaf[j] : NodeRec{};
+                        const uint32_t lc = j < j1 ? lf.cnt : 0u;
+                        uint32_t tot;
+                        const uint32_t pos = wave_excl_scan(lc, &tot);
+                        const uint32_t* s = t.slots + (uint64_t)lf.slot * (D + 1) * C + D * C;
+                        for (uint32_t e = 0; e < lc; ++e)
+                            if (o + pos + e < lim) out[o + pos + e] = s[e];
+                        o += tot;
+                    }
+                }
+            }
+            return;
+        }
+        // leaf level: inside leaves, one leaf per lane
+        {
+            const uint32_t lc = rel == 2 ? r.cnt : 0u;
+            uint32_t tot;
+            const uint32_t pos = wave_excl_scan(lc, &tot);
+            if (REPORT && lc) {
+                const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C + D * C;
+                for (uint32_t e = 0; e < lc; ++e)
+                    if (o + pos + e < lim) out[o + pos + e] = s[e];
+            }
+            if (REPORT) o += tot;
+            else cnt += tot;
+        }
+        // straddling leaves, one entry per lane
+        uint64_t m = partial;
+        while (m) {
+            const uint32_t c = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t rc = shfl_u32(r.cnt, (int)c);
+            const uint32_t rs = shfl_u32(r.slot, (int)c);
+            const uint32_t* s = t.slots + (uint64_t)rs * (D + 1) * C;
+            for (uint32_t e0 = 0; e0 < rc; e0 += 64) {
+                const uint32_t e = e0 + lane;
+                bool in = false;
+                if (e < rc) {
+                    uint32_t p[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+                    in = in_box<D>(p, lo, hi);
+                }
+                const uint64_t hit = ballot(in);
+                if (REPORT && in) {
+                    const uint64_t dst = o + count_below(hit);
+                    if (dst < lim) out[dst] = s[D * C + e];
+                }
+                if (REPORT) o += (uint32_t)__popcll(hit);
+                else cnt += (uint32_t)__popcll(hit);
+            }
+        }
+    };
+
+    if (!empty && t.L > 0) {
+        visit(0, 0, 1);
+        int d = 0;
+        while (h > 0 && d >= 0) {
+            const uint64_t m = s_mask[w][d];
+            if (m == 0) {
+                --d;
+                continue;
+            }
+            const uint32_t bit = (uint32_t)__builtin_ctzll(m);
+            s_mask[w][d] = m & (m - 1);
+            const uint64_t node = s_base[w][d] + bit;
+            const uint64_t c0 = node * B;
+            const uint32_t nc = (uint32_t)min<uint64_t>(B, s_lv[d + 1].n - c0);
+            visit((uint32_t)d + 1, c0, nc);
+            if ((uint32_t)d + 1 < h) ++d;
+        }
+    }
+    if (!REPORT && lane == 0) counts[b] = cnt;
+}
+
 }  // namespace
 
-void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, uint64_t nq, uint32_t k,
-                uint32_t* ids, uint64_t* d2) {
+void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
+                const uint32_t* order, uint32_t k, int variant, uint32_t* ids, uint64_t* d2) {
     if (nq == 0) return;
     const unsigned gl = blocks_for(nq, 256);
     const unsigned gw = blocks_for(nq, KW_WAVES);
-#define PSI_KL(D, K) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, ids, d2)
+#define PSI_KL(D, K)                                                                                             \
+    do {                                                                                                         \
+        if (variant == 1) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, order, ids, d2); \
+        else hipLaunchKernelGGL((k_knn_seed<D, K>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, ids, d2); \
+    } while (0)
 #define PSI_KL_ALL(D)                                                                                    \
     switch (k) {                                                                                         \
         case 1: PSI_KL(D, 1); break;   case 2: PSI_KL(D, 2); break;   case 3: PSI_KL(D, 3); break;       \
@@ -454,9 +720,9 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, u
         case 13: PSI_KL(D, 13); break; case 14: PSI_KL(D, 14); break; case 15: PSI_KL(D, 15); break;     \
         case 16: PSI_KL(D, 16); break;                                                                   \
         default:                                                                                         \
-            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
-            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
-            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, nq, k, ids, d2); \
+            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
+            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
+            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
     }
     if (dim == 2) { PSI_KL_ALL(2) } else { PSI_KL_ALL(3) }
 #undef PSI_KL_ALL
@@ -464,19 +730,27 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, u
 }
 
 void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
-                        uint64_t* counts) {
+                        const uint32_t* order, uint64_t* counts) {
+    if (nb == 0) return;
+    const unsigned g = blocks_for(nb, RW_WAVES);
+    if (dim == 2) hipLaunchKernelGGL((k_range_wave<2, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, order, counts, nullptr, nullptr);
+    else hipLaunchKernelGGL((k_range_wave<3, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, order, counts, nullptr, nullptr);
+}
+
+void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                         const uint32_t* order, const uint64_t* offsets, uint32_t* ids) {
+    if (nb == 0) return;
+    const unsigned g = blocks_for(nb, RW_WAVES);
+    if (dim == 2) hipLaunchKernelGGL((k_range_wave<2, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, order, nullptr, offsets, ids);
+    else hipLaunchKernelGGL((k_range_wave<3, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, order, nullptr, offsets, ids);
+}
+
+void launch_range_count_lane(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                             uint64_t* counts) {
     if (nb == 0) return;
     const unsigned g = blocks_for(nb, 256);
     if (dim == 2) hipLaunchKernelGGL((k_range<2, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, counts, nullptr, nullptr);
     else hipLaunchKernelGGL((k_range<3, false>), dim3(g), dim3(256), 0, st, t, boxes, nb, counts, nullptr, nullptr);
-}
-
-void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
-                         const uint64_t* offsets, uint32_t* ids) {
-    if (nb == 0) return;
-    const unsigned g = blocks_for(nb, 256);
-    if (dim == 2) hipLaunchKernelGGL((k_range<2, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, nullptr, offsets, ids);
-    else hipLaunchKernelGGL((k_range<3, true>), dim3(g), dim3(256), 0, st, t, boxes, nb, nullptr, offsets, ids);
 }
 
 }  // namespace psi

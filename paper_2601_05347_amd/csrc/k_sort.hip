@@ -93,6 +93,22 @@ __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict_
     }
 }
 
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_encode_boxes(const uint32_t* __restrict__ boxes, uint64_t n,
+                                                      uint64_t* __restrict__ keys) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t lo = boxes[i * 2 * D + d], hi = boxes[i * 2 * D + D + d];
+        uint32_t v = lo <= hi ? lo + (hi - lo) / 2 : lo;
+        v = min(v, D == 2 ? 0x7FFFFFFFu : 0x1FFFFFu);
+        c[d] = v;
+    }
+    keys[i] = sfc_key<D, CURVE>(c);
+}
+
 __global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ off) {
     __shared__ uint32_t s_w[WAVES];
@@ -331,6 +347,15 @@ void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint
     if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
     if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
     if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+}
+
+void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* boxes, uint64_t n, uint64_t* keys) {
+    if (n == 0) return;
+    const unsigned g = blocks_for(n, 256);
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_boxes<2, 0>), dim3(g), dim3(256), 0, st, boxes, n, keys);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_boxes<2, 1>), dim3(g), dim3(256), 0, st, boxes, n, keys);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_boxes<3, 0>), dim3(g), dim3(256), 0, st, boxes, n, keys);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_boxes<3, 1>), dim3(g), dim3(256), 0, st, boxes, n, keys);
 }
 
 void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint32_t* off) {

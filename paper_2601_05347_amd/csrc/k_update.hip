@@ -366,65 +366,87 @@ __global__ void k_del_kill(const uint32_t* __restrict__ ci, const uint32_t* __re
     idkey[ci[e]] = DEAD_KEY;
 }
 
+// One wave per run: lane e holds leaf entry e; entries whose id is in the
+// run are dropped and the survivors are compacted stably in place.
 template <int D>
-__global__ void k_del_remove(const uint32_t* __restrict__ ci, const uint32_t* __restrict__ run_leaf,
-                             const uint32_t* __restrict__ run_beg, const uint32_t* __restrict__ ctr, uint64_t m,
-                             NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots, uint32_t C,
-                             uint32_t* __restrict__ err, Caps cap) {
-    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__ ci,
+                                                    const uint32_t* __restrict__ run_leaf,
+                                                    const uint32_t* __restrict__ run_beg,
+                                                    const uint32_t* __restrict__ ctr, uint64_t m,
+                                                    NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
+                                                    uint32_t C, uint32_t* __restrict__ err, Caps cap) {
+    const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = lane_id();
     const uint32_t R = ctr[1];
     if (r >= R) return;
     const uint32_t V = ctr[0];
     const uint32_t j = run_leaf[r];
     const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, V);
     NodeRec rec = leaf[j];
-    if (rec.slot >= cap.slots || rec.cnt > C) {
-        atomicOr(err, ERR_CAPACITY);
+    if (rec.slot >= cap.slots || rec.cnt > C || rec.cnt > 64) {
+        if (lane == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
     uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
-    uint32_t w = 0, removed = 0;
-    uint32_t lo[D], hi[D];
+    const bool on = lane < rec.cnt;
+    uint32_t p[D];
+    uint32_t id = PAD_ID;
+    if (on) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s[d * C + lane];
+        id = s[D * C + lane];
+    }
+    bool del = false;
+    for (uint32_t x0 = beg; x0 < end; x0 += 64) {  // the run's ids, 64 at a time
+        const uint32_t rid = x0 + lane < end ? ci[x0 + lane] : PAD_ID;
+        const uint32_t nx = min(64u, end - x0);
+        for (uint32_t x = 0; x < nx; ++x) del = del || (on && shfl_u32(rid, (int)x) == id);
+    }
+    // `valid` is always true (stored coordinates are below 2^31) but makes the
+    // ballot depend on every loaded coordinate, so all loads of the wave have
+    // completed before the in-place stores below are issued.
+    uint32_t any = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) any |= on ? p[d] : 0u;
+    const bool valid = any < 0x80000000u;
+    const bool keep = on && !del && valid;
+    const uint64_t km = ballot(keep);
+    const uint32_t removed = (uint32_t)__popcll(ballot(on && del));
+    const uint32_t pos = count_below(km);
+    if (keep && pos != lane) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d * C + pos] = p[d];
+        s[D * C + pos] = id;
+    }
+    const uint32_t w = (uint32_t)__popcll(km);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        lo[d] = 0xFFFFFFFFu;
-        hi[d] = 0u;
+        rec.lo[d] = wave_min_u32(keep ? p[d] : 0xFFFFFFFFu);
+        rec.hi[d] = wave_max_u32(keep ? p[d] : 0u);
     }
-    for (uint32_t e = 0; e < rec.cnt; ++e) {
-        const uint32_t id = s[D * C + e];
-        bool del = false;
-        for (uint32_t x = beg; x < end; ++x) del = del || ci[x] == id;
-        if (del) {
-            ++removed;
-            continue;
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const uint32_t v = s[d * C + e];
-            if (w != e) s[d * C + w] = v;
-            lo[d] = min(lo[d], v);
-            hi[d] = max(hi[d], v);
-        }
-        if (w != e) s[D * C + w] = id;
-        ++w;
+    if (lane == 0) {
+        if (removed != end - beg) atomicOr(err, ERR_DELETE);
+        rec.cnt = w;
+        leaf[j] = rec;
     }
-    if (removed != end - beg) atomicOr(err, ERR_DELETE);
-    rec.cnt = w;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        rec.lo[d] = lo[d];
-        rec.hi[d] = hi[d];
-    }
-    leaf[j] = rec;
 }
 
 __global__ void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half, uint32_t* __restrict__ cnt,
                              uint32_t* __restrict__ ctr) {
+    __shared__ uint32_t s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L) return;
-    const uint32_t c = leaf[j].cnt;
-    cnt[j] = c;
-    if (c >= half) atomicMax(&ctr[7], (uint32_t)(j + 1));
+    uint32_t last = 0;
+    if (j < L) {
+        const uint32_t c = leaf[j].cnt;
+        cnt[j] = c;
+        if (c >= half) last = (uint32_t)(j + 1);
+    }
+    last = wave_max_u32(last);
+    if (lane_id() == 0 && last) atomicMax(&s_max, last);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax(&ctr[7], s_max);
 }
 
 __global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t L, uint32_t half,
@@ -682,7 +704,7 @@ void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint6
 }
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
                     const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
-    PSI_D(k_del_remove, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
+    PSI_D(k_del_remove, dim3(blocks_for(m, 4)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
 }
 void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
                   uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,

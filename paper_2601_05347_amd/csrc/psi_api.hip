@@ -160,12 +160,38 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
     return build_nodes(ix);
 }
 
+// Processing order of a query batch: the batch's positions sorted by the
+// curve key of each query point (or box centre), so that the queries one
+// wave handles lie close together in space and share tree nodes and leaves.
+// Query points are also range-checked here (errors are latched).
+static const uint64_t ORDER_MIN = 4096;
+
+static psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool boxes, const uint32_t** order) {
+    *order = nullptr;
+    const bool sort = n >= ORDER_MIN && !(ix->flags & PSI_FLAG_INPUT_ORDER);
+    if (boxes && !sort) return PSI_OK;
+    psi_status s;
+    if ((s = ix->scr.c.ensure(n * 8)) != PSI_OK) return s;
+    uint64_t* keys = ix->scr.c.as<uint64_t>();
+    {
+        ProfScope ps(ix, "order", n * (boxes ? 8ull * ix->D : 4ull * ix->D) + n * 8);
+        if (boxes) launch_encode_boxes(ix->st, ix->D, ix->curve, d_items, n, keys);
+        else launch_encode(ix->st, ix->D, ix->curve, d_items, n, keys, ix->err.as<uint32_t>());
+    }
+    if (!sort) return last_launch();
+    int w = 0;
+    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w)) != PSI_OK) return s;
+    *order = ix->sorter.i[w].as<uint32_t>();
+    return last_launch();
+}
+
 }  // namespace psi
 
 psi::TreeView psi_index_s::view() const {
     psi::TreeView t{};
     t.inner = inner.as<psi::NodeRec>();
     t.leaf = leaf[cur].as<psi::NodeRec>();
+    t.pkey = pkey[cur].as<uint64_t>();
     t.slots = slots.as<uint32_t>();
     t.h = h;
     t.B = B;
@@ -195,7 +221,7 @@ psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out) {
     if (!prm || !out) return PSI_E_ARG;
     *out = nullptr;
     if ((prm->dim != 2 && prm->dim != 3) || prm->curve > 1 || prm->leaf_size < 2 || prm->leaf_size > 32 ||
-        prm->fanout < 2 || prm->fanout > 32 || prm->flags != 0)
+        prm->fanout < 2 || prm->fanout > 32 || (prm->flags & ~(uint32_t)(PSI_FLAG_INPUT_ORDER | PSI_FLAG_KNN_NEAREST_FIRST)) != 0)
         return PSI_E_ARG;
     psi_index ix = new (std::nothrow) psi_index_s;
     if (!ix) return PSI_E_NOMEM;
@@ -204,6 +230,7 @@ psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out) {
     ix->phi = prm->leaf_size;
     ix->C = (2 * prm->leaf_size + 3) & ~3u;
     ix->B = prm->fanout;
+    ix->flags = prm->flags;
     ix->st = static_cast<hipStream_t>(hip_stream);
     psi_status s = ix->err.ensure(64);
     if (s == PSI_OK) s = hip_ok(hipHostMalloc(&ix->pinned, 4096, hipHostMallocDefault));
@@ -258,16 +285,23 @@ psi_status psi_batch_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uin
 psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids, uint64_t* d_d2) {
     if (!ix || k == 0 || k > 128 || (nq && (!d_q || !d_ids || !d_d2))) return PSI_E_ARG;
     if (nq == 0) return PSI_OK;
+    const uint32_t* order = nullptr;
+    psi_status s = query_order(ix, d_q, nq, false, &order);
+    if (s != PSI_OK) return s;
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
-    launch_knn(ix->st, ix->D, ix->view(), d_q, nq, k, d_ids, d_d2);
+    launch_knn(ix->st, ix->D, ix->view(), d_q, ix->scr.c.as<uint64_t>(), nq, order, k,
+               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, d_ids, d_d2);
     return last_launch();
 }
 
 psi_status psi_range_count(psi_index ix, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts) {
     if (!ix || (nb && (!d_boxes || !d_counts))) return PSI_E_ARG;
     if (nb == 0) return PSI_OK;
+    const uint32_t* order = nullptr;
+    psi_status s = query_order(ix, d_boxes, nb, true, &order);
+    if (s != PSI_OK) return s;
     ProfScope ps(ix, "range_count", nb * (8ull * ix->D + 8));
-    launch_range_count(ix->st, ix->D, ix->view(), d_boxes, nb, d_counts);
+    launch_range_count(ix->st, ix->D, ix->view(), d_boxes, nb, order, d_counts);
     return last_launch();
 }
 
@@ -275,8 +309,11 @@ psi_status psi_range_report(psi_index ix, const uint32_t* d_boxes, uint64_t nb, 
                             uint32_t* d_ids) {
     if (!ix || (nb && (!d_boxes || !d_offsets))) return PSI_E_ARG;
     if (nb == 0) return PSI_OK;
+    const uint32_t* order = nullptr;
+    psi_status s = query_order(ix, d_boxes, nb, true, &order);
+    if (s != PSI_OK) return s;
     ProfScope ps(ix, "range_report", nb * (8ull * ix->D + 16));
-    launch_range_report(ix->st, ix->D, ix->view(), d_boxes, nb, d_offsets, d_ids);
+    launch_range_report(ix->st, ix->D, ix->view(), d_boxes, nb, order, d_offsets, d_ids);
     return last_launch();
 }
 

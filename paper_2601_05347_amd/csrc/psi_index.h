@@ -128,6 +128,7 @@ struct psi_index_s {
     uint32_t phi = 32;
     uint32_t C = 64;  // slot capacity (2 phi rounded up to a multiple of 4)
     uint32_t B = 8;
+    uint32_t flags = 0;
     hipStream_t st = nullptr;
 
     // id -> key table (DEAD_KEY for deleted or never used ids)

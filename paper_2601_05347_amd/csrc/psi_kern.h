@@ -31,6 +31,8 @@ void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids
 // (hist zeroed, [8][256]); coordinates out of range set ERR_RANGE.
 void launch_encode_hist(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
                         uint32_t* hist, uint32_t* err);
+// Curve keys of box centres (boxes [n][2][dim]); used to order box batches.
+void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* boxes, uint64_t n, uint64_t* keys);
 // Curve keys only.
 void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
                    uint32_t* err);
@@ -68,6 +70,7 @@ void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n
 struct TreeView {
     const NodeRec* inner;   // levels 0..h-1
     const NodeRec* leaf;    // level h (the directory)
+    const uint64_t* pkey;   // leaf pivot keys (ascending)
     const uint32_t* slots;
     uint32_t h;
     uint32_t B;
@@ -75,12 +78,22 @@ struct TreeView {
     uint64_t L;
     LevelInfo lv[MAX_LEVELS];  // levels 0..h (passed by value with every launch)
 };
-void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, uint64_t nq, uint32_t k,
-                uint32_t* ids, uint64_t* d2);
+// Queries are processed in the order `order` gives (nullptr: input order);
+// results always land in the query's own row.
+// qkeys: curve keys of the queries in input order (seeds the search with the
+// leaves around each query's own curve position). variant 0: seeded
+// fixed-order traversal; 1: nearest-child-first traversal.
+void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
+                const uint32_t* order, uint32_t k, int variant, uint32_t* ids, uint64_t* d2);
+// Boxes are processed in the order `order` gives (nullptr: input order);
+// results always land at the box's own index.
 void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
-                        uint64_t* counts);
+                        const uint32_t* order, uint64_t* counts);
 void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
-                         const uint64_t* offsets, uint32_t* ids);
+                         const uint32_t* order, const uint64_t* offsets, uint32_t* ids);
+// One thread per box (kept for comparison in tests and benchmarks).
+void launch_range_count_lane(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
+                             uint64_t* counts);
 
 // ----------------------------------------------------------------- export
 // Prefix sums of leaf counts -> entry offsets (u64, L+1 entries).

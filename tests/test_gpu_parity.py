@@ -145,12 +145,15 @@ def test_build_deterministic(psi):
 
 
 # --------------------------------------------------------------------- kNN
+@pytest.mark.parametrize("variant", [0, 2])
 @pytest.mark.parametrize("k", [1, 10, 16, 17, 50, 100, 128])
 @pytest.mark.parametrize("dim,curve", [(2, 1), (3, 1), (3, 0)])
-def test_knn_parity(psi, dim, curve, k):
-    say(f"knn dim={dim} curve={curve} k={k}")
-    data, _, q = synth.workload("varden", dim, bits_of(dim), seed=k, n=60_000, n_query=1500)
-    ix, ref = make_pair(psi, dim, curve, data)
+def test_knn_parity(psi, dim, curve, k, variant):
+    say(f"knn dim={dim} curve={curve} k={k} flags={variant}")
+    data, _, q = synth.workload("varden", dim, bits_of(dim), seed=k, n=60_000, n_query=5000)
+    ix = psi.Index(dim, curve, 32, 8, flags=variant).build(data)
+    ref = oracle.RefIndex(dim, curve, 32, 8)
+    ref.build(data)
     ids, d2 = ix.knn(q, k)
     eids, ed2 = ref.knn(q, k)
     np.testing.assert_array_equal(psi.to_u64(d2), ed2)
@@ -164,10 +167,12 @@ def test_knn_ties_small_domain(psi, k):
     pts = synth.uniform(20_000, 2, 4, seed=k)
     q = synth.uniform(700, 2, 4, seed=k, purpose=synth.P_QUERY)
     ix, ref = make_pair(psi, 2, 1, pts, phi=8, B=4)
-    ids, d2 = ix.knn(q, k)
+    alt = psi.Index(2, 1, 8, 4, flags=psi.FLAG_KNN_NEAREST_FIRST).build(pts)
     eids, ed2 = ref.knn(q, k)
-    np.testing.assert_array_equal(psi.to_u64(d2), ed2)
-    np.testing.assert_array_equal(psi.to_u32(ids), eids)
+    for g in (ix, alt):
+        ids, d2 = g.knn(q, k)
+        np.testing.assert_array_equal(psi.to_u64(d2), ed2)
+        np.testing.assert_array_equal(psi.to_u32(ids), eids)
 
 
 def test_knn_full_width_2d(psi):
@@ -202,7 +207,7 @@ def test_knn_k_exceeds_n(psi, n):
 def test_range_parity(psi, dim, curve):
     say(f"range dim={dim} curve={curve}")
     bits = bits_of(dim)
-    data, _, q = synth.workload("varden", dim, bits, seed=31, n=80_000, n_query=3000)
+    data, _, q = synth.workload("varden", dim, bits, seed=31, n=80_000, n_query=5000)
     bx = synth.boxes(q, bits, seed=32, side_lo=8, side_hi=22 if dim == 2 else 16)
     ix, ref = make_pair(psi, dim, curve, data)
     cnt = psi.to_u64(ix.range_count(bx))
@@ -229,3 +234,47 @@ def test_range_edge_boxes(psi):
     np.testing.assert_array_equal(cnt, ref.range_count(bx))
     off, ids = ix.range_report(bx)
     assert np.array_equal(np.sort(psi.to_u32(ids)[:20_000]), np.arange(20_000, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("dim,curve", [(2, 0), (3, 1)])
+def test_query_order_is_invisible(psi, dim, curve):
+    # batches of >= 4096 queries are processed in curve order; the results
+    # must equal input-order processing and the oracle
+    say(f"query order dim={dim} curve={curve}")
+    bits = bits_of(dim)
+    data, _, q = synth.workload("uniform", dim, bits, seed=41, n=200_000, n_query=20_000)
+    a = psi.Index(dim, curve).build(data)
+    b = psi.Index(dim, curve, flags=psi.FLAG_INPUT_ORDER).build(data)
+    for k in (4, 24):
+        ia, da = a.knn(q, k)
+        ib, db = b.knn(q, k)
+        np.testing.assert_array_equal(psi.to_u32(ia), psi.to_u32(ib))
+        np.testing.assert_array_equal(psi.to_u64(da), psi.to_u64(db))
+        sample = synth.sample_rows(len(q), 300, seed=k)
+        eids, ed2 = oracle.knn_points(data, q[sample], k)
+        np.testing.assert_array_equal(psi.to_u32(ia)[sample], eids)
+        np.testing.assert_array_equal(psi.to_u64(da)[sample], ed2)
+    bx = synth.boxes(q[:6000], bits, seed=42, side_lo=8, side_hi=20 if dim == 2 else 15)
+    ca, cb = psi.to_u64(a.range_count(bx)), psi.to_u64(b.range_count(bx))
+    np.testing.assert_array_equal(ca, cb)
+    np.testing.assert_array_equal(ca[:500], oracle.range_count_points(data, bx[:500]))
+    oa, ra = a.range_report(bx)
+    ob, rb = b.range_report(bx)
+    oa, ra, rb = psi.to_u64(oa), psi.to_u32(ra), psi.to_u32(rb)
+    for i in range(0, len(bx), 97):
+        np.testing.assert_array_equal(np.sort(ra[oa[i]:oa[i + 1]]), np.sort(rb[oa[i]:oa[i + 1]]))
+
+
+@pytest.mark.parametrize("B,phi,n", [(2, 4, 3000), (3, 7, 5000), (32, 32, 70_000), (8, 32, 20)])
+def test_range_fanouts(psi, B, phi, n):
+    say(f"range fanout B={B} phi={phi} n={n}")
+    pts = synth.varden(n, 3, 21, seed=B)
+    ix, ref = make_pair(psi, 3, 1, pts, phi=phi, B=B)
+    bx = synth.boxes(synth.varden(700, 3, 21, seed=B + 1), 21, seed=B + 2, side_lo=4, side_hi=20)
+    np.testing.assert_array_equal(psi.to_u64(ix.range_count(bx)), ref.range_count(bx))
+    off, ids = ix.range_report(bx)
+    off, ids = psi.to_u64(off), psi.to_u32(ids)
+    eoff, eids = ref.range_report(bx)
+    np.testing.assert_array_equal(off, eoff)
+    got = np.concatenate([np.sort(ids[off[b]:off[b + 1]]) for b in range(len(bx))])
+    np.testing.assert_array_equal(got, eids)
