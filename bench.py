@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpoints/s build & batch-update, kNN queries/s (1e8 pts, 3D); p99 latency"
 HBM_PEAK_GBS = 8000.0
+CALIB_BYTES = 1 << 30
 
 WORKLOADS = {
     # the metric's configuration: 3D, 1e8 points, 21-bit coordinates
@@ -60,6 +61,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=16_000_000, help="points in the oracle's timed sample")
     return ap.parse_args()
+
+
+def profiled_traffic(profile: str, kernel_source: str):
+    """HBM bytes per launch recorded by a rocprofv3 counter run, if the kernel's
+    source is unchanged since (profiles/*.md carry the source hash)."""
+    import hashlib
+    import re
+    try:
+        txt = open(os.path.join(ROOT, "profiles", profile)).read()
+        src = open(os.path.join(ROOT, "paper_2601_05347_amd", "csrc", kernel_source), "rb").read()
+    except OSError:
+        return None
+    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    if not (m_t and m_h) or m_h.group(1) != hashlib.sha256(src).hexdigest():
+        return None
+    return int(m_t.group(1))
 
 
 def cpu_baseline(cfg, args):
@@ -164,6 +182,14 @@ def main():
     def events():
         return {p: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for p in phases}
 
+    # A plain device copy of known size (1 GiB read + 1 GiB written), outside
+    # the timed region: rocprofv3 counter runs scale FETCH_SIZE / WRITE_SIZE
+    # of the other kernels by what the counters read for this copy.
+    calib_src = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device=dev)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    del calib_src, calib_dst
+
     for _ in range(max(args.warmup, 1 if "range" in ops else 0)):
         step(events())
     ix.sync()
@@ -187,18 +213,22 @@ def main():
     value = upd_pts / (upd_ms / 1e3) / 1e6 if upd_ms > 0 else 0.0
 
     # dominant kernel family and its roofline
-    fams = ["radix_pass", "encode_hist", "leaf_fill", "nodes", "hist", "knn", "range_count", "range_report",
-            "update"]
+    fams = ["radix_pass", "encode_hist", "leaf_fill", "nodes", "hist", "radix_update", "radix_order", "order", "knn",
+            "range_count", "range_report", "update"]
     prof = {f: ix.prof_get(f) for f in fams}
-    mem_fams = [f for f in fams if f not in ("knn", "range_count", "range_report") and prof[f][1] > 0]
+    # the dominant streaming kernel of the build & update path
+    mem_fams = [f for f in ("radix_pass", "encode_hist", "leaf_fill", "nodes") if prof[f][1] > 0]
     dom = max(mem_fams, key=lambda f: prof[f][0]) if mem_fams else None
     roof = None
     if dom:
         tms, launches, byt = prof[dom]
         avg_s = tms / launches / 1e3
         achieved = byt / launches / avg_s / 1e9
+        traffic = None
+        if dom == "radix_pass" and args.workload == "3d-1e8" and args.dist == "uniform" and n == 100_000_000:
+            traffic = profiled_traffic("onesweep_pass_3d_1e8_uniform.md", "k_sort.hip")
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": byt // launches, "avg_launch_ms": round(tms / launches, 4)}
     kernel_ms = {f: round(prof[f][0] / args.steps, 3) for f in fams if prof[f][1]}
 

@@ -400,7 +400,10 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
     for (uint32_t x0 = beg; x0 < end; x0 += 64) {  // the run's ids, 64 at a time
         const uint32_t rid = x0 + lane < end ? ci[x0 + lane] : PAD_ID;
         const uint32_t nx = min(64u, end - x0);
-        for (uint32_t x = 0; x < nx; ++x) del = del || (on && shfl_u32(rid, (int)x) == id);
+        for (uint32_t x = 0; x < nx; ++x) {
+            const uint32_t other = shfl_u32(rid, (int)x);  // every lane takes part in the shuffle
+            del = del | (on & (other == id));
+        }
     }
     // `valid` is always true (stored coordinates are below 2^31) but makes the
     // ballot depend on every loaded coordinate, so all loads of the wave have

@@ -26,7 +26,7 @@ psi_status readback(psi_index ix, const void* dev, size_t bytes) {
 // Passes: optionally the four id bytes first (so equal keys end up in id
 // order whatever the input order), then the eight key bytes.
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
-                      bool id_digits, bool hist_ready, int* which) {
+                      bool id_digits, bool hist_ready, int* which, const char* fam) {
     Sorter& S = ix->sorter;
     PassList pl{};
     pl.n = 0;
@@ -65,7 +65,7 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
             launch_fill_u32(ix->st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
         }
         {
-            ProfScope ps(ix, "radix_pass", n * 24);
+            ProfScope ps(ix, fam, n * 24);
             launch_onesweep(ix->st, p == 0 && iin == nullptr, pl.src[p] == 1, ksrc, isrc, id_base,
                             S.k[dst].as<uint64_t>(), S.i[dst].as<uint32_t>(), n, pl.shift[p],
                             S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(),
@@ -140,7 +140,7 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
         launch_encode_hist(ix->st, ix->D, ix->curve, d_pts, n, keys, S.hist.as<uint32_t>(), ix->err.as<uint32_t>());
     }
     int w = 0;
-    if ((s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w)) != PSI_OK) return s;
+    if ((s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w, "radix_pass")) != PSI_OK) return s;
     const uint64_t L = (n + ix->phi - 1) / ix->phi;
     const int c = ix->cur;
     if ((s = ix->slots.ensure(L * ix->slot_words() * 4)) != PSI_OK) return s;
@@ -180,7 +180,7 @@ static psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n,
     }
     if (!sort) return last_launch();
     int w = 0;
-    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w)) != PSI_OK) return s;
+    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order")) != PSI_OK) return s;
     *order = ix->sorter.i[w].as<uint32_t>();
     return last_launch();
 }
@@ -412,7 +412,7 @@ psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_
     psi_status s = psi_create(&prm, hip_stream, &ix);
     if (s != PSI_OK) return s;
     int w = 0;
-    s = sort_pairs(ix, d_keys, d_ids, 0, n, true, false, &w);
+    s = sort_pairs(ix, d_keys, d_ids, 0, n, true, false, &w, "radix_pass");
     if (s == PSI_OK) s = hip_ok(hipMemcpyAsync(d_keys_out, ix->sorter.k[w].p, n * 8, hipMemcpyDeviceToDevice, ix->st));
     if (s == PSI_OK) s = hip_ok(hipMemcpyAsync(d_ids_out, ix->sorter.i[w].p, n * 4, hipMemcpyDeviceToDevice, ix->st));
     psi_status e = psi_sync(ix);

@@ -191,7 +191,7 @@ struct ProfScope {
 
 psi_status hip_ok(hipError_t e);
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
-                      bool id_digits, bool hist_ready, int* which);
+                      bool id_digits, bool hist_ready, int* which, const char* fam);
 psi_status build_nodes(psi_index ix);
 psi_status readback(psi_index ix, const void* dev, size_t bytes);  // into ix->pinned, waits
 

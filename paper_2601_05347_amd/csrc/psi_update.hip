@@ -84,7 +84,7 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     uint64_t* keys = ix->idkey.as<uint64_t>() + base_id;
     launch_encode_hist(st, ix->D, ix->curve, d_pts, m, keys, S.hist.as<uint32_t>(), ix->err.as<uint32_t>());
     int w = 0;
-    if ((s = sort_pairs(ix, keys, nullptr, base_id, m, false, true, &w)) != PSI_OK) return s;
+    if ((s = sort_pairs(ix, keys, nullptr, base_id, m, false, true, &w, "radix_update")) != PSI_OK) return s;
     const uint64_t* bk = S.k[w].as<uint64_t>();
     const uint32_t* bi = S.i[w].as<uint32_t>();
     if (d_new_ids) launch_iota_u32(st, d_new_ids, m, base_id);
@@ -230,7 +230,7 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
     launch_fill_u32(st, a.ctr, 16, 0u);
     upd_del_gather(st, d_ids, m, ix->idkey.as<uint64_t>(), ix->next_id, a.dk, a.di);
     int w = 0;
-    if ((s = sort_pairs(ix, a.dk, a.di, 0, m, true, false, &w)) != PSI_OK) return s;
+    if ((s = sort_pairs(ix, a.dk, a.di, 0, m, true, false, &w, "radix_update")) != PSI_OK) return s;
     upd_del_compact(st, ix->sorter.k[w].as<uint64_t>(), ix->sorter.i[w].as<uint32_t>(), m, a.flag, a.pos, a.ctr + 0,
                     a.ck, a.ci, a.tmp);
     upd_del_kill(st, a.ci, a.ctr, m, ix->idkey.as<uint64_t>(), d_ndeleted);
