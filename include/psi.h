@@ -75,6 +75,7 @@ typedef struct {
 } psi_params;
 
 typedef struct psi_index_s* psi_index;
+typedef struct psi_multi_s* psi_multi;
 
 const char* psi_status_str(psi_status s);
 
@@ -165,6 +166,37 @@ psi_status psi_encode(uint32_t dim, uint32_t curve, const uint32_t* d_pts, uint6
  * therefore waits on the stream before returning. */
 psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_t n,
                           uint64_t* d_keys_out, uint32_t* d_ids_out, void* hip_stream);
+
+/* --- many independent indexes (batched small indexes) -------------------- */
+
+/* Build `num` independent indexes from one CSR batch: index s holds the
+ * points d_pts[d_pt_off[s] .. d_pt_off[s+1]) (d_pt_off: device uint64
+ * [num+1], d_pt_off[0] = 0) with local ids 0.. in that order. All indexes are
+ * encoded, sorted (one segment per index), cut into leaves and given their
+ * node levels by the same launches; each index's structure equals what
+ * psi_build makes from its points alone. At most 2^24 points per index and
+ * 2^32 - 1 in total. Waits on the stream (the offsets are read on the host). */
+psi_status psi_multi_build(const psi_params* prm, void* hip_stream, uint32_t num, const uint64_t* d_pt_off,
+                           const uint32_t* d_pts, psi_multi* out);
+psi_status psi_multi_destroy(psi_multi mx);
+/* kNN (as psi_knn) of query batches of uneven sizes: the queries
+ * d_q[d_q_off[s] .. d_q_off[s+1]) search index s; rows of d_ids/d_d2
+ * ([total queries][k]) follow d_q. All batches run in ONE persistent launch
+ * whose waves take (index, 64-query chunk) items from an atomic counter.
+ * k in {1, 2, 4, 8, 10, 16}. Never waits on the stream. */
+psi_status psi_multi_knn(psi_multi mx, const uint64_t* d_q_off, const uint32_t* d_q, uint32_t k,
+                         uint32_t* d_ids, uint64_t* d_d2);
+/* Waits for the stream; returns the first latched device error. */
+psi_status psi_multi_sync(psi_multi mx);
+/* Shape and structure of index `index` (as psi_shape / psi_export_structure). */
+psi_status psi_multi_shape(psi_multi mx, uint32_t index, uint64_t* h_n_leaves, uint32_t* h_height,
+                           uint64_t* h_level_sizes);
+psi_status psi_multi_export_structure(psi_multi mx, uint32_t index, uint64_t* d_piv_key, uint32_t* d_piv_id,
+                                      uint32_t* d_leaf_cnt, uint32_t* d_leaf_lo, uint32_t* d_leaf_hi,
+                                      uint32_t* d_node_lo, uint32_t* d_node_hi, uint64_t* d_node_cnt);
+/* Entries of every index, index by index, each in (key, id) order (local
+ * ids); lengths follow the build's offsets. */
+psi_status psi_multi_export(psi_multi mx, uint64_t* d_keys, uint32_t* d_ids, uint32_t* d_pts);
 
 /* --- kernel timing ------------------------------------------------------ */
 

@@ -49,6 +49,13 @@ SIGNATURES = {
     "psi_export_leaves": (_i, [_P, _P, _P]),
     "psi_encode": (_i, [_u32, _u32, _P, _u64, _P, _P]),
     "psi_sort_pairs": (_i, [_P, _P, _u64, _P, _P, _P]),
+    "psi_multi_build": (_i, [_P, _P, _u32, _P, _P, _P]),
+    "psi_multi_destroy": (_i, [_P]),
+    "psi_multi_knn": (_i, [_P, _P, _P, _u32, _P, _P]),
+    "psi_multi_sync": (_i, [_P]),
+    "psi_multi_shape": (_i, [_P, _u32, _P, _P, _P]),
+    "psi_multi_export_structure": (_i, [_P, _u32, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "psi_multi_export": (_i, [_P, _P, _P, _P]),
     "psi_prof_enable": (_i, [_P, _i]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
@@ -233,6 +240,45 @@ def psi_sort_pairs(keys, ids, n: int, keys_out, ids_out, stream=None):
                                 _stream_ptr(stream)), "psi_sort_pairs")
 
 
+def psi_multi_build(dim: int, curve: int, num: int, pt_off, pts, leaf_size: int = 32, fanout: int = 8,
+                    stream=None):
+    h = C.c_void_p()
+    prm = psi_params(dim, curve, leaf_size, fanout, 0)
+    _check(lib().psi_multi_build(C.byref(prm), _stream_ptr(stream), num, _dev_ptr(pt_off), _dev_ptr(pts),
+                                 C.byref(h)), "psi_multi_build")
+    return h
+
+
+def psi_multi_destroy(h):
+    _check(lib().psi_multi_destroy(h), "psi_multi_destroy")
+
+
+def psi_multi_knn(h, q_off, q, k: int, ids, d2):
+    _check(lib().psi_multi_knn(h, _dev_ptr(q_off), _dev_ptr(q), k, _dev_ptr(ids), _dev_ptr(d2)), "psi_multi_knn")
+
+
+def psi_multi_sync(h):
+    _check(lib().psi_multi_sync(h), "psi_multi_sync")
+
+
+def psi_multi_shape(h, index: int):
+    L = C.c_uint64()
+    hh = C.c_uint32()
+    sizes = (C.c_uint64 * 64)()
+    _check(lib().psi_multi_shape(h, index, C.byref(L), C.byref(hh), sizes), "psi_multi_shape")
+    return L.value, hh.value, [sizes[i] for i in range(hh.value + 1)] if L.value else []
+
+
+def psi_multi_export_structure(h, index, piv_key, piv_id, leaf_cnt, leaf_lo, leaf_hi, node_lo, node_hi, node_cnt):
+    _check(lib().psi_multi_export_structure(h, index, *[_dev_ptr(t) for t in (piv_key, piv_id, leaf_cnt, leaf_lo,
+                                                                              leaf_hi, node_lo, node_hi, node_cnt)]),
+           "psi_multi_export_structure")
+
+
+def psi_multi_export(h, keys, ids, pts):
+    _check(lib().psi_multi_export(h, _dev_ptr(keys), _dev_ptr(ids), _dev_ptr(pts)), "psi_multi_export")
+
+
 def psi_prof_enable(h, on: bool):
     _check(lib().psi_prof_enable(h, 1 if on else 0), "psi_prof_enable")
 
@@ -388,6 +434,76 @@ class Index:
 
     def prof_get(self, family: str):
         return psi_prof_get(self._h, family)
+
+
+class MultiIndex:
+    """Many independent SPaC-trees built and queried together (one CSR batch)."""
+
+    def __init__(self, dim: int, curve: int, pt_off, pts, leaf_size: int = 32, fanout: int = 8, device="cuda"):
+        torch = _torch()
+        self.dim, self.curve = dim, curve
+        self.device = torch.device(device)
+        self.off = _as_u64(pt_off, self.device).reshape(-1).contiguous()
+        self.num = self.off.numel() - 1
+        p = _as_u32(pts, self.device).reshape(-1, dim).contiguous()
+        self._h = psi_multi_build(dim, curve, self.num, self.off, p, leaf_size, fanout)
+        self.n_total = p.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            psi_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def knn(self, q_off, q, k: int):
+        torch = _torch()
+        qo = _as_u64(q_off, self.device).reshape(-1).contiguous()
+        qq = _as_u32(q, self.device).reshape(-1, self.dim).contiguous()
+        nq = qq.shape[0]
+        ids = torch.empty((max(nq, 1), k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((max(nq, 1), k), dtype=torch.int64, device=self.device)
+        psi_multi_knn(self._h, qo, qq, k, ids, d2)
+        return ids[:nq], d2[:nq]
+
+    def sync(self):
+        psi_multi_sync(self._h)
+
+    def export(self):
+        torch = _torch()
+        n = self.n_total
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        i = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        p = torch.empty((max(n, 1), self.dim), dtype=torch.int32, device=self.device)
+        psi_multi_export(self._h, k, i, p)
+        self.sync()
+        return to_u64(k[:n]), to_u32(i[:n]), to_u32(p[:n])
+
+    def structure(self, index: int) -> dict:
+        torch = _torch()
+        L, h, sizes = psi_multi_shape(self._h, index)
+        nn = int(sum(sizes)) if L else 0
+        D, dev = self.dim, self.device
+        t = dict(piv_key=torch.empty(max(L, 1), dtype=torch.int64, device=dev),
+                 piv_id=torch.empty(max(L, 1), dtype=torch.int32, device=dev),
+                 leaf_cnt=torch.empty(max(L, 1), dtype=torch.int32, device=dev),
+                 leaf_lo=torch.empty((max(L, 1), D), dtype=torch.int32, device=dev),
+                 leaf_hi=torch.empty((max(L, 1), D), dtype=torch.int32, device=dev),
+                 node_lo=torch.empty((max(nn, 1), D), dtype=torch.int32, device=dev),
+                 node_hi=torch.empty((max(nn, 1), D), dtype=torch.int32, device=dev),
+                 node_cnt=torch.empty(max(nn, 1), dtype=torch.int64, device=dev))
+        psi_multi_export_structure(self._h, index, t["piv_key"], t["piv_id"], t["leaf_cnt"], t["leaf_lo"],
+                                   t["leaf_hi"], t["node_lo"], t["node_hi"], t["node_cnt"])
+        self.sync()
+        out = dict(n_leaves=L, height=h, level_sizes=np.array(sizes, dtype=np.int64))
+        for name, ten in t.items():
+            cut = ten[:L] if name.startswith(("piv", "leaf")) else ten[:nn]
+            out[name] = to_u64(cut) if ten.dtype == torch.int64 else to_u32(cut)
+        return out
 
 
 def encode(pts, dim: int, curve: int):

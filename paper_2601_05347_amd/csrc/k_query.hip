@@ -196,6 +196,69 @@ __device__ __forceinline__ void scan_leaf(const TreeView& t, const NodeRec& r, c
     }
 }
 
+// Seeded search over any tree exposed through an accessor `T` with
+// L(), h(), B(), levn(l) (nodes of level l), node(l, i), leaf(i), pkey(i).
+template <int D, int K, class T>
+__device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, const uint32_t* q, uint64_t key,
+                                           uint64_t (&bd)[K], uint32_t (&bi)[K]) {
+    const uint32_t L = tr.L();
+    if (L == 0) return;
+    uint32_t lo = 0, hi = L;  // first pivot key above the query's key
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tr.pkey(mid) <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t j = lo ? lo - 1 : 0u;
+    const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
+    for (uint32_t x = ja; x <= jb; ++x) scan_leaf<D, K>(tv, tr.leaf(x), q, bd, bi);
+    const uint32_t B = tr.B(), h = tr.h();
+    uint32_t l = 0, i = 0;
+    for (;;) {
+        const NodeRec r = l == h ? tr.leaf(i) : tr.node(l, i);
+        bool descend = false;
+        if (r.cnt && box_dist<D>(q, r) <= bd[K - 1]) {
+            if (l == h) {
+                if (i < ja || i > jb) scan_leaf<D, K>(tv, r, q, bd, bi);
+            } else {
+                descend = true;
+            }
+        }
+        if (descend) {
+            ++l;
+            i *= B;
+            continue;
+        }
+        bool done = false;
+        for (;;) {
+            if (l == 0) {
+                done = true;
+                break;
+            }
+            if ((i + 1) % B != 0 && i + 1 < tr.levn(l)) {
+                ++i;
+                break;
+            }
+            --l;
+            i /= B;
+        }
+        if (done) break;
+    }
+}
+
+// Accessor of a single index whose level table sits in LDS.
+struct SingleTree {
+    const TreeView& t;
+    const LevelInfo* lv;
+    __device__ uint32_t L() const { return (uint32_t)t.L; }
+    __device__ uint32_t h() const { return t.h; }
+    __device__ uint32_t B() const { return t.B; }
+    __device__ uint32_t levn(uint32_t l) const { return (uint32_t)lv[l].n; }
+    __device__ NodeRec node(uint32_t l, uint32_t i) const { return t.inner[lv[l].off + i]; }
+    __device__ NodeRec leaf(uint32_t i) const { return t.leaf[i]; }
+    __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
+};
+
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
@@ -217,54 +280,82 @@ __global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __
         bd[j] = PAD_D2;
         bi[j] = PAD_ID;
     }
-    if (t.L > 0) {
-        const uint64_t key = qkeys[qi];
-        uint32_t lo = 0, hi = (uint32_t)t.L;  // first pivot key above the query's key
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (t.pkey[mid] <= key) lo = mid + 1;
-            else hi = mid;
-        }
-        const uint32_t j = lo ? lo - 1 : 0u;
-        const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, (uint32_t)t.L - 1);
-        for (uint32_t x = ja; x <= jb; ++x) scan_leaf<D, K>(t, t.leaf[x], q, bd, bi);
-        const uint32_t B = t.B, h = t.h;
-        uint32_t l = 0, i = 0;
-        for (;;) {
-            const NodeRec r = l == h ? t.leaf[i] : t.inner[s_lv[l].off + i];
-            bool descend = false;
-            if (r.cnt && box_dist<D>(q, r) <= bd[K - 1]) {
-                if (l == h) {
-                    if (i < ja || i > jb) scan_leaf<D, K>(t, r, q, bd, bi);
-                } else {
-                    descend = true;
-                }
-            }
-            if (descend) {
-                ++l;
-                i *= B;
-                continue;
-            }
-            bool done = false;
-            for (;;) {
-                if (l == 0) {
-                    done = true;
-                    break;
-                }
-                if ((i + 1) % B != 0 && i + 1 < s_lv[l].n) {
-                    ++i;
-                    break;
-                }
-                --l;
-                i /= B;
-            }
-            if (done) break;
-        }
-    }
+    const SingleTree tr{t, s_lv};
+    knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         out_ids[qi * K + j] = bi[j];
         out_d2[qi * K + j] = bd[j];
+    }
+}
+
+// ---------------------------------------------- kNN over many small indexes
+// Accessor of index m among a batch of indexes sharing global arrays.
+struct MultiTree {
+    const IdxMeta* m;
+    const NodeRec* inner;
+    const NodeRec* leafs;
+    const uint64_t* pk;
+    uint32_t b;
+    __device__ uint32_t L() const { return m->L; }
+    __device__ uint32_t h() const { return m->h; }
+    __device__ uint32_t B() const { return b; }
+    __device__ uint32_t levn(uint32_t l) const { return m->lvl_n[l]; }
+    __device__ NodeRec node(uint32_t l, uint32_t i) const { return inner[m->inner_base + m->lvl_off[l] + i]; }
+    __device__ NodeRec leaf(uint32_t i) const { return leafs[m->leaf_base + i]; }
+    __device__ uint64_t pkey(uint32_t i) const { return pk[m->leaf_base + i]; }
+};
+
+__global__ void k_chunk_counts(const uint64_t* __restrict__ q_off, uint32_t num, uint32_t* __restrict__ cnt) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < num) cnt[s] = (uint32_t)((q_off[s + 1] - q_off[s] + 63) / 64);
+}
+
+// Persistent: every wave takes (index, 64-query chunk) items from an atomic
+// counter until none are left, so uneven batches spread over the whole GPU.
+template <int D, int CURVE, int K>
+__global__ __launch_bounds__(256) void k_multi_knn(TreeView tv, const IdxMeta* __restrict__ meta, uint32_t num,
+                                                   const uint64_t* __restrict__ q_off, const uint32_t* __restrict__ qp,
+                                                   const uint32_t* __restrict__ pref, uint32_t* __restrict__ work_ctr,
+                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2,
+                                                   uint32_t* __restrict__ err) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = pref[num];
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(work_ctr, 1u);
+        item = shfl_u32(item, 0);
+        if (item >= W) break;
+        uint32_t lo = 0, hi = num;  // index of the item: largest s with pref[s] <= item
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pref[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t s = lo;
+        const uint64_t qb = q_off[s] + (uint64_t)(item - pref[s]) * 64;
+        const uint64_t qe = min<uint64_t>(qb + 64, q_off[s + 1]);
+        const uint64_t qi = qb + lane;
+        if (qi < qe) {
+            uint32_t q[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+            if (!coord_ok<D>(q)) atomicOr(err, ERR_RANGE);
+            uint64_t bd[K];
+            uint32_t bi[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                bd[j] = PAD_D2;
+                bi[j] = PAD_ID;
+            }
+            const MultiTree tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
+            knn_seeded<D, K>(tr, tv, q, sfc_key<D, CURVE>(q), bd, bi);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                out_ids[qi * K + j] = bi[j];
+                out_d2[qi * K + j] = bd[j];
+            }
+        }
     }
 }
 
@@ -727,6 +818,31 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, c
     if (dim == 2) { PSI_KL_ALL(2) } else { PSI_KL_ALL(3) }
 #undef PSI_KL_ALL
 #undef PSI_KL
+}
+
+void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, const IdxMeta* meta, uint32_t num,
+                      const uint64_t* q_off, const uint32_t* q, uint32_t* chunk_pref, uint32_t* work_ctr, uint32_t k,
+                      uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err) {
+    if (num == 0) return;
+    hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(num, 256)), dim3(256), 0, st, q_off, num, chunk_pref);
+    launch_scan_u32(st, chunk_pref, chunk_pref, num, chunk_pref + num, tmp);
+    launch_fill_u32(st, work_ctr, 1, 0u);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const dim3 g((unsigned)(cus * 8));
+#define PSI_MK(D, CV, K) hipLaunchKernelGGL((k_multi_knn<D, CV, K>), g, dim3(256), 0, st, tv, meta, num, q_off, q, chunk_pref, work_ctr, ids, d2, err)
+#define PSI_MK_K(D, CV)                                                                                  \
+    switch (k) {                                                                                         \
+        case 1: PSI_MK(D, CV, 1); break;  case 2: PSI_MK(D, CV, 2); break;  case 4: PSI_MK(D, CV, 4); break; \
+        case 8: PSI_MK(D, CV, 8); break;  case 10: PSI_MK(D, CV, 10); break; case 16: PSI_MK(D, CV, 16); break; \
+        default: break;                                                                                  \
+    }
+    if (dim == 2 && curve == 0) { PSI_MK_K(2, 0) }
+    else if (dim == 2) { PSI_MK_K(2, 1) }
+    else if (curve == 0) { PSI_MK_K(3, 0) }
+    else { PSI_MK_K(3, 1) }
+#undef PSI_MK_K
+#undef PSI_MK
 }
 
 void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,

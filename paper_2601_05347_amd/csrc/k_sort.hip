@@ -117,12 +117,15 @@ __global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restric
     off[blockIdx.x * RADIX + threadIdx.x] = inc - v;
 }
 
-template <bool IMPLICIT_ID, bool DIGIT_ID>
+// SEG: the pairs form consecutive segments sorted independently (one index
+// each); tiles never straddle a segment, digit offsets are per segment and
+// the look-back stops at the segment's first tile.
+template <bool IMPLICIT_ID, bool DIGIT_ID, bool SEG>
 __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin, uint32_t id_base,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n, uint32_t shift,
     const uint32_t* __restrict__ dig_off, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
-    uint32_t epoch, uint32_t* __restrict__ err) {
+    uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg) {
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_id[SORT_TILE];
     __shared__ uint32_t s_wcnt[WAVES][RADIX];  // running counts per wave, then wave prefixes
@@ -142,7 +145,19 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
         if (tid == 0) atomicOr(err, ERR_SPIN);
         return;
     }
-    const uint64_t wbase = (uint64_t)tile * SORT_TILE + (uint64_t)w * (SORT_IPT * 64);
+    uint64_t tbeg, tend;
+    uint32_t first = 0;
+    if (SEG) {
+        const uint32_t sgi = sg.tile_seg[tile];
+        tbeg = sg.tile_beg[tile];
+        tend = min<uint64_t>(tbeg + SORT_TILE, sg.seg_end[sgi]);
+        first = sg.seg_first_tile[sgi];
+        dig_off += (uint64_t)sgi * sg.off_stride;
+    } else {
+        tbeg = (uint64_t)tile * SORT_TILE;
+        tend = min<uint64_t>(tbeg + SORT_TILE, n);
+    }
+    const uint64_t wbase = tbeg + (uint64_t)w * (SORT_IPT * 64);
 
     uint64_t k[SORT_IPT];
     uint32_t id[SORT_IPT];
@@ -150,14 +165,14 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
 #pragma unroll
     for (int i = 0; i < SORT_IPT; ++i) {
         const uint64_t pos = wbase + (uint64_t)i * 64 + lane;
-        const bool ok = pos < n;
+        const bool ok = pos < tend;
         k[i] = ok ? kin[pos] : 0ull;
         id[i] = ok ? (IMPLICIT_ID ? id_base + (uint32_t)pos : iin[pos]) : 0u;
     }
     // Rank inside the wave, item by item (stable: item order = position order).
 #pragma unroll
     for (int i = 0; i < SORT_IPT; ++i) {
-        const bool ok = wbase + (uint64_t)i * 64 + lane < n;
+        const bool ok = wbase + (uint64_t)i * 64 + lane < tend;
         const uint32_t dg = (DIGIT_ID ? (uint64_t)id[i] >> shift : k[i] >> shift) & (RADIX - 1);
         uint64_t peers = ballot(ok);
 #pragma unroll
@@ -183,16 +198,16 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
         tot += c;
     }
     uint64_t* my = status + (uint64_t)tile * RADIX + d;
-    __hip_atomic_store(my, pack_status(epoch, tile == 0 ? FLAG_INC : FLAG_AGG, tot), __ATOMIC_RELAXED,
+    __hip_atomic_store(my, pack_status(epoch, tile == first ? FLAG_INC : FLAG_AGG, tot), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t loc = block_incl_scan256(tot, s_wsum) - tot;
     s_loc[d] = loc;
 
     uint32_t excl = 0;
-    if (tile > 0) {
+    if (tile > first) {
         int64_t t = (int64_t)tile - 1;
         uint32_t spins = 0;
-        while (t >= 0) {
+        while (t >= (int64_t)first) {
             const uint64_t s = __hip_atomic_load(status + (uint64_t)t * RADIX + d, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t fl = (uint32_t)(s >> 32) & 3u;
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     // Stage in LDS in (digit, position) order.
 #pragma unroll
     for (int i = 0; i < SORT_IPT; ++i) {
-        const bool ok = wbase + (uint64_t)i * 64 + lane < n;
+        const bool ok = wbase + (uint64_t)i * 64 + lane < tend;
         if (ok) {
             const uint32_t dg = (DIGIT_ID ? (uint64_t)id[i] >> shift : k[i] >> shift) & (RADIX - 1);
             const uint32_t lp = s_loc[dg] + s_wcnt[w][dg] + rk[i];
@@ -227,8 +242,7 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     }
     __syncthreads();
 
-    const uint64_t tstart = (uint64_t)tile * SORT_TILE;
-    const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)SORT_TILE, n - tstart);
+    const uint32_t nvalid = (uint32_t)(tend - tbeg);
     for (uint32_t j = tid; j < nvalid; j += SORT_WG) {
         const uint64_t kk = s_key[j];
         const uint32_t ii = s_id[j];
@@ -365,17 +379,21 @@ void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint3
 void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
                      const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
                      uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
-                     uint32_t epoch, uint32_t* err) {
+                     uint32_t epoch, uint32_t* err, const SegTiles* seg, uint64_t seg_tiles) {
     if (n == 0) return;
-    const unsigned g = blocks_for(n, SORT_TILE);
-    if (implicit_ids && !digit_from_id)
-        hipLaunchKernelGGL((k_onesweep<true, false>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
-    else if (implicit_ids && digit_from_id)
-        hipLaunchKernelGGL((k_onesweep<true, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
-    else if (digit_from_id)
-        hipLaunchKernelGGL((k_onesweep<false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
-    else
-        hipLaunchKernelGGL((k_onesweep<false, false>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err);
+    SegTiles sg{};
+    if (seg) sg = *seg;
+    const unsigned g = seg ? (unsigned)seg_tiles : blocks_for(n, SORT_TILE);
+    if (g == 0) return;
+#define PSI_OS(I, Dg, S) hipLaunchKernelGGL((k_onesweep<I, Dg, S>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg)
+    if (seg) {
+        if (implicit_ids) PSI_OS(true, false, true);
+        else PSI_OS(false, false, true);
+    } else if (implicit_ids && !digit_from_id) PSI_OS(true, false, false);
+    else if (implicit_ids && digit_from_id) PSI_OS(true, true, false);
+    else if (digit_from_id) PSI_OS(false, true, false);
+    else PSI_OS(false, false, false);
+#undef PSI_OS
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {

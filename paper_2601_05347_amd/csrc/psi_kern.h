@@ -41,10 +41,20 @@ void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint3
 // One stable scatter pass (decoupled look-back over tiles taken in launch
 // order). status holds n_tiles*256 words tagged with `epoch`; tile_ctr must
 // be zero.
+// Segmented sorts (many independent indexes in one launch): tile t covers
+// [tile_beg[t], min(tile_beg[t] + SORT_TILE, seg_end[tile_seg[t]])); digit
+// offsets are per segment at dig_off + seg * off_stride.
+struct SegTiles {
+    const uint32_t* tile_seg;
+    const uint32_t* tile_beg;
+    const uint32_t* seg_first_tile;
+    const uint32_t* seg_end;
+    uint32_t off_stride;
+};
 void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
                      const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
                      uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
-                     uint32_t epoch, uint32_t* err);
+                     uint32_t epoch, uint32_t* err, const SegTiles* seg = nullptr, uint64_t seg_tiles = 0);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 
@@ -106,5 +116,37 @@ void launch_export_structure(hipStream_t st, int dim, const TreeView& t, uint64_
                              const uint64_t* piv_key_src, const uint32_t* piv_id_src, uint64_t* piv_key,
                              uint32_t* piv_id, uint32_t* leaf_cnt, uint32_t* leaf_lo, uint32_t* leaf_hi,
                              uint32_t* node_lo, uint32_t* node_hi, uint64_t* node_cnt);
+
+// ------------------------------------------------------------ many indexes
+// Per-index tree metadata of a batch of independent indexes built together.
+constexpr int MULTI_LEVELS = 26;
+struct IdxMeta {
+    uint32_t L, h, leaf_base, inner_base;  // leaves, height, first global leaf / inner node
+    uint32_t n, pt_base, pad0, pad1;       // points and first global point
+    uint32_t lvl_off[MULTI_LEVELS];        // first node of level l among the index's inner nodes
+    uint32_t lvl_n[MULTI_LEVELS];          // nodes of level l (level h = the leaves)
+};
+
+// Encode + per-segment digit histograms, one block per tile (tile tables as in
+// SegTiles); hist is [num][8][256], zeroed.
+void launch_encode_hist_seg(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t ntiles,
+                            const SegTiles& sg, uint64_t* keys, uint32_t* hist, uint32_t* err);
+// off[s][p][d] = seg_begin[s] + exclusive prefix over digits of hist[s][p][.]
+void launch_seg_digit_offsets(hipStream_t st, uint32_t num, const uint32_t* hist, const uint64_t* seg_begin,
+                              uint32_t* off);
+// Leaves of every index: global leaf g belongs to index s with
+// leaf_off[s] <= g < leaf_off[s+1]; ids stored are local (position - pt_base).
+void launch_build_leaves_seg(hipStream_t st, int dim, int curve, uint32_t num, uint64_t total_leaves,
+                             const uint32_t* leaf_off, const IdxMeta* meta, const uint64_t* sk, const uint32_t* sid,
+                             uint32_t C, uint32_t* slots, uint64_t* piv_key, uint32_t* piv_id, NodeRec* leafrec);
+// Parents at height u (1 = parents of leaves) of every index with h >= u;
+// pref[s] = number of such parents before index s (num + 1 entries).
+void launch_node_step_seg(hipStream_t st, int dim, uint32_t num, uint64_t nparents, uint32_t u, const uint32_t* pref,
+                          const IdxMeta* meta, const NodeRec* leafrec, NodeRec* inner, uint32_t B);
+// kNN over many indexes in one persistent launch; work items are (index,
+// chunk of 64 queries) taken from an atomic counter (zeroed before launch).
+void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, const IdxMeta* meta, uint32_t num,
+                      const uint64_t* q_off, const uint32_t* q, uint32_t* chunk_pref, uint32_t* work_ctr, uint32_t k,
+                      uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err);
 
 }  // namespace psi
