@@ -76,6 +76,7 @@ typedef struct {
 
 typedef struct psi_index_s* psi_index;
 typedef struct psi_multi_s* psi_multi;
+typedef struct psi_graph_s* psi_graph;
 
 const char* psi_status_str(psi_status s);
 
@@ -197,6 +198,20 @@ psi_status psi_multi_export_structure(psi_multi mx, uint32_t index, uint64_t* d_
 /* Entries of every index, index by index, each in (key, id) order (local
  * ids); lengths follow the build's offsets. */
 psi_status psi_multi_export(psi_multi mx, uint64_t* d_keys, uint32_t* d_ids, uint32_t* d_pts);
+
+/* --- graph capture of query steps ----------------------------------------- */
+
+/* Capture the query calls (psi_knn, psi_range_count, psi_range_report,
+ * psi_multi_knn) issued on `hip_stream` between psi_graph_begin and
+ * psi_graph_end into a hipGraph; psi_graph_launch replays them with the same
+ * buffers and sizes. Inside a capture no memory is allocated: run each call
+ * once with the same sizes before capturing (a call that would need a larger
+ * buffer returns PSI_E_STATE). Build and updates wait on the host and return
+ * PSI_E_STATE while their stream is being captured. */
+psi_status psi_graph_begin(void* hip_stream);
+psi_status psi_graph_end(void* hip_stream, psi_graph* out);
+psi_status psi_graph_launch(psi_graph g, void* hip_stream);
+psi_status psi_graph_destroy(psi_graph g);
 
 /* --- kernel timing ------------------------------------------------------ */
 

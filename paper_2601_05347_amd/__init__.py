@@ -56,6 +56,10 @@ SIGNATURES = {
     "psi_multi_shape": (_i, [_P, _u32, _P, _P, _P]),
     "psi_multi_export_structure": (_i, [_P, _u32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "psi_multi_export": (_i, [_P, _P, _P, _P]),
+    "psi_graph_begin": (_i, [_P]),
+    "psi_graph_end": (_i, [_P, _P]),
+    "psi_graph_launch": (_i, [_P, _P]),
+    "psi_graph_destroy": (_i, [_P]),
     "psi_prof_enable": (_i, [_P, _i]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
@@ -277,6 +281,24 @@ def psi_multi_export_structure(h, index, piv_key, piv_id, leaf_cnt, leaf_lo, lea
 
 def psi_multi_export(h, keys, ids, pts):
     _check(lib().psi_multi_export(h, _dev_ptr(keys), _dev_ptr(ids), _dev_ptr(pts)), "psi_multi_export")
+
+
+def psi_graph_begin(stream=None):
+    _check(lib().psi_graph_begin(_stream_ptr(stream)), "psi_graph_begin")
+
+
+def psi_graph_end(stream=None):
+    g = C.c_void_p()
+    _check(lib().psi_graph_end(_stream_ptr(stream), C.byref(g)), "psi_graph_end")
+    return g
+
+
+def psi_graph_launch(g, stream=None):
+    _check(lib().psi_graph_launch(g, _stream_ptr(stream)), "psi_graph_launch")
+
+
+def psi_graph_destroy(g):
+    _check(lib().psi_graph_destroy(g), "psi_graph_destroy")
 
 
 def psi_prof_enable(h, on: bool):

@@ -16,6 +16,21 @@ psi_status hip_ok(hipError_t e) {
 
 static psi_status last_launch() { return hip_ok(hipGetLastError()); }
 
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs == hipStreamCaptureStatusActive;
+}
+
+psi_status ensure_q(Buf& b, size_t need, hipStream_t st) {
+    if (need <= b.bytes) return PSI_OK;
+    if (capturing(st)) return PSI_E_STATE;
+    return b.ensure(need);
+}
+
 psi_status readback(psi_index ix, const void* dev, size_t bytes) {
     psi_status s = hip_ok(hipMemcpyAsync(ix->pinned, dev, bytes, hipMemcpyDeviceToHost, ix->st));
     if (s != PSI_OK) return s;
@@ -34,16 +49,18 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
         for (int b = 0; b < 4; ++b) { pl.src[pl.n] = 1; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
     for (int b = 0; b < 8; ++b) { pl.src[pl.n] = 0; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
     psi_status s;
-    if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
-    if ((s = S.off.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
-    if ((s = S.ctr.ensure(MAX_PASSES * 4)) != PSI_OK) return s;
+    hipStream_t st = ix->st;
+    const bool cap = capturing(st);
+    if ((s = ensure_q(S.hist, MAX_PASSES * RADIX * 4, st)) != PSI_OK) return s;
+    if ((s = ensure_q(S.off, MAX_PASSES * RADIX * 4, st)) != PSI_OK) return s;
+    if ((s = ensure_q(S.ctr, MAX_PASSES * 4, st)) != PSI_OK) return s;
     for (int b = 0; b < 2; ++b) {
-        if ((s = S.k[b].ensure(n * 8)) != PSI_OK) return s;
-        if ((s = S.i[b].ensure(n * 4)) != PSI_OK) return s;
+        if ((s = ensure_q(S.k[b], n * 8, st)) != PSI_OK) return s;
+        if ((s = ensure_q(S.i[b], n * 4, st)) != PSI_OK) return s;
     }
     const uint64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
     if (tiles * RADIX > S.status_words) {
-        if ((s = S.status.ensure(tiles * RADIX * 8)) != PSI_OK) return s;
+        if ((s = ensure_q(S.status, tiles * RADIX * 8, st)) != PSI_OK) return s;
         S.status_words = S.status.bytes / 8;
         launch_fill_u32(ix->st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
     }
@@ -64,6 +81,8 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
             S.epoch = 1;
             launch_fill_u32(ix->st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
         }
+        // a graph replays the epoch it was captured with: clear the words first
+        if (cap) launch_fill_u32(ix->st, S.status.as<uint32_t>(), tiles * RADIX * 2, 0u);
         {
             ProfScope ps(ix, fam, n * 24);
             launch_onesweep(ix->st, p == 0 && iin == nullptr, pl.src[p] == 1, ksrc, isrc, id_base,
@@ -171,7 +190,7 @@ static psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n,
     const bool sort = n >= ORDER_MIN && !(ix->flags & PSI_FLAG_INPUT_ORDER);
     if (boxes && !sort) return PSI_OK;
     psi_status s;
-    if ((s = ix->scr.c.ensure(n * 8)) != PSI_OK) return s;
+    if ((s = ensure_q(ix->scr.c, n * 8, ix->st)) != PSI_OK) return s;
     uint64_t* keys = ix->scr.c.as<uint64_t>();
     {
         ProfScope ps(ix, "order", n * (boxes ? 8ull * ix->D : 4ull * ix->D) + n * 8);
@@ -262,6 +281,7 @@ psi_status psi_set_stream(psi_index ix, void* hip_stream) {
 
 psi_status psi_build(psi_index ix, const uint32_t* d_pts, uint64_t n) {
     if (!ix || (n && !d_pts)) return PSI_E_ARG;
+    if (capturing(ix->st)) return PSI_E_STATE;
     if (n > 0xFFFFFFFFull) return PSI_E_CAPACITY;
     ix->next_id = 0;
     psi_status s = do_build(ix, d_pts, n, 0);
@@ -271,6 +291,7 @@ psi_status psi_build(psi_index ix, const uint32_t* d_pts, uint64_t n) {
 
 psi_status psi_batch_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids) {
     if (!ix || (m && !d_pts)) return PSI_E_ARG;
+    if (capturing(ix->st)) return PSI_E_STATE;
     if ((uint64_t)ix->next_id + m > 0xFFFFFFFFull) return PSI_E_CAPACITY;
     if (m == 0) return PSI_OK;
     return do_insert(ix, d_pts, m, d_new_ids);
@@ -278,6 +299,7 @@ psi_status psi_batch_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uin
 
 psi_status psi_batch_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
     if (!ix || (m && !d_ids)) return PSI_E_ARG;
+    if (capturing(ix->st)) return PSI_E_STATE;
     if (m > 0xFFFFFFFFull) return PSI_E_ARG;
     return do_delete(ix, d_ids, m, d_ndeleted);
 }
@@ -419,6 +441,49 @@ psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_
     if (s == PSI_OK) s = e;
     psi_destroy(ix);
     return s;
+}
+
+struct psi_graph_s {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+};
+
+psi_status psi_graph_begin(void* hip_stream) {
+    return hip_ok(hipStreamBeginCapture(static_cast<hipStream_t>(hip_stream), hipStreamCaptureModeThreadLocal));
+}
+
+psi_status psi_graph_end(void* hip_stream, psi_graph* out) {
+    if (!out) return PSI_E_ARG;
+    *out = nullptr;
+    psi_graph g = new (std::nothrow) psi_graph_s;
+    hipGraph_t graph = nullptr;
+    psi_status s = hip_ok(hipStreamEndCapture(static_cast<hipStream_t>(hip_stream), &graph));
+    if (!g) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return PSI_E_NOMEM;
+    }
+    if (s == PSI_OK) s = hip_ok(hipGraphInstantiate(&g->e, graph, nullptr, nullptr, 0));
+    g->g = graph;
+    if (s != PSI_OK) {
+        if (g->g) (void)hipGraphDestroy(g->g);
+        delete g;
+        return s;
+    }
+    *out = g;
+    return PSI_OK;
+}
+
+psi_status psi_graph_launch(psi_graph g, void* hip_stream) {
+    if (!g) return PSI_E_ARG;
+    return hip_ok(hipGraphLaunch(g->e, static_cast<hipStream_t>(hip_stream)));
+}
+
+psi_status psi_graph_destroy(psi_graph g) {
+    if (!g) return PSI_E_ARG;
+    if (g->e) (void)hipGraphExecDestroy(g->e);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
+    return PSI_OK;
 }
 
 psi_status psi_prof_enable(psi_index ix, int on) {

@@ -190,6 +190,11 @@ struct ProfScope {
 };
 
 psi_status hip_ok(hipError_t e);
+// True while `st` is being captured into a graph: no allocation, no waiting.
+bool capturing(hipStream_t st);
+// Buf::ensure for paths that may run under graph capture: growing a buffer
+// there is refused (PSI_E_STATE); a call outside capture sizes it first.
+psi_status ensure_q(Buf& b, size_t need, hipStream_t st);
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
                       bool id_digits, bool hist_ready, int* which, const char* fam);
 psi_status build_nodes(psi_index ix);

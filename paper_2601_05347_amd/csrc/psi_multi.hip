@@ -242,7 +242,8 @@ psi_status psi_multi_knn(psi_multi mx, const uint64_t* d_q_off, const uint32_t* 
     if (!mx || !d_q_off || !d_q || !d_ids || !d_d2) return PSI_E_ARG;
     if (k != 1 && k != 2 && k != 4 && k != 8 && k != 10 && k != 16) return PSI_E_ARG;
     psi_status s;
-    if ((s = mx->qtmp.ensure(((uint64_t)mx->num + 1 + scan_tmp_words(mx->num) + 64) * 4)) != PSI_OK) return s;
+    if ((s = ensure_q(mx->qtmp, ((uint64_t)mx->num + 1 + scan_tmp_words(mx->num) + 64) * 4, mx->st)) != PSI_OK)
+        return s;
     uint32_t* pref = mx->qtmp.as<uint32_t>();
     uint32_t* work = pref + mx->num + 1;
     uint32_t* tmp = work + 16;
