@@ -204,3 +204,78 @@ def sample_rows(n_total: int, count: int, seed: int) -> np.ndarray:
         return np.zeros(0, dtype=np.int64)
     r = draws(stream_key(seed, P_AUX), 0, n_total)
     return np.sort(np.argpartition(r, count - 1)[:count]) if count < n_total else np.arange(n_total)
+
+
+# ---------------------------------------------------------- request streams
+
+def log_uniform_ints(key: np.uint64, start: int, count: int, lo: float, hi: float) -> np.ndarray:
+    """`count` integers floor(10^(log10 lo + u (log10 hi - log10 lo))), >= 1."""
+    u = unit(draws(key, start, count))
+    return np.maximum(1, np.floor(10 ** (np.log10(lo) + u * (np.log10(hi) - np.log10(lo))))).astype(np.int64)
+
+
+def request_stream(n_requests: int, n0: int, dim: int, bits: int, seed: int, rate_per_s: float,
+                   mix=(0.4, 0.2, 0.3, 0.1), upd_size=(1e3, 1e6), knn_size=(1, 1e5), range_size=(1, 1e4),
+                   dist: str = "uniform"):
+    """A Poisson stream of mixed requests against an index built from `n0`
+    points with ids 0..n0-1.
+
+    Returns a list of dicts with keys kind ('insert'|'delete'|'knn'|'range'),
+    arrival (seconds), and the payload: points (insert), ids (delete), queries
+    (knn) or boxes (range). Delete requests name ids that are live when the
+    request arrives, given that every earlier insert took the next ids in
+    arrival order. Only bookkeeping here: no index arithmetic.
+    """
+    key = stream_key(seed, P_AUX + 10)
+    gaps = -np.log1p(-unit(draws(key, 0, n_requests))) / rate_per_s
+    arrivals = np.cumsum(gaps)
+    kinds_u = unit(draws(key, n_requests, n_requests))
+    edges = np.cumsum(mix)
+    kinds = np.searchsorted(edges, kinds_u * edges[-1], side="right")
+    sizes_upd = log_uniform_ints(key, 2 * n_requests, n_requests, *upd_size)
+    sizes_knn = log_uniform_ints(key, 3 * n_requests, n_requests, *knn_size)
+    sizes_rng = log_uniform_ints(key, 4 * n_requests, n_requests, *range_size)
+    is_ins = kinds == 0
+    cap = n0 + int(sizes_upd[is_ins].sum())
+    live = np.zeros(cap, dtype=bool)
+    live[:n0] = True
+    n_live = n0
+    next_id = n0
+    out = []
+    for r in range(n_requests):
+        kind = ("insert", "delete", "knn", "range")[min(int(kinds[r]), 3)]
+        req = {"kind": kind, "arrival": float(arrivals[r])}
+        s = seed * 100_003 + r
+        if kind == "insert":
+            m = int(sizes_upd[r])
+            req["points"] = points(dist, m, dim, bits, s, P_INSERT)
+            live[next_id:next_id + m] = True
+            next_id += m
+            n_live += m
+        elif kind == "delete":
+            # uniform draws over [0, next_id), keeping live ids at their first
+            # occurrence (rejection sampling; the live fraction stays high)
+            want = min(int(sizes_upd[r]), n_live)
+            dkey = stream_key(s, P_DELETE)
+            got = np.zeros(0, dtype=np.int64)
+            pos = 0
+            while got.size < want:
+                cnt = max(2 * (want - got.size), 64)
+                cand = _bounded(draws(dkey, pos, cnt), next_id).astype(np.int64)
+                pos += cnt
+                cand = cand[live[cand]]
+                allc = np.concatenate([got, cand])
+                _, first = np.unique(allc, return_index=True)
+                got = allc[np.sort(first)]
+            ids = got[:want].astype(np.uint32)
+            live[ids] = False
+            n_live -= want
+            req["ids"] = ids
+        elif kind == "knn":
+            req["queries"] = points(dist, int(sizes_knn[r]), dim, bits, s, P_QUERY)
+            req["k"] = 10
+        else:
+            c = points(dist, int(sizes_rng[r]), dim, bits, s, P_QUERY)
+            req["boxes"] = boxes(c, bits, s)
+        out.append(req)
+    return out
