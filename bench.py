@@ -37,6 +37,10 @@ WORKLOADS = {
     "2d-1e8": dict(dim=2, bits=30, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
     # small configuration (seconds on the oracle)
     "2d-1e6": dict(dim=2, bits=30, n=1_000_000, m=100_000, nq=10_000, k=10, nb=10_000),
+    # serving: resident 3D SPaC-H of 5e7 points, mixed Poisson request stream
+    "serve": dict(dim=3, bits=21, n=50_000_000, m=0, nq=0, k=10, nb=0),
+    # 4096 independent 2D SPaC-Z indexes (sizes log-uniform 1e3..1e6), kNN k = 8
+    "multi": dict(dim=2, bits=30, n=0, m=0, nq=0, k=8, nb=0),
 }
 
 
@@ -60,6 +64,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=16_000_000, help="points in the oracle's timed sample")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: requests per stream")
+    ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
+    ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
     return ap.parse_args()
 
 
@@ -102,12 +109,164 @@ def cpu_baseline(cfg, args):
                       f"single-threaded std::sort/std::merge oracle, {dt:.2f} s"}
 
 
+def bench_serve(args):
+    """Serving configuration: plain per-request path vs continuous batching."""
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+    from paper_2601_05347_amd import serve
+    cfg = WORKLOADS["serve"]
+    dim, bits, n0 = cfg["dim"], cfg["bits"], args.n or cfg["n"]
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    base = synth.uniform(n0, dim, bits, args.seed)
+    reqs = synth.request_stream(args.requests, n0, dim, bits, args.seed + 7, rate_per_s=1.0)
+    log(f"serve: {len(reqs)} requests generated in {time.perf_counter() - t:.1f} s")
+    d_base = torch.from_numpy(base.view(np.int32)).to(dev)
+
+    def fresh():
+        ix = psi.Index(dim, psi.HILBERT, args.leaf, args.fanout, device=dev)
+        psi.psi_build(ix._h, d_base, n0)
+        ix.sync()
+        return ix
+
+    # capacity of the plain path: back-to-back service of a prefix of the stream
+    probe = [dict(r) for r in reqs[:400]]
+    ix = fresh()
+    serve.PlainServer(ix).run(probe, realtime=False)
+    lam_plain = len(probe) / probe[-1]["done_s"]  # back-to-back service from t = 0
+    log(f"serve: plain path capacity {lam_plain:.1f} requests/s")
+    del ix
+    runs = {}
+    for rho in [float(x) for x in args.rho.split(",")]:
+        lam = rho * lam_plain
+        stream_r = [dict(r, arrival=r["arrival"] / lam) for r in reqs]
+        res = {}
+        for name, cls in (("plain", serve.PlainServer), ("batched", serve.BatchServer)):
+            ix = fresh()
+            rs = [dict(r) for r in stream_r]
+            cls(ix).run(rs, realtime=True)
+            ix.sync()
+            res[name] = serve.summarize(rs)
+            log(f"serve rho={rho} {name}: p99 {res[name]['all']['p99_ms']:.1f} ms, "
+                f"{res[name]['throughput_req_s']:.1f} req/s")
+            del ix, rs
+        runs[f"rho={rho}"] = res
+    b = runs[max(runs)]["batched"]
+    out = {"metric": "p99 latency (ms) of mixed requests, continuous batching, 1 GPU", "value": round(b["all"]["p99_ms"], 3),
+           "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64",
+           "data": "synthetic",
+           "config": {"workload": "serve: resident 3D SPaC-H, uniform", "n0": n0, "requests": args.requests,
+                      "mix": "40/20/30/10 insert/delete/knn/range", "plain_capacity_req_s": round(lam_plain, 2)},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
+def bench_multi(args):
+    """Batched small indexes: one segmented build + one persistent kNN launch
+    vs per-index builds and launches (and those launches replayed as a graph)."""
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+    num = args.indexes
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)  # a created stream: the null stream cannot be captured
+    with torch.cuda.stream(stream):
+        _bench_multi(args, num, dev, stream, np, torch, psi, synth)
+
+
+def _bench_multi(args, num, dev, stream, np, torch, psi, synth):
+    r = synth.unit(synth.draws(synth.stream_key(args.seed, 77), 0, 2 * num))
+    sizes = np.floor(10 ** (3 + 3 * r[:num])).astype(np.int64)
+    qsizes = np.floor(10 ** (4 * r[num:])).astype(np.int64).clip(1, 10_000)
+    t = time.perf_counter()
+    pts = np.concatenate([synth.uniform(int(n), 2, 30, 1000 + i) for i, n in enumerate(sizes)])
+    qs = np.concatenate([synth.uniform(int(n), 2, 30, 1000 + i, synth.P_QUERY) for i, n in enumerate(qsizes)])
+    log(f"multi: {num} indexes, {len(pts)} points, {len(qs)} queries generated in {time.perf_counter() - t:.1f} s")
+    off = np.concatenate(([0], np.cumsum(sizes))).astype(np.uint64)
+    qoff = np.concatenate(([0], np.cumsum(qsizes))).astype(np.uint64)
+    d_pts = torch.from_numpy(pts.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(qs.view(np.int32)).to(dev)
+    d_off = torch.from_numpy(off.view(np.int64)).to(dev)
+    d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
+    k = 8
+    ids = torch.empty((len(qs), k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((len(qs), k), dtype=torch.int64, device=dev)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best * 1e3
+
+    holder = {}
+
+    def multi_build():
+        if "m" in holder:
+            psi.psi_multi_destroy(holder.pop("m"))
+        holder["m"] = psi.psi_multi_build(2, psi.MORTON, num, d_off, d_pts, args.leaf, args.fanout)
+
+    t_mb = timed(multi_build)
+    t_mk = timed(lambda: psi.psi_multi_knn(holder["m"], d_qoff, d_q, k, ids, d2))
+    m_ids, m_d2 = ids.clone(), d2.clone()
+    # per-index path: num separate indexes, num builds, num kNN calls
+    singles = [psi.Index(2, psi.MORTON, args.leaf, args.fanout, device=dev) for _ in range(num)]
+    pv = [d_pts[int(off[i]):int(off[i + 1])] for i in range(num)]
+    qv = [d_q[int(qoff[i]):int(qoff[i + 1])] for i in range(num)]
+    iv = [ids[int(qoff[i]):int(qoff[i + 1])] for i in range(num)]
+    dv = [d2[int(qoff[i]):int(qoff[i + 1])] for i in range(num)]
+
+    def single_build():
+        for i in range(num):
+            psi.psi_build(singles[i]._h, pv[i], int(sizes[i]))
+
+    def single_knn():
+        for i in range(num):
+            psi.psi_knn(singles[i]._h, qv[i], int(qsizes[i]), k, iv[i], dv[i])
+
+    t_sb = timed(single_build)
+    t_sk = timed(single_knn)
+    same = bool(torch.equal(ids, m_ids) and torch.equal(d2, m_d2))
+    # the per-index launches captured once and replayed as one hipGraph
+    psi.psi_graph_begin(stream)
+    single_knn()
+    g = psi.psi_graph_end(stream)
+    t_gk = timed(lambda: psi.psi_graph_launch(g, stream))
+    same_g = bool(torch.equal(ids, m_ids) and torch.equal(d2, m_d2))
+    psi.psi_graph_destroy(g)
+    out = {"metric": "batched small indexes: build points/s and kNN queries/s, one persistent launch",
+           "value": round(len(qs) / (t_mk / 1e3), 1), "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": round(t_mb + t_mk, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32/u64", "data": "synthetic",
+           "config": {"workload": "multi: 2D SPaC-Z, sizes log-uniform 1e3..1e6, queries 1..1e4, k=8",
+                      "indexes": num, "points": int(len(pts)), "queries": int(len(qs))},
+           "multi": {"build_ms": round(t_mb, 3), "knn_ms": round(t_mk, 3),
+                     "build_mpts_s": round(len(pts) / t_mb / 1e3, 1)},
+           "per_index": {"build_ms": round(t_sb, 3), "knn_ms": round(t_sk, 3), "knn_graph_ms": round(t_gk, 3)},
+           "results_identical": same and same_g}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "multi":
+        return bench_multi(args)
     import numpy as np
     import torch
 

@@ -21,23 +21,6 @@ __device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint32_t flag, u
     return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | v;
 }
 
-// Inclusive scan of one value per thread over a 256-thread block.
-__device__ __forceinline__ uint32_t block_incl_scan256(uint32_t v, uint32_t* s_wsum) {
-    const uint32_t lane = lane_id();
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = shfl_u32(v, (int)lane - o);
-        if (lane >= (uint32_t)o) v += t;
-    }
-    if (lane == 63) s_wsum[w] = v;
-    __syncthreads();
-    uint32_t add = 0;
-    for (int i = 0; i < w; ++i) add += s_wsum[i];
-    __syncthreads();
-    return v + add;
-}
-
 __global__ __launch_bounds__(256) void k_hist_pairs(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ ids, uint32_t id_base,
                                                     uint64_t n, PassList pl, uint32_t* __restrict__ hist) {
@@ -128,9 +111,10 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg) {
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_id[SORT_TILE];
-    __shared__ uint32_t s_wcnt[WAVES][RADIX];  // running counts per wave, then wave prefixes
-    __shared__ uint32_t s_loc[RADIX];          // first local slot of each digit
-    __shared__ uint32_t s_base[RADIX];         // global destination of local slot 0 of each digit
+    // running counts per wave, then each wave's first LDS slot per digit; once
+    // the tile is staged, row 0 is reused for the global destination of each
+    // digit's first slot (52 KB in all: three tiles fit in one CU's LDS)
+    __shared__ uint32_t s_wcnt[WAVES][RADIX];
     __shared__ uint32_t s_wsum[WAVES];
     __shared__ uint32_t s_tile;
 
@@ -201,7 +185,8 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     __hip_atomic_store(my, pack_status(epoch, tile == first ? FLAG_INC : FLAG_AGG, tot), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t loc = block_incl_scan256(tot, s_wsum) - tot;
-    s_loc[d] = loc;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) s_wcnt[x][d] += loc;
 
     uint32_t excl = 0;
     if (tile > first) {
@@ -226,7 +211,7 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
         __hip_atomic_store(my, pack_status(epoch, FLAG_INC, excl + tot), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_base[d] = dig_off[d] + excl - loc;
+    const uint32_t my_base = dig_off[d] + excl - loc;
     __syncthreads();
 
     // Stage in LDS in (digit, position) order.
@@ -235,11 +220,14 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
         const bool ok = wbase + (uint64_t)i * 64 + lane < tend;
         if (ok) {
             const uint32_t dg = (DIGIT_ID ? (uint64_t)id[i] >> shift : k[i] >> shift) & (RADIX - 1);
-            const uint32_t lp = s_loc[dg] + s_wcnt[w][dg] + rk[i];
+            const uint32_t lp = s_wcnt[w][dg] + rk[i];
             s_key[lp] = k[i];
             s_id[lp] = id[i];
         }
     }
+    __syncthreads();
+    uint32_t* s_base = &s_wcnt[0][0];
+    s_base[d] = my_base;
     __syncthreads();
 
     const uint32_t nvalid = (uint32_t)(tend - tbeg);

@@ -198,4 +198,22 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
+// Inclusive scan of one value per thread over a 256-thread block (all
+// threads must call it; s_wsum holds 4 words of LDS).
+__device__ __forceinline__ uint32_t block_incl_scan256(uint32_t v, uint32_t* s_wsum) {
+    const uint32_t lane = lane_id();
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = shfl_u32(v, (int)lane - o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    if (lane == 63) s_wsum[w] = v;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int i = 0; i < w; ++i) add += s_wsum[i];
+    __syncthreads();
+    return v + add;
+}
+
 }  // namespace psi
