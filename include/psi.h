@@ -59,8 +59,19 @@ typedef enum { PSI_MORTON = 0, PSI_HILBERT = 1 } psi_curve;
  * tree in fixed child order, pruning by the k-th distance;
  * PSI_FLAG_KNN_NEAREST_FIRST instead descends to the nearest child first and
  * re-scores siblings on the way back (App. C's visiting order). Both return
- * the same exact result. */
-enum { PSI_FLAG_INPUT_ORDER = 1, PSI_FLAG_KNN_NEAREST_FIRST = 2 };
+ * the same exact result.
+ * A build of 2^24 or more points sorts its (key, id) pairs in two levels:
+ * two global radix passes on the top 16 key bits, then each bucket in one
+ * workgroup's local memory (the distribute-then-sort-locally shape of
+ * Alg. 3); smaller builds take eight global passes. PSI_FLAG_SORT_BUCKETS and
+ * PSI_FLAG_SORT_LSD force one or the other (not both); the result is the
+ * same. */
+enum {
+    PSI_FLAG_INPUT_ORDER = 1,
+    PSI_FLAG_KNN_NEAREST_FIRST = 2,
+    PSI_FLAG_SORT_BUCKETS = 4,
+    PSI_FLAG_SORT_LSD = 8
+};
 
 /* dim: 2 or 3. curve: psi_curve. leaf_size: phi, the largest leaf a build
  * makes (2..32); a leaf slot holds 2*phi entries so that inserts can append

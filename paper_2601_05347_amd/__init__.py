@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libpsi.so")
 MORTON, HILBERT = 0, 1
 FLAG_INPUT_ORDER = 1
 FLAG_KNN_NEAREST_FIRST = 2
+FLAG_SORT_BUCKETS = 4
+FLAG_SORT_LSD = 8
 PAD_ID = 0xFFFFFFFF
 PAD_D2 = 0xFFFFFFFFFFFFFFFF
 

@@ -1,0 +1,346 @@
+// Two-level sort of a build's (key, id) pairs.
+//
+// The build sort of Alg. 3 is a sample sort: distribute the (code, id) pairs
+// into buckets, then sort every bucket on its own, where it fits in cache.
+// The same shape here, with radix digits in place of sampled pivots: two
+// global LSD passes order the pairs by their top 16 key bits (65536
+// buckets), then every bucket of at most BUCKET_MAX pairs is sorted entirely
+// inside one workgroup's LDS, in place: one counting pass into 256
+// sub-buckets, then one thread sorts each sub-bucket in registers. Larger
+// buckets (clustered data) are sorted by six segmented global passes
+// instead. Traffic for uniform data: two global passes plus one read and one
+// write of every pair, instead of eight global passes.
+#include "psi_kern.h"
+
+namespace psi {
+
+namespace {
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+constexpr int LS_IPT = BUCKET_MAX / 256;  // items per thread at the largest bucket
+
+// bstart[t] = first position whose top bits (key >> shift) are >= t, for
+// t in [0, nb]; the keys are already ordered by those bits.
+__global__ void k_bucket_starts(const uint64_t* __restrict__ keys, uint64_t n, uint32_t shift, uint32_t nb,
+                                uint32_t* __restrict__ bstart) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > nb) return;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> shift) < t) lo = mid + 1;
+        else hi = mid;
+    }
+    bstart[t] = (uint32_t)lo;
+}
+
+// Ascending bitonic network over N (key, id) pairs held in registers; pairs
+// compare lexicographically (ids are unique, so the order is total).
+template <int N>
+__device__ __forceinline__ void bitonic(uint64_t (&k)[N], uint32_t (&id)[N]) {
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ stride;
+                if (l > i) {
+                    const bool up = (i & size) == 0;
+                    const bool gt = k[i] > k[l] || (k[i] == k[l] && id[i] > id[l]);
+                    if (gt == up) {
+                        const uint64_t tk = k[i];
+                        k[i] = k[l];
+                        k[l] = tk;
+                        const uint32_t ti = id[i];
+                        id[i] = id[l];
+                        id[l] = ti;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Sorts the run s_k/s_i[s0, s0 + c) (c <= N) in place, in registers.
+template <int N>
+__device__ __forceinline__ void sort_run(uint64_t* s_k, uint32_t* s_i, uint32_t s0, uint32_t c) {
+    uint64_t k[N];
+    uint32_t id[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const bool ok = (uint32_t)j < c;
+        k[j] = ok ? s_k[s0 + j] : ~0ull;
+        id[j] = ok ? s_i[s0 + j] : ~0u;
+    }
+    bitonic<N>(k, id);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if ((uint32_t)j < c) {
+            s_k[s0 + j] = k[j];
+            s_i[s0 + j] = id[j];
+        }
+    }
+}
+
+constexpr uint32_t RUN_MAX = 32;  // largest sub-bucket sorted by one thread
+
+// One workgroup per bucket of at most BUCKET_MAX pairs, sorted in place by
+// (key, id). The pairs arrive in id order (the global passes are stable).
+// Sub-buckets: the 8 key bits just below the highest bit in which the
+// bucket's keys differ (so that clustered buckets still spread); each thread
+// sorts one sub-bucket in registers. A bucket with a sub-bucket of more than
+// RUN_MAX pairs is sorted instead by stable 8-bit LSD passes over the bits
+// [0, lo_bits) in LDS. Larger buckets are only flagged (big[t] = 1).
+// Decreasing bucket starts (pairs not ordered by their top bits) latch
+// ERR_SPIN and the bucket is left alone.
+__global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                    const uint32_t* __restrict__ bstart, uint32_t lo_bits,
+                                                    uint32_t* __restrict__ big, uint32_t* __restrict__ err) {
+    __shared__ uint64_t s_k[BUCKET_MAX];
+    __shared__ uint32_t s_i[BUCKET_MAX];
+    __shared__ uint32_t s_cnt[4][RADIX];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint64_t s_red[8];
+    __shared__ uint32_t s_wmax[4];
+    __shared__ uint32_t s_skip[8];  // one flag per LSD pass: no reset races between passes
+    const uint32_t t = blockIdx.x;
+    const uint32_t b = bstart[t], e = bstart[t + 1];
+    if (e < b) {
+        if (threadIdx.x == 0) {
+            big[t] = 0u;
+            atomicOr(err, ERR_SPIN);
+        }
+        return;
+    }
+    const uint32_t size = e - b;
+    if (threadIdx.x == 0) big[t] = size > BUCKET_MAX ? 1u : 0u;
+    if (size <= 1 || size > BUCKET_MAX) return;
+    const int w = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    // wave w owns positions [w*chunk, (w+1)*chunk): all four waves stay busy
+    // and item order (wave, item, lane) is position order
+    const uint32_t chunk = ((size + 3) / 4 + 63) & ~63u;
+    const uint32_t nit = chunk / 64;
+    uint64_t k[LS_IPT];
+    uint32_t id[LS_IPT];
+    uint32_t rk[LS_IPT];
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int i = 0; i < LS_IPT; ++i) {
+        const uint32_t pos = w * chunk + i * 64 + lane;
+        const bool ok = (uint32_t)i < nit && pos < size;
+        k[i] = ok ? keys[b + pos] : 0ull;
+        id[i] = ok ? ids[b + pos] : 0u;
+        if (ok) {
+            mn = min(mn, k[i]);
+            mx = max(mx, k[i]);
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        mn = min(mn, shfl_u64(mn, (int)(lane ^ o)));
+        mx = max(mx, shfl_u64(mx, (int)(lane ^ o)));
+    }
+    for (int x = threadIdx.x; x < RADIX; x += 256) s_cnt[0][x] = 0;
+    if (threadIdx.x < 8) s_skip[threadIdx.x] = 0;
+    if (lane == 0) {
+        s_red[w] = mn;
+        s_red[4 + w] = mx;
+    }
+    __syncthreads();
+    mn = min(min(s_red[0], s_red[1]), min(s_red[2], s_red[3]));
+    mx = max(max(s_red[4], s_red[5]), max(s_red[6], s_red[7]));
+    if (mn == mx) return;  // one key: already in id order
+    const int hb = 63 - __clzll(mn ^ mx);
+    const uint32_t sh = hb >= 7 ? (uint32_t)hb - 7 : 0u;
+    // sub-bucket counts; the slot inside a sub-bucket is arbitrary (the
+    // register sort orders it)
+#pragma unroll
+    for (int i = 0; i < LS_IPT; ++i) {
+        if ((uint32_t)i >= nit) break;
+        const uint32_t pos = w * chunk + i * 64 + lane;
+        if (pos < size) rk[i] = atomicAdd(&s_cnt[0][(uint32_t)(k[i] >> sh) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = s_cnt[0][threadIdx.x];
+    const uint32_t s0 = block_incl_scan256(c, s_wsum) - c;
+    const uint32_t wm = wave_max_u32(c);
+    s_cnt[1][threadIdx.x] = s0;
+    if (lane == 0) s_wmax[w] = wm;
+    __syncthreads();
+    const uint32_t bm = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
+    if (bm <= RUN_MAX) {
+#pragma unroll
+        for (int i = 0; i < LS_IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            if (pos < size) {
+                const uint32_t lp = s_cnt[1][(uint32_t)(k[i] >> sh) & (RADIX - 1)] + rk[i];
+                s_k[lp] = k[i];
+                s_i[lp] = id[i];
+            }
+        }
+        __syncthreads();
+        if (wm <= 8) sort_run<8>(s_k, s_i, s0, c);  // wm is uniform over the wave
+        else if (wm <= 16) sort_run<16>(s_k, s_i, s0, c);
+        else sort_run<32>(s_k, s_i, s0, c);
+        __syncthreads();
+        for (uint32_t pos = threadIdx.x; pos < size; pos += 256) {
+            keys[b + pos] = s_k[pos];
+            ids[b + pos] = s_i[pos];
+        }
+        return;
+    }
+    // skewed bucket: stable LSD passes in LDS
+    for (uint32_t shift = 0, pass = 0; shift < lo_bits; shift += RADIX_BITS, ++pass) {
+        for (int x = threadIdx.x; x < 4 * RADIX; x += 256) (&s_cnt[0][0])[x] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < LS_IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            const bool ok = pos < size;
+            const uint32_t dg = (uint32_t)(k[i] >> shift) & (RADIX - 1);
+            uint64_t peers = ballot(ok);
+#pragma unroll
+            for (int bb = 0; bb < RADIX_BITS; ++bb) {
+                const bool bit = (dg >> bb) & 1u;
+                const uint64_t m = ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t below = count_below(peers);
+            const uint32_t base = s_cnt[w][dg];
+            if (ok && below == 0) s_cnt[w][dg] = base + (uint32_t)__popcll(peers);
+            rk[i] = base + below;
+        }
+        __syncthreads();
+        const uint32_t d = threadIdx.x;
+        uint32_t tot = 0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const uint32_t cc = s_cnt[x][d];
+            s_cnt[x][d] = tot;
+            tot += cc;
+        }
+        if (tot == size) s_skip[pass] = 1;  // every pair has this digit: the pass changes nothing
+        const uint32_t loc = block_incl_scan256(tot, s_wsum) - tot;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) s_cnt[x][d] += loc;
+        __syncthreads();
+        if (s_skip[pass]) continue;  // uniform over the block
+#pragma unroll
+        for (int i = 0; i < LS_IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            if (pos < size) {
+                const uint32_t dg = (uint32_t)(k[i] >> shift) & (RADIX - 1);
+                const uint32_t lp = s_cnt[w][dg] + rk[i];
+                s_k[lp] = k[i];
+                s_i[lp] = id[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < LS_IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            if (pos < size) {
+                k[i] = s_k[pos];
+                id[i] = s_i[pos];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < LS_IPT; ++i) {
+        if ((uint32_t)i >= nit) break;
+        const uint32_t pos = w * chunk + i * 64 + lane;
+        if (pos < size) {
+            keys[b + pos] = k[i];
+            ids[b + pos] = id[i];
+        }
+    }
+}
+
+__global__ void k_big_count(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ big, uint32_t nb,
+                            uint32_t* __restrict__ ntiles) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    ntiles[t] = big[t] ? (bstart[t + 1] - bstart[t] + SORT_TILE - 1) / SORT_TILE : 0u;
+}
+
+// Segment tables of the big buckets (segment s = the s-th big bucket).
+__global__ void k_big_tables(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ big,
+                             const uint32_t* __restrict__ big_idx, const uint32_t* __restrict__ tile_off,
+                             uint32_t nb, uint32_t* __restrict__ tile_seg, uint32_t* __restrict__ tile_beg,
+                             uint32_t* __restrict__ seg_first, uint32_t* __restrict__ seg_end,
+                             uint64_t* __restrict__ seg_begin) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb || !big[t]) return;
+    const uint32_t s = big_idx[t];
+    const uint32_t b = bstart[t], e = bstart[t + 1];
+    seg_first[s] = tile_off[t];
+    seg_end[s] = e;
+    seg_begin[s] = b;
+    uint32_t j = tile_off[t];
+    for (uint32_t p = b; p < e; p += SORT_TILE, ++j) {
+        tile_seg[j] = s;
+        tile_beg[j] = p;
+    }
+}
+
+// Per-segment histograms of the low six digits, one block per tile.
+__global__ __launch_bounds__(256) void k_seg_hist_keys(const uint64_t* __restrict__ keys, SegTiles sg,
+                                                       uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[6][RADIX];
+    for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t s = sg.tile_seg[blockIdx.x];
+    const uint64_t beg = sg.tile_beg[blockIdx.x];
+    const uint64_t end = min<uint64_t>(beg + SORT_TILE, sg.seg_end[s]);
+    for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const uint64_t k = keys[i];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t* hs = hist + (uint64_t)s * 8 * RADIX;
+    for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(&hs[i], v);
+    }
+}
+
+}  // namespace
+
+void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
+                          uint32_t nb) {
+    hipLaunchKernelGGL(k_bucket_starts, dim3(blocks_for((uint64_t)nb + 1, 256)), dim3(256), 0, st, keys, n, shift,
+                       nb, bstart);
+}
+
+void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err) {
+    hipLaunchKernelGGL(k_local_sort, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+}
+
+void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,
+                       uint32_t* tile_off, uint32_t* big_idx, uint32_t* totals, uint32_t* tmp) {
+    hipLaunchKernelGGL(k_big_count, dim3(blocks_for(nb, 256)), dim3(256), 0, st, bstart, big, nb, ntiles);
+    launch_scan_u32(st, ntiles, tile_off, nb, totals, tmp);
+    launch_scan_u32(st, big, big_idx, nb, totals + 1, tmp);
+}
+
+void launch_big_fill(hipStream_t st, const uint32_t* bstart, const uint32_t* big, const uint32_t* big_idx,
+                     const uint32_t* tile_off, uint32_t nb, const SegTiles& sg, uint64_t* seg_begin) {
+    hipLaunchKernelGGL(k_big_tables, dim3(blocks_for(nb, 256)), dim3(256), 0, st, bstart, big, big_idx, tile_off, nb,
+                       const_cast<uint32_t*>(sg.tile_seg), const_cast<uint32_t*>(sg.tile_beg),
+                       const_cast<uint32_t*>(sg.seg_first_tile), const_cast<uint32_t*>(sg.seg_end), seg_begin);
+}
+
+void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist) {
+    if (ntiles) hipLaunchKernelGGL(k_seg_hist_keys, dim3((unsigned)ntiles), dim3(256), 0, st, keys, sg, hist);
+}
+
+}  // namespace psi

@@ -46,8 +46,11 @@ __global__ __launch_bounds__(256) void k_hist_pairs(const uint64_t* __restrict__
 template <int D, int CURVE, bool HIST>
 __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict__ pts, uint64_t n,
                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ hist,
-                                                     uint32_t* __restrict__ err) {
+                                                     uint32_t* __restrict__ err, int rows, uint32_t shift0,
+                                                     uint64_t* __restrict__ kmax) {
     __shared__ uint32_t h[HIST ? 8 : 1][RADIX];
+    __shared__ uint64_t s_max[4];
+    uint64_t km = 0;
     if (HIST) {
         for (int i = threadIdx.x; i < 8 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
         __syncthreads();
@@ -61,15 +64,25 @@ __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict_
         bad |= !coord_ok<D>(p);
         const uint64_t k = sfc_key<D, CURVE>(p);
         keys[i] = k;
+        km = max(km, k);
         if (HIST) {
 #pragma unroll
-            for (int b = 0; b < 8; ++b) atomicAdd(&h[b][(k >> (8 * b)) & 255u], 1u);
+            for (int b = 0; b < 8; ++b)
+                if (b < rows) atomicAdd(&h[b][(k >> (shift0 + 8 * b)) & 255u], 1u);
         }
     }
     if (bad) atomicOr(err, ERR_RANGE);
+    if (kmax) {  // largest key: one atomic per block
+        for (int o = 32; o >= 1; o >>= 1) km = max(km, shfl_u64(km, (int)(lane_id() ^ o)));
+        if (lane_id() == 0) s_max[threadIdx.x >> 6] = km;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(kmax),
+                      (unsigned long long)max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3])));
+    }
     if (HIST) {
         __syncthreads();
-        for (int i = threadIdx.x; i < 8 * RADIX; i += blockDim.x) {
+        for (int i = threadIdx.x; i < rows * RADIX; i += blockDim.x) {
             const uint32_t v = (&h[0][0])[i];
             if (v) atomicAdd(&hist[i], v);
         }
@@ -330,25 +343,25 @@ void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids
 }
 
 void launch_encode_hist(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
-                        uint32_t* hist, uint32_t* err) {
+                        uint32_t* hist, uint32_t* err, int rows, uint32_t shift0) {
     if (n == 0) return;
     unsigned g = blocks_for(n, 256 * 16);
     if (g > 4096) g = 4096;
-    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
-    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
-    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
-    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err);
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err, rows, shift0, nullptr);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err, rows, shift0, nullptr);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err, rows, shift0, nullptr);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, true>), dim3(g), dim3(256), 0, st, pts, n, keys, hist, err, rows, shift0, nullptr);
 }
 
 void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
-                   uint32_t* err) {
+                   uint32_t* err, uint64_t* kmax) {
     if (n == 0) return;
     unsigned g = blocks_for(n, 256 * 4);
     if (g > 8192) g = 8192;
-    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
-    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
-    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
-    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err);
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_hist<2, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
 }
 
 void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* boxes, uint64_t n, uint64_t* keys) {

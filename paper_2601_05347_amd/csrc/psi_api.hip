@@ -97,6 +97,121 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
     return last_launch();
 }
 
+// Build sort of n pairs (key, id_base + position), all keys below 2^(top+16):
+// two global passes on the key bits [top, top + 16), then every bucket (pairs
+// equal in those bits) sorted by its low `top` bits in LDS; buckets too large
+// for that take segmented global passes over the low bits. Same result as the
+// eight-pass LSD sort: keys ascending, equal keys in id order. Ends with one
+// readback (the big-bucket totals); not for graph capture.
+constexpr uint64_t BUCKET_MIN_N = 1ull << 24;
+
+psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uint64_t n, uint32_t top, int* which) {
+    Sorter& S = ix->sorter;
+    hipStream_t st = ix->st;
+    psi_status s;
+    if ((s = S.off.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    if ((s = S.ctr.ensure(MAX_PASSES * 4)) != PSI_OK) return s;
+    for (int b = 0; b < 2; ++b) {
+        if ((s = S.k[b].ensure(n * 8)) != PSI_OK) return s;
+        if ((s = S.i[b].ensure(n * 4)) != PSI_OK) return s;
+    }
+    auto ensure_status = [&](uint64_t tiles) -> psi_status {
+        if (tiles * RADIX <= S.status_words) return PSI_OK;
+        psi_status r = S.status.ensure(tiles * RADIX * 8);
+        if (r != PSI_OK) return r;
+        S.status_words = S.status.bytes / 8;
+        launch_fill_u32(st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
+        return PSI_OK;
+    };
+    auto next_epoch = [&]() {
+        if (++S.epoch >= (1u << 30)) {
+            S.epoch = 1;
+            launch_fill_u32(st, S.status.as<uint32_t>(), S.status_words * 2, 0u);
+        }
+        return S.epoch;
+    };
+    if ((s = ensure_status((n + SORT_TILE - 1) / SORT_TILE)) != PSI_OK) return s;
+    const uint32_t nb = BUCKET_COUNT;
+    const uint64_t tmpw = scan_tmp_words(nb);
+    if ((s = S.bk.ensure(((uint64_t)nb * 5 + 1 + 2 + tmpw) * 4)) != PSI_OK) return s;
+    uint32_t* bstart = S.bk.as<uint32_t>();  // nb + 1
+    uint32_t* big = bstart + nb + 1;
+    uint32_t* ntiles = big + nb;
+    uint32_t* tile_off = ntiles + nb;
+    uint32_t* big_idx = tile_off + nb;
+    uint32_t* totals = big_idx + nb;  // 2
+    uint32_t* tmp = totals + 2;
+    if (top > 48) return PSI_E_INTERNAL;  // the low bits take at most six 8-bit passes
+    if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    {
+        PassList pl{};
+        pl.n = 2;
+        pl.shift[0] = (uint8_t)top;
+        pl.shift[1] = (uint8_t)(top + 8);
+        launch_fill_u32(st, S.hist.as<uint32_t>(), 2 * RADIX, 0u);
+        ProfScope ps(ix, "hist", n * 8);
+        launch_hist_pairs(st, keys, nullptr, id_base, n, pl, S.hist.as<uint32_t>());
+    }
+    launch_digit_offsets(st, 2, S.hist.as<uint32_t>(), S.off.as<uint32_t>());
+    launch_fill_u32(st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);
+    for (int p = 0; p < 2; ++p) {
+        const uint32_t shift = top + 8 * p;
+        ProfScope ps(ix, "radix_pass", n * 24);
+        launch_onesweep(st, p == 0, false, p == 0 ? keys : S.k[0].as<uint64_t>(), p == 0 ? nullptr : S.i[0].as<uint32_t>(),
+                        id_base, S.k[p].as<uint64_t>(), S.i[p].as<uint32_t>(), n, shift,
+                        S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(), S.ctr.as<uint32_t>() + p,
+                        next_epoch(), ix->err.as<uint32_t>());
+    }
+    uint64_t* K = S.k[1].as<uint64_t>();
+    uint32_t* I = S.i[1].as<uint32_t>();
+    {
+        ProfScope ps(ix, "local_sort", n * 24);
+        launch_bucket_starts(st, K, n, top, bstart, nb);
+        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>());
+    }
+    launch_big_tables(st, bstart, big, nb, ntiles, tile_off, big_idx, totals, tmp);
+    if ((s = last_launch()) != PSI_OK) return s;
+    uint32_t* hp = static_cast<uint32_t*>(ix->pinned);
+    if ((s = hip_ok(hipMemcpyAsync(hp, totals, 8, hipMemcpyDeviceToHost, st))) != PSI_OK) return s;
+    if ((s = hip_ok(hipMemcpyAsync(hp + 2, ix->err.as<uint32_t>(), 4, hipMemcpyDeviceToHost, st))) != PSI_OK)
+        return s;
+    if ((s = hip_ok(hipStreamSynchronize(st))) != PSI_OK) return s;
+    const uint32_t btiles = hp[0], nbig = hp[1];
+    *which = 1;
+    // a failed pass is latched in the error word and reported by psi_sync
+    if (btiles == 0 || (hp[2] & (ERR_SPIN | ERR_CAPACITY))) return PSI_OK;
+    // big buckets: segmented passes over their tiles only (k/i[1] -> [0] -> ... -> [1])
+    if (btiles > (n + SORT_TILE - 1) / SORT_TILE + nbig || nbig > nb) return PSI_E_INTERNAL;
+    if ((s = ensure_status(btiles)) != PSI_OK) return s;
+    const uint64_t seg_words = (uint64_t)btiles * 2 + (uint64_t)nbig * 2;
+    if ((s = S.bseg.ensure(seg_words * 4 + (uint64_t)nbig * 8 + 8)) != PSI_OK) return s;
+    if ((s = S.shist.ensure((uint64_t)nbig * 8 * RADIX * 4)) != PSI_OK) return s;
+    if ((s = S.soff.ensure((uint64_t)nbig * 8 * RADIX * 4)) != PSI_OK) return s;
+    uint64_t* seg_begin = S.bseg.as<uint64_t>();
+    uint32_t* tile_seg = reinterpret_cast<uint32_t*>(seg_begin + nbig);
+    uint32_t* tile_beg = tile_seg + btiles;
+    uint32_t* seg_first = tile_beg + btiles;
+    uint32_t* seg_end = seg_first + nbig;
+    SegTiles sg{tile_seg, tile_beg, seg_first, seg_end, 8 * RADIX};
+    // passes over the low bits, an even number so that the result lands in
+    // k/i[1] again: an added pass reads bits [8 p, 8 p + 8) inside the
+    // bucket bits, constant in a bucket, and changes nothing
+    int np = (int)((top + 7) / 8);
+    np += np & 1;
+    ProfScope ps(ix, "radix_big", (uint64_t)btiles * SORT_TILE * 24 * np);
+    launch_big_fill(st, bstart, big, big_idx, tile_off, nb, sg, seg_begin);
+    launch_fill_u32(st, S.shist.as<uint32_t>(), (uint64_t)nbig * 8 * RADIX, 0u);
+    launch_seg_hist_keys(st, K, btiles, sg, S.shist.as<uint32_t>());
+    launch_seg_digit_offsets(st, nbig, S.shist.as<uint32_t>(), seg_begin, S.soff.as<uint32_t>());
+    for (int p = 0; p < np; ++p) {
+        const int src = (p & 1) ? 0 : 1, dst = 1 - src;
+        launch_onesweep(st, false, false, S.k[src].as<uint64_t>(), S.i[src].as<uint32_t>(), 0, S.k[dst].as<uint64_t>(),
+                        S.i[dst].as<uint32_t>(), n, 8 * p, S.soff.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(),
+                        S.ctr.as<uint32_t>() + 2 + p, next_epoch(), ix->err.as<uint32_t>(), &sg, btiles);
+    }
+    return last_launch();
+}
+
 // Node levels over the current directory: shape on the host, unions on the
 // device, from the level just above the leaves up to the root.
 psi_status build_nodes(psi_index ix) {
@@ -154,12 +269,32 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
     if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
     launch_fill_u32(ix->st, S.hist.as<uint32_t>(), 8 * RADIX, 0u);
     uint64_t* keys = ix->idkey.as<uint64_t>() + id_base;
-    {
-        ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
-        launch_encode_hist(ix->st, ix->D, ix->curve, d_pts, n, keys, S.hist.as<uint32_t>(), ix->err.as<uint32_t>());
-    }
+    const bool two_level = ((ix->flags & PSI_FLAG_SORT_BUCKETS) ||
+                            (n >= BUCKET_MIN_N && !(ix->flags & PSI_FLAG_SORT_LSD))) &&
+                           !capturing(ix->st);
     int w = 0;
-    if ((s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w, "radix_pass")) != PSI_OK) return s;
+    if (two_level) {
+        // keys and their maximum; the bucket bits are the 16 below its leading bit
+        if ((s = S.kmax.ensure(8)) != PSI_OK) return s;
+        launch_fill_u32(ix->st, S.kmax.as<uint32_t>(), 2, 0u);
+        {
+            ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
+            launch_encode(ix->st, ix->D, ix->curve, d_pts, n, keys, ix->err.as<uint32_t>(), S.kmax.as<uint64_t>());
+        }
+        if ((s = last_launch()) != PSI_OK) return s;
+        if ((s = readback(ix, S.kmax.p, 8)) != PSI_OK) return s;
+        const uint64_t km = *static_cast<const uint64_t*>(ix->pinned);
+        const uint32_t bits = km ? 64u - (uint32_t)__builtin_clzll(km) : 0u;
+        s = bucket_sort(ix, keys, id_base, n, bits > 16 ? bits - 16 : 0u, &w);
+    } else {
+        {
+            ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
+            launch_encode_hist(ix->st, ix->D, ix->curve, d_pts, n, keys, S.hist.as<uint32_t>(),
+                               ix->err.as<uint32_t>());
+        }
+        s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w, "radix_pass");
+    }
+    if (s != PSI_OK) return s;
     const uint64_t L = (n + ix->phi - 1) / ix->phi;
     const int c = ix->cur;
     if ((s = ix->slots.ensure(L * ix->slot_words() * 4)) != PSI_OK) return s;
@@ -240,7 +375,9 @@ psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out) {
     if (!prm || !out) return PSI_E_ARG;
     *out = nullptr;
     if ((prm->dim != 2 && prm->dim != 3) || prm->curve > 1 || prm->leaf_size < 2 || prm->leaf_size > 32 ||
-        prm->fanout < 2 || prm->fanout > 32 || (prm->flags & ~(uint32_t)(PSI_FLAG_INPUT_ORDER | PSI_FLAG_KNN_NEAREST_FIRST)) != 0)
+        prm->fanout < 2 || prm->fanout > 32 || (prm->flags & ~(uint32_t)(PSI_FLAG_INPUT_ORDER | PSI_FLAG_KNN_NEAREST_FIRST | PSI_FLAG_SORT_BUCKETS |
+                                  PSI_FLAG_SORT_LSD)) != 0 ||
+        (prm->flags & (PSI_FLAG_SORT_BUCKETS | PSI_FLAG_SORT_LSD)) == (PSI_FLAG_SORT_BUCKETS | PSI_FLAG_SORT_LSD))
         return PSI_E_ARG;
     psi_index ix = new (std::nothrow) psi_index_s;
     if (!ix) return PSI_E_NOMEM;

@@ -112,6 +112,8 @@ struct Prof {
 // the two ping-pong pair buffers.
 struct Sorter {
     Buf hist, off, ctr, status, k[2], i[2];
+    Buf bk, bseg, shist, soff;  // two-level build sort: bucket tables, big-bucket segments
+    Buf kmax;                   // largest key of a build (u64)
     uint32_t epoch = 0;
     uint64_t status_words = 0;
 };

@@ -27,15 +27,17 @@ struct PassList {
 // id = id_base + position. hist must be zeroed ([pl.n][256] u32).
 void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids, uint32_t id_base,
                        uint64_t n, const PassList& pl, uint32_t* hist);
-// Curve keys of points (AoS) -> keys[i]; histograms of the 8 key digits
-// (hist zeroed, [8][256]); coordinates out of range set ERR_RANGE.
+// Curve keys of points (AoS) -> keys[i]; histograms of `rows` 8-bit key
+// digits (row r: bits shift0 + 8 r ..; hist zeroed, [rows][256], rows <= 8);
+// coordinates out of range set ERR_RANGE.
 void launch_encode_hist(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
-                        uint32_t* hist, uint32_t* err);
+                        uint32_t* hist, uint32_t* err, int rows = 8, uint32_t shift0 = 0);
 // Curve keys of box centres (boxes [n][2][dim]); used to order box batches.
 void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* boxes, uint64_t n, uint64_t* keys);
-// Curve keys only.
+// Curve keys only; kmax (optional, zeroed by the caller) receives the
+// largest key.
 void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
-                   uint32_t* err);
+                   uint32_t* err, uint64_t* kmax = nullptr);
 // Exclusive scan of every pass's 256 counts: off[p][d].
 void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint32_t* off);
 // One stable scatter pass (decoupled look-back over tiles taken in launch
@@ -57,6 +59,32 @@ void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, cons
                      uint32_t epoch, uint32_t* err, const SegTiles* seg = nullptr, uint64_t seg_tiles = 0);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
+
+// ------------------------------------------------- two-level build sort
+// Pairs already ordered by their top bits (key >> shift) fall into buckets;
+// a bucket of at most BUCKET_MAX pairs is sorted in one workgroup's LDS.
+// Buckets are the 16 key bits [top, top + 16) just below the largest key's
+// leading bit.
+constexpr int BUCKET_MAX = 4096;
+constexpr uint32_t BUCKET_COUNT = 1u << 16;
+// bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
+void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
+                          uint32_t nb);
+// Sorts every bucket of at most BUCKET_MAX pairs by key bits [0, lo_bits) in
+// place (stable); big[t] = 1 for the larger buckets, else 0. Decreasing
+// bucket starts latch ERR_SPIN.
+void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err);
+// Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
+// bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
+// big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).
+void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,
+                       uint32_t* tile_off, uint32_t* big_idx, uint32_t* totals, uint32_t* tmp);
+// Segment tables (segment = big bucket) for the segmented passes.
+void launch_big_fill(hipStream_t st, const uint32_t* bstart, const uint32_t* big, const uint32_t* big_idx,
+                     const uint32_t* tile_off, uint32_t nb, const SegTiles& sg, uint64_t* seg_begin);
+// Per-segment histograms of the six low key digits: hist [num][8][256], zeroed.
+void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist);
 
 // ------------------------------------------------------------------ scans
 // Exclusive prefix sums; `total` (device, may be null) receives the sum.

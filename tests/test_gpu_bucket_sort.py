@@ -1,0 +1,152 @@
+"""GPU parity of the two-level build sort (top-bit buckets, then per-bucket
+LDS sort; oversized buckets through segmented global passes) against the
+oracle, and against the eight-pass LSD build, bit-exact.
+
+Bucket = the top 16 bits of the curve key (62 bits in 2D, 63 in 3D). For a
+2D Morton key those are bits 23..30 of both coordinates, which lets the tests place exact
+bucket sizes (4096 = the largest a workgroup sorts in LDS, 4097 = the
+smallest that takes the segmented passes).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CURVES = [(2, 0), (2, 1), (3, 0), (3, 1)]
+FIELDS = ("level_sizes", "piv_key", "piv_id", "leaf_cnt", "leaf_lo", "leaf_hi", "node_lo", "node_hi", "node_cnt")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def psi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2601_05347_amd as psi
+    psi.lib()
+    return psi
+
+
+def bits_of(dim):
+    return 30 if dim == 2 else 21
+
+
+def check(psi, dim, curve, pts, phi=32, B=8):
+    """Two-level build == oracle (structure, sorted dump) == LSD build (raw leaves)."""
+    ix = psi.Index(dim, curve, phi, B, flags=psi.FLAG_SORT_BUCKETS).build(pts)
+    ref = oracle.RefIndex(dim, curve, phi, B)
+    ref.build(pts)
+    g, e = ix.structure(), ref.structure()
+    assert g["n_leaves"] == e["n_leaves"] and g["height"] == e["height"]
+    for f in FIELDS:
+        np.testing.assert_array_equal(g[f], e[f], err_msg=f)
+    for a, b in zip(ix.export(), ref.dump()):
+        np.testing.assert_array_equal(a, b)
+    lsd = psi.Index(dim, curve, phi, B, flags=psi.FLAG_SORT_LSD).build(pts)
+    for a, b in zip(ix.leaves(), lsd.leaves()):
+        np.testing.assert_array_equal(a, b)
+    ix.sync()
+    lsd.sync()
+    return ix, ref
+
+
+@pytest.mark.parametrize("n", [1, 33, 4097, 100_003, 1_000_003])
+@pytest.mark.parametrize("dim,curve", CURVES)
+def test_two_level_uniform(psi, dim, curve, n):
+    say(f"two-level uniform dim={dim} curve={curve} n={n}")
+    check(psi, dim, curve, synth.uniform(n, dim, bits_of(dim), seed=n + 11))
+
+
+def test_bucket_size_boundaries(psi):
+    """Buckets of exactly 4096 (LDS) and 4097 (segmented) pairs, an empty
+    bucket between them, a bucket of 1 and a uniform remainder."""
+    say("two-level bucket boundaries")
+    r = synth.uniform(4096 + 4097 + 1 + 50_000, 2, 23, seed=3)  # low 23 bits of each coordinate
+    hi = np.zeros((len(r), 2), np.uint32)
+    hi[4096:8193, 0] = 1          # bucket 1 (x bit 23 -> key bit 46)
+    hi[8193, 1] = 3               # bucket morton(0, 3) = 10
+    hi[8194:, 0] = synth.uniform(50_000, 1, 8, seed=4)[:, 0]
+    hi[8194:, 1] = synth.uniform(50_000, 1, 8, seed=5)[:, 0] | 4  # never buckets 0 or 1
+    pts = (r | (hi << np.uint32(23))).astype(np.uint32)
+    perm = np.argsort(synth.draws(synth.stream_key(9, synth.P_AUX), 0, len(pts)), kind="stable")
+    check(psi, 2, 0, pts[perm])
+
+
+@pytest.mark.parametrize("dim,curve", [(2, 0), (3, 1)])
+def test_single_big_bucket(psi, dim, curve):
+    """Every key in one bucket: the whole sort runs in the segmented passes."""
+    say(f"two-level one big bucket dim={dim} curve={curve}")
+    check(psi, dim, curve, synth.uniform(300_007, dim, 12 if dim == 2 else 8, seed=7))
+
+
+def test_mixed_big_and_small_buckets(psi):
+    say("two-level mixed buckets")
+    a = synth.uniform(200_000, 3, 21, seed=12)
+    b = synth.uniform(150_000, 3, 6, seed=13) + np.uint32(1 << 20)  # one dense corner cell
+    pts = np.concatenate([a, b]).astype(np.uint32)
+    check(psi, 3, 1, pts[np.argsort(synth.draws(synth.stream_key(14, synth.P_AUX), 0, len(pts)), kind="stable")])
+
+
+def test_clustered_varden(psi):
+    say("two-level varden 2D/3D")
+    check(psi, 2, 1, synth.varden(1_000_000, 2, 30, seed=21))
+    check(psi, 3, 0, synth.varden(1_000_000, 3, 21, seed=22))
+
+
+def test_equal_keys_keep_id_order(psi):
+    """Equal keys (duplicate points) stay in id order, in small and big buckets."""
+    say("two-level duplicates")
+    check(psi, 3, 1, synth.uniform(60_000, 3, 3, seed=5))  # 512 distinct points
+    same = np.tile(np.array([[123456, 7654321]], np.uint32), (20_000, 1))
+    check(psi, 2, 1, same)
+
+
+def test_fanouts_leaf_sizes_and_updates(psi):
+    say("two-level phi/B and updates")
+    pts = synth.varden(80_000, 2, 30, seed=31)
+    for phi, B in ((4, 2), (17, 3), (32, 32)):
+        check(psi, 2, 1, pts, phi=phi, B=B)
+    ix, ref = check(psi, 3, 1, synth.uniform(120_000, 3, 21, seed=32))
+    ins = synth.uniform(5000, 3, 21, seed=33, purpose=synth.P_INSERT)
+    np.testing.assert_array_equal(psi.to_u32(ix.batch_insert(ins)), ref.batch_insert(ins))
+    dels = synth.delete_ids(np.arange(ref.next_id(), dtype=np.uint32), 7000, seed=34)
+    assert int(psi.to_u64(ix.batch_delete(dels))[0]) == ref.batch_delete(dels)
+    for a, b in zip(ix.export(), ref.dump()):
+        np.testing.assert_array_equal(a, b)
+    ix.sync()
+
+
+def test_flags_validated(psi):
+    with pytest.raises(psi.PsiError):
+        psi.Index(2, 0, flags=psi.FLAG_SORT_BUCKETS | psi.FLAG_SORT_LSD)
+
+
+def _bucket0(n_spread, n_cluster, cluster_bits, seed):
+    """2D Morton points of bucket 0 (coordinates below 2^23): n_spread spread
+    over the whole bucket, n_cluster inside [0, 2^cluster_bits)^2."""
+    a = synth.uniform(n_spread, 2, 23, seed=seed)
+    c = synth.uniform(n_cluster, 2, cluster_bits, seed=seed + 1)
+    return np.concatenate([a, c])
+
+
+def test_skewed_buckets(psi):
+    """Sub-buckets of 17..32 pairs (the 32-wide register network), a bucket
+    whose pairs crowd into one sub-bucket (the LDS LSD fallback), and a
+    bucket of equal keys, among uniform buckets."""
+    say("two-level skewed buckets")
+    rest = synth.uniform(200_000, 2, 31, seed=40)
+    rest = rest[(rest[:, 0] >> 23) + (rest[:, 1] >> 23) > 1]  # keep buckets 0..3 for the parts below
+    net32 = _bucket0(900, 20, 10, seed=41)                     # bucket 0
+    crowd = _bucket0(12, 3000, 4, seed=43) | np.array([1 << 23, 0], np.uint32)   # bucket 1
+    same = np.tile(np.array([[77, 1 << 23]], np.uint32), (2500, 1))            # bucket 2
+    pts = np.concatenate([rest, net32, crowd, same]).astype(np.uint32)
+    pts = pts[np.argsort(synth.draws(synth.stream_key(44, synth.P_AUX), 0, len(pts)), kind="stable")]
+    check(psi, 2, 0, pts)
