@@ -6,6 +6,7 @@
 // one 32-lane group per leaf. A key is a bijection of its grid point, so the
 // point is decoded from the key instead of gathered by id: the fill reads the
 // sorted pairs once, in order, and never touches the input coordinates again.
+#include "psi_hilbert.h"
 #include "psi_kern.h"
 
 namespace psi {
@@ -30,45 +31,54 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
                                                       uint32_t C, uint32_t* __restrict__ slots,
                                                       uint64_t* __restrict__ piv_key, uint32_t* __restrict__ piv_id,
                                                       NodeRec* __restrict__ leafrec) {
-    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;  // leaf of this half-wave
+    // Hilbert keys decode through the curve's state tables, staged once per
+    // workgroup (the grid is sized to the chip; half-waves stride over leaves)
+    __shared__ uint16_t s_h[CURVE ? HilbertFsm<D>::ENTRIES : 1];
+    if (CURVE) {
+        stage_hilbert<D>(s_h, false);
+        __syncthreads();
+    }
     const uint32_t t = threadIdx.x & 31;
-    if (j >= L) return;  // whole half-waves leave together
-    const uint64_t b = j * n / L, e = (j + 1) * n / L;
-    const uint32_t cnt = (uint32_t)(e - b);
-    const bool on = t < cnt;
-    uint32_t p[D];
-    uint64_t key = 0;
-    uint32_t id = 0;
-    if (on) {
-        key = sk[b + t];
-        id = sid[b + t];
-        sfc_point<D, CURVE>(key, p);
-        uint32_t* s = slots + j * (uint64_t)(D + 1) * C;
+    const uint64_t nhw = ((uint64_t)gridDim.x * blockDim.x) >> 5;
+    for (uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; j < L; j += nhw) {
+        const uint64_t b = j * n / L, e = (j + 1) * n / L;
+        const uint32_t cnt = (uint32_t)(e - b);
+        const bool on = t < cnt;
+        uint32_t p[D];
+        uint64_t key = 0;
+        uint32_t id = 0;
+        if (on) {
+            key = sk[b + t];
+            id = sid[b + t];
+            if (CURVE) hilbert_point_fsm<D>(key, p, s_h);
+            else morton_point<D>(key, p);
+            uint32_t* s = slots + j * (uint64_t)(D + 1) * C;
 #pragma unroll
-        for (int d = 0; d < D; ++d) s[d * C + t] = p[d];
-        s[D * C + t] = id;
-    } else {
+            for (int d = 0; d < D; ++d) s[d * C + t] = p[d];
+            s[D * C + t] = id;
+        } else {
 #pragma unroll
-        for (int d = 0; d < D; ++d) p[d] = 0;
-    }
-    NodeRec r;
+            for (int d = 0; d < D; ++d) p[d] = 0;
+        }
+        NodeRec r;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        r.lo[d] = 0xFFFFFFFFu;
-        r.hi[d] = 0u;
-    }
+        for (int d = 0; d < 3; ++d) {
+            r.lo[d] = 0xFFFFFFFFu;
+            r.hi[d] = 0u;
+        }
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        r.lo[d] = half_min(on ? p[d] : 0xFFFFFFFFu);
-        r.hi[d] = half_max(on ? p[d] : 0u);
-    }
-    if (t == 0) {
-        r.cnt = cnt;
-        r.slot = (uint32_t)j;
-        if (D == 2) { r.lo[2] = 0; r.hi[2] = 0; }
-        leafrec[j] = r;
-        piv_key[j] = key;
-        piv_id[j] = id;
+        for (int d = 0; d < D; ++d) {
+            r.lo[d] = half_min(on ? p[d] : 0xFFFFFFFFu);
+            r.hi[d] = half_max(on ? p[d] : 0u);
+        }
+        if (t == 0) {
+            r.cnt = cnt;
+            r.slot = (uint32_t)j;
+            if (D == 2) { r.lo[2] = 0; r.hi[2] = 0; }
+            leafrec[j] = r;
+            piv_key[j] = key;
+            piv_id[j] = id;
+        }
     }
 }
 
@@ -218,7 +228,8 @@ void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk,
                          uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
                          uint32_t* piv_id, NodeRec* leafrec) {
     if (L == 0) return;
-    const unsigned g = blocks_for(L, 256 / 32);
+    unsigned g = blocks_for(L, 256 / 32);
+    if (g > 2048) g = 2048;  // 8 workgroups per CU; half-waves stride over the leaves
 #define PSI_BL(D, CV) hipLaunchKernelGGL((k_build_leaves<D, CV>), dim3(g), dim3(256), 0, st, sk, sid, n, L, C, slots, piv_key, piv_id, leafrec)
     if (dim == 2 && curve == 0) PSI_BL(2, 0);
     if (dim == 2 && curve == 1) PSI_BL(2, 1);

@@ -7,6 +7,7 @@
 // read and one write of the pairs: a tile ranks its pairs with wave ballots,
 // learns its global offset by a decoupled look-back over earlier tiles, stages
 // the pairs in LDS in digit order and writes them out in digit runs.
+#include "psi_hilbert.h"
 #include "psi_kern.h"
 
 namespace psi {
@@ -50,11 +51,14 @@ __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict_
                                                      uint64_t* __restrict__ kmax) {
     __shared__ uint32_t h[HIST ? 8 : 1][RADIX];
     __shared__ uint64_t s_max[4];
+    // Hilbert keys come from the curve's state tables, staged once per
+    // workgroup (grid-stride loop below)
+    __shared__ uint16_t s_h[CURVE ? HilbertFsm<D>::ENTRIES : 1];
     uint64_t km = 0;
-    if (HIST) {
+    if (HIST)
         for (int i = threadIdx.x; i < 8 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
-        __syncthreads();
-    }
+    if (CURVE) stage_hilbert<D>(s_h, true);
+    if (HIST || CURVE) __syncthreads();
     bool bad = false;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict_
 #pragma unroll
         for (int d = 0; d < D; ++d) p[d] = pts[i * D + d];
         bad |= !coord_ok<D>(p);
-        const uint64_t k = sfc_key<D, CURVE>(p);
+        const uint64_t k = CURVE ? hilbert_key_fsm<D>(p, s_h) : morton_key<D>(p);
         keys[i] = k;
         km = max(km, k);
         if (HIST) {
