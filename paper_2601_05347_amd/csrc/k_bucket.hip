@@ -263,6 +263,37 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
     }
 }
 
+// Histograms of the two bucket digits (bits [s0, s0 + 8) and [s1, s1 + 8))
+// of every key; eight loads in flight per thread.
+__global__ __launch_bounds__(256) void k_hist_keys2(const uint64_t* __restrict__ keys, uint64_t n, uint32_t s0,
+                                                    uint32_t s1, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[2][RADIX];
+    for (int i = threadIdx.x; i < 2 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        uint64_t k[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) k[j] = keys[i + j * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            atomicAdd(&h[0][(uint32_t)(k[j] >> s0) & (RADIX - 1)], 1u);
+            atomicAdd(&h[1][(uint32_t)(k[j] >> s1) & (RADIX - 1)], 1u);
+        }
+    }
+    for (; i < n; i += stride) {
+        const uint64_t k = keys[i];
+        atomicAdd(&h[0][(uint32_t)(k >> s0) & (RADIX - 1)], 1u);
+        atomicAdd(&h[1][(uint32_t)(k >> s1) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * RADIX; x += blockDim.x) {
+        const uint32_t v = (&h[0][0])[x];
+        if (v) atomicAdd(&hist[x], v);
+    }
+}
+
 __global__ void k_big_count(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ big, uint32_t nb,
                             uint32_t* __restrict__ ntiles) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,6 +368,13 @@ void launch_big_fill(hipStream_t st, const uint32_t* bstart, const uint32_t* big
     hipLaunchKernelGGL(k_big_tables, dim3(blocks_for(nb, 256)), dim3(256), 0, st, bstart, big, big_idx, tile_off, nb,
                        const_cast<uint32_t*>(sg.tile_seg), const_cast<uint32_t*>(sg.tile_beg),
                        const_cast<uint32_t*>(sg.seg_first_tile), const_cast<uint32_t*>(sg.seg_end), seg_begin);
+}
+
+void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* hist) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 8);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_hist_keys2, dim3(g), dim3(256), 0, st, keys, n, s0, s1, hist);
 }
 
 void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist) {

@@ -130,7 +130,6 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
         }
         return S.epoch;
     };
-    if ((s = ensure_status((n + SORT_TILE - 1) / SORT_TILE)) != PSI_OK) return s;
     const uint32_t nb = BUCKET_COUNT;
     const uint64_t tmpw = scan_tmp_words(nb);
     if ((s = S.bk.ensure(((uint64_t)nb * 5 + 1 + 2 + tmpw) * 4)) != PSI_OK) return s;
@@ -142,15 +141,12 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     uint32_t* totals = big_idx + nb;  // 2
     uint32_t* tmp = totals + 2;
     if (top > 48) return PSI_E_INTERNAL;  // the low bits take at most six 8-bit passes
+    if ((s = ensure_status((n + SORT_TILE - 1) / SORT_TILE)) != PSI_OK) return s;
     if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
+    launch_fill_u32(st, S.hist.as<uint32_t>(), 2 * RADIX, 0u);
     {
-        PassList pl{};
-        pl.n = 2;
-        pl.shift[0] = (uint8_t)top;
-        pl.shift[1] = (uint8_t)(top + 8);
-        launch_fill_u32(st, S.hist.as<uint32_t>(), 2 * RADIX, 0u);
         ProfScope ps(ix, "hist", n * 8);
-        launch_hist_pairs(st, keys, nullptr, id_base, n, pl, S.hist.as<uint32_t>());
+        launch_hist_keys2(st, keys, n, top, top + 8, S.hist.as<uint32_t>());
     }
     launch_digit_offsets(st, 2, S.hist.as<uint32_t>(), S.off.as<uint32_t>());
     launch_fill_u32(st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);

@@ -67,6 +67,9 @@ void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 // leading bit.
 constexpr int BUCKET_MAX = 4096;
 constexpr uint32_t BUCKET_COUNT = 1u << 16;
+// Histograms of two 8-bit key digits (rows at bits s0 and s1; hist [2][256],
+// zeroed).
+void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* hist);
 // bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
 void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
                           uint32_t nb);
