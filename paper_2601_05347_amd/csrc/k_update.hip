@@ -368,6 +368,21 @@ __global__ void k_del_kill(const uint32_t* __restrict__ ci, const uint32_t* __re
 
 // One wave per run: lane e holds leaf entry e; entries whose id is in the
 // run are dropped and the survivors are compacted stably in place.
+// Deletes inside one leaf per 16-lane group (four leaves per wave): lane g of
+// the group holds entries g, g + 16, g + 32, g + 48 (a slot has at most 64).
+// Entries whose id is in the leaf's run are removed and the rest are
+// compacted in place, keeping their order; the box is recomputed exactly.
+constexpr uint32_t DEL_G = 16;
+constexpr int DEL_Q = 4;
+__device__ __forceinline__ uint32_t grp_min(uint32_t v) {
+    for (int o = DEL_G / 2; o >= 1; o >>= 1) v = min(v, shfl_u32(v, (int)(lane_id() ^ o)));
+    return v;
+}
+__device__ __forceinline__ uint32_t grp_max(uint32_t v) {
+    for (int o = DEL_G / 2; o >= 1; o >>= 1) v = max(v, shfl_u32(v, (int)(lane_id() ^ o)));
+    return v;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__ ci,
                                                     const uint32_t* __restrict__ run_leaf,
@@ -375,70 +390,101 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ ctr, uint64_t m,
                                                     NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
                                                     uint32_t C, uint32_t* __restrict__ err, Caps cap) {
-    const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / DEL_G;
     const uint32_t lane = lane_id();
+    const uint32_t gl = lane % DEL_G, gbase = lane - gl;  // lane in the group, group's first lane
     const uint32_t R = ctr[1];
-    if (r >= R) return;
+    // groups past the last run stay for the wave-wide ballots below
+    bool act = r < R;
     const uint32_t V = ctr[0];
-    const uint32_t j = run_leaf[r];
-    const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, V);
-    NodeRec rec = leaf[j];
-    if (rec.slot >= cap.slots || rec.cnt > C || rec.cnt > 64) {
-        if (lane == 0) atomicOr(err, ERR_CAPACITY);
-        return;
+    const uint32_t j = act ? run_leaf[r] : 0u;
+    const uint32_t beg = act ? run_beg[r] : 0u;
+    const uint32_t end = act ? run_end(run_beg, (uint32_t)r, R, V) : 0u;
+    NodeRec rec = {};
+    if (act) rec = leaf[j];
+    if (act && (rec.slot >= cap.slots || rec.cnt > C || rec.cnt > DEL_G * DEL_Q)) {
+        if (gl == 0) atomicOr(err, ERR_CAPACITY);
+        act = false;
     }
-    uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
-    const bool on = lane < rec.cnt;
-    uint32_t p[D];
-    uint32_t id = PAD_ID;
-    if (on) {
+    uint32_t* s = slots + (uint64_t)(act ? rec.slot : 0u) * (D + 1) * C;
+    bool on[DEL_Q];
+    uint32_t p[DEL_Q][D];
+    uint32_t id[DEL_Q];
 #pragma unroll
-        for (int d = 0; d < D; ++d) p[d] = s[d * C + lane];
-        id = s[D * C + lane];
+    for (int q = 0; q < DEL_Q; ++q) {
+        const uint32_t e = gl + DEL_G * q;
+        on[q] = act && e < rec.cnt;
+        id[q] = PAD_ID;
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[q][d] = 0;
+        if (on[q]) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) p[q][d] = s[d * C + e];
+            id[q] = s[D * C + e];
+        }
     }
-    bool del = false;
-    for (uint32_t x0 = beg; x0 < end; x0 += 64) {  // the run's ids, 64 at a time
-        const uint32_t rid = x0 + lane < end ? ci[x0 + lane] : PAD_ID;
-        const uint32_t nx = min(64u, end - x0);
+    bool del[DEL_Q] = {};
+    for (uint32_t x0 = beg; x0 < end; x0 += DEL_G) {  // the run's ids, 16 at a time
+        const uint32_t rid = x0 + gl < end ? ci[x0 + gl] : PAD_ID;
+        const uint32_t nx = min(DEL_G, end - x0);
         for (uint32_t x = 0; x < nx; ++x) {
-            const uint32_t other = shfl_u32(rid, (int)x);  // every lane takes part in the shuffle
-            del = del | (on & (other == id));
+            const uint32_t other = shfl_u32(rid, (int)(gbase + x));  // the group's lanes all shuffle
+#pragma unroll
+            for (int q = 0; q < DEL_Q; ++q) del[q] = del[q] | (on[q] & (other == id[q]));
         }
     }
     // `valid` is always true (stored coordinates are below 2^31) but makes the
-    // ballot depend on every loaded coordinate, so all loads of the wave have
+    // ballots depend on every loaded coordinate, so all loads of the wave have
     // completed before the in-place stores below are issued.
     uint32_t any = 0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) any |= on ? p[d] : 0u;
-    const bool valid = any < 0x80000000u;
-    const bool keep = on && !del && valid;
-    const uint64_t km = ballot(keep);
-    const uint32_t removed = (uint32_t)__popcll(ballot(on && del));
-    const uint32_t pos = count_below(km);
-    if (keep && pos != lane) {
+    for (int q = 0; q < DEL_Q; ++q)
 #pragma unroll
-        for (int d = 0; d < D; ++d) s[d * C + pos] = p[d];
-        s[D * C + pos] = id;
+        for (int d = 0; d < D; ++d) any |= p[q][d];
+    const bool valid = any < 0x80000000u;
+    const uint64_t gmask = 0xFFFFull << gbase;
+    uint32_t kept_before = 0, removed = 0;
+    uint32_t pos[DEL_Q];
+    bool keep[DEL_Q];
+#pragma unroll
+    for (int q = 0; q < DEL_Q; ++q) {
+        keep[q] = on[q] && !del[q] && valid;
+        const uint64_t km = ballot(keep[q]) & gmask;
+        removed += (uint32_t)__popcll(ballot(on[q] && del[q]) & gmask);
+        pos[q] = kept_before + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
+        kept_before += (uint32_t)__popcll(km);
     }
-    const uint32_t w = (uint32_t)__popcll(km);
+#pragma unroll
+    for (int q = 0; q < DEL_Q; ++q) {
+        if (keep[q] && pos[q] != gl + DEL_G * q) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) s[d * C + pos[q]] = p[q][d];
+            s[D * C + pos[q]] = id[q];
+        }
+    }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        rec.lo[d] = wave_min_u32(keep ? p[d] : 0xFFFFFFFFu);
-        rec.hi[d] = wave_max_u32(keep ? p[d] : 0u);
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+        for (int q = 0; q < DEL_Q; ++q) {
+            lo = min(lo, keep[q] ? p[q][d] : 0xFFFFFFFFu);
+            hi = max(hi, keep[q] ? p[q][d] : 0u);
+        }
+        rec.lo[d] = grp_min(lo);
+        rec.hi[d] = grp_max(hi);
     }
-    if (lane == 0) {
+    if (act && gl == 0) {
         if (removed != end - beg) atomicOr(err, ERR_DELETE);
-        rec.cnt = w;
+        rec.cnt = kept_before;
         leaf[j] = rec;
     }
 }
 
-__global__ void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half, uint32_t* __restrict__ cnt,
-                             uint32_t* __restrict__ ctr) {
-    __shared__ uint32_t s_max;
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
+// Per-leaf counts, and per workgroup 1 + its last leaf holding at least
+// `half` entries (0 if none) in bmax[blockIdx.x].
+__global__ __launch_bounds__(256) void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half,
+                                                    uint32_t* __restrict__ cnt, uint32_t* __restrict__ bmax) {
+    __shared__ uint32_t s_w[4];
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t last = 0;
     if (j < L) {
@@ -447,9 +493,21 @@ __global__ void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint3
         if (c >= half) last = (uint32_t)(j + 1);
     }
     last = wave_max_u32(last);
-    if (lane_id() == 0 && last) atomicMax(&s_max, last);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = last;
     __syncthreads();
-    if (threadIdx.x == 0 && s_max) atomicMax(&ctr[7], s_max);
+    if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(s_w[0], s_w[1]), max(s_w[2], s_w[3]));
+}
+
+// ctr[7] = max over the nb per-workgroup values (one workgroup).
+__global__ __launch_bounds__(256) void k_del_last_full(const uint32_t* __restrict__ bmax, uint64_t nb,
+                                                       uint32_t* __restrict__ ctr) {
+    __shared__ uint32_t s_w[4];
+    uint32_t m = 0;
+    for (uint64_t i = threadIdx.x; i < nb; i += 256) m = max(m, bmax[i]);
+    m = wave_max_u32(m);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) ctr[7] = max(max(s_w[0], s_w[1]), max(s_w[2], s_w[3]));
 }
 
 __global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t L, uint32_t half,
@@ -707,7 +765,7 @@ void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint6
 }
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
                     const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
-    PSI_D(k_del_remove, dim3(blocks_for(m, 4)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
+    PSI_D(k_del_remove, dim3(blocks_for(m, 256 / DEL_G)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
 }
 void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
                   uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,
@@ -715,7 +773,9 @@ void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi,
                   uint32_t* chunk_off, uint32_t* alloc_off, uint32_t* free_off, uint32_t* tmp) {
     const uint32_t half = (phi + 1) / 2;
     const unsigned g = blocks_for(L, 256);
-    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, cnt, ctr);
+    // start[] holds the per-workgroup maxima until k_del_starts fills it
+    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, cnt, start);
+    hipLaunchKernelGGL(k_del_last_full, dim3(1), dim3(256), 0, st, start, (uint64_t)g, ctr);
     launch_scan_u32(st, cnt, cum, L, cum + L, tmp);
     hipLaunchKernelGGL(k_del_starts, dim3(g), dim3(256), 0, st, cnt, L, half, ctr, start);
     launch_scan_u32(st, start, gidx, L, ctr + 6, tmp);
