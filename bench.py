@@ -372,11 +372,11 @@ def main():
     value = upd_pts / (upd_ms / 1e3) / 1e6 if upd_ms > 0 else 0.0
 
     # dominant kernel family and its roofline
-    fams = ["radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes", "hist", "radix_update",
-            "radix_order", "order", "knn", "range_count", "range_report", "update"]
+    fams = ["radix_first", "radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes", "hist",
+            "radix_update", "radix_order", "order", "knn", "range_count", "range_report", "update"]
     prof = {f: ix.prof_get(f) for f in fams}
     # the dominant streaming kernel of the build & update path
-    mem_fams = [f for f in ("radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes")
+    mem_fams = [f for f in ("radix_first", "radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes")
                 if prof[f][1] > 0]
     dom = max(mem_fams, key=lambda f: prof[f][0]) if mem_fams else None
     roof = None

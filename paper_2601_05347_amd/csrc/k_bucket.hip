@@ -18,7 +18,6 @@ namespace {
 
 inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
-constexpr int LS_IPT = BUCKET_MAX / 256;  // items per thread at the largest bucket
 
 // bstart[t] = first position whose top bits (key >> shift) are >= t, for
 // t in [0, nb]; the keys are already ordered by those bits.
@@ -84,22 +83,52 @@ __device__ __forceinline__ void sort_run(uint64_t* s_k, uint32_t* s_i, uint32_t 
     }
 }
 
-constexpr uint32_t RUN_MAX = 32;  // largest sub-bucket sorted by one thread
+constexpr uint32_t RUN_NET = 16;  // largest sub-bucket one thread sorts with a network
+constexpr uint32_t RUN_WAVE = 64;  // largest sub-bucket a wave sorts by ranking
 
-// One workgroup per bucket of at most BUCKET_MAX pairs, sorted in place by
-// (key, id). The pairs arrive in id order (the global passes are stable).
+// A wave sorts the sub-buckets of its lanes that hold more than RUN_NET pairs
+// (and at most RUN_WAVE), one after the other: lane x takes pair x and counts
+// the pairs of the sub-bucket that precede it.
+__device__ __forceinline__ void rank_runs(uint64_t* s_k, uint32_t* s_i, uint32_t s0, uint32_t c) {
+    const uint32_t lane = lane_id();
+    uint64_t todo = ballot(c > RUN_NET);
+    while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const uint32_t rs = shfl_u32(s0, src), rc = shfl_u32(c, src);
+        const bool on = lane < rc;
+        const uint64_t mk = on ? s_k[rs + lane] : ~0ull;
+        const uint32_t mi = on ? s_i[rs + lane] : ~0u;
+        uint32_t rank = 0;
+        for (uint32_t x = 0; x < rc; ++x) {  // same trip count on every lane: all reads precede the writes
+            const uint64_t ok = s_k[rs + x];
+            const uint32_t oi = s_i[rs + x];
+            rank += (ok < mk || (ok == mk && oi < mi)) ? 1u : 0u;
+        }
+        if (on) {
+            s_k[rs + rank] = mk;
+            s_i[rs + rank] = mi;
+        }
+    }
+}
+
+// One workgroup per bucket of at most BMAX pairs, sorted in place by (key,
+// id). The pairs arrive in id order (the global passes are stable).
 // Sub-buckets: the 8 key bits just below the highest bit in which the
-// bucket's keys differ (so that clustered buckets still spread); each thread
-// sorts one sub-bucket in registers. A bucket with a sub-bucket of more than
-// RUN_MAX pairs is sorted instead by stable 8-bit LSD passes over the bits
-// [0, lo_bits) in LDS. Larger buckets are only flagged (big[t] = 1).
-// Decreasing bucket starts (pairs not ordered by their top bits) latch
-// ERR_SPIN and the bucket is left alone.
+// bucket's keys differ (so that clustered buckets still spread); a thread
+// sorts its sub-bucket in registers (at most RUN_NET pairs), a wave ranks the
+// larger ones (at most RUN_WAVE). A bucket with a larger sub-bucket is sorted
+// instead by stable 8-bit LSD passes over the bits [0, lo_bits) in LDS.
+// Larger buckets are only flagged (big[t] = 1). Decreasing bucket starts
+// (pairs not ordered by their top bits) latch ERR_SPIN and the bucket is left
+// alone.
+template <int BMAX>
 __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
                                                     const uint32_t* __restrict__ bstart, uint32_t lo_bits,
                                                     uint32_t* __restrict__ big, uint32_t* __restrict__ err) {
-    __shared__ uint64_t s_k[BUCKET_MAX];
-    __shared__ uint32_t s_i[BUCKET_MAX];
+    constexpr int IPT = BMAX / 256;  // items per thread at the largest bucket
+    __shared__ uint64_t s_k[BMAX];
+    __shared__ uint32_t s_i[BMAX];
     __shared__ uint32_t s_cnt[4][RADIX];
     __shared__ uint32_t s_wsum[4];
     __shared__ uint64_t s_red[8];
@@ -115,20 +144,20 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         return;
     }
     const uint32_t size = e - b;
-    if (threadIdx.x == 0) big[t] = size > BUCKET_MAX ? 1u : 0u;
-    if (size <= 1 || size > BUCKET_MAX) return;
+    if (threadIdx.x == 0) big[t] = size > (uint32_t)BMAX ? 1u : 0u;
+    if (size <= 1 || size > (uint32_t)BMAX) return;
     const int w = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
     // wave w owns positions [w*chunk, (w+1)*chunk): all four waves stay busy
     // and item order (wave, item, lane) is position order
     const uint32_t chunk = ((size + 3) / 4 + 63) & ~63u;
     const uint32_t nit = chunk / 64;
-    uint64_t k[LS_IPT];
-    uint32_t id[LS_IPT];
-    uint32_t rk[LS_IPT];
+    uint64_t k[IPT];
+    uint32_t id[IPT];
+    uint32_t rk[IPT];
     uint64_t mn = ~0ull, mx = 0;
 #pragma unroll
-    for (int i = 0; i < LS_IPT; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         const uint32_t pos = w * chunk + i * 64 + lane;
         const bool ok = (uint32_t)i < nit && pos < size;
         k[i] = ok ? keys[b + pos] : 0ull;
@@ -155,9 +184,9 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
     const int hb = 63 - __clzll(mn ^ mx);
     const uint32_t sh = hb >= 7 ? (uint32_t)hb - 7 : 0u;
     // sub-bucket counts; the slot inside a sub-bucket is arbitrary (the
-    // register sort orders it)
+    // sub-bucket sort orders it)
 #pragma unroll
-    for (int i = 0; i < LS_IPT; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         if ((uint32_t)i >= nit) break;
         const uint32_t pos = w * chunk + i * 64 + lane;
         if (pos < size) rk[i] = atomicAdd(&s_cnt[0][(uint32_t)(k[i] >> sh) & (RADIX - 1)], 1u);
@@ -165,14 +194,14 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
     __syncthreads();
     const uint32_t c = s_cnt[0][threadIdx.x];
     const uint32_t s0 = block_incl_scan256(c, s_wsum) - c;
-    const uint32_t wm = wave_max_u32(c);
+    const uint32_t wm = wave_max_u32(c);  // all lanes take part in the shuffles
     s_cnt[1][threadIdx.x] = s0;
     if (lane == 0) s_wmax[w] = wm;
     __syncthreads();
     const uint32_t bm = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
-    if (bm <= RUN_MAX) {
+    if (bm <= RUN_WAVE) {
 #pragma unroll
-        for (int i = 0; i < LS_IPT; ++i) {
+        for (int i = 0; i < IPT; ++i) {
             if ((uint32_t)i >= nit) break;
             const uint32_t pos = w * chunk + i * 64 + lane;
             if (pos < size) {
@@ -182,9 +211,11 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
             }
         }
         __syncthreads();
-        if (wm <= 8) sort_run<8>(s_k, s_i, s0, c);  // wm is uniform over the wave
-        else if (wm <= 16) sort_run<16>(s_k, s_i, s0, c);
-        else sort_run<32>(s_k, s_i, s0, c);
+        const uint32_t cn = c <= RUN_NET ? c : 0u;
+        const uint32_t wn = wave_max_u32(cn);  // uniform over the wave
+        if (wn <= 8) sort_run<8>(s_k, s_i, s0, cn);
+        else sort_run<16>(s_k, s_i, s0, cn);
+        rank_runs(s_k, s_i, s0, c);
         __syncthreads();
         for (uint32_t pos = threadIdx.x; pos < size; pos += 256) {
             keys[b + pos] = s_k[pos];
@@ -197,7 +228,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         for (int x = threadIdx.x; x < 4 * RADIX; x += 256) (&s_cnt[0][0])[x] = 0;
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < LS_IPT; ++i) {
+        for (int i = 0; i < IPT; ++i) {
             if ((uint32_t)i >= nit) break;
             const uint32_t pos = w * chunk + i * 64 + lane;
             const bool ok = pos < size;
@@ -230,7 +261,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         __syncthreads();
         if (s_skip[pass]) continue;  // uniform over the block
 #pragma unroll
-        for (int i = 0; i < LS_IPT; ++i) {
+        for (int i = 0; i < IPT; ++i) {
             if ((uint32_t)i >= nit) break;
             const uint32_t pos = w * chunk + i * 64 + lane;
             if (pos < size) {
@@ -242,7 +273,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < LS_IPT; ++i) {
+        for (int i = 0; i < IPT; ++i) {
             if ((uint32_t)i >= nit) break;
             const uint32_t pos = w * chunk + i * 64 + lane;
             if (pos < size) {
@@ -253,7 +284,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < LS_IPT; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         if ((uint32_t)i >= nit) break;
         const uint32_t pos = w * chunk + i * 64 + lane;
         if (pos < size) {
@@ -352,8 +383,11 @@ void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint
 }
 
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t* big, uint32_t* err) {
-    hipLaunchKernelGGL(k_local_sort, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+                       uint32_t lo_bits, uint32_t bmax, uint32_t* big, uint32_t* err) {
+    if (bmax == BUCKET_SMALL)
+        hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+    else
+        hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
 }
 
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,

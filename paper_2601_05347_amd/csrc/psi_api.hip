@@ -152,7 +152,8 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     launch_fill_u32(st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);
     for (int p = 0; p < 2; ++p) {
         const uint32_t shift = top + 8 * p;
-        ProfScope ps(ix, "radix_pass", n * 24);
+        // first pass: 8 B key read (ids implicit), 12 B written; second: 12 B each way
+        ProfScope ps(ix, p == 0 ? "radix_first" : "radix_pass", n * (p == 0 ? 20 : 24));
         launch_onesweep(st, p == 0, false, p == 0 ? keys : S.k[0].as<uint64_t>(), p == 0 ? nullptr : S.i[0].as<uint32_t>(),
                         id_base, S.k[p].as<uint64_t>(), S.i[p].as<uint32_t>(), n, shift,
                         S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(), S.ctr.as<uint32_t>() + p,
@@ -163,7 +164,9 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     {
         ProfScope ps(ix, "local_sort", n * 24);
         launch_bucket_starts(st, K, n, top, bstart, nb);
-        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>());
+        // the lighter variant while an average bucket is well below its capacity
+        const uint32_t bmax = n <= (uint64_t)nb * (BUCKET_SMALL * 3 / 4) ? BUCKET_SMALL : BUCKET_MAX;
+        launch_local_sort(st, K, I, bstart, nb, top, bmax, big, ix->err.as<uint32_t>());
     }
     launch_big_tables(st, bstart, big, nb, ntiles, tile_off, big_idx, totals, tmp);
     if ((s = last_launch()) != PSI_OK) return s;
