@@ -15,15 +15,26 @@ namespace {
 
 inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
-// 32-lane group reductions (xor offsets below 32 stay inside the half-wave).
-__device__ __forceinline__ uint32_t half_min(uint32_t v) {
-    for (int o = 16; o >= 1; o >>= 1) v = min(v, shfl_u32(v, (int)(lane_id() ^ o)));
-    return v;
+// 32-lane group reductions on the VALU's cross-lane paths: two quad swaps,
+// the half-row and row mirrors (each lane then holds its 16-lane row's
+// result) and a swizzle that exchanges the two rows of the 32-lane group.
+// Every lane of the group must be active.
+constexpr int DPP_QUAD_SWAP1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_SWAP2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+constexpr int SWZ_XOR16 = (16 << 10) | 0x1F;  // bitmask mode: lane ^ 16 inside 32 lanes
+template <bool MIN>
+__device__ __forceinline__ uint32_t half_reduce(uint32_t v) {
+    auto op = [](uint32_t a, uint32_t b) { return MIN ? min(a, b) : max(a, b); };
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_QUAD_SWAP1, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_QUAD_SWAP2, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_HALF_MIRROR, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_MIRROR, 0xF, 0xF, false));
+    return op(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, SWZ_XOR16));
 }
-__device__ __forceinline__ uint32_t half_max(uint32_t v) {
-    for (int o = 16; o >= 1; o >>= 1) v = max(v, shfl_u32(v, (int)(lane_id() ^ o)));
-    return v;
-}
+__device__ __forceinline__ uint32_t half_min(uint32_t v) { return half_reduce<true>(v); }
+__device__ __forceinline__ uint32_t half_max(uint32_t v) { return half_reduce<false>(v); }
 
 template <int D, int CURVE>
 __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict__ sk,
