@@ -70,19 +70,29 @@ def parse():
     return ap.parse_args()
 
 
-def profiled_traffic(profile: str, kernel_source: str):
-    """HBM bytes per launch recorded by a rocprofv3 counter run, if the kernel's
-    source is unchanged since (profiles/*.md carry the source hash)."""
+def csrc_hash() -> str:
+    """SHA-256 over the library's kernel sources (names and contents, sorted)."""
     import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2601_05347_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(profile: str, family: str):
+    """HBM bytes per launch of a kernel family recorded by rocprofv3 counter
+    runs, if no kernel source changed since (the profile carries the hash)."""
     import re
     try:
         txt = open(os.path.join(ROOT, "profiles", profile)).read()
-        src = open(os.path.join(ROOT, "paper_2601_05347_amd", "csrc", kernel_source), "rb").read()
     except OSError:
         return None
-    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
-    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    if not (m_t and m_h) or m_h.group(1) != hashlib.sha256(src).hexdigest():
+    m_t = re.search(r"traffic\[%s\]:\s*(\d+)" % re.escape(family), txt)
+    m_h = re.search(r"csrc_sha256:\s*([0-9a-f]{64})", txt)
+    if not (m_t and m_h) or m_h.group(1) != csrc_hash():
         return None
     return int(m_t.group(1))
 
@@ -385,8 +395,8 @@ def main():
         avg_s = tms / launches / 1e3
         achieved = byt / launches / avg_s / 1e9
         traffic = None
-        if dom == "radix_pass" and args.workload == "3d-1e8" and args.dist == "uniform" and n == 100_000_000:
-            traffic = profiled_traffic("onesweep_pass_3d_1e8_uniform.md", "k_sort.hip")
+        if args.workload == "3d-1e8" and args.dist == "uniform" and n == 100_000_000 and curve == 1:
+            traffic = profiled_traffic("build_kernels_3d_1e8_uniform.md", dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": byt // launches, "avg_launch_ms": round(tms / launches, 4)}
