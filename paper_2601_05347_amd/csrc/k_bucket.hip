@@ -113,7 +113,9 @@ __device__ __forceinline__ void rank_runs(uint64_t* s_k, uint32_t* s_i, uint32_t
 }
 
 // One workgroup per bucket of at most BMAX pairs, sorted in place by (key,
-// id). The pairs arrive in id order (the global passes are stable).
+// id). The BUCKET_SMALL variant runs first over all buckets and flags the
+// larger ones; the BUCKET_MAX variant then takes those of at most BUCKET_MAX
+// pairs (half the occupancy, for the rare large buckets). The pairs arrive in id order (the global passes are stable).
 // Sub-buckets: the 8 key bits just below the highest bit in which the
 // bucket's keys differ (so that clustered buckets still spread); a thread
 // sorts its sub-bucket in registers (at most RUN_NET pairs), a wave ranks the
@@ -144,8 +146,13 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         return;
     }
     const uint32_t size = e - b;
-    if (threadIdx.x == 0) big[t] = size > (uint32_t)BMAX ? 1u : 0u;
-    if (size <= 1 || size > (uint32_t)BMAX) return;
+    if (BMAX == BUCKET_SMALL) {  // first launch: every bucket gets its flag
+        if (threadIdx.x == 0) big[t] = size > (uint32_t)BMAX ? 1u : 0u;
+        if (size <= 1 || size > (uint32_t)BMAX) return;
+    } else {  // second launch: only the buckets the first one left
+        if (size <= (uint32_t)BUCKET_SMALL || size > (uint32_t)BMAX) return;
+        if (threadIdx.x == 0) big[t] = 0u;
+    }
     const int w = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
     // wave w owns positions [w*chunk, (w+1)*chunk): all four waves stay busy
@@ -383,11 +390,9 @@ void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint
 }
 
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t bmax, uint32_t* big, uint32_t* err) {
-    if (bmax == BUCKET_SMALL)
-        hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
-    else
-        hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err) {
+    hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+    hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
 }
 
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,

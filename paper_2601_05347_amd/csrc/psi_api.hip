@@ -164,9 +164,7 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     {
         ProfScope ps(ix, "local_sort", n * 24);
         launch_bucket_starts(st, K, n, top, bstart, nb);
-        // the lighter variant while an average bucket is well below its capacity
-        const uint32_t bmax = n <= (uint64_t)nb * (BUCKET_SMALL * 3 / 4) ? BUCKET_SMALL : BUCKET_MAX;
-        launch_local_sort(st, K, I, bstart, nb, top, bmax, big, ix->err.as<uint32_t>());
+        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>());
     }
     launch_big_tables(st, bstart, big, nb, ntiles, tile_off, big_idx, totals, tmp);
     if ((s = last_launch()) != PSI_OK) return s;

@@ -66,7 +66,7 @@ void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 // Buckets are the 16 key bits [top, top + 16) just below the largest key's
 // leading bit.
 constexpr int BUCKET_MAX = 4096;
-constexpr int BUCKET_SMALL = 2048;  // lighter variant (half the LDS) when buckets are small
+constexpr int BUCKET_SMALL = 2048;  // lighter variant (half the LDS) for the common bucket sizes
 constexpr uint32_t BUCKET_COUNT = 1u << 16;
 // Histograms of two 8-bit key digits (rows at bits s0 and s1; hist [2][256],
 // zeroed).
@@ -74,11 +74,11 @@ void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_
 // bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
 void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
                           uint32_t nb);
-// Sorts every bucket of at most bmax (BUCKET_SMALL or BUCKET_MAX) pairs by
-// (key, id) in place; big[t] = 1 for the larger buckets, else 0. Decreasing
-// bucket starts latch ERR_SPIN.
+// Sorts every bucket of at most BUCKET_MAX pairs by (key, id) in place (the
+// ones of at most BUCKET_SMALL with a lighter variant); big[t] = 1 for the
+// larger buckets, else 0. Decreasing bucket starts latch ERR_SPIN.
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t bmax, uint32_t* big, uint32_t* err);
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err);
 // Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
 // bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
 // big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).

@@ -151,14 +151,50 @@ def _fetch(r):
     return (off - np.uint64(base)).astype(np.uint64), to_u32(res[1][base:int(off[-1])])
 
 
+class _PinnedRing:
+    """Pinned host staging area allocated once: payloads are copied into it
+    and uploaded from it asynchronously; space is reused once the upload that
+    read it has completed (events checked oldest first)."""
+
+    def __init__(self, nbytes: int):
+        import torch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        self.np = self.buf.numpy()
+        self.size = nbytes
+        self.head = 0
+        self.live = deque()  # (start, end, event) of uploads in flight
+
+    def _reclaim(self, block: bool):
+        while self.live and (block or self.live[0][2].query()):
+            self.live[0][2].synchronize()
+            self.live.popleft()
+            block = False
+
+    def take(self, n: int):
+        """Offset of n free bytes (n <= size), 256-aligned."""
+        n = (n + 255) & ~255
+        while True:
+            self._reclaim(False)
+            start = self.head if self.head + n <= self.size else 0
+            end = start + n
+            if all(e <= start or s >= end for s, e, _ in self.live):
+                self.head = end
+                return start
+            self._reclaim(True)
+
+    def done(self, start: int, n: int, event):
+        self.live.append((start, start + ((n + 255) & ~255), event))
+
+
 class BatchServer:
     """Continuous batching with HBM-budget admission (see module docstring)."""
 
-    def __init__(self, index: Index, budget_bytes: int = 32 << 30):
+    def __init__(self, index: Index, budget_bytes: int = 32 << 30, staging_bytes: int = 64 << 20):
         import torch
         self.ix = index
         self.budget = budget_bytes
         self.copy_stream = torch.cuda.Stream(device=index.device)
+        self.ring = _PinnedRing(staging_bytes)
 
     # payload upload on the copy stream; compute waits on the event
     def _stage(self, r):
@@ -166,12 +202,21 @@ class BatchServer:
         dev = self.ix.device
         arr = r.get("points", r.get("ids", r.get("queries", r.get("boxes"))))
         a = np.ascontiguousarray(arr)
-        host = torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).pin_memory()
+        a = a.view(np.int32) if a.dtype == np.uint32 else a
+        nb = a.nbytes
+        if nb == 0 or nb > self.ring.size:  # too large to stage: plain pinned copy
+            host = torch.from_numpy(a).pin_memory()
+            r["_host"] = host
+        else:
+            off = self.ring.take(nb)
+            self.ring.np[off:off + nb] = a.reshape(-1).view(np.uint8)
+            host = self.ring.buf[off:off + nb].view(torch.int32 if a.dtype == np.int32 else torch.int64)
         with torch.cuda.stream(self.copy_stream):
-            r["dev"] = host.to(dev, non_blocking=True)
+            r["dev"] = host.to(dev, non_blocking=True).reshape(a.shape)
             r["ready"] = torch.cuda.Event()
             r["ready"].record(self.copy_stream)
-        r["_host"] = host  # keep the pinned buffer alive until the copy is done
+        if 0 < nb <= self.ring.size:
+            self.ring.done(off, nb, r["ready"])
 
     def run(self, reqs, realtime: bool = True):
         import torch

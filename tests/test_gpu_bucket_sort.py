@@ -2,10 +2,12 @@
 LDS sort; oversized buckets through segmented global passes) against the
 oracle, and against the eight-pass LSD build, bit-exact.
 
-Bucket = the top 16 bits of the curve key (62 bits in 2D, 63 in 3D). For a
-2D Morton key those are bits 23..30 of both coordinates, which lets the tests place exact
-bucket sizes (4096 = the largest a workgroup sorts in LDS, 4097 = the
-smallest that takes the segmented passes).
+Bucket = the 16 key bits below the largest key's leading bit. With 2D Morton
+keys and a largest coordinate of 2^31 - 1 those are bits 23..30 of both
+coordinates, which lets the tests place exact bucket sizes: 2048 (the largest
+the light LDS variant sorts), 2049 (the smallest the wide variant takes), 4096
+(the largest the wide variant sorts) and 4097 (the smallest that takes the
+segmented global passes).
 """
 import sys
 
@@ -66,15 +68,22 @@ def test_two_level_uniform(psi, dim, curve, n):
 
 
 def test_bucket_size_boundaries(psi):
-    """Buckets of exactly 4096 (LDS) and 4097 (segmented) pairs, an empty
-    bucket between them, a bucket of 1 and a uniform remainder."""
+    """Buckets of exactly 2048, 2049, 4096 and 4097 pairs, an empty bucket
+    between them, a bucket of 1 and a uniform remainder (2D Morton: bucket
+    bit j is bit 23 + j // 2 of axis j % 2)."""
     say("two-level bucket boundaries")
-    r = synth.uniform(4096 + 4097 + 1 + 50_000, 2, 23, seed=3)  # low 23 bits of each coordinate
+    sizes = [(2048, (1, 0)), (2049, (0, 1)), (4096, (1, 1)), (4097, (2, 0)), (1, (0, 3))]
+    rest = 50_000
+    r = synth.uniform(sum(c for c, _ in sizes) + rest, 2, 23, seed=3)  # low 23 bits of each coordinate
     hi = np.zeros((len(r), 2), np.uint32)
-    hi[4096:8193, 0] = 1          # bucket 1 (x bit 23 -> key bit 46)
-    hi[8193, 1] = 3               # bucket morton(0, 3) = 10
-    hi[8194:, 0] = synth.uniform(50_000, 1, 8, seed=4)[:, 0]
-    hi[8194:, 1] = synth.uniform(50_000, 1, 8, seed=5)[:, 0] | 4  # never buckets 0 or 1
+    o = 0
+    for c, (hx, hy) in sizes:  # buckets 1, 2, 3, 4 and 10
+        hi[o:o + c, 0] = hx
+        hi[o:o + c, 1] = hy
+        o += c
+    hi[o:, 0] = synth.uniform(rest, 1, 8, seed=4)[:, 0]
+    hi[o:, 1] = synth.uniform(rest, 1, 8, seed=5)[:, 0] | 4  # bucket bit 5 set: never one of the above
+    hi[-1] = (255, 255)  # the largest coordinates: key bit length 62
     pts = (r | (hi << np.uint32(23))).astype(np.uint32)
     perm = np.argsort(synth.draws(synth.stream_key(9, synth.P_AUX), 0, len(pts)), kind="stable")
     check(psi, 2, 0, pts[perm])
