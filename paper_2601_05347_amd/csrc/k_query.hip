@@ -760,6 +760,27 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) 
     return x - v;
 }
 
+// Copies the ids of the leaves held by the lanes in `m` (lane x: count lc,
+// exclusive output position pos, slot) to out[o + pos ..], one leaf at a time
+// with the whole wave, so that every store is one contiguous run.
+template <int D>
+__device__ __forceinline__ void copy_leaf_ids(const TreeView& t, uint64_t m, uint32_t lc, uint32_t pos, uint32_t slot,
+                                              uint64_t o, uint64_t lim, uint32_t* __restrict__ out) {
+    const uint32_t lane = lane_id();
+    while (m) {
+        const int x = __builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t cx = (uint32_t)__builtin_amdgcn_readlane((int)lc, x);
+        const uint32_t px = (uint32_t)__builtin_amdgcn_readlane((int)pos, x);
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)slot, x);
+        const uint32_t* s = t.slots + (uint64_t)sx * (D + 1) * t.C + D * t.C;
+        for (uint32_t e = lane; e < cx; e += 64) {
+            const uint64_t dst = o + px + e;
+            if (dst < lim) out[dst] = s[e];
+        }
+    }
+}
+
 template <int D, bool REPORT>
 __global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
                                                     const uint32_t* __restrict__ order,
@@ -823,9 +844,7 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* 
                         const uint32_t lc = j < j1 ? lf.cnt : 0u;
                         uint32_t tot;
                         const uint32_t pos = wave_excl_scan(lc, &tot);
-                        const uint32_t* s = t.slots + (uint64_t)lf.slot * (D + 1) * C + D * C;
-                        for (uint32_t e = 0; e < lc; ++e)
-                            if (o + pos + e < lim) out[o + pos + e] = s[e];
+                        copy_leaf_ids<D>(t, ballot(lc != 0), lc, pos, lf.slot, o, lim, out);
                         o += tot;
                     }
                 }
@@ -837,11 +856,7 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* 
             const uint32_t lc = rel == 2 ? r.cnt : 0u;
             uint32_t tot;
             const uint32_t pos = wave_excl_scan(lc, &tot);
-            if (REPORT && lc) {
-                const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C + D * C;
-                for (uint32_t e = 0; e < lc; ++e)
-                    if (o + pos + e < lim) out[o + pos + e] = s[e];
-            }
+            if (REPORT) copy_leaf_ids<D>(t, ballot(lc != 0), lc, pos, r.slot, o, lim, out);
             if (REPORT) o += tot;
             else cnt += tot;
         }
