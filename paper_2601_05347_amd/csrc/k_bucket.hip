@@ -332,6 +332,98 @@ __global__ __launch_bounds__(256) void k_hist_keys2(const uint64_t* __restrict__
     }
 }
 
+// Counts for the two chunked bucket passes (bits [s0, s0 + 8) = d0 and
+// [s1, s1 + 8) = d1 of every key): cnt[0][x][d0] over the keys of input chunk
+// x (tiles T x / 8 .. T (x + 1) / 8), cnt[1][g][d1] over the keys whose d0
+// lies in [32 g, 32 g + 32) (the g-th group of the first pass's output).
+// Each workgroup reads one contiguous range, eight loads in flight per thread.
+__global__ __launch_bounds__(256) void k_hist_chunks(const uint64_t* __restrict__ keys, uint64_t n, uint32_t s0,
+                                                     uint32_t s1, uint64_t T, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t h[2][XCD_CHUNKS][RADIX];
+    for (int i = threadIdx.x; i < 2 * (int)XCD_CHUNKS * RADIX; i += blockDim.x) (&h[0][0][0])[i] = 0;
+    __syncthreads();
+    uint64_t bnd[XCD_CHUNKS];  // first tile of chunks 1 .. 7 (bnd[0] unused)
+#pragma unroll
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) bnd[x] = T * x / XCD_CHUNKS;
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b = (uint64_t)blockIdx.x * per, e = min<uint64_t>(b + per, n);
+    auto count = [&](uint64_t i, uint64_t k) {
+        const uint64_t t = i / SORT_TILE;
+        uint32_t x = 0;
+#pragma unroll
+        for (uint32_t y = 1; y < XCD_CHUNKS; ++y) x += t >= bnd[y] ? 1u : 0u;
+        const uint32_t d0 = (uint32_t)(k >> s0) & (RADIX - 1), d1 = (uint32_t)(k >> s1) & (RADIX - 1);
+        atomicAdd(&h[0][x][d0], 1u);
+        atomicAdd(&h[1][d0 >> 5][d1], 1u);
+    };
+    uint64_t i = b + threadIdx.x;
+    for (; i + 7 * blockDim.x < e; i += 8 * blockDim.x) {
+        uint64_t k[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) k[j] = keys[i + j * blockDim.x];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) count(i + j * blockDim.x, k[j]);
+    }
+    for (; i < e; i += blockDim.x) count(i, keys[i]);
+    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * (int)XCD_CHUNKS * RADIX; x += blockDim.x) {
+        const uint32_t v = (&h[0][0][0])[x];
+        if (v) atomicAdd(&cnt[x], v);
+    }
+}
+
+// From those counts (one workgroup of 256 threads): the digit offsets of
+// every chunk of both passes and the chunk tables (tb1 / tb2: first tile,
+// tiles, first position, end position; XCD_CHUNKS entries each).
+__global__ __launch_bounds__(256) void k_chunk_offsets(const uint32_t* __restrict__ cnt, uint64_t n, uint64_t T,
+                                                       uint32_t* __restrict__ off1, uint32_t* __restrict__ off2,
+                                                       uint32_t* __restrict__ tb1_first, uint32_t* __restrict__ tb1_nt,
+                                                       uint64_t* __restrict__ tb1_b, uint64_t* __restrict__ tb1_e,
+                                                       uint32_t* __restrict__ tb2_first, uint32_t* __restrict__ tb2_nt,
+                                                       uint64_t* __restrict__ tb2_b, uint64_t* __restrict__ tb2_e) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_g0[RADIX];
+    __shared__ uint32_t s_nt[XCD_CHUNKS];
+    const uint32_t d = threadIdx.x;
+    const uint32_t* c1 = cnt;
+    const uint32_t* c2 = cnt + XCD_CHUNKS * RADIX;
+    uint32_t t0 = 0, t1 = 0;
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) {
+        t0 += c1[x * RADIX + d];
+        t1 += c2[x * RADIX + d];
+    }
+    const uint32_t g0 = block_incl_scan256(t0, s_wsum) - t0;
+    const uint32_t g1 = block_incl_scan256(t1, s_wsum) - t1;
+    s_g0[d] = g0;
+    uint32_t r0 = g0, r1 = g1;
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) {
+        off1[x * RADIX + d] = r0;
+        r0 += c1[x * RADIX + d];
+        off2[x * RADIX + d] = r1;
+        r1 += c2[x * RADIX + d];
+    }
+    __syncthreads();
+    if (d < XCD_CHUNKS) {
+        const uint64_t fb = T * d / XCD_CHUNKS, fe = T * (d + 1) / XCD_CHUNKS;
+        tb1_first[d] = (uint32_t)fb;
+        tb1_nt[d] = (uint32_t)(fe - fb);
+        tb1_b[d] = min<uint64_t>(fb * SORT_TILE, n);
+        tb1_e[d] = min<uint64_t>(fe * SORT_TILE, n);
+        const uint64_t sb = s_g0[32 * d], se = d + 1 < XCD_CHUNKS ? s_g0[32 * (d + 1)] : n;
+        const uint32_t nt = (uint32_t)((se - sb + SORT_TILE - 1) / SORT_TILE);
+        s_nt[d] = nt;
+        tb2_nt[d] = nt;
+        tb2_b[d] = sb;
+        tb2_e[d] = se;
+    }
+    __syncthreads();
+    if (d < XCD_CHUNKS) {
+        uint32_t f = 0;
+        for (uint32_t x = 0; x < d; ++x) f += s_nt[x];
+        tb2_first[d] = f;
+    }
+}
+
 __global__ void k_big_count(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ big, uint32_t nb,
                             uint32_t* __restrict__ ntiles) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -414,6 +506,20 @@ void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_
     unsigned g = blocks_for(n, 256 * 8);
     if (g > 2048) g = 2048;
     hipLaunchKernelGGL(k_hist_keys2, dim3(g), dim3(256), 0, st, keys, n, s0, s1, hist);
+}
+
+void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 64);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_hist_chunks, dim3(g), dim3(256), 0, st, keys, n, s0, s1, (n + SORT_TILE - 1) / SORT_TILE, cnt);
+}
+
+void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint32_t* off1, uint32_t* off2,
+                          ChunkTables tb1, ChunkTables tb2) {
+    hipLaunchKernelGGL(k_chunk_offsets, dim3(1), dim3(256), 0, st, cnt, n, (n + SORT_TILE - 1) / SORT_TILE, off1, off2,
+                       tb1.first_tile, tb1.ntiles, tb1.pos_begin, tb1.pos_end, tb2.first_tile, tb2.ntiles,
+                       tb2.pos_begin, tb2.pos_end);
 }
 
 void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist) {

@@ -120,12 +120,18 @@ __global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restric
 // SEG: the pairs form consecutive segments sorted independently (one index
 // each); tiles never straddle a segment, digit offsets are per segment and
 // the look-back stops at the segment's first tile.
-template <bool IMPLICIT_ID, bool DIGIT_ID, bool SEG>
+// XCD: the pass is cut into XCD_CHUNKS chunks of consecutive tiles, chunk x
+// sorted by the workgroups with blockIdx.x % XCD_CHUNKS == x (which the
+// hardware places on one XCD), with its own digit offsets (dig_off row x) and
+// a look-back that stops at the chunk's first tile. Consecutive tiles then
+// write their digit runs through the same L2, which merges the partial lines.
+// Correctness does not depend on the placement.
+template <bool IMPLICIT_ID, bool DIGIT_ID, bool SEG, bool XCD = false>
 __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin, uint32_t id_base,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n, uint32_t shift,
     const uint32_t* __restrict__ dig_off, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
-    uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg) {
+    uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg, XcdChunks xc) {
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_id[SORT_TILE];
     // running counts per wave, then each wave's first LDS slot per digit; once
@@ -133,22 +139,39 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     // digit's first slot (52 KB in all: three tiles fit in one CU's LDS)
     __shared__ uint32_t s_wcnt[WAVES][RADIX];
     __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_nth;
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const uint32_t lane = lane_id();
     for (int i = tid; i < WAVES * RADIX; i += SORT_WG) (&s_wcnt[0][0])[i] = 0;
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    if (tid == 0) {
+        if (XCD) {
+            const uint32_t x = blockIdx.x % XCD_CHUNKS;
+            const uint32_t t = atomicAdd(tile_ctr + x, 1u);
+            s_nth = t;
+            s_tile = t < xc.ntiles[x] ? xc.first_tile[x] + t : ~0u;
+        } else {
+            s_tile = atomicAdd(tile_ctr, 1u);
+        }
+    }
     __syncthreads();
     const uint32_t tile = s_tile;
-    if (tile >= gridDim.x) {  // counter not reset: never index past the status array
+    if (XCD) {
+        if (tile == ~0u) return;  // every tile of this chunk is taken
+    } else if (tile >= gridDim.x) {  // counter not reset: never index past the status array
         if (tid == 0) atomicOr(err, ERR_SPIN);
         return;
     }
     uint64_t tbeg, tend;
     uint32_t first = 0;
-    if (SEG) {
+    if (XCD) {
+        const uint32_t x = blockIdx.x % XCD_CHUNKS;
+        tbeg = xc.pos_begin[x] + (uint64_t)s_nth * SORT_TILE;
+        tend = min<uint64_t>(tbeg + SORT_TILE, xc.pos_end[x]);
+        first = xc.first_tile[x];
+        dig_off += (uint64_t)x * RADIX;
+    } else if (SEG) {
         const uint32_t sgi = sg.tile_seg[tile];
         tbeg = sg.tile_beg[tile];
         tend = min<uint64_t>(tbeg + SORT_TILE, sg.seg_end[sgi]);
@@ -390,7 +413,7 @@ void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, cons
     if (seg) sg = *seg;
     const unsigned g = seg ? (unsigned)seg_tiles : blocks_for(n, SORT_TILE);
     if (g == 0) return;
-#define PSI_OS(I, Dg, S) hipLaunchKernelGGL((k_onesweep<I, Dg, S>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg)
+#define PSI_OS(I, Dg, S) hipLaunchKernelGGL((k_onesweep<I, Dg, S>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg, XcdChunks{})
     if (seg) {
         if (implicit_ids) PSI_OS(true, false, true);
         else PSI_OS(false, false, true);
@@ -399,6 +422,20 @@ void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, cons
     else if (digit_from_id) PSI_OS(false, true, false);
     else PSI_OS(false, false, false);
 #undef PSI_OS
+}
+
+void launch_onesweep_xcd(hipStream_t st, bool implicit_ids, const uint64_t* kin, const uint32_t* iin,
+                         uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n, uint32_t shift,
+                         const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, uint32_t* err,
+                         const XcdChunks& xc, uint32_t max_chunk_tiles) {
+    if (n == 0 || max_chunk_tiles == 0) return;
+    const unsigned g = XCD_CHUNKS * max_chunk_tiles;
+    if (implicit_ids)
+        hipLaunchKernelGGL((k_onesweep<true, false, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base,
+                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc);
+    else
+        hipLaunchKernelGGL((k_onesweep<false, false, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base,
+                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc);
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {

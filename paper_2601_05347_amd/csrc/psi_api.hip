@@ -110,7 +110,9 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     hipStream_t st = ix->st;
     psi_status s;
     if ((s = S.off.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
-    if ((s = S.ctr.ensure(MAX_PASSES * 4)) != PSI_OK) return s;
+    // tile counters: [0, 8) first pass, [8, 16) second pass, [16, 22) big buckets
+    constexpr uint32_t CTR_WORDS = 2 * XCD_CHUNKS + 8;
+    if ((s = S.ctr.ensure(CTR_WORDS * 4)) != PSI_OK) return s;
     for (int b = 0; b < 2; ++b) {
         if ((s = S.k[b].ensure(n * 8)) != PSI_OK) return s;
         if ((s = S.i[b].ensure(n * 4)) != PSI_OK) return s;
@@ -141,23 +143,46 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     uint32_t* totals = big_idx + nb;  // 2
     uint32_t* tmp = totals + 2;
     if (top > 48) return PSI_E_INTERNAL;  // the low bits take at most six 8-bit passes
-    if ((s = ensure_status((n + SORT_TILE - 1) / SORT_TILE)) != PSI_OK) return s;
-    if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
-    launch_fill_u32(st, S.hist.as<uint32_t>(), 2 * RADIX, 0u);
+    // The two bucket passes, each cut into one chunk of consecutive tiles per
+    // XCD: per-chunk counts of both digits in one read of the keys, then
+    // per-chunk digit offsets and chunk tables (one readback: the tile counts
+    // of the second pass's chunks, whose sizes depend on the data).
+    const uint64_t T = (n + SORT_TILE - 1) / SORT_TILE;
+    if ((s = ensure_status(T + XCD_CHUNKS)) != PSI_OK) return s;
+    const uint64_t xt_words = 2 * XCD_CHUNKS * RADIX * 2 + XCD_CHUNKS * 4 + XCD_CHUNKS * 8 + 16;
+    if ((s = S.xt.ensure(xt_words * 4)) != PSI_OK) return s;
+    uint32_t* cnt = S.xt.as<uint32_t>();             // [2][8][256]
+    uint32_t* off1 = cnt + 2 * XCD_CHUNKS * RADIX;   // [8][256]
+    uint32_t* off2 = off1 + XCD_CHUNKS * RADIX;      // [8][256]
+    uint32_t* tw = off2 + XCD_CHUNKS * RADIX;        // first/ntiles of both passes
+    uint64_t* tq = reinterpret_cast<uint64_t*>(S.xt.as<char>() + ((reinterpret_cast<char*>(tw + 4 * XCD_CHUNKS) - S.xt.as<char>() + 7) & ~(uint64_t)7));
+    ChunkTables tb1{tw, tw + XCD_CHUNKS, tq, tq + XCD_CHUNKS};
+    ChunkTables tb2{tw + 2 * XCD_CHUNKS, tw + 3 * XCD_CHUNKS, tq + 2 * XCD_CHUNKS, tq + 3 * XCD_CHUNKS};
+    launch_fill_u32(st, cnt, 2 * XCD_CHUNKS * RADIX, 0u);
+    launch_fill_u32(st, S.ctr.as<uint32_t>(), CTR_WORDS, 0u);
     {
         ProfScope ps(ix, "hist", n * 8);
-        launch_hist_keys2(st, keys, n, top, top + 8, S.hist.as<uint32_t>());
+        launch_hist_chunks(st, keys, n, top, top + 8, cnt);
+        launch_chunk_offsets(st, cnt, n, off1, off2, tb1, tb2);
     }
-    launch_digit_offsets(st, 2, S.hist.as<uint32_t>(), S.off.as<uint32_t>());
-    launch_fill_u32(st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);
-    for (int p = 0; p < 2; ++p) {
-        const uint32_t shift = top + 8 * p;
-        // first pass: 8 B key read (ids implicit), 12 B written; second: 12 B each way
-        ProfScope ps(ix, p == 0 ? "radix_first" : "radix_pass", n * (p == 0 ? 20 : 24));
-        launch_onesweep(st, p == 0, false, p == 0 ? keys : S.k[0].as<uint64_t>(), p == 0 ? nullptr : S.i[0].as<uint32_t>(),
-                        id_base, S.k[p].as<uint64_t>(), S.i[p].as<uint32_t>(), n, shift,
-                        S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(), S.ctr.as<uint32_t>() + p,
-                        next_epoch(), ix->err.as<uint32_t>());
+    if ((s = last_launch()) != PSI_OK) return s;
+    if ((s = readback(ix, tb2.ntiles, XCD_CHUNKS * 4)) != PSI_OK) return s;
+    uint32_t max2 = 0;
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) max2 = std::max(max2, static_cast<const uint32_t*>(ix->pinned)[x]);
+    const XcdChunks xc1{tb1.first_tile, tb1.ntiles, tb1.pos_begin, tb1.pos_end};
+    const XcdChunks xc2{tb2.first_tile, tb2.ntiles, tb2.pos_begin, tb2.pos_end};
+    {
+        // 8 B key read (ids implicit), 12 B written
+        ProfScope ps(ix, "radix_first", n * 20);
+        launch_onesweep_xcd(st, true, keys, nullptr, id_base, S.k[0].as<uint64_t>(), S.i[0].as<uint32_t>(), n, top,
+                            off1, S.status.as<uint64_t>(), S.ctr.as<uint32_t>(), next_epoch(), ix->err.as<uint32_t>(),
+                            xc1, (uint32_t)((T + XCD_CHUNKS - 1) / XCD_CHUNKS));
+    }
+    {
+        ProfScope ps(ix, "radix_pass", n * 24);
+        launch_onesweep_xcd(st, false, S.k[0].as<uint64_t>(), S.i[0].as<uint32_t>(), 0, S.k[1].as<uint64_t>(),
+                            S.i[1].as<uint32_t>(), n, top + 8, off2, S.status.as<uint64_t>(),
+                            S.ctr.as<uint32_t>() + XCD_CHUNKS, next_epoch(), ix->err.as<uint32_t>(), xc2, max2);
     }
     uint64_t* K = S.k[1].as<uint64_t>();
     uint32_t* I = S.i[1].as<uint32_t>();
@@ -204,7 +229,7 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
         const int src = (p & 1) ? 0 : 1, dst = 1 - src;
         launch_onesweep(st, false, false, S.k[src].as<uint64_t>(), S.i[src].as<uint32_t>(), 0, S.k[dst].as<uint64_t>(),
                         S.i[dst].as<uint32_t>(), n, 8 * p, S.soff.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(),
-                        S.ctr.as<uint32_t>() + 2 + p, next_epoch(), ix->err.as<uint32_t>(), &sg, btiles);
+                        S.ctr.as<uint32_t>() + 2 * XCD_CHUNKS + p, next_epoch(), ix->err.as<uint32_t>(), &sg, btiles);
     }
     return last_launch();
 }

@@ -114,6 +114,7 @@ struct Sorter {
     Buf hist, off, ctr, status, k[2], i[2];
     Buf bk, bseg, shist, soff;  // two-level build sort: bucket tables, big-bucket segments
     Buf kmax;                   // largest key of a build (u64)
+    Buf xt;                     // chunked bucket passes: counts, digit offsets, chunk tables
     uint32_t epoch = 0;
     uint64_t status_words = 0;
 };

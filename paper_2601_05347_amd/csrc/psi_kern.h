@@ -53,10 +53,28 @@ struct SegTiles {
     const uint32_t* seg_end;
     uint32_t off_stride;
 };
+// A pass cut into XCD_CHUNKS chunks of consecutive tiles, one per XCD (the
+// workgroups with blockIdx % XCD_CHUNKS == x sort chunk x); device arrays of
+// XCD_CHUNKS entries. Tiles of chunk x: global tile ids first_tile[x] ..
+// first_tile[x] + ntiles[x] - 1 covering positions [pos_begin[x], pos_end[x]).
+constexpr uint32_t XCD_CHUNKS = 8;
+struct XcdChunks {
+    const uint32_t* first_tile;
+    const uint32_t* ntiles;
+    const uint64_t* pos_begin;
+    const uint64_t* pos_end;
+};
 void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
                      const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
                      uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
                      uint32_t epoch, uint32_t* err, const SegTiles* seg = nullptr, uint64_t seg_tiles = 0);
+// Chunked pass: dig_off is [XCD_CHUNKS][256] (chunk x's destination of digit
+// d); tile_ctr holds XCD_CHUNKS zeroed counters; max_chunk_tiles bounds
+// ntiles[x] (XCD_CHUNKS * max_chunk_tiles workgroups are launched).
+void launch_onesweep_xcd(hipStream_t st, bool implicit_ids, const uint64_t* kin, const uint32_t* iin,
+                         uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n, uint32_t shift,
+                         const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, uint32_t* err,
+                         const XcdChunks& xc, uint32_t max_chunk_tiles);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 
@@ -71,6 +89,19 @@ constexpr uint32_t BUCKET_COUNT = 1u << 16;
 // Histograms of two 8-bit key digits (rows at bits s0 and s1; hist [2][256],
 // zeroed).
 void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* hist);
+// Chunked bucket passes: cnt ([2][XCD_CHUNKS][256], zeroed) counts the first
+// digit per input chunk and the second digit per group of 32 first-digit
+// values; launch_chunk_offsets turns them into per-chunk digit offsets
+// (off1, off2: [XCD_CHUNKS][256]) and the chunk tables of both passes.
+struct ChunkTables {
+    uint32_t* first_tile;
+    uint32_t* ntiles;
+    uint64_t* pos_begin;
+    uint64_t* pos_end;
+};
+void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt);
+void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint32_t* off1, uint32_t* off2,
+                          ChunkTables tb1, ChunkTables tb2);
 // bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
 void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
                           uint32_t nb);
