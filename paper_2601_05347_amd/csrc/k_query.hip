@@ -259,63 +259,20 @@ struct SingleTree {
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
 };
 
-// kNN for a wave of queries taken together (k <= 16, queries in curve
-// order, so that a wave's 64 queries are neighbours in space). Each lane keeps
-// its own k best in registers; the wave walks the tree once for all of them:
-//  1. seed: the leaves spanning the wave's keys (the leaf holding the smallest
-//     key minus one to the leaf holding the largest plus one) are scanned by
-//     the whole wave: lanes load the leaf's points, every point is broadcast
-//     (readlane) and each lane scores it against its own query. A wave whose
-//     keys spread over more than KG_WIN leaves (sparse or unsorted batches)
-//     seeds every lane with the leaves around its own key instead;
-//  2. one depth-first walk in fixed child order: a node is entered if its box
-//     is within the current k-th distance of at least one lane's query
-//     (ballot), a leaf is scanned as in 1 by the lanes whose ball it meets
-//     and which did not scan it while seeding.
-// Exact: a lane skips a box only when its distance is strictly greater than
-// the lane's current k-th distance, which never grows.
-constexpr uint32_t KG_WIN = 32;
-
-// Every lane of the wave calls this with the same leaf; lanes with `mine`
-// score its points.
 template <int D, int K>
-__device__ __forceinline__ void group_scan_leaf(const TreeView& t, const NodeRec& r, bool mine, const uint32_t* q,
-                                                uint64_t (&bd)[K], uint32_t (&bi)[K]) {
-    const uint32_t lane = lane_id();
-    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.cnt);
-    const uint32_t* s = t.slots + (uint64_t)__builtin_amdgcn_readfirstlane((int)r.slot) * (D + 1) * t.C;
-    uint32_t px[D], pid = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) px[d] = lane < cnt ? s[d * t.C + lane] : 0u;
-    if (lane < cnt) pid = s[D * t.C + lane];
-    for (uint32_t u = 0; u < cnt; ++u) {
-        uint32_t p[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) p[d] = (uint32_t)__builtin_amdgcn_readlane((int)px[d], (int)u);
-        const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)pid, (int)u);
-        const uint64_t dd = pt_dist<D>(q, p);
-        if (mine && pair_less(dd, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, id);
-    }
-}
-
-template <int D, int K>
-__global__ __launch_bounds__(256) void k_knn_group(TreeView t, const uint32_t* __restrict__ qp,
-                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
-                                                   const uint32_t* __restrict__ order,
-                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
+__global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __restrict__ qp,
+                                                  const uint64_t* __restrict__ qkeys, uint64_t nq,
+                                                  const uint32_t* __restrict__ order,
+                                                  uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
     __syncthreads();
-    const uint32_t lane = lane_id();
-    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);  // the wave's first slot
-    if (base >= nq) return;  // whole waves leave together
-    const uint64_t tq = base + lane;
-    const bool act = tq < nq;
-    const uint64_t qi = act ? (order ? order[tq] : tq) : 0;
+    const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tq >= nq) return;
+    const uint64_t qi = order ? order[tq] : tq;
     uint32_t q[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) q[d] = act ? qp[qi * D + d] : 0u;
-    const uint64_t key = act ? qkeys[qi] : 0ull;
+    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
     uint64_t bd[K];
     uint32_t bi[K];
 #pragma unroll
@@ -323,73 +280,12 @@ __global__ __launch_bounds__(256) void k_knn_group(TreeView t, const uint32_t* _
         bd[j] = PAD_D2;
         bi[j] = PAD_ID;
     }
-    const uint32_t L = (uint32_t)t.L;
-    if (L > 0) {
-        const uint32_t last = (uint32_t)min<uint64_t>(63, nq - 1 - base);
-        // leaf holding a key: the last one whose pivot key is <= it
-        auto leaf_of_key = [&](uint64_t k) {
-            uint32_t lo = 0, hi = L;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (t.pkey[mid] <= k) lo = mid + 1;
-                else hi = mid;
-            }
-            return lo ? lo - 1 : 0u;
-        };
-        uint32_t j = 0;
-        if (lane == 0 || lane == last) j = leaf_of_key(key);
-        const uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)j, 0);
-        const uint32_t j1 = (uint32_t)__builtin_amdgcn_readlane((int)j, (int)last);
-        uint32_t ja, jb;  // this lane's seed leaves
-        if (j1 >= j0 && j1 - j0 + 3 <= KG_WIN) {
-            ja = j0 ? j0 - 1 : 0u;
-            jb = min(j1 + 1, L - 1);
-            for (uint32_t x = ja; x <= jb; ++x) group_scan_leaf<D, K>(t, t.leaf[x], act, q, bd, bi);
-        } else {
-            j = leaf_of_key(key);
-            ja = j ? j - 1 : 0u;
-            jb = min(j + 1, L - 1);
-            if (act)
-                for (uint32_t x = ja; x <= jb; ++x) scan_leaf<D, K>(t, t.leaf[x], q, bd, bi);
-        }
-        const uint32_t B = t.B, h = t.h;
-        uint32_t l = 0;
-        uint64_t i = 0;
-        for (;;) {
-            const NodeRec r = l == h ? t.leaf[i] : t.inner[s_lv[l].off + i];
-            const bool want = act && r.cnt && box_dist<D>(q, r) <= bd[K - 1];
-            bool descend = false;
-            if (ballot(want)) {
-                if (l == h) group_scan_leaf<D, K>(t, r, want && (i < ja || i > jb), q, bd, bi);
-                else descend = true;
-            }
-            if (descend) {
-                ++l;
-                i *= B;
-                continue;
-            }
-            bool done = false;
-            for (;;) {
-                if (l == 0) {
-                    done = true;
-                    break;
-                }
-                if ((i + 1) % B != 0 && i + 1 < s_lv[l].n) {
-                    ++i;
-                    break;
-                }
-                --l;
-                i /= B;
-            }
-            if (done) break;
-        }
-    }
-    if (act) {
+    const SingleTree tr{t, s_lv};
+    knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            out_ids[qi * K + j] = bi[j];
-            out_d2[qi * K + j] = bd[j];
-        }
+    for (int j = 0; j < K; ++j) {
+        out_ids[qi * K + j] = bi[j];
+        out_d2[qi * K + j] = bd[j];
     }
 }
 
@@ -919,7 +815,7 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, c
 #define PSI_KL(D, K)                                                                                             \
     do {                                                                                                         \
         if (variant == 1) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, order, ids, d2); \
-        else hipLaunchKernelGGL((k_knn_group<D, K>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, ids, d2); \
+        else hipLaunchKernelGGL((k_knn_seed<D, K>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, ids, d2); \
     } while (0)
 #define PSI_KL_ALL(D)                                                                                    \
     switch (k) {                                                                                         \

@@ -41,13 +41,14 @@ psi_status readback(psi_index ix, const void* dev, size_t bytes) {
 // Passes: optionally the four id bytes first (so equal keys end up in id
 // order whatever the input order), then the eight key bytes.
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
-                      bool id_digits, bool hist_ready, int* which, const char* fam) {
+                      bool id_digits, bool hist_ready, int* which, const char* fam, uint32_t key_shift0,
+                      int key_passes) {
     Sorter& S = ix->sorter;
     PassList pl{};
     pl.n = 0;
     if (id_digits)
         for (int b = 0; b < 4; ++b) { pl.src[pl.n] = 1; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
-    for (int b = 0; b < 8; ++b) { pl.src[pl.n] = 0; pl.shift[pl.n] = (uint8_t)(8 * b); ++pl.n; }
+    for (int b = 0; b < key_passes; ++b) { pl.src[pl.n] = 0; pl.shift[pl.n] = (uint8_t)(key_shift0 + 8 * b); ++pl.n; }
     psi_status s;
     hipStream_t st = ix->st;
     const bool cap = capturing(st);
@@ -355,8 +356,12 @@ static psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n,
         else launch_encode(ix->st, ix->D, ix->curve, d_items, n, keys, ix->err.as<uint32_t>());
     }
     if (!sort) return last_launch();
+    // Only locality matters here (results never depend on the order): the top
+    // 24 bits of the curve key (cells of about 2^-24 of the domain) in three
+    // passes instead of all 64 bits in eight.
     int w = 0;
-    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order")) != PSI_OK) return s;
+    const uint32_t kb = ix->D == 2 ? 62u : 63u;
+    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order", kb - 24, 3)) != PSI_OK) return s;
     *order = ix->sorter.i[w].as<uint32_t>();
     return last_launch();
 }

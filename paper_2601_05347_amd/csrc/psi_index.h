@@ -199,7 +199,8 @@ bool capturing(hipStream_t st);
 // there is refused (PSI_E_STATE); a call outside capture sizes it first.
 psi_status ensure_q(Buf& b, size_t need, hipStream_t st);
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
-                      bool id_digits, bool hist_ready, int* which, const char* fam);
+                      bool id_digits, bool hist_ready, int* which, const char* fam, uint32_t key_shift0 = 0,
+                      int key_passes = 8);
 psi_status build_nodes(psi_index ix);
 psi_status readback(psi_index ix, const void* dev, size_t bytes);  // into ix->pinned, waits
 
