@@ -93,32 +93,47 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
     }
 }
 
-template <int D>
+// One node level: parent i = union of children [B i, B i + B) one level down.
+// G = B rounded up to a power of two lanes per parent: every lane loads one
+// child record (a parent's children are one contiguous run of records) and the
+// group reduces counts and boxes by xor shuffles.
+template <int D, int G>
 __global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ child, uint64_t n_child,
                                                     NodeRec* __restrict__ parent, uint64_t n_parent, uint32_t B) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_parent) return;
-    NodeRec r;
-    for (int d = 0; d < 3; ++d) {
-        r.lo[d] = 0xFFFFFFFFu;
-        r.hi[d] = 0u;
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const uint32_t g = threadIdx.x % G;
+    const uint64_t c = i * B + g;
+    const bool on = i < n_parent && g < B && c < n_child;  // all lanes stay for the shuffles
+    NodeRec x = {};
+    if (on) x = child[c];
+    uint32_t cnt = on ? x.cnt : 0u;
+    uint32_t lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = cnt ? x.lo[d] : 0xFFFFFFFFu;
+        hi[d] = cnt ? x.hi[d] : 0u;
     }
-    uint32_t cnt = 0;
-    const uint64_t c0 = i * B, c1 = min<uint64_t>(c0 + B, n_child);
-    for (uint64_t c = c0; c < c1; ++c) {
-        const NodeRec x = child[c];
-        if (x.cnt == 0) continue;
-        cnt += x.cnt;
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) {
+        const int src = (int)(lane_id() ^ (uint32_t)o);
+        cnt += shfl_u32(cnt, src);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            r.lo[d] = min(r.lo[d], x.lo[d]);
-            r.hi[d] = max(r.hi[d], x.hi[d]);
+            lo[d] = min(lo[d], shfl_u32(lo[d], src));
+            hi[d] = max(hi[d], shfl_u32(hi[d], src));
         }
     }
-    r.cnt = cnt;
-    r.slot = 0xFFFFFFFFu;
-    if (D == 2 && cnt) { r.lo[2] = 0; r.hi[2] = 0; }
-    parent[i] = r;
+    if (g == 0 && i < n_parent) {
+        NodeRec r;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r.lo[d] = d < D ? lo[d % D] : (cnt ? 0u : 0xFFFFFFFFu);
+            r.hi[d] = d < D ? hi[d % D] : 0u;
+        }
+        r.cnt = cnt;
+        r.slot = 0xFFFFFFFFu;
+        parent[i] = r;
+    }
 }
 
 __global__ void k_leaf_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t* __restrict__ cnt) {
@@ -252,10 +267,24 @@ void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk,
 void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
                        uint64_t n_parent, uint32_t B) {
     if (n_parent == 0) return;
-    if (dim == 2)
-        hipLaunchKernelGGL(k_node_level<2>, dim3(blocks_for(n_parent, 256)), dim3(256), 0, st, child, n_child, parent, n_parent, B);
-    else
-        hipLaunchKernelGGL(k_node_level<3>, dim3(blocks_for(n_parent, 256)), dim3(256), 0, st, child, n_child, parent, n_parent, B);
+    uint32_t G = 2;
+    while (G < B) G <<= 1;
+    const unsigned g = blocks_for(n_parent * G, 256);
+#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, child, n_child, parent, n_parent, B)
+#define PSI_NL2(GG)              \
+    do {                         \
+        if (dim == 2) PSI_NL(2, GG); \
+        else PSI_NL(3, GG);      \
+    } while (0)
+    switch (G) {
+        case 2: PSI_NL2(2); break;
+        case 4: PSI_NL2(4); break;
+        case 8: PSI_NL2(8); break;
+        case 16: PSI_NL2(16); break;
+        default: PSI_NL2(32); break;
+    }
+#undef PSI_NL2
+#undef PSI_NL
 }
 
 void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp) {
