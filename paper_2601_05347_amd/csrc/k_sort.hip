@@ -297,10 +297,16 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n, uint32_t base) {
 // ---- exclusive scan (reduce, scan of tile sums, downsweep) ----
 constexpr int SCAN_WG = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_WG * SCAN_IPT;
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
-                                                     uint32_t* __restrict__ sums) {
+// Exclusive scans of up to four arrays at once: blockIdx.y picks the array,
+// so one set of three launches serves them all. Tile sums of array y live at
+// sums[y * stride ...].
+__global__ __launch_bounds__(256) void k_scan_reduce(ScanSet s, uint32_t* __restrict__ sums, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
+    const int y = blockIdx.y;
+    const uint32_t* __restrict__ in = s.in[y];
+    const uint64_t n = s.n[y];
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
     uint32_t v = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_IPT; ++i) {
@@ -313,15 +319,18 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int i = 0; i < WAVES; ++i) t += s_w[i];
-        sums[blockIdx.x] = t;
+        sums[y * stride + blockIdx.x] = t;
     }
 }
 
-// Single block: exclusive scan of m tile sums in place; total -> *total.
-__global__ __launch_bounds__(256) void k_scan_sums(uint32_t* __restrict__ sums, uint64_t m,
-                                                   uint32_t* __restrict__ total) {
+// One block per array: exclusive scan of its tile sums in place; the array's
+// total goes to s.total[y] when that is set.
+__global__ __launch_bounds__(256) void k_scan_sums(ScanSet s, uint32_t* __restrict__ sums_all, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
     __shared__ uint32_t s_tot;
+    const int y = blockIdx.x;
+    uint32_t* __restrict__ sums = sums_all + y * stride;
+    const uint64_t m = (s.n[y] + SCAN_TILE - 1) / SCAN_TILE;
     uint32_t carry = 0;
     for (uint64_t b = 0; b < m; b += SCAN_WG) {
         const uint64_t p = b + threadIdx.x;
@@ -333,23 +342,27 @@ __global__ __launch_bounds__(256) void k_scan_sums(uint32_t* __restrict__ sums, 
         carry += s_tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0 && total) *total = carry;
+    if (threadIdx.x == 0 && s.total[y]) *s.total[y] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, uint64_t n,
-                                                   const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_down(ScanSet s, const uint32_t* __restrict__ sums, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
+    const int y = blockIdx.y;
+    const uint32_t* __restrict__ in = s.in[y];
+    uint32_t* __restrict__ out = s.out[y];
+    const uint64_t n = s.n[y];
+    if ((uint64_t)blockIdx.x * SCAN_TILE >= n) return;
     // blocked layout: thread t owns items [t*IPT, t*IPT+IPT) of the tile
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_IPT;
     uint32_t v[SCAN_IPT];
-    uint32_t s = 0;
+    uint32_t t = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_IPT; ++i) {
         v[i] = base + i < n ? in[base + i] : 0u;
-        s += v[i];
+        t += v[i];
     }
-    const uint32_t inc = block_incl_scan256(s, s_w);
-    uint32_t run = sums[blockIdx.x] + inc - s;
+    const uint32_t inc = block_incl_scan256(t, s_w);
+    uint32_t run = sums[y * stride + blockIdx.x] + inc - t;
 #pragma unroll
     for (int i = 0; i < SCAN_IPT; ++i) {
         if (base + i < n) out[base + i] = run;
@@ -447,16 +460,31 @@ void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base) {
 
 uint64_t scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
+void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp) {
+    ScanSet z = s;
+    uint64_t tiles = 0, stride = 0;
+    for (int y = k; y < SCAN_MULTI; ++y) z.in[y] = nullptr, z.out[y] = nullptr, z.total[y] = nullptr, z.n[y] = 0;
+    for (int y = 0; y < k; ++y) {
+        tiles = std::max<uint64_t>(tiles, (z.n[y] + SCAN_TILE - 1) / SCAN_TILE);
+        stride = std::max<uint64_t>(stride, scan_tmp_words(z.n[y]));
+    }
+    if (tiles) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles, k), dim3(SCAN_WG), 0, st, z, tmp, stride);
+    hipLaunchKernelGGL(k_scan_sums, dim3(k), dim3(SCAN_WG), 0, st, z, tmp, stride);
+    if (tiles) hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles, k), dim3(SCAN_WG), 0, st, z, tmp, stride);
+}
+
 void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
                      uint32_t* tmp) {
     if (n == 0) {
         if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, (uint64_t)1, 0u);
         return;
     }
-    const uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_WG), 0, st, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_WG), 0, st, tmp, tiles, total);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(SCAN_WG), 0, st, in, n, tmp, out);
+    ScanSet s{};
+    s.in[0] = in;
+    s.out[0] = out;
+    s.total[0] = total;
+    s.n[0] = n;
+    launch_scan_multi(st, s, 1, tmp);
 }
 
 }  // namespace psi

@@ -781,10 +781,11 @@ void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi,
     launch_scan_u32(st, start, gidx, L, ctr + 6, tmp);
     hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, L, grp_first);
     hipLaunchKernelGGL(k_del_gplan, dim3(g), dim3(256), 0, st, grp_first, ctr, L, cum, phi, gpieces, gchunks, galloc, gfree, gchanged);
-    launch_scan_u32(st, gpieces, gpos, L, ctr + 2, tmp);
-    launch_scan_u32(st, galloc, alloc_off, L, ctr + 3, tmp);
-    launch_scan_u32(st, gchunks, chunk_off, L, ctr + 4, tmp);
-    launch_scan_u32(st, gfree, free_off, L, ctr + 5, tmp);
+    ScanSet sc{{gpieces, galloc, gchunks, gfree},
+               {gpos, alloc_off, chunk_off, free_off},
+               {ctr + 2, ctr + 3, ctr + 4, ctr + 5},
+               {L, L, L, L}};
+    launch_scan_multi(st, sc, 4, tmp);
 }
 void upd_del_gcopy(hipStream_t st, const uint32_t* grp_first, const uint32_t* ctr, uint64_t L,
                    const uint32_t* gchanged, const uint32_t* gpos, const NodeRec* src, const uint64_t* spk,

@@ -127,6 +127,17 @@ void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles,
 uint64_t scan_tmp_words(uint64_t n);
 void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
                      uint32_t* tmp);
+// Up to SCAN_MULTI independent scans (in[y] -> out[y], n[y] items, total[y]
+// may be null) in one set of launches; tmp needs SCAN_MULTI times
+// scan_tmp_words of the largest n[y]. An empty array gets total 0.
+constexpr int SCAN_MULTI = 4;
+struct ScanSet {
+    const uint32_t* in[SCAN_MULTI];
+    uint32_t* out[SCAN_MULTI];
+    uint32_t* total[SCAN_MULTI];
+    uint64_t n[SCAN_MULTI];
+};
+void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp);
 
 // ------------------------------------------------------------------ build
 // Fill leaves from sorted pairs: leaf j takes sorted positions

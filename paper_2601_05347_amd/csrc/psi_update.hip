@@ -111,7 +111,7 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
         a.free_off = c.take<uint32_t>(m + 1);
         a.pieces = c.take<uint32_t>(L);
         a.newpos = c.take<uint32_t>(L + 1);
-        a.tmp = c.take<uint32_t>(scan_tmp_words(std::max<uint64_t>(m, L)) + 4);
+        a.tmp = c.take<uint32_t>(SCAN_MULTI * scan_tmp_words(std::max<uint64_t>(m, L)) + 4);
         return a;
     };
     carve(cv);
@@ -126,10 +126,11 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     launch_fill_u32(st, a.pieces, L, 1u);
     upd_ins_plan(st, a.run_leaf, a.run_beg, a.ctr, m, ix->leaf[cur].as<NodeRec>(), ix->C, ix->phi, a.pieces,
                  a.rpieces, a.rchunks, a.rsplit);
-    launch_scan_u32(st, a.pieces, a.newpos, L, a.ctr + 2, a.tmp);
-    launch_scan_u32(st, a.rpieces, a.piece_off, m, a.ctr + 3, a.tmp);
-    launch_scan_u32(st, a.rchunks, a.chunk_off, m, a.ctr + 4, a.tmp);
-    launch_scan_u32(st, a.rsplit, a.free_off, m, a.ctr + 5, a.tmp);
+    ScanSet sc{{a.pieces, a.rpieces, a.rchunks, a.rsplit},
+               {a.newpos, a.piece_off, a.chunk_off, a.free_off},
+               {a.ctr + 2, a.ctr + 3, a.ctr + 4, a.ctr + 5},
+               {L, m, m, m}};
+    launch_scan_multi(st, sc, 4, a.tmp);
     if ((s = launched()) != PSI_OK) return s;
     if ((s = readback(ix, a.ctr, 8 * 4)) != PSI_OK) return s;
     uint32_t c[8];
@@ -217,7 +218,7 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
         a.chunk_off = c.take<uint32_t>(L + 1);
         a.alloc_off = c.take<uint32_t>(L + 1);
         a.free_off = c.take<uint32_t>(L + 1);
-        a.tmp = c.take<uint32_t>(scan_tmp_words(std::max<uint64_t>(m, L)) + 4);
+        a.tmp = c.take<uint32_t>(SCAN_MULTI * scan_tmp_words(std::max<uint64_t>(m, L)) + 4);
         return a;
     };
     Carver cv;
