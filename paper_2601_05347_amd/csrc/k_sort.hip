@@ -93,6 +93,58 @@ __global__ __launch_bounds__(256) void k_encode_hist(const uint32_t* __restrict_
     }
 }
 
+// Keys plus the largest key (as k_encode_hist) and, in the same read of the
+// points, the per-chunk counts of the two bucket digits at bits s0 and s1
+// that the chunked bucket passes take (the counts k_hist_chunks makes from
+// the keys). Each workgroup encodes one contiguous range, so its first-digit
+// counts fall in one or two chunks.
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_encode_chunks(const uint32_t* __restrict__ pts, uint64_t n,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ err,
+                                                       uint64_t* __restrict__ kmax, uint32_t s0, uint32_t s1,
+                                                       uint64_t T, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t h[2][XCD_CHUNKS][RADIX];
+    __shared__ uint64_t s_max[WAVES];
+    __shared__ uint16_t s_h[CURVE ? HilbertFsm<D>::ENTRIES : 1];
+    for (int i = threadIdx.x; i < 2 * (int)XCD_CHUNKS * RADIX; i += blockDim.x) (&h[0][0][0])[i] = 0;
+    if (CURVE) stage_hilbert<D>(s_h, true);
+    __syncthreads();
+    uint64_t bnd[XCD_CHUNKS];  // first tile of chunks 1 .. 7 (bnd[0] unused)
+#pragma unroll
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) bnd[x] = T * x / XCD_CHUNKS;
+    const uint64_t per = ((n + gridDim.x - 1) / gridDim.x + 255) & ~(uint64_t)255;
+    const uint64_t b = (uint64_t)blockIdx.x * per, e = min<uint64_t>(b + per, n);
+    uint64_t km = 0;
+    bool bad = false;
+    for (uint64_t i = b + threadIdx.x; i < e; i += 256) {
+        uint32_t p[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = pts[i * D + d];
+        bad |= !coord_ok<D>(p);
+        const uint64_t k = CURVE ? hilbert_key_fsm<D>(p, s_h) : morton_key<D>(p);
+        keys[i] = k;
+        km = max(km, k);
+        const uint64_t t = i / SORT_TILE;
+        uint32_t x = 0;
+#pragma unroll
+        for (uint32_t y = 1; y < XCD_CHUNKS; ++y) x += t >= bnd[y] ? 1u : 0u;
+        const uint32_t d0 = (uint32_t)(k >> s0) & (RADIX - 1), d1 = (uint32_t)(k >> s1) & (RADIX - 1);
+        atomicAdd(&h[0][x][d0], 1u);
+        atomicAdd(&h[1][d0 >> 5][d1], 1u);
+    }
+    if (bad) atomicOr(err, ERR_RANGE);
+    for (int o = 32; o >= 1; o >>= 1) km = max(km, shfl_u64(km, (int)(lane_id() ^ o)));
+    if (lane_id() == 0) s_max[threadIdx.x >> 6] = km;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(kmax),
+                  (unsigned long long)max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3])));
+    for (int x = threadIdx.x; x < 2 * (int)XCD_CHUNKS * RADIX; x += blockDim.x) {
+        const uint32_t v = (&h[0][0][0])[x];
+        if (v) atomicAdd(&cnt[x], v);
+    }
+}
+
 template <int D, int CURVE>
 __global__ __launch_bounds__(256) void k_encode_boxes(const uint32_t* __restrict__ boxes, uint64_t n,
                                                       uint64_t* __restrict__ keys) {
@@ -402,6 +454,19 @@ void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint
     if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_hist<2, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
     if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_hist<3, 0, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
     if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_hist<3, 1, false>), dim3(g), dim3(256), 0, st, pts, n, keys, nullptr, err, 0, 0u, kmax);
+}
+
+void launch_encode_chunks(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                          uint32_t* err, uint64_t* kmax, uint32_t s0, uint32_t* cnt) {
+    if (n == 0) return;
+    unsigned g = blocks_for(n, 256 * 4);
+    if (g > 8192) g = 8192;
+    const uint64_t T = (n + SORT_TILE - 1) / SORT_TILE;
+    const uint32_t s1 = s0 + 8;
+    if (dim == 2 && curve == 0) hipLaunchKernelGGL((k_encode_chunks<2, 0>), dim3(g), dim3(256), 0, st, pts, n, keys, err, kmax, s0, s1, T, cnt);
+    if (dim == 2 && curve == 1) hipLaunchKernelGGL((k_encode_chunks<2, 1>), dim3(g), dim3(256), 0, st, pts, n, keys, err, kmax, s0, s1, T, cnt);
+    if (dim == 3 && curve == 0) hipLaunchKernelGGL((k_encode_chunks<3, 0>), dim3(g), dim3(256), 0, st, pts, n, keys, err, kmax, s0, s1, T, cnt);
+    if (dim == 3 && curve == 1) hipLaunchKernelGGL((k_encode_chunks<3, 1>), dim3(g), dim3(256), 0, st, pts, n, keys, err, kmax, s0, s1, T, cnt);
 }
 
 void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* boxes, uint64_t n, uint64_t* keys) {

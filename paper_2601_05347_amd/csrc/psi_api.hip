@@ -106,7 +106,14 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
 // readback (the big-bucket totals); not for graph capture.
 constexpr uint64_t BUCKET_MIN_N = 1ull << 24;
 
-psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uint64_t n, uint32_t top, int* which) {
+// Counts, digit offsets and chunk tables of the two bucket passes, in one
+// buffer: cnt [2][XCD_CHUNKS][256] first.
+constexpr uint64_t XT_WORDS = 2 * XCD_CHUNKS * RADIX * 2 + XCD_CHUNKS * 4 + XCD_CHUNKS * 8 + 16;
+
+// counted: the chunk counts for these bucket bits are already in the buffer
+// (made while encoding).
+psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uint64_t n, uint32_t top, bool counted,
+                       int* which) {
     Sorter& S = ix->sorter;
     hipStream_t st = ix->st;
     psi_status s;
@@ -150,8 +157,7 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     // of the second pass's chunks, whose sizes depend on the data).
     const uint64_t T = (n + SORT_TILE - 1) / SORT_TILE;
     if ((s = ensure_status(T + XCD_CHUNKS)) != PSI_OK) return s;
-    const uint64_t xt_words = 2 * XCD_CHUNKS * RADIX * 2 + XCD_CHUNKS * 4 + XCD_CHUNKS * 8 + 16;
-    if ((s = S.xt.ensure(xt_words * 4)) != PSI_OK) return s;
+    if ((s = S.xt.ensure(XT_WORDS * 4)) != PSI_OK) return s;
     uint32_t* cnt = S.xt.as<uint32_t>();             // [2][8][256]
     uint32_t* off1 = cnt + 2 * XCD_CHUNKS * RADIX;   // [8][256]
     uint32_t* off2 = off1 + XCD_CHUNKS * RADIX;      // [8][256]
@@ -159,11 +165,13 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     uint64_t* tq = reinterpret_cast<uint64_t*>(S.xt.as<char>() + ((reinterpret_cast<char*>(tw + 4 * XCD_CHUNKS) - S.xt.as<char>() + 7) & ~(uint64_t)7));
     ChunkTables tb1{tw, tw + XCD_CHUNKS, tq, tq + XCD_CHUNKS};
     ChunkTables tb2{tw + 2 * XCD_CHUNKS, tw + 3 * XCD_CHUNKS, tq + 2 * XCD_CHUNKS, tq + 3 * XCD_CHUNKS};
-    launch_fill_u32(st, cnt, 2 * XCD_CHUNKS * RADIX, 0u);
     launch_fill_u32(st, S.ctr.as<uint32_t>(), CTR_WORDS, 0u);
     {
-        ProfScope ps(ix, "hist", n * 8);
-        launch_hist_chunks(st, keys, n, top, top + 8, cnt);
+        ProfScope ps(ix, "hist", counted ? 0 : n * 8);
+        if (!counted) {
+            launch_fill_u32(st, cnt, 2 * XCD_CHUNKS * RADIX, 0u);
+            launch_hist_chunks(st, keys, n, top, top + 8, cnt);
+        }
         launch_chunk_offsets(st, cnt, n, off1, off2, tb1, tb2);
     }
     if ((s = last_launch()) != PSI_OK) return s;
@@ -297,18 +305,28 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
                            !capturing(ix->st);
     int w = 0;
     if (two_level) {
-        // keys and their maximum; the bucket bits are the 16 below its leading bit
+        // keys and their maximum; the bucket bits are the 16 below its leading
+        // bit. The bucket digits are counted while encoding for a guess of
+        // those bits (the previous build's, else the top of the key width);
+        // a wrong guess costs one more read of the keys, never a different
+        // result.
         if ((s = S.kmax.ensure(8)) != PSI_OK) return s;
+        if ((s = S.xt.ensure(XT_WORDS * 4)) != PSI_OK) return s;
+        const uint32_t guess = ix->bucket_top <= 48 ? ix->bucket_top : (ix->D == 2 ? 62u : 63u) - 16u;
         launch_fill_u32(ix->st, S.kmax.as<uint32_t>(), 2, 0u);
+        launch_fill_u32(ix->st, S.xt.as<uint32_t>(), 2 * XCD_CHUNKS * RADIX, 0u);
         {
             ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
-            launch_encode(ix->st, ix->D, ix->curve, d_pts, n, keys, ix->err.as<uint32_t>(), S.kmax.as<uint64_t>());
+            launch_encode_chunks(ix->st, ix->D, ix->curve, d_pts, n, keys, ix->err.as<uint32_t>(),
+                                 S.kmax.as<uint64_t>(), guess, S.xt.as<uint32_t>());
         }
         if ((s = last_launch()) != PSI_OK) return s;
         if ((s = readback(ix, S.kmax.p, 8)) != PSI_OK) return s;
         const uint64_t km = *static_cast<const uint64_t*>(ix->pinned);
         const uint32_t bits = km ? 64u - (uint32_t)__builtin_clzll(km) : 0u;
-        s = bucket_sort(ix, keys, id_base, n, bits > 16 ? bits - 16 : 0u, &w);
+        const uint32_t top = bits > 16 ? bits - 16 : 0u;
+        ix->bucket_top = top;
+        s = bucket_sort(ix, keys, id_base, n, top, top == guess, &w);
     } else {
         {
             ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));

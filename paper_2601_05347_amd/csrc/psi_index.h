@@ -156,6 +156,8 @@ struct psi_index_s {
     uint32_t h = 0;
     std::vector<psi::LevelInfo> lv;
 
+    uint32_t bucket_top = ~0u;  // bucket bits of the last two-level build sort
+
     psi::Buf err;      // device u32 error bits
     void* pinned = nullptr;  // host readback area (4 KiB)
     psi::Sorter sorter;

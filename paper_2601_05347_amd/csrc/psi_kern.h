@@ -38,6 +38,11 @@ void launch_encode_boxes(hipStream_t st, int dim, int curve, const uint32_t* box
 // largest key.
 void launch_encode(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
                    uint32_t* err, uint64_t* kmax = nullptr);
+// Curve keys, the largest key (kmax, zeroed by the caller) and the
+// per-chunk bucket digit counts for bucket bits [s0, s0 + 16), as
+// launch_hist_chunks makes them (cnt [2][XCD_CHUNKS][256], zeroed).
+void launch_encode_chunks(hipStream_t st, int dim, int curve, const uint32_t* pts, uint64_t n, uint64_t* keys,
+                          uint32_t* err, uint64_t* kmax, uint32_t s0, uint32_t* cnt);
 // Exclusive scan of every pass's 256 counts: off[p][d].
 void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint32_t* off);
 // One stable scatter pass (decoupled look-back over tiles taken in launch

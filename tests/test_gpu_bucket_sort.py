@@ -159,3 +159,19 @@ def test_skewed_buckets(psi):
     pts = np.concatenate([rest, net32, crowd, same]).astype(np.uint32)
     pts = pts[np.argsort(synth.draws(synth.stream_key(44, synth.P_AUX), 0, len(pts)), kind="stable")]
     check(psi, 2, 0, pts)
+
+
+def test_rebuild_with_other_key_widths(psi):
+    """One index rebuilt over data of different key widths: the bucket digits
+    counted while encoding are for the previous build's bucket bits, right or
+    wrong for the new data; the result is the same either way."""
+    say("two-level rebuilds across key widths")
+    ix = psi.Index(3, 1, 32, 8, flags=psi.FLAG_SORT_BUCKETS)
+    for bits, seed in ((21, 51), (21, 52), (9, 53), (9, 54), (17, 55), (21, 56), (4, 57)):
+        pts = synth.uniform(70_001, 3, bits, seed=seed)
+        ix.build(pts)
+        ref = oracle.RefIndex(3, 1, 32, 8)
+        ref.build(pts)
+        for a, b in zip(ix.export(), ref.dump()):
+            np.testing.assert_array_equal(a, b)
+    ix.sync()
