@@ -50,17 +50,39 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
         __syncthreads();
     }
     const uint32_t t = threadIdx.x & 31;
-    const uint64_t nhw = ((uint64_t)gridDim.x * blockDim.x) >> 5;
-    for (uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; j < L; j += nhw) {
-        const uint64_t b = j * n / L, e = (j + 1) * n / L;
-        const uint32_t cnt = (uint32_t)(e - b);
+    const int hb = (int)(threadIdx.x & 32);  // first lane of this half-wave
+    const uint64_t step = ((uint64_t)gridDim.x * blockDim.x) >> 5;
+    const uint64_t j_first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    // Lanes 0 and 1 of a half-wave follow the first sorted positions of leaves
+    // j and j + 1, floor(j n / L), as quotient q and remainder r; a stride of
+    // `step` leaves adds floor(step n / L) and step n mod L, so the loop
+    // divides nothing. Past the last leaf the position is clamped to n;
+    // positions fit in 32 bits since ids do.
+    const uint64_t sq = step * n / L;
+    const uint32_t sr = (uint32_t)(step * n % L), Lw = (uint32_t)L;  // L < 2^32
+    uint64_t q = 0;
+    uint32_t r = 0;
+    if (t <= 1) {
+        const uint64_t x = (j_first + t) * n;
+        q = x / L;
+        r = (uint32_t)(x % L);
+    }
+    for (uint64_t j = j_first; j < L; j += step) {
+        const uint32_t bt = (uint32_t)min<uint64_t>(q, n);
+        q += sq;
+        r += sr;  // below 2 L: a wrap past 2^32 shows as r < sr
+        if (r >= Lw || r < sr) {
+            r -= Lw;
+            ++q;
+        }
+        const uint32_t b = shfl_u32(bt, hb), cnt = shfl_u32(bt, hb + 1) - b;
         const bool on = t < cnt;
         uint32_t p[D];
         uint64_t key = 0;
         uint32_t id = 0;
         if (on) {
-            key = sk[b + t];
-            id = sid[b + t];
+            key = sk[(uint64_t)b + t];
+            id = sid[(uint64_t)b + t];
             if (CURVE) hilbert_point_fsm<D>(key, p, s_h);
             else morton_point<D>(key, p);
             uint32_t* s = slots + j * (uint64_t)(D + 1) * C;
@@ -71,22 +93,22 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
 #pragma unroll
             for (int d = 0; d < D; ++d) p[d] = 0;
         }
-        NodeRec r;
+        NodeRec rec;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            r.lo[d] = 0xFFFFFFFFu;
-            r.hi[d] = 0u;
+            rec.lo[d] = 0xFFFFFFFFu;
+            rec.hi[d] = 0u;
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            r.lo[d] = half_min(on ? p[d] : 0xFFFFFFFFu);
-            r.hi[d] = half_max(on ? p[d] : 0u);
+            rec.lo[d] = half_min(on ? p[d] : 0xFFFFFFFFu);
+            rec.hi[d] = half_max(on ? p[d] : 0u);
         }
         if (t == 0) {
-            r.cnt = cnt;
-            r.slot = (uint32_t)j;
-            if (D == 2) { r.lo[2] = 0; r.hi[2] = 0; }
-            leafrec[j] = r;
+            rec.cnt = cnt;
+            rec.slot = (uint32_t)j;
+            if (D == 2) { rec.lo[2] = 0; rec.hi[2] = 0; }
+            leafrec[j] = rec;
             piv_key[j] = key;
             piv_id[j] = id;
         }

@@ -84,15 +84,18 @@ __global__ __launch_bounds__(256) void k_build_leaves_seg(uint32_t num, uint64_t
     const uint32_t s = owner_of(leaf_off, num, g);
     const uint32_t n = meta[s].n, L = meta[s].L, base = meta[s].pt_base;
     const uint64_t j = g - leaf_off[s];
-    const uint64_t b = j * n / L, e = (j + 1) * n / L;
-    const uint32_t cnt = (uint32_t)(e - b);
+    // one division per lane: lane 0 of the half-wave takes the leaf's first
+    // position, lane 1 the next leaf's (below 2^32: n is)
+    const uint32_t bt = (uint32_t)((j + (t & 1)) * n / L);
+    const int hb = (int)(threadIdx.x & 32);
+    const uint32_t b = shfl_u32(bt, hb), cnt = shfl_u32(bt, hb + 1) - b;
     const bool on = t < cnt;
     uint32_t p[D];
     uint64_t key = 0;
     uint32_t id = 0;
     if (on) {
-        key = sk[base + b + t];
-        id = sid[base + b + t] - base;  // local id
+        key = sk[(uint64_t)base + b + t];
+        id = sid[(uint64_t)base + b + t] - base;  // local id
         sfc_point<D, CURVE>(key, p);
         uint32_t* sl = slots + g * (uint64_t)(D + 1) * C;
 #pragma unroll
