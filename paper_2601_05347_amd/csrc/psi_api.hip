@@ -76,6 +76,9 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
     launch_fill_u32(ix->st, S.ctr.as<uint32_t>(), MAX_PASSES, 0u);
     const uint64_t* ksrc = kin;
     const uint32_t* isrc = iin;
+    // one timing scope for all passes: an event pair per pass would space the
+    // short passes of a small batch apart
+    ProfScope ps(ix, fam, n * 24 * pl.n);
     for (int p = 0; p < pl.n; ++p) {
         const int dst = p & 1;
         if (++S.epoch >= (1u << 30)) {
@@ -84,13 +87,10 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
         }
         // a graph replays the epoch it was captured with: clear the words first
         if (cap) launch_fill_u32(ix->st, S.status.as<uint32_t>(), tiles * RADIX * 2, 0u);
-        {
-            ProfScope ps(ix, fam, n * 24);
-            launch_onesweep(ix->st, p == 0 && iin == nullptr, pl.src[p] == 1, ksrc, isrc, id_base,
-                            S.k[dst].as<uint64_t>(), S.i[dst].as<uint32_t>(), n, pl.shift[p],
-                            S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(),
-                            S.ctr.as<uint32_t>() + p, S.epoch, ix->err.as<uint32_t>());
-        }
+        launch_onesweep(ix->st, p == 0 && iin == nullptr, pl.src[p] == 1, ksrc, isrc, id_base,
+                        S.k[dst].as<uint64_t>(), S.i[dst].as<uint32_t>(), n, pl.shift[p],
+                        S.off.as<uint32_t>() + p * RADIX, S.status.as<uint64_t>(), S.ctr.as<uint32_t>() + p,
+                        S.epoch, ix->err.as<uint32_t>());
         ksrc = S.k[dst].as<uint64_t>();
         isrc = S.i[dst].as<uint32_t>();
     }

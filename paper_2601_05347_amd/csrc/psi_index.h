@@ -81,8 +81,10 @@ struct Prof {
             pool.pop_back();
             return e;
         }
+        // timing only: no system-scope fence (no cache writeback between the
+        // kernels the events bracket)
         hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
+        (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         return e;
     }
     void resolve() {
