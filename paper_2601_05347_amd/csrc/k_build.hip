@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_export_sorted(TreeView t, const uint64_
 #pragma unroll
             for (int d = 0; d < D; ++d) p[d] = s[d * t.C + e];
             id = s[D * t.C + e];
-            key = sfc_key<D, CURVE>(p);
+            key = sfc_key_tab<D, CURVE>(p);
         }
         // rank against every entry of the leaf
         uint32_t rank = 0;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_export_sorted(TreeView t, const uint64_
 #pragma unroll
                 for (int d = 0; d < D; ++d) q[d] = s[d * t.C + f];
                 fid = s[D * t.C + f];
-                fkey = sfc_key<D, CURVE>(q);
+                fkey = sfc_key_tab<D, CURVE>(q);
             }
             const uint32_t lim = min(64u, r.cnt - f0);
             for (uint32_t x = 0; x < lim; ++x) {

@@ -2,6 +2,7 @@
 // segmented encode, one segmented radix sort (a segment per index), one
 // leaf fill and one launch per tree height for the node levels of all
 // indexes at once.
+#include "psi_hilbert.h"
 #include "psi_kern.h"
 
 namespace psi {
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(256) void k_encode_hist_seg(const uint32_t* __restr
 #pragma unroll
         for (int d = 0; d < D; ++d) p[d] = pts[i * D + d];
         bad |= !coord_ok<D>(p);
-        const uint64_t k = sfc_key<D, CURVE>(p);
+        const uint64_t k = sfc_key_tab<D, CURVE>(p);
         keys[i] = k;
 #pragma unroll
         for (int b = 0; b < 8; ++b) atomicAdd(&h[b][(k >> (8 * b)) & 255u], 1u);
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(256) void k_build_leaves_seg(uint32_t num, uint64_t
     if (on) {
         key = sk[(uint64_t)base + b + t];
         id = sid[(uint64_t)base + b + t] - base;  // local id
-        sfc_point<D, CURVE>(key, p);
+        sfc_point_tab<D, CURVE>(key, p);
         uint32_t* sl = slots + g * (uint64_t)(D + 1) * C;
 #pragma unroll
         for (int d = 0; d < D; ++d) sl[d * C + t] = p[d];

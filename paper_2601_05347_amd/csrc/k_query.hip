@@ -11,6 +11,7 @@
 // Exactness: a subtree is skipped only when its box distance is strictly
 // greater than the k-th distance, so an equal-distance point with a smaller
 // id can still enter the result.
+#include "psi_hilbert.h"
 #include "psi_kern.h"
 
 namespace psi {
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(256) void k_multi_knn(TreeView tv, const IdxMeta* _
                 bi[j] = PAD_ID;
             }
             const MultiTree tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
-            knn_seeded<D, K>(tr, tv, q, sfc_key<D, CURVE>(q), bd, bi);
+            knn_seeded<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 out_ids[qi * K + j] = bi[j];

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_encode_boxes(const uint32_t* __restrict
         v = min(v, D == 2 ? 0x7FFFFFFFu : 0x1FFFFFu);
         c[d] = v;
     }
-    keys[i] = sfc_key<D, CURVE>(c);
+    keys[i] = sfc_key_tab<D, CURVE>(c);
 }
 
 __global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restrict__ hist,

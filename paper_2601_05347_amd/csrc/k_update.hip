@@ -18,6 +18,7 @@
 //   ctr[0] valid batch entries, [1] runs, [2] new leaf count, [3] slots to
 //   allocate, [4] output chunks, [5] slots freed, [6] groups, [7] 1 + index
 //   of the last full-enough leaf.
+#include "psi_hilbert.h"
 #include "psi_kern.h"
 #include "psi_update.h"
 
@@ -155,7 +156,7 @@ __global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __
     uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
     for (uint32_t e = beg; e < end; ++e) {
         uint32_t p[D];
-        sfc_point<D, CURVE>(bk[e], p);
+        sfc_point_tab<D, CURVE>(bk[e], p);
         const uint32_t o = rec.cnt + (e - beg);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
 #pragma unroll
         for (int d = 0; d < D; ++d) p[d] = s[d * C + tid];
         id = s[D * C + tid];
-        key = sfc_key<D, CURVE>(p);
+        key = sfc_key_tab<D, CURVE>(p);
         s_uk[tid] = key;
         s_ui[tid] = id;
     }
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
     } else {
         key = bk[beg + kb];
         id = bi[beg + kb];
-        sfc_point<D, CURVE>(key, p);
+        sfc_point_tab<D, CURVE>(key, p);
     }
     const uint32_t pc = (uint32_t)(((k + 1) * P - 1) / t);
     const uint32_t p0 = (uint32_t)((uint64_t)pc * t / P), p1 = (uint32_t)((uint64_t)(pc + 1) * t / P);
@@ -374,14 +375,20 @@ __global__ void k_del_kill(const uint32_t* __restrict__ ci, const uint32_t* __re
 // compacted in place, keeping their order; the box is recomputed exactly.
 constexpr uint32_t DEL_G = 16;
 constexpr int DEL_Q = 4;
-__device__ __forceinline__ uint32_t grp_min(uint32_t v) {
-    for (int o = DEL_G / 2; o >= 1; o >>= 1) v = min(v, shfl_u32(v, (int)(lane_id() ^ o)));
-    return v;
+// Group reductions on the VALU's cross-lane paths (a group is one 16-lane
+// row): two quad swaps, then the half-row and row mirrors. Every lane of the
+// row must be active.
+template <bool MIN>
+__device__ __forceinline__ uint32_t grp_reduce(uint32_t v) {
+    static_assert(DEL_G == 16, "a group is one DPP row");
+    auto op = [](uint32_t a, uint32_t b) { return MIN ? min(a, b) : max(a, b); };
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1, 0, 3, 2]
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2, 3, 0, 1]
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    return op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
 }
-__device__ __forceinline__ uint32_t grp_max(uint32_t v) {
-    for (int o = DEL_G / 2; o >= 1; o >>= 1) v = max(v, shfl_u32(v, (int)(lane_id() ^ o)));
-    return v;
-}
+__device__ __forceinline__ uint32_t grp_min(uint32_t v) { return grp_reduce<true>(v); }
+__device__ __forceinline__ uint32_t grp_max(uint32_t v) { return grp_reduce<false>(v); }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__ ci,
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(256) void k_sort_leaves(const uint32_t* __restrict_
 #pragma unroll
         for (int d = 0; d < D; ++d) p[d] = s[d * C + lane];
         id = s[D * C + lane];
-        key = sfc_key<D, CURVE>(p);
+        key = sfc_key_tab<D, CURVE>(p);
     }
     uint32_t rank = 0;
     for (uint32_t x = 0; x < rec.cnt; ++x) {
@@ -657,7 +664,7 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
     o[D * C + off] = id;
     if (off == 0) {
         const uint32_t q = (uint32_t)qq;
-        dpk[q] = sfc_key<D, CURVE>(p);
+        dpk[q] = sfc_key_tab<D, CURVE>(p);
         dpi[q] = id;
         NodeRec nr;
         for (int d = 0; d < 3; ++d) {

@@ -178,4 +178,16 @@ template <int D> __device__ __forceinline__ void hilbert_point_fsm(uint64_t k, u
     morton_point<D>(m, p);
 }
 
+// Curve keys and points through the tables read straight from constant
+// memory (for kernels that code a few keys per thread and do not stage the
+// tables); Morton keys need no table.
+template <int D, int CURVE> __device__ __forceinline__ uint64_t sfc_key_tab(const uint32_t* p) {
+    if constexpr (CURVE == 0) return morton_key<D>(p);
+    else return hilbert_key_fsm<D>(p, hilbert_fsm<D>().enc);
+}
+template <int D, int CURVE> __device__ __forceinline__ void sfc_point_tab(uint64_t k, uint32_t* p) {
+    if constexpr (CURVE == 0) morton_point<D>(k, p);
+    else hilbert_point_fsm<D>(k, p, hilbert_fsm<D>().dec);
+}
+
 }  // namespace psi
