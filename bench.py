@@ -385,7 +385,8 @@ def main():
     value = upd_pts / (upd_ms / 1e3) / 1e6 if upd_ms > 0 else 0.0
 
     # dominant kernel family and its roofline
-    fams = ["radix_first", "radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes", "hist",
+    fams = ["radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide", "radix_big", "encode_hist",
+            "leaf_fill", "nodes", "hist",
             "radix_update", "radix_order", "order", "knn", "range_count", "range_report", "update"]
     prof = {f: ix.prof_get(f) for f in fams}
     # the dominant streaming kernel of the build & update path

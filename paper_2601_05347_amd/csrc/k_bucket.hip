@@ -482,9 +482,9 @@ void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint
 }
 
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t* big, uint32_t* err) {
-    hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
-    hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err, bool wide) {
+    if (wide) hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+    else hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
 }
 
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,

@@ -195,10 +195,19 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     }
     uint64_t* K = S.k[1].as<uint64_t>();
     uint32_t* I = S.i[1].as<uint32_t>();
+    // timing scopes: the light variant alone (it sorts all but the rare
+    // buckets of more than BUCKET_SMALL pairs, whose bytes it is charged)
+    {
+        ProfScope ps(ix, "bucket_starts", (uint64_t)nb * 8);
+        launch_bucket_starts(st, K, n, top, bstart, nb);
+    }
     {
         ProfScope ps(ix, "local_sort", n * 24);
-        launch_bucket_starts(st, K, n, top, bstart, nb);
-        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>());
+        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>(), false);
+    }
+    {
+        ProfScope ps(ix, "local_sort_wide", 0);
+        launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>(), true);
     }
     launch_big_tables(st, bstart, big, nb, ntiles, tile_off, big_idx, totals, tmp);
     if ((s = last_launch()) != PSI_OK) return s;

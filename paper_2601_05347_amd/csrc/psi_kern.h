@@ -110,11 +110,12 @@ void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint3
 // bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
 void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
                           uint32_t nb);
-// Sorts every bucket of at most BUCKET_MAX pairs by (key, id) in place (the
-// ones of at most BUCKET_SMALL with a lighter variant); big[t] = 1 for the
-// larger buckets, else 0. Decreasing bucket starts latch ERR_SPIN.
+// Sorts buckets by (key, id) in place, in two launches: wide = false takes
+// every bucket of at most BUCKET_SMALL pairs and sets big[t] = 1 for the
+// larger ones (else 0); wide = true then takes those of at most BUCKET_MAX
+// and clears their flag. Decreasing bucket starts latch ERR_SPIN.
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t* big, uint32_t* err);
+                       uint32_t lo_bits, uint32_t* big, uint32_t* err, bool wide);
 // Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
 // bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
 // big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).
