@@ -41,6 +41,9 @@ WORKLOADS = {
     "serve": dict(dim=3, bits=21, n=50_000_000, m=0, nq=0, k=10, nb=0),
     # 4096 independent 2D SPaC-Z indexes (sizes log-uniform 1e3..1e6), kNN k = 8
     "multi": dict(dim=2, bits=30, n=0, m=0, nq=0, k=8, nb=0),
+    # incremental workload: 3D, 1e8 points inserted into an empty index in n/b
+    # batches, then deleted in n/b batches; 1e7 10-NN queries at the halfway points
+    "incr": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=0),
 }
 
 
@@ -54,7 +57,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d-1e8", choices=sorted(WORKLOADS))
-    ap.add_argument("--dist", default="uniform", choices=["uniform", "varden"])
+    ap.add_argument("--dist", default="uniform", choices=["uniform", "varden", "sweepline"])
     ap.add_argument("--curve", default="hilbert", choices=["hilbert", "morton"])
     ap.add_argument("--leaf", type=int, default=32)
     ap.add_argument("--fanout", type=int, default=8)
@@ -67,6 +70,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests per stream")
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
+    ap.add_argument("--batch-frac", default="0.1,0.01,0.001,0.0001", help="incr: batch sizes as fractions of n")
     return ap.parse_args()
 
 
@@ -175,6 +179,125 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_incr(args):
+    """The paper's incremental workload (Sec. 5.1): build from empty by n/b
+    batch insertions, empty by n/b batch deletions (ids in insertion order),
+    10-NN queries in and out of distribution after half of each, beside the
+    same queries on static builds of the same points. Every batch call is
+    timed; the queries are not part of the update totals."""
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+    cfg = WORKLOADS["incr"]
+    dim, bits, k = cfg["dim"], cfg["bits"], args.k or cfg["k"]
+    n = args.n or cfg["n"]
+    nq = cfg["nq"] if n >= 10_000_000 else max(1000, n // 10)
+    curve = psi.HILBERT if args.curve == "hilbert" else psi.MORTON
+    dist = args.dist
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t = time.perf_counter()
+    data = synth.points(dist, n, dim, bits, args.seed)
+    ind = synth.points("uniform" if dist == "sweepline" else dist, nq, dim, bits, args.seed + 3, synth.P_QUERY)
+    ood = synth.points("uniform" if dist == "varden" else "varden", nq, dim, bits, args.seed + 4, synth.P_QUERY)
+    log(f"incr: {n} {dist} points, 2 x {nq} queries generated in {time.perf_counter() - t:.1f} s")
+    d_data = torch.from_numpy(data.view(np.int32)).to(dev)
+    d_q = {"ind": torch.from_numpy(ind.view(np.int32)).to(dev), "ood": torch.from_numpy(ood.view(np.int32)).to(dev)}
+    d_ids = torch.arange(n, dtype=torch.int32, device=dev)
+    half = n // 2
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def queries(ix):
+        out, ms = {}, {}
+        for name, q in d_q.items():
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
+            a = ev()
+            psi.psi_knn(ix._h, q, nq, k, ids, d2)
+            b = ev()
+            b.synchronize()
+            out[name], ms[name] = (ids, d2), round(a.elapsed_time(b), 3)
+        return out, ms
+
+    # static references: the first half (ids 0 .. n/2 - 1) and the second half
+    # (built alone its ids are 0 .. n/2 - 1: the incremental ids minus n/2)
+    st1 = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
+    psi.psi_build(st1._h, d_data[:half], half)
+    ref1, ms1 = queries(st1)
+    del st1
+    st2 = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
+    psi.psi_build(st2._h, d_data[half:], n - half)
+    ref2, ms2 = queries(st2)
+    del st2
+    runs = {}
+    for frac in [float(x) for x in args.batch_frac.split(",")]:
+        s = max(1, int(round(n * frac)))
+        nbat = n // s
+        ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
+        psi.psi_build(ix._h, d_data[:0], 0)
+        torch.cuda.synchronize()
+        ins_ms = del_ms = 0.0
+        same = True
+        a = ev()
+        for i in range(nbat):
+            psi.psi_batch_insert(ix._h, d_data[i * s:(i + 1) * s], s, None)
+            if i == nbat // 2 - 1:
+                b = ev()
+                b.synchronize()
+                ins_ms += a.elapsed_time(b)
+                got, q_ins = queries(ix)
+                if (i + 1) * s == half:
+                    for name in got:
+                        same &= bool(torch.equal(got[name][1], ref1[name][1]) and torch.equal(got[name][0], ref1[name][0]))
+                a = ev()
+        b = ev()
+        b.synchronize()
+        ins_ms += a.elapsed_time(b)
+        a = ev()
+        for i in range(nbat):
+            psi.psi_batch_delete(ix._h, d_ids[i * s:(i + 1) * s], s, None)
+            if i == nbat // 2 - 1:
+                b = ev()
+                b.synchronize()
+                del_ms += a.elapsed_time(b)
+                got, q_del = queries(ix)
+                if (i + 1) * s == half and nbat * s == n:
+                    for name in got:
+                        gi, gd = got[name]
+                        ri, rd = ref2[name]
+                        same &= bool(torch.equal(gd, rd) and torch.equal(gi, torch.where(ri >= 0, ri + half, ri)))
+                a = ev()
+        b = ev()
+        b.synchronize()
+        del_ms += a.elapsed_time(b)
+        ix.sync()
+        left = ix.size()
+        del ix
+        runs[f"b={frac}"] = {"batch": s, "batches": nbat, "insert_ms": round(ins_ms, 3), "delete_ms": round(del_ms, 3),
+                             "insert_mpts_s": round(nbat * s / ins_ms / 1e3, 1),
+                             "delete_mpts_s": round(nbat * s / del_ms / 1e3, 1),
+                             "knn_ms_after_half_inserts": q_ins, "knn_ms_after_half_deletes": q_del,
+                             "left_after_deletes": left, "results_identical_to_static": same}
+        log(f"incr b={frac}: {nbat} x {s}: insert {ins_ms:.1f} ms, delete {del_ms:.1f} ms, "
+            f"kNN after half {q_ins} / {q_del} ms, identical {same}")
+    small = runs[min(runs, key=lambda r: runs[r]["batch"])]
+    tot = small["insert_ms"] + small["delete_ms"]
+    out = {"metric": "incremental build & empty by n/b batches: Mpoints/s (smallest b)",
+           "value": round(2 * small["batches"] * small["batch"] / tot / 1e3, 2), "unit": "Mpoints/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": round(tot, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+           "config": {"workload": f"incremental: {dim}D {dist} {args.curve}", "n": n, "queries": nq, "k": k,
+                      "leaf_size": args.leaf, "fanout": args.fanout},
+           "static_knn_ms": {"first_half": ms1, "second_half": ms2}, "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def bench_multi(args):
     """Batched small indexes: one segmented build + one persistent kNN launch
     vs per-index builds and launches (and those launches replayed as a graph)."""
@@ -277,6 +400,8 @@ def main():
         return bench_serve(args)
     if args.workload == "multi":
         return bench_multi(args)
+    if args.workload == "incr":
+        return bench_incr(args)
     import numpy as np
     import torch
 

@@ -354,6 +354,7 @@ constexpr int SCAN_WG = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_WG * SCAN_IPT;
 // sums[y * stride ...].
 __global__ __launch_bounds__(256) void k_scan_reduce(ScanSet s, uint32_t* __restrict__ sums, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
+    if (s.gate && *s.gate == 0) return;
     const int y = blockIdx.y;
     const uint32_t* __restrict__ in = s.in[y];
     const uint64_t n = s.n[y];
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(ScanSet s, uint32_t* __rest
 __global__ __launch_bounds__(256) void k_scan_sums(ScanSet s, uint32_t* __restrict__ sums_all, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
     __shared__ uint32_t s_tot;
+    if (s.gate && *s.gate == 0) return;
     const int y = blockIdx.x;
     uint32_t* __restrict__ sums = sums_all + y * stride;
     const uint64_t m = (s.n[y] + SCAN_TILE - 1) / SCAN_TILE;
@@ -399,6 +401,7 @@ __global__ __launch_bounds__(256) void k_scan_sums(ScanSet s, uint32_t* __restri
 
 __global__ __launch_bounds__(256) void k_scan_down(ScanSet s, const uint32_t* __restrict__ sums, uint64_t stride) {
     __shared__ uint32_t s_w[WAVES];
+    if (s.gate && *s.gate == 0) return;
     const int y = blockIdx.y;
     const uint32_t* __restrict__ in = s.in[y];
     uint32_t* __restrict__ out = s.out[y];
@@ -539,12 +542,13 @@ void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp) {
 }
 
 void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
-                     uint32_t* tmp) {
-    if (n == 0) {
+                     uint32_t* tmp, const uint32_t* gate) {
+    if (n == 0 && !gate) {
         if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, (uint64_t)1, 0u);
         return;
     }
     ScanSet s{};
+    s.gate = gate;
     s.in[0] = in;
     s.out[0] = out;
     s.total[0] = total;

@@ -17,7 +17,8 @@
 // Counters shared between kernels live in a small device array:
 //   ctr[0] valid batch entries, [1] runs, [2] new leaf count, [3] slots to
 //   allocate, [4] output chunks, [5] slots freed, [6] groups, [7] 1 + index
-//   of the last full-enough leaf.
+//   of the last full-enough leaf, [8] nonzero if a delete left a leaf below
+//   the minimum (only then do leaves regroup).
 #include "psi_hilbert.h"
 #include "psi_kern.h"
 #include "psi_update.h"
@@ -79,7 +80,7 @@ __device__ __forceinline__ uint32_t run_end(const uint32_t* run_beg, uint32_t r,
 
 __global__ void k_ins_plan(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
                            const uint32_t* __restrict__ ctr, uint64_t m, const NodeRec* __restrict__ leaf,
-                           uint32_t C, uint32_t phi, uint32_t* __restrict__ pieces, uint32_t* __restrict__ rpieces,
+                           uint32_t C, uint32_t phi, uint32_t* __restrict__ rpieces,
                            uint32_t* __restrict__ rchunks, uint32_t* __restrict__ rsplit) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
@@ -95,11 +96,20 @@ __global__ void k_ins_plan(const uint32_t* __restrict__ run_leaf, const uint32_t
         rpieces[r] = rchunks[r] = rsplit[r] = 0u;
     } else {
         const uint32_t P = (t + phi - 1) / phi;
-        pieces[j] = P;
         rpieces[r] = P;
         rchunks[r] = (t + UPD_CHUNK - 1) / UPD_CHUNK;
         rsplit[r] = 1u;
     }
+}
+
+// pieces[run_leaf[r]] = rpieces[r] for the runs whose leaf is re-cut (the
+// other leaves keep the one piece the caller filled in).
+__global__ void k_ins_pieces(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ ctr, uint64_t m,
+                             const uint32_t* __restrict__ rpieces, const uint32_t* __restrict__ rsplit,
+                             uint32_t* __restrict__ pieces) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m || r >= ctr[1] || !rsplit[r]) return;
+    pieces[run_leaf[r]] = rpieces[r];
 }
 
 __global__ void k_alloc(uint32_t* __restrict__ slot_alloc, uint64_t A, const uint32_t* __restrict__ free_stack,
@@ -143,7 +153,7 @@ __global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __
     if (r >= R || rsplit[r]) return;
     const uint32_t j = run_leaf[r];
     const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, (uint32_t)m);
-    const uint32_t q = newpos[j];
+    const uint32_t q = newpos ? newpos[j] : j;  // no re-cut leaves: the directory keeps its order
     if (q >= cap.leaves) {
         atomicOr(err, ERR_CAPACITY);
         return;
@@ -396,7 +406,10 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ run_beg,
                                                     const uint32_t* __restrict__ ctr, uint64_t m,
                                                     NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
-                                                    uint32_t C, uint32_t* __restrict__ err, Caps cap) {
+                                                    uint32_t C, uint32_t half, uint32_t* __restrict__ under,
+                                                    uint32_t* __restrict__ err, Caps cap) {
+    __shared__ uint32_t s_under;
+    if (threadIdx.x == 0) s_under = 0;
     const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / DEL_G;
     const uint32_t lane = lane_id();
     const uint32_t gl = lane % DEL_G, gbase = lane - gl;  // lane in the group, group's first lane
@@ -482,16 +495,24 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
     }
     if (act && gl == 0) {
         if (removed != end - beg) atomicOr(err, ERR_DELETE);
+        if (kept_before < half) s_under = 1u;
         rec.cnt = kept_before;
         leaf[j] = rec;
     }
+    // one device atomic per workgroup at most, none once the flag is up
+    // (every thread reaches the barrier: no thread returns early)
+    __syncthreads();
+    if (threadIdx.x == 0 && s_under && __hip_atomic_load(under, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        atomicOr(under, 1u);
 }
 
 // Per-leaf counts, and per workgroup 1 + its last leaf holding at least
 // `half` entries (0 if none) in bmax[blockIdx.x].
 __global__ __launch_bounds__(256) void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half,
-                                                    uint32_t* __restrict__ cnt, uint32_t* __restrict__ bmax) {
+                                                    const uint32_t* __restrict__ ctr, uint32_t* __restrict__ cnt,
+                                                    uint32_t* __restrict__ bmax) {
     __shared__ uint32_t s_w[4];
+    if (ctr[8] == 0) return;  // no leaf below the minimum: no regrouping
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t last = 0;
     if (j < L) {
@@ -509,6 +530,7 @@ __global__ __launch_bounds__(256) void k_del_counts(const NodeRec* __restrict__ 
 __global__ __launch_bounds__(256) void k_del_last_full(const uint32_t* __restrict__ bmax, uint64_t nb,
                                                        uint32_t* __restrict__ ctr) {
     __shared__ uint32_t s_w[4];
+    if (ctr[8] == 0) return;
     uint32_t m = 0;
     for (uint64_t i = threadIdx.x; i < nb; i += 256) m = max(m, bmax[i]);
     m = wave_max_u32(m);
@@ -520,13 +542,14 @@ __global__ __launch_bounds__(256) void k_del_last_full(const uint32_t* __restric
 __global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t L, uint32_t half,
                              const uint32_t* __restrict__ ctr, uint32_t* __restrict__ start) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L) return;
+    if (j >= L || ctr[8] == 0) return;
     start[j] = (j == 0 || (cnt[j - 1] >= half && j < ctr[7])) ? 1u : 0u;
 }
 
 __global__ void k_del_groups(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx, uint64_t L,
-                             uint32_t* __restrict__ grp_first) {
+                             const uint32_t* __restrict__ ctr, uint32_t* __restrict__ grp_first) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ctr[8] == 0) return;
     if (j < L && start[j]) grp_first[gidx[j]] = (uint32_t)j;
 }
 
@@ -534,6 +557,7 @@ __global__ void k_del_gplan(const uint32_t* __restrict__ grp_first, const uint32
                             const uint32_t* __restrict__ cum, uint32_t phi, uint32_t* __restrict__ gpieces,
                             uint32_t* __restrict__ gchunks, uint32_t* __restrict__ galloc,
                             uint32_t* __restrict__ gfree, uint32_t* __restrict__ gchanged) {
+    if (ctr[8] == 0) return;
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= L) return;
     const uint32_t G = ctr[6];
@@ -721,9 +745,13 @@ void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_
     hipLaunchKernelGGL(k_run_write, dim3(blocks_for(n, 256)), dim3(256), 0, st, leaf_of, flag, ridx, n, run_leaf, run_beg);
 }
 void upd_ins_plan(hipStream_t st, const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
-                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* pieces, uint32_t* rpieces,
-                  uint32_t* rchunks, uint32_t* rsplit) {
-    hipLaunchKernelGGL(k_ins_plan, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, run_beg, ctr, m, leaf, C, phi, pieces, rpieces, rchunks, rsplit);
+                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* rpieces, uint32_t* rchunks,
+                  uint32_t* rsplit) {
+    hipLaunchKernelGGL(k_ins_plan, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, run_beg, ctr, m, leaf, C, phi, rpieces, rchunks, rsplit);
+}
+void upd_ins_pieces(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rpieces,
+                    const uint32_t* rsplit, uint32_t* pieces) {
+    hipLaunchKernelGGL(k_ins_pieces, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rpieces, rsplit, pieces);
 }
 void upd_alloc(hipStream_t st, uint32_t* slot_alloc, uint64_t A, const uint32_t* free_stack, uint64_t n_free,
                uint64_t slot_top, Caps cap) {
@@ -771,8 +799,10 @@ void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint6
     hipLaunchKernelGGL(k_del_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, ctr, m, idkey, ndel);
 }
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
-                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
-    PSI_D(k_del_remove, dim3(blocks_for(m, 256 / DEL_G)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, err, cap);
+                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t phi,
+                    uint32_t* under, uint32_t* err, Caps cap) {
+    const uint32_t half = (phi + 1) / 2;
+    PSI_D(k_del_remove, dim3(blocks_for(m, 256 / DEL_G)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, half, under, err, cap);
 }
 void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
                   uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,
@@ -781,17 +811,20 @@ void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi,
     const uint32_t half = (phi + 1) / 2;
     const unsigned g = blocks_for(L, 256);
     // start[] holds the per-workgroup maxima until k_del_starts fills it
-    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, cnt, start);
+    // every launch below exits at once unless the delete left a leaf below
+    // the minimum (ctr[8]); the totals then stay 0 and nothing regroups
+    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, ctr, cnt, start);
     hipLaunchKernelGGL(k_del_last_full, dim3(1), dim3(256), 0, st, start, (uint64_t)g, ctr);
-    launch_scan_u32(st, cnt, cum, L, cum + L, tmp);
+    launch_scan_u32(st, cnt, cum, L, cum + L, tmp, ctr + 8);
     hipLaunchKernelGGL(k_del_starts, dim3(g), dim3(256), 0, st, cnt, L, half, ctr, start);
-    launch_scan_u32(st, start, gidx, L, ctr + 6, tmp);
-    hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, L, grp_first);
+    launch_scan_u32(st, start, gidx, L, ctr + 6, tmp, ctr + 8);
+    hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, L, ctr, grp_first);
     hipLaunchKernelGGL(k_del_gplan, dim3(g), dim3(256), 0, st, grp_first, ctr, L, cum, phi, gpieces, gchunks, galloc, gfree, gchanged);
     ScanSet sc{{gpieces, galloc, gchunks, gfree},
                {gpos, alloc_off, chunk_off, free_off},
                {ctr + 2, ctr + 3, ctr + 4, ctr + 5},
-               {L, L, L, L}};
+               {L, L, L, L},
+               ctr + 8};
     launch_scan_multi(st, sc, 4, tmp);
 }
 void upd_del_gcopy(hipStream_t st, const uint32_t* grp_first, const uint32_t* ctr, uint64_t L,

@@ -131,17 +131,21 @@ void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles,
 // Exclusive prefix sums; `total` (device, may be null) receives the sum.
 // tmp needs scan_tmp_words(n) words.
 uint64_t scan_tmp_words(uint64_t n);
+// gate (device, may be null): if it reads 0 when the kernels run, they do
+// nothing (outputs and total untouched).
 void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
-                     uint32_t* tmp);
+                     uint32_t* tmp, const uint32_t* gate = nullptr);
 // Up to SCAN_MULTI independent scans (in[y] -> out[y], n[y] items, total[y]
 // may be null) in one set of launches; tmp needs SCAN_MULTI times
-// scan_tmp_words of the largest n[y]. An empty array gets total 0.
+// scan_tmp_words of the largest n[y]. An empty array gets total 0. With a
+// gate as above.
 constexpr int SCAN_MULTI = 4;
 struct ScanSet {
     const uint32_t* in[SCAN_MULTI];
     uint32_t* out[SCAN_MULTI];
     uint32_t* total[SCAN_MULTI];
     uint64_t n[SCAN_MULTI];
+    const uint32_t* gate = nullptr;
 };
 void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp);
 

@@ -22,8 +22,11 @@ void upd_route(hipStream_t st, const uint64_t* bk, const uint32_t* bi, uint64_t 
 void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_t* n_dev, uint32_t* flag,
               uint32_t* ridx, uint32_t* run_leaf, uint32_t* run_beg, uint32_t* R_dev, uint32_t* tmp);
 void upd_ins_plan(hipStream_t st, const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
-                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* pieces, uint32_t* rpieces,
-                  uint32_t* rchunks, uint32_t* rsplit);
+                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* rpieces, uint32_t* rchunks,
+                  uint32_t* rsplit);
+// Piece counts of the re-cut leaves into pieces[] (filled with 1 before).
+void upd_ins_pieces(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rpieces,
+                    const uint32_t* rsplit, uint32_t* pieces);
 void upd_alloc(hipStream_t st, uint32_t* slot_alloc, uint64_t A, const uint32_t* free_stack, uint64_t n_free,
                uint64_t slot_top, Caps cap);
 void upd_dir_copy(hipStream_t st, const NodeRec* src, const uint64_t* spk, const uint32_t* spi, const uint32_t* pieces,
@@ -48,8 +51,11 @@ void upd_del_compact(hipStream_t st, const uint64_t* sk, const uint32_t* si, uin
                      uint32_t* pos, uint32_t* V_dev, uint64_t* ck, uint32_t* ci, uint32_t* tmp);
 void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint64_t m, uint64_t* idkey,
                   uint64_t* ndel);
+// Removes the runs' ids from their leaves; *under |= 1 if a leaf ends below
+// ceil(phi / 2) entries.
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
-                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t* err, Caps cap);
+                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t phi,
+                    uint32_t* under, uint32_t* err, Caps cap);
 void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
                   uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,
                   uint32_t* gchunks, uint32_t* galloc, uint32_t* gfree, uint32_t* gchanged, uint32_t* gpos,

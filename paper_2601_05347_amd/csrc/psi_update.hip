@@ -123,21 +123,29 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     launch_fill_u32(st, a.ctr, 16, 0u);
     upd_route(st, bk, bi, m, nullptr, ix->pkey[cur].as<uint64_t>(), ix->pid[cur].as<uint32_t>(), L, a.leaf_of);
     upd_runs(st, a.leaf_of, m, nullptr, a.flag, a.ridx, a.run_leaf, a.run_beg, a.ctr + 1, a.tmp);
-    launch_fill_u32(st, a.pieces, L, 1u);
-    upd_ins_plan(st, a.run_leaf, a.run_beg, a.ctr, m, ix->leaf[cur].as<NodeRec>(), ix->C, ix->phi, a.pieces,
-                 a.rpieces, a.rchunks, a.rsplit);
-    ScanSet sc{{a.pieces, a.rpieces, a.rchunks, a.rsplit},
-               {a.newpos, a.piece_off, a.chunk_off, a.free_off},
-               {a.ctr + 2, a.ctr + 3, a.ctr + 4, a.ctr + 5},
-               {L, m, m, m}};
-    launch_scan_multi(st, sc, 4, a.tmp);
+    upd_ins_plan(st, a.run_leaf, a.run_beg, a.ctr, m, ix->leaf[cur].as<NodeRec>(), ix->C, ix->phi, a.rpieces,
+                 a.rchunks, a.rsplit);
+    ScanSet sc{{a.rpieces, a.rchunks, a.rsplit, nullptr},
+               {a.piece_off, a.chunk_off, a.free_off, nullptr},
+               {a.ctr + 3, a.ctr + 4, a.ctr + 5, nullptr},
+               {m, m, m, 0}};
+    launch_scan_multi(st, sc, 3, a.tmp);
     if ((s = launched()) != PSI_OK) return s;
     if ((s = readback(ix, a.ctr, 8 * 4)) != PSI_OK) return s;
     uint32_t c[8];
     std::memcpy(c, ix->pinned, sizeof c);
-    const uint64_t Lnew = c[2], A = c[3], NCH = c[4], F = c[5];
+    // A new slots (pieces of the re-cut leaves), F re-cut leaves (one freed
+    // slot each): L - F + A leaves after the splice
+    const uint64_t A = c[3], NCH = c[4], F = c[5];
+    if (F > L || F > A) return PSI_E_INTERNAL;
+    const uint64_t Lnew = L - F + A;
 
     const bool recut = A > 0;
+    if (recut) {  // new directory positions: exclusive scan of the per-leaf piece counts
+        launch_fill_u32(st, a.pieces, L, 1u);
+        upd_ins_pieces(st, a.run_leaf, a.ctr, m, a.rpieces, a.rsplit, a.pieces);
+        launch_scan_u32(st, a.pieces, a.newpos, L, a.ctr + 2, a.tmp);
+    }
     const int dst = recut ? 1 - cur : cur;
     if (recut && (s = ensure_dir(ix, dst, Lnew)) != PSI_OK) return s;
     uint64_t new_top = ix->slot_top, n_free_after = ix->n_free, push_base = ix->n_free;
@@ -155,8 +163,9 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     if (recut)
         upd_dir_copy(st, ix->leaf[cur].as<NodeRec>(), ix->pkey[cur].as<uint64_t>(), ix->pid[cur].as<uint32_t>(),
                      a.pieces, a.newpos, L, dleaf, dpk, dpi, cap);
-    upd_ins_append(st, ix->D, ix->curve, bk, bi, a.run_leaf, a.run_beg, a.ctr, m, a.rsplit, a.newpos, dleaf, dpk,
-                   dpi, ix->slots.as<uint32_t>(), ix->C, ix->err.as<uint32_t>(), cap);
+    upd_ins_append(st, ix->D, ix->curve, bk, bi, a.run_leaf, a.run_beg, a.ctr, m, a.rsplit,
+                   recut ? a.newpos : nullptr, dleaf, dpk, dpi, ix->slots.as<uint32_t>(), ix->C,
+                   ix->err.as<uint32_t>(), cap);
     if (recut) {
         upd_ins_split(st, ix->D, ix->curve, NCH, bk, bi, a.run_leaf, a.run_beg, a.ctr, m, a.chunk_off, a.piece_off,
                       a.newpos, slot_alloc, ix->leaf[cur].as<NodeRec>(), dleaf, dpk, dpi, piece_pos,
@@ -238,7 +247,10 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
     upd_route(st, a.ck, a.ci, m, a.ctr + 0, ix->pkey[cur].as<uint64_t>(), ix->pid[cur].as<uint32_t>(), L, a.leaf_of);
     upd_runs(st, a.leaf_of, m, a.ctr + 0, a.flag, a.ridx, a.run_leaf, a.run_beg, a.ctr + 1, a.tmp);
     upd_del_remove(st, ix->D, a.ci, a.run_leaf, a.run_beg, a.ctr, m, ix->leaf[cur].as<NodeRec>(),
-                   ix->slots.as<uint32_t>(), ix->C, ix->err.as<uint32_t>(), caps_of(ix, cur, 0));
+                   ix->slots.as<uint32_t>(), ix->C, ix->phi, a.ctr + 8, ix->err.as<uint32_t>(), caps_of(ix, cur, 0));
+    // Leaves below the minimum can only come from this delete (every update
+    // leaves all leaves at or above it): with none (ctr[8] = 0) the plan's
+    // launches exit at once, F stays 0, and only the node levels change.
     upd_del_plan(st, ix->leaf[cur].as<NodeRec>(), L, ix->phi, a.ctr, a.cnt, a.cum, a.start, a.gidx, a.grp_first,
                  a.gpieces, a.gchunks, a.galloc, a.gfree, a.gchanged, a.gpos, a.chunk_off, a.alloc_off, a.free_off,
                  a.tmp);

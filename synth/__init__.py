@@ -140,11 +140,22 @@ def varden(n: int, dim: int, bits: int, seed: int, purpose: int = P_DATA,
     return out[perm]
 
 
+def sweepline(n: int, dim: int, bits: int, seed: int, purpose: int = P_DATA) -> np.ndarray:
+    """The uniform points of `uniform(n, ...)` ordered by their first
+    coordinate (stable: equal first coordinates keep their draw order), the
+    skewed update order of the paper's Sweepline workload (Sec. 5.1): batches
+    taken in this order are slabs of space."""
+    u = uniform(n, dim, bits, seed, purpose)
+    return u[np.argsort(u[:, 0], kind="stable")] if n else u
+
+
 def points(dist: str, n: int, dim: int, bits: int, seed: int, purpose: int = P_DATA) -> np.ndarray:
     if dist == "uniform":
         return uniform(n, dim, bits, seed, purpose)
     if dist == "varden":
         return varden(n, dim, bits, seed, purpose)
+    if dist == "sweepline":
+        return sweepline(n, dim, bits, seed, purpose)
     raise ValueError(f"unknown distribution {dist!r}")
 
 

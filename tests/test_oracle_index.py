@@ -241,3 +241,22 @@ def test_range_invariants(ora, dim):
     empty = bx[:3].copy()
     empty[:, 0, dim - 1] = empty[:, 1, dim - 1] + 1
     assert R.range_count(empty).tolist() == [0, 0, 0]
+
+
+@pytest.mark.parametrize("dist", ["sweepline", "varden"])
+def test_incremental_batches_equal_one_build(ora, dist):
+    """Building from empty by many insertion batches gives the set (keys, ids,
+    points) of one build of all points, and deleting in batches empties it
+    (the paper's incremental workload, Sec. 5.1, on the oracle)."""
+    pts = synth.points(dist, 6000, 2, 30, seed=71)
+    inc = ora.RefIndex(2, 1, 8, 4)
+    inc.build(np.zeros((0, 2), np.uint32))
+    for i in range(0, 6000, 250):
+        np.testing.assert_array_equal(inc.batch_insert(pts[i:i + 250]), np.arange(i, i + 250, dtype=np.uint32))
+    one = ora.RefIndex(2, 1, 8, 4)
+    one.build(pts)
+    for a, b in zip(inc.dump(), one.dump()):
+        np.testing.assert_array_equal(a, b)
+    for i in range(0, 6000, 250):
+        assert inc.batch_delete(np.arange(i, i + 250, dtype=np.uint32)) == 250
+    assert inc.size() == 0
