@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
     ap.add_argument("--batch-frac", default="0.1,0.01,0.001,0.0001", help="incr: batch sizes as fractions of n")
+    ap.add_argument("--sorted-leaves", action="store_true",
+                    help="keep every leaf in (key, id) order after updates (the total-order ablation)")
     return ap.parse_args()
 
 
@@ -239,7 +241,8 @@ def bench_incr(args):
     for frac in [float(x) for x in args.batch_frac.split(",")]:
         s = max(1, int(round(n * frac)))
         nbat = n // s
-        ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
+        ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev,
+                       flags=psi.FLAG_SORTED_LEAVES if args.sorted_leaves else 0)
         psi.psi_build(ix._h, d_data[:0], 0)
         torch.cuda.synchronize()
         ins_ms = del_ms = 0.0
@@ -293,7 +296,7 @@ def bench_incr(args):
            "steps": 1, "warmup": 0, "ms_per_step": round(tot, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
            "config": {"workload": f"incremental: {dim}D {dist} {args.curve}", "n": n, "queries": nq, "k": k,
-                      "leaf_size": args.leaf, "fanout": args.fanout},
+                      "leaf_size": args.leaf, "fanout": args.fanout, "sorted_leaves": args.sorted_leaves},
            "static_knn_ms": {"first_half": ms1, "second_half": ms2}, "runs": runs}
     print(json.dumps(out), flush=True)
 
@@ -431,7 +434,8 @@ def main():
     d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
     del data, ins, q
     stream = torch.cuda.current_stream(dev)
-    ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev, stream=stream)
+    ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev, stream=stream,
+                   flags=psi.FLAG_SORTED_LEAVES if args.sorted_leaves else 0)
     h = ix._h
     new_ids = torch.empty(m, dtype=torch.int32, device=dev)
     nd = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -546,7 +550,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {args.dist} SPaC-{'H' if curve else 'Z'}", "n": n, "dim": dim,
                    "coord_bits": bits, "insert": m, "delete": m, "queries": nq, "k": k, "boxes": nb,
-                   "leaf_size": args.leaf, "fanout": args.fanout, "ops": sorted(ops)},
+                   "leaf_size": args.leaf, "fanout": args.fanout, "ops": sorted(ops),
+                   **({"sorted_leaves": True} if args.sorted_leaves else {})},
         "phases": {
             **{f"{p}_ms": round(v, 3) for p, v in ms.items()},
             "build_mpts_s": round(n / ms["build"] / 1e3, 1) if ms["build"] > 0 else None,

@@ -65,12 +65,19 @@ typedef enum { PSI_MORTON = 0, PSI_HILBERT = 1 } psi_curve;
  * workgroup's local memory (the distribute-then-sort-locally shape of
  * Alg. 3); smaller builds take eight global passes. PSI_FLAG_SORT_BUCKETS and
  * PSI_FLAG_SORT_LSD force one or the other (not both); the result is the
- * same. */
+ * same.
+ * Leaves keep their entries unsorted after inserts (Sec. 4.2: an insert
+ * appends to its leaf; only a leaf that is re-cut is sorted).
+ * PSI_FLAG_SORTED_LEAVES keeps every leaf in (key, id) order after every
+ * update instead, the total order a CPAM-style tree maintains (Sec. 4 and
+ * Sec. 5.1.2 compare the two): each insert re-sorts the leaves it appended
+ * to. Query results and the set are the same; only update cost differs. */
 enum {
     PSI_FLAG_INPUT_ORDER = 1,
     PSI_FLAG_KNN_NEAREST_FIRST = 2,
     PSI_FLAG_SORT_BUCKETS = 4,
-    PSI_FLAG_SORT_LSD = 8
+    PSI_FLAG_SORT_LSD = 8,
+    PSI_FLAG_SORTED_LEAVES = 16
 };
 
 /* dim: 2 or 3. curve: psi_curve. leaf_size: phi, the largest leaf a build

@@ -23,6 +23,7 @@ FLAG_INPUT_ORDER = 1
 FLAG_KNN_NEAREST_FIRST = 2
 FLAG_SORT_BUCKETS = 4
 FLAG_SORT_LSD = 8
+FLAG_SORTED_LEAVES = 16
 PAD_ID = 0xFFFFFFFF
 PAD_D2 = 0xFFFFFFFFFFFFFFFF
 

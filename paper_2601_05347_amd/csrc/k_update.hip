@@ -632,6 +632,48 @@ __global__ __launch_bounds__(256) void k_sort_leaves(const uint32_t* __restrict_
     }
 }
 
+// After appends, with leaves kept in total order: one wave per run whose
+// leaf took its entries by appending re-sorts that leaf (rank of each entry
+// among the leaf's entries by (key, id), keys recomputed from the points).
+template <int D, int CURVE>
+__global__ __launch_bounds__(256) void k_sort_appended(const uint32_t* __restrict__ run_leaf,
+                                                       const uint32_t* __restrict__ ctr, uint64_t m,
+                                                       const uint32_t* __restrict__ rsplit,
+                                                       const uint32_t* __restrict__ newpos,
+                                                       const NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
+                                                       uint32_t C, Caps cap) {
+    const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = lane_id();
+    if (r >= m || r >= ctr[1] || rsplit[r]) return;  // uniform over the wave
+    const uint32_t j = run_leaf[r];
+    const uint32_t q = newpos ? newpos[j] : j;
+    if (q >= cap.leaves) return;
+    const NodeRec rec = leaf[q];
+    if (rec.cnt <= 1 || rec.cnt > 64 || rec.cnt > C || rec.slot >= cap.slots) return;
+    uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
+    const bool on = lane < rec.cnt;
+    uint32_t p[D];
+    uint32_t id = PAD_ID;
+    uint64_t key = ~0ull;
+    if (on) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s[d * C + lane];
+        id = s[D * C + lane];
+        key = sfc_key_tab<D, CURVE>(p);
+    }
+    uint32_t rank = 0;
+    for (uint32_t x = 0; x < rec.cnt; ++x) {  // all reads precede the writes: shuffles only
+        const uint64_t ok = shfl_u64(key, (int)x);
+        const uint32_t oi = shfl_u32(id, (int)x);
+        rank += pair_less(ok, oi, key, id) ? 1u : 0u;
+    }
+    if (on) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d * C + rank] = p[d];
+        s[D * C + rank] = id;
+    }
+}
+
 // Concatenate the (sorted) leaves of a changed group and cut into P pieces.
 template <int D, int CURVE>
 __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
@@ -766,6 +808,11 @@ void upd_ins_append(hipStream_t st, int dim, int curve, const uint64_t* bk, cons
                     const uint32_t* rsplit, const uint32_t* newpos, NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi,
                     uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
     PSI_DC(k_ins_append, dim3(blocks_for(m, 256)), dim3(256), 0, st, bk, bi, run_leaf, run_beg, ctr, m, rsplit, newpos, dleaf, dpk, dpi, slots, C, err, cap);
+}
+void upd_sort_appended(hipStream_t st, int dim, int curve, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m,
+                       const uint32_t* rsplit, const uint32_t* newpos, const NodeRec* leaf, uint32_t* slots,
+                       uint32_t C, Caps cap) {
+    PSI_DC(k_sort_appended, dim3(blocks_for(m, 4)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, newpos, leaf, slots, C, cap);
 }
 void upd_ins_split(hipStream_t st, int dim, int curve, uint64_t nchunks, const uint64_t* bk, const uint32_t* bi,
                    const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,

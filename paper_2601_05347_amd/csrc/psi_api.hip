@@ -430,7 +430,7 @@ psi_status psi_create(const psi_params* prm, void* hip_stream, psi_index* out) {
     *out = nullptr;
     if ((prm->dim != 2 && prm->dim != 3) || prm->curve > 1 || prm->leaf_size < 2 || prm->leaf_size > 32 ||
         prm->fanout < 2 || prm->fanout > 32 || (prm->flags & ~(uint32_t)(PSI_FLAG_INPUT_ORDER | PSI_FLAG_KNN_NEAREST_FIRST | PSI_FLAG_SORT_BUCKETS |
-                                  PSI_FLAG_SORT_LSD)) != 0 ||
+                                  PSI_FLAG_SORT_LSD | PSI_FLAG_SORTED_LEAVES)) != 0 ||
         (prm->flags & (PSI_FLAG_SORT_BUCKETS | PSI_FLAG_SORT_LSD)) == (PSI_FLAG_SORT_BUCKETS | PSI_FLAG_SORT_LSD))
         return PSI_E_ARG;
     psi_index ix = new (std::nothrow) psi_index_s;

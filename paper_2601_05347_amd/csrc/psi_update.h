@@ -24,6 +24,11 @@ void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_
 void upd_ins_plan(hipStream_t st, const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
                   const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* rpieces, uint32_t* rchunks,
                   uint32_t* rsplit);
+// Re-sorts, by (key, id), every leaf that took a run by appending (leaves in
+// total order).
+void upd_sort_appended(hipStream_t st, int dim, int curve, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m,
+                       const uint32_t* rsplit, const uint32_t* newpos, const NodeRec* leaf, uint32_t* slots,
+                       uint32_t C, Caps cap);
 // Piece counts of the re-cut leaves into pieces[] (filled with 1 before).
 void upd_ins_pieces(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rpieces,
                     const uint32_t* rsplit, uint32_t* pieces);

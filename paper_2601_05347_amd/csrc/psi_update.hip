@@ -166,6 +166,11 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     upd_ins_append(st, ix->D, ix->curve, bk, bi, a.run_leaf, a.run_beg, a.ctr, m, a.rsplit,
                    recut ? a.newpos : nullptr, dleaf, dpk, dpi, ix->slots.as<uint32_t>(), ix->C,
                    ix->err.as<uint32_t>(), cap);
+    if (ix->flags & PSI_FLAG_SORTED_LEAVES) {
+        ProfScope ps(ix, "sort_appended", 0);
+        upd_sort_appended(st, ix->D, ix->curve, a.run_leaf, a.ctr, m, a.rsplit, recut ? a.newpos : nullptr, dleaf,
+                          ix->slots.as<uint32_t>(), ix->C, cap);
+    }
     if (recut) {
         upd_ins_split(st, ix->D, ix->curve, NCH, bk, bi, a.run_leaf, a.run_beg, a.ctr, m, a.chunk_off, a.piece_off,
                       a.newpos, slot_alloc, ix->leaf[cur].as<NodeRec>(), dleaf, dpk, dpi, piece_pos,
