@@ -119,15 +119,21 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
 // G = B rounded up to a power of two lanes per parent: every lane loads one
 // child record (a parent's children are one contiguous run of records) and the
 // group reduces counts and boxes by xor shuffles.
+// cchild (may be null) and cparent receive the packed boxes of the children
+// and of the parents (the kNN's box tests read those).
 template <int D, int G>
 __global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ child, uint64_t n_child,
-                                                    NodeRec* __restrict__ parent, uint64_t n_parent, uint32_t B) {
+                                                    NodeRec* __restrict__ parent, uint64_t n_parent, uint32_t B,
+                                                    uint4* __restrict__ cchild, uint4* __restrict__ cparent) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const uint32_t g = threadIdx.x % G;
     const uint64_t c = i * B + g;
     const bool on = i < n_parent && g < B && c < n_child;  // all lanes stay for the shuffles
     NodeRec x = {};
-    if (on) x = child[c];
+    if (on) {
+        x = child[c];
+        if (cchild) cchild[c] = packed_box<D>(x);
+    }
     uint32_t cnt = on ? x.cnt : 0u;
     uint32_t lo[D], hi[D];
 #pragma unroll
@@ -155,7 +161,15 @@ __global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ 
         r.cnt = cnt;
         r.slot = 0xFFFFFFFFu;
         parent[i] = r;
+        cparent[i] = packed_box<D>(r);
     }
+}
+
+// Packed boxes of n records (a tree whose root is a leaf).
+template <int D>
+__global__ void k_pack_boxes(const NodeRec* __restrict__ rec, uint64_t n, uint4* __restrict__ out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = packed_box<D>(rec[i]);
 }
 
 __global__ void k_leaf_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t* __restrict__ cnt) {
@@ -286,13 +300,19 @@ void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk,
 #undef PSI_BL
 }
 
+void launch_pack_boxes(hipStream_t st, int dim, const NodeRec* rec, uint64_t n, uint4* out) {
+    if (!n) return;
+    if (dim == 2) hipLaunchKernelGGL(k_pack_boxes<2>, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, n, out);
+    else hipLaunchKernelGGL(k_pack_boxes<3>, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, n, out);
+}
+
 void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
-                       uint64_t n_parent, uint32_t B) {
+                       uint64_t n_parent, uint32_t B, uint4* cchild, uint4* cparent) {
     if (n_parent == 0) return;
     uint32_t G = 2;
     while (G < B) G <<= 1;
     const unsigned g = blocks_for(n_parent * G, 256);
-#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, child, n_child, parent, n_parent, B)
+#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, child, n_child, parent, n_parent, B, cchild, cparent)
 #define PSI_NL2(GG)              \
     do {                         \
         if (dim == 2) PSI_NL(2, GG); \

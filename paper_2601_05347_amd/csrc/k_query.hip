@@ -172,33 +172,44 @@ __global__ __launch_bounds__(256) void k_knn_lane(TreeView t, const uint32_t* __
 // current k-th distance and the seed leaves already scanned. A good seed
 // radius makes this visit little more than the leaves the final k-th
 // distance ball touches, without re-scoring siblings.
+// Four distances at a time; the candidates among them go through one
+// insertion site (not unrolled: the k-best list is the register budget).
+// lazy: an entry's id is read only when its distance could place it among
+// the k best (after the first leaves fill the list that is rare); otherwise
+// the ids are loaded four at a time with the coordinates.
 template <int D, int K>
-__device__ __forceinline__ void scan_leaf(const TreeView& t, const NodeRec& r, const uint32_t* q, uint64_t (&bd)[K],
-                                          uint32_t (&bi)[K]) {
+__device__ __forceinline__ void scan_leaf(const TreeView& t, uint32_t slot, uint32_t cnt, const uint32_t* q,
+                                          uint64_t (&bd)[K], uint32_t (&bi)[K], bool lazy) {
     const uint32_t C = t.C;
-    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
-    for (uint32_t e = 0; e < r.cnt; e += 4) {
+    const uint32_t* s = t.slots + (uint64_t)slot * (D + 1) * C;
+    for (uint32_t e = 0; e < cnt; e += 4) {
         uint4 X[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e);
-        const uint4 I = *reinterpret_cast<const uint4*>(s + D * C + e);
+        uint4 I = make_uint4(0u, 0u, 0u, 0u);
+        if (!lazy) I = *reinterpret_cast<const uint4*>(s + D * C + e);
         const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
                                    {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
                                    {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
                                    {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
-        const uint32_t is[4] = {I.x, I.y, I.z, I.w};
+        uint64_t dd[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (e + u < r.cnt) {
-                const uint64_t dd = pt_dist<D>(q, xs[u]);
-                if (pair_less(dd, is[u], bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, is[u]);
-            }
+        for (int u = 0; u < 4; ++u) dd[u] = pt_dist<D>(q, xs[u]);
+        const uint32_t nu = min(cnt - e, 4u);
+#pragma unroll 1
+        for (uint32_t u = 0; u < nu; ++u) {
+            const uint64_t d = u == 0 ? dd[0] : (u == 1 ? dd[1] : (u == 2 ? dd[2] : dd[3]));
+            if (d > bd[K - 1]) continue;
+            const uint32_t id = lazy ? s[D * C + e + u] : (u == 0 ? I.x : (u == 1 ? I.y : (u == 2 ? I.z : I.w)));
+            if (pair_less(d, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, d, id);
         }
     }
 }
 
 // Seeded search over any tree exposed through an accessor `T` with
-// L(), h(), B(), levn(l) (nodes of level l), node(l, i), leaf(i), pkey(i).
+// L(), h(), B(), levn(l) (nodes of level l), dist(l, i, q) (squared distance
+// from q to the box of node i of level l, the leaves being level h; PAD_D2
+// for an empty node), leaf_sc(i) (slot and count of leaf i) and pkey(i).
 template <int D, int K, class T>
 __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, const uint32_t* q, uint64_t key,
                                            uint64_t (&bd)[K], uint32_t (&bi)[K]) {
@@ -212,15 +223,21 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     }
     const uint32_t j = lo ? lo - 1 : 0u;
     const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
-    for (uint32_t x = ja; x <= jb; ++x) scan_leaf<D, K>(tv, tr.leaf(x), q, bd, bi);
+    for (uint32_t x = ja; x <= jb; ++x) {
+        const uint2 sc = tr.leaf_sc(x);  // (count, slot)
+        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, false);
+    }
     const uint32_t B = tr.B(), h = tr.h();
     uint32_t l = 0, i = 0;
     for (;;) {
-        const NodeRec r = l == h ? tr.leaf(i) : tr.node(l, i);
+        const uint64_t bdist = tr.dist(l, i, q);
         bool descend = false;
-        if (r.cnt && box_dist<D>(q, r) <= bd[K - 1]) {
+        if (bdist != PAD_D2 && bdist <= bd[K - 1]) {
             if (l == h) {
-                if (i < ja || i > jb) scan_leaf<D, K>(tv, r, q, bd, bi);
+                if (i < ja || i > jb) {
+                    const uint2 sc = tr.leaf_sc(i);
+                    scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, true);
+                }
             } else {
                 descend = true;
             }
@@ -247,7 +264,26 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     }
 }
 
-// Accessor of a single index whose level table sits in LDS.
+// Squared distance from q to a packed box (PAD_D2 for an empty node).
+template <int D>
+__device__ __forceinline__ uint64_t packed_dist(const uint32_t* q, uint4 v) {
+    const uint64_t a = ((uint64_t)v.y << 32) | v.x, b = ((uint64_t)v.w << 32) | v.z;
+    if (a >> 63) return PAD_D2;
+    constexpr int W = BoxBits<D>::W;
+    constexpr uint64_t M = (1ull << W) - 1;
+    uint64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t lo = (uint32_t)((a >> (d * W)) & M), hi = (uint32_t)((b >> (d * W)) & M);
+        const uint32_t x = q[d] < lo ? lo - q[d] : (q[d] > hi ? q[d] - hi : 0u);
+        s += (uint64_t)x * x;
+    }
+    return s;
+}
+
+// Accessor of a single index whose level table sits in LDS: box tests read
+// the packed boxes, leaf scans the slot and count of the leaf record.
+template <int D>
 struct SingleTree {
     const TreeView& t;
     const LevelInfo* lv;
@@ -255,8 +291,10 @@ struct SingleTree {
     __device__ uint32_t h() const { return t.h; }
     __device__ uint32_t B() const { return t.B; }
     __device__ uint32_t levn(uint32_t l) const { return (uint32_t)lv[l].n; }
-    __device__ NodeRec node(uint32_t l, uint32_t i) const { return t.inner[lv[l].off + i]; }
-    __device__ NodeRec leaf(uint32_t i) const { return t.leaf[i]; }
+    __device__ uint64_t dist(uint32_t l, uint32_t i, const uint32_t* q) const {
+        return packed_dist<D>(q, l == t.h ? t.cleaf[i] : t.cinner[lv[l].off + i]);
+    }
+    __device__ uint2 leaf_sc(uint32_t i) const { return *reinterpret_cast<const uint2*>(&t.leaf[i].cnt); }
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
 };
 
@@ -281,7 +319,7 @@ __global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __
         bd[j] = PAD_D2;
         bi[j] = PAD_ID;
     }
-    const SingleTree tr{t, s_lv};
+    const SingleTree<D> tr{t, s_lv};
     knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -292,6 +330,7 @@ __global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __
 
 // ---------------------------------------------- kNN over many small indexes
 // Accessor of index m among a batch of indexes sharing global arrays.
+template <int D>
 struct MultiTree {
     const IdxMeta* m;
     const NodeRec* inner;
@@ -304,6 +343,13 @@ struct MultiTree {
     __device__ uint32_t levn(uint32_t l) const { return m->lvl_n[l]; }
     __device__ NodeRec node(uint32_t l, uint32_t i) const { return inner[m->inner_base + m->lvl_off[l] + i]; }
     __device__ NodeRec leaf(uint32_t i) const { return leafs[m->leaf_base + i]; }
+    __device__ uint64_t dist(uint32_t l, uint32_t i, const uint32_t* q) const {
+        return box_dist<D>(q, l == m->h ? leaf(i) : node(l, i));
+    }
+    __device__ uint2 leaf_sc(uint32_t i) const {
+        const NodeRec r = leaf(i);
+        return make_uint2(r.cnt, r.slot);
+    }
     __device__ uint64_t pkey(uint32_t i) const { return pk[m->leaf_base + i]; }
 };
 
@@ -349,7 +395,7 @@ __global__ __launch_bounds__(256) void k_multi_knn(TreeView tv, const IdxMeta* _
                 bd[j] = PAD_D2;
                 bi[j] = PAD_ID;
             }
-            const MultiTree tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
+            const MultiTree<D> tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
             knn_seeded<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi);
 #pragma unroll
             for (int j = 0; j < K; ++j) {

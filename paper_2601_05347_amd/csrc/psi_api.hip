@@ -283,12 +283,18 @@ psi_status build_nodes(psi_index ix) {
     ix->n_inner = off;
     psi_status s = ix->inner.ensure(std::max<uint64_t>(off, 1) * sizeof(NodeRec));
     if (s != PSI_OK) return s;
+    if ((s = ix->cinner.ensure(std::max<uint64_t>(off, 1) * 16)) != PSI_OK) return s;
+    if ((s = ix->cleaf.ensure(ix->L * 16)) != PSI_OK) return s;
     NodeRec* inner = ix->inner.as<NodeRec>();
+    uint4* cinner = ix->cinner.as<uint4>();
     const NodeRec* leaf = ix->leaf[ix->cur].as<NodeRec>();
-    ProfScope ps(ix, "nodes", off * 32 + ix->L * 32);
+    ProfScope ps(ix, "nodes", off * 48 + ix->L * 48);
+    if (h == 0) launch_pack_boxes(ix->st, ix->D, leaf, ix->L, ix->cleaf.as<uint4>());
     for (int l = (int)h - 1; l >= 0; --l) {
-        const NodeRec* child = (l + 1 == (int)h) ? leaf : inner + ix->lv[l + 1].off;
-        launch_node_level(ix->st, ix->D, child, ix->lv[l + 1].n, inner + ix->lv[l].off, ix->lv[l].n, ix->B);
+        const bool low = l + 1 == (int)h;
+        const NodeRec* child = low ? leaf : inner + ix->lv[l + 1].off;
+        launch_node_level(ix->st, ix->D, child, ix->lv[l + 1].n, inner + ix->lv[l].off, ix->lv[l].n, ix->B,
+                          low ? ix->cleaf.as<uint4>() : nullptr, cinner + ix->lv[l].off);
     }
     return last_launch();
 }
@@ -399,6 +405,8 @@ psi::TreeView psi_index_s::view() const {
     psi::TreeView t{};
     t.inner = inner.as<psi::NodeRec>();
     t.leaf = leaf[cur].as<psi::NodeRec>();
+    t.cinner = cinner.as<uint4>();
+    t.cleaf = cleaf.as<uint4>();
     t.pkey = pkey[cur].as<uint64_t>();
     t.slots = slots.as<uint32_t>();
     t.h = h;

@@ -22,13 +22,37 @@ constexpr uint64_t DEAD_KEY = ~0ull;  // id-table entry of a deleted or unused i
 
 // A node of the tree, leaves included (32 bytes). Boxes are closed; an empty
 // node has lo = 0xFFFFFFFF, hi = 0 and cnt = 0. `slot` is the leaf's storage
-// slot at the leaf level and unused above it.
+// slot at the leaf level and unused above it; cnt and slot share one 8-byte
+// word (what a leaf scan needs).
 struct alignas(16) NodeRec {
     uint32_t lo[3];
-    uint32_t cnt;
     uint32_t hi[3];
+    uint32_t cnt;
     uint32_t slot;
 };
+
+// A node's box in 16 bytes, for the kNN box tests (one 16-byte load each):
+// the low corner in the first 64-bit word, the high corner in the second,
+// axis d at bit d * W (W = 21 in 3D, 31 in 2D: coordinates are below 2^W,
+// so the box is exact). Bit 63 of the first word marks an empty node.
+template <int D> struct BoxBits { static constexpr int W = D == 2 ? 31 : 21; };
+template <int D> PSI_HD void pack_box(const NodeRec& r, uint64_t& a, uint64_t& b) {
+    a = 0;
+    b = 0;
+    for (int d = 0; d < D; ++d) {
+        a |= (uint64_t)r.lo[d] << (d * BoxBits<D>::W);
+        b |= (uint64_t)r.hi[d] << (d * BoxBits<D>::W);
+    }
+    if (r.cnt == 0) {
+        a = 1ull << 63;
+        b = 0;
+    }
+}
+template <int D> PSI_HD uint4 packed_box(const NodeRec& r) {
+    uint64_t a, b;
+    pack_box<D>(r, a, b);
+    return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
 
 // Node levels of the B-ary tree: level l (0 = root) has n[l] nodes stored at
 // inner[off[l] ..]; level h is the leaf directory itself.

@@ -156,14 +156,19 @@ void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp);
 void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
                          uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
                          uint32_t* piv_id, NodeRec* leafrec);
-// One node level: parent i = union of children [B i, B i + B) one level down.
+// One node level: parent i = union of children [B i, B i + B) one level down;
+// packed boxes of the children (cchild, may be null) and of the parents.
 void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
-                       uint64_t n_parent, uint32_t B);
+                       uint64_t n_parent, uint32_t B, uint4* cchild, uint4* cparent);
+// Packed boxes of n records.
+void launch_pack_boxes(hipStream_t st, int dim, const NodeRec* rec, uint64_t n, uint4* out);
 
 // ---------------------------------------------------------------- queries
 struct TreeView {
     const NodeRec* inner;   // levels 0..h-1
     const NodeRec* leaf;    // level h (the directory)
+    const uint4* cinner;    // packed boxes of inner (same positions)
+    const uint4* cleaf;     // packed boxes of leaf
     const uint64_t* pkey;   // leaf pivot keys (ascending)
     const uint32_t* slots;
     uint32_t h;
