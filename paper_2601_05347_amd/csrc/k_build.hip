@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ 
         r.cnt = cnt;
         r.slot = 0xFFFFFFFFu;
         parent[i] = r;
-        cparent[i] = packed_box<D>(r);
+        if (cparent) cparent[i] = packed_box<D>(r);
     }
 }
 

@@ -283,18 +283,18 @@ psi_status build_nodes(psi_index ix) {
     ix->n_inner = off;
     psi_status s = ix->inner.ensure(std::max<uint64_t>(off, 1) * sizeof(NodeRec));
     if (s != PSI_OK) return s;
-    if ((s = ix->cinner.ensure(std::max<uint64_t>(off, 1) * 16)) != PSI_OK) return s;
-    if ((s = ix->cleaf.ensure(ix->L * 16)) != PSI_OK) return s;
+    // the packed boxes follow on the next kNN (sized here: a captured kNN
+    // cannot allocate)
+    ix->boxes_fresh = false;
+    if ((s = ensure_q(ix->cinner, std::max<uint64_t>(off, 1) * 16, ix->st)) != PSI_OK) return s;
+    if ((s = ensure_q(ix->cleaf, std::max<uint64_t>(ix->L, 1) * 16, ix->st)) != PSI_OK) return s;
     NodeRec* inner = ix->inner.as<NodeRec>();
-    uint4* cinner = ix->cinner.as<uint4>();
     const NodeRec* leaf = ix->leaf[ix->cur].as<NodeRec>();
-    ProfScope ps(ix, "nodes", off * 48 + ix->L * 48);
-    if (h == 0) launch_pack_boxes(ix->st, ix->D, leaf, ix->L, ix->cleaf.as<uint4>());
+    ProfScope ps(ix, "nodes", off * 32 + ix->L * 32);
     for (int l = (int)h - 1; l >= 0; --l) {
-        const bool low = l + 1 == (int)h;
-        const NodeRec* child = low ? leaf : inner + ix->lv[l + 1].off;
+        const NodeRec* child = (l + 1 == (int)h) ? leaf : inner + ix->lv[l + 1].off;
         launch_node_level(ix->st, ix->D, child, ix->lv[l + 1].n, inner + ix->lv[l].off, ix->lv[l].n, ix->B,
-                          low ? ix->cleaf.as<uint4>() : nullptr, cinner + ix->lv[l].off);
+                          nullptr, nullptr);
     }
     return last_launch();
 }
@@ -509,6 +509,17 @@ psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, u
     const uint32_t* order = nullptr;
     psi_status s = query_order(ix, d_q, nq, false, &order);
     if (s != PSI_OK) return s;
+    // The box tests read the packed boxes: rewritten after the tree changed,
+    // and always inside a captured graph (a replay may follow updates).
+    const bool cap = capturing(ix->st);
+    if (ix->L && (!ix->boxes_fresh || cap)) {
+        if ((s = ensure_q(ix->cinner, std::max<uint64_t>(ix->n_inner, 1) * 16, ix->st)) != PSI_OK) return s;
+        if ((s = ensure_q(ix->cleaf, ix->L * 16, ix->st)) != PSI_OK) return s;
+        ProfScope pb(ix, "pack_boxes", (ix->n_inner + ix->L) * 48);
+        launch_pack_boxes(ix->st, ix->D, ix->leaf[ix->cur].as<NodeRec>(), ix->L, ix->cleaf.as<uint4>());
+        launch_pack_boxes(ix->st, ix->D, ix->inner.as<NodeRec>(), ix->n_inner, ix->cinner.as<uint4>());
+        if (!cap) ix->boxes_fresh = true;
+    }
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
     launch_knn(ix->st, ix->D, ix->view(), d_q, ix->scr.c.as<uint64_t>(), nq, order, k,
                (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, d_ids, d_d2);

@@ -1,4 +1,4 @@
-// Table-driven Hilbert keys for the hot kernels (build encode, leaf fill).
+// Table-driven Hilbert keys for the kernels (build encode, leaf fill, updates, queries).
 //
 // The Hilbert key of Sec. 2.2 (Skilling's construction, as computed by
 // hilbert_key in psi_dev.h) reads the point plane by plane from the top.
@@ -6,9 +6,11 @@
 // the exchanges and reflections applied so far to the lower planes (a signed
 // permutation of the axes) plus the parity that the Gray-code step carries
 // down from the planes above. Walking that finite-state machine over the
-// point's Morton key (the same bits, interleaved), several planes per table
-// lookup, gives the same key with a fraction of the ALU work; the inverse
-// machine walks a key back to the Morton key of its point.
+// point's bit planes, several planes per table lookup, gives the same key
+// with a fraction of the ALU work; the inverse machine walks a key back to
+// the point. A lookup's chunk holds the P plane bits of each axis side by
+// side (axis d at bits [d P, d P + P)), so both directions take them from and
+// give them to the coordinates with one bit-field operation per axis.
 //
 // The tables are generated at compile time from the plane rule itself:
 //  * current bits  c_d = o[perm[d]] ^ flip_d   (o: the point's bits in the plane)
@@ -35,9 +37,10 @@ template <int D> struct HilbertFsm {
     static constexpr int MAIN = S * CH;
     static constexpr int ENTRIES = MAIN + (TOP ? (1 << D) : 0);
     static_assert(TOP + STEPS * P == W, "planes must split into the lookups");
-    // entry = (next state << 8) | output chunk; enc maps Morton chunk -> key
-    // chunk, dec maps key chunk -> Morton chunk. The single-plane entries of
-    // the top step (from state 0) follow the main table.
+    // entry = (next state << 8) | output chunk; enc maps an axis-grouped
+    // chunk -> key chunk, dec maps key chunk -> axis-grouped chunk. The
+    // single-plane entries of the top step (from state 0) follow the main
+    // table (one bit per axis, axis d at bit d).
     uint16_t enc[ENTRIES];
     uint16_t dec[ENTRIES];
 };
@@ -76,6 +79,16 @@ constexpr int plane(St& st, int o, int D) {
 }
 
 constexpr int code(const St& x) { return ((x.perm[0] + 3 * x.perm[1] + 9 * x.perm[2]) * 8 + x.flip) * 2 + x.par; }
+
+// Plane-major chunk (plane j's axis bits at [D j, D j + D), axis d at bit d of
+// its plane) -> axis-grouped chunk (axis d's plane bits at [d P, d P + P),
+// plane j at bit j).
+constexpr int grouped(int ch, int D, int P) {
+    int g = 0;
+    for (int j = 0; j < P; ++j)
+        for (int d = 0; d < D; ++d) g |= ((ch >> (D * j + d)) & 1) << (d * P + j);
+    return g;
+}
 constexpr int CODES = 27 * 8 * 2;
 
 template <int D> constexpr HilbertFsm<D> make() {
@@ -103,8 +116,9 @@ template <int D> constexpr HilbertFsm<D> make() {
             int out = 0;
             for (int j = F::P - 1; j >= 0; --j) out = (out << D) | plane(x, (ch >> (D * j)) & ((1 << D) - 1), D);
             const int nx = idx[code(x)];
-            t.enc[s * F::CH + ch] = (uint16_t)((nx << 8) | out);
-            t.dec[s * F::CH + out] = (uint16_t)((nx << 8) | ch);
+            const int g = grouped(ch, D, F::P);
+            t.enc[s * F::CH + g] = (uint16_t)((nx << 8) | out);
+            t.dec[s * F::CH + out] = (uint16_t)((nx << 8) | g);
         }
     }
     if (F::TOP) {
@@ -141,17 +155,21 @@ __device__ __forceinline__ void stage_hilbert(uint16_t* s_tab, bool enc) {
 
 template <int D> __device__ __forceinline__ uint64_t hilbert_key_fsm(const uint32_t* p, const uint16_t* s_enc) {
     using F = HilbertFsm<D>;
-    const uint64_t m = morton_key<D>(p);
     uint32_t st = 0;
     uint64_t k = 0;
     if constexpr (F::TOP == 1) {
-        const uint32_t e = s_enc[F::MAIN + (uint32_t)(m >> (D * (F::W - 1)))];
+        uint32_t v = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) v |= ((p[d] >> (F::W - 1)) & 1u) << d;
+        const uint32_t e = s_enc[F::MAIN + v];
         k = e & 0xFFu;
         st = e >> 8;
     }
 #pragma unroll
     for (int c = F::STEPS - 1; c >= 0; --c) {
-        const uint32_t ch = (uint32_t)(m >> (D * F::P * c)) & (F::CH - 1);
+        uint32_t ch = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ch |= ((p[d] >> (F::P * c)) & ((1u << F::P) - 1u)) << (d * F::P);
         const uint32_t e = s_enc[st * F::CH + ch];
         k = (k << (D * F::P)) | (e & 0xFFu);
         st = e >> 8;
@@ -162,20 +180,25 @@ template <int D> __device__ __forceinline__ uint64_t hilbert_key_fsm(const uint3
 template <int D> __device__ __forceinline__ void hilbert_point_fsm(uint64_t k, uint32_t* p, const uint16_t* s_dec) {
     using F = HilbertFsm<D>;
     uint32_t st = 0;
-    uint64_t m = 0;
+    uint32_t x[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = 0;
     if constexpr (F::TOP == 1) {
         const uint32_t e = s_dec[F::MAIN + (uint32_t)(k >> (D * (F::W - 1)))];
-        m = e & 0xFFu;
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = (e >> d) & 1u;
         st = e >> 8;
     }
 #pragma unroll
     for (int c = F::STEPS - 1; c >= 0; --c) {
         const uint32_t ch = (uint32_t)(k >> (D * F::P * c)) & (F::CH - 1);
         const uint32_t e = s_dec[st * F::CH + ch];
-        m = (m << (D * F::P)) | (e & 0xFFu);
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = (x[d] << F::P) | ((e >> (d * F::P)) & ((1u << F::P) - 1u));
         st = e >> 8;
     }
-    morton_point<D>(m, p);
+#pragma unroll
+    for (int d = 0; d < D; ++d) p[d] = x[d];
 }
 
 // Curve keys and points through the tables read straight from constant

@@ -155,6 +155,7 @@ struct psi_index_s {
     // node levels 0..h-1, level-major from the root
     psi::Buf inner;
     psi::Buf cinner, cleaf;  // packed boxes of the inner nodes and of the leaves
+    bool boxes_fresh = false;  // packed boxes match the current tree
     uint64_t n_inner = 0;
     uint32_t h = 0;
     std::vector<psi::LevelInfo> lv;
