@@ -704,21 +704,28 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) 
 }
 
 // Copies the ids of the leaves held by the lanes in `m` (lane x: count lc,
-// exclusive output position pos, slot) to out[o + pos ..], one leaf at a time
-// with the whole wave, so that every store is one contiguous run.
+// exclusive output position pos, slot) to out[o + pos ..], two leaves at a
+// time, one per half-wave, so that every store is two contiguous runs.
+// All lanes of the wave take part.
 template <int D>
 __device__ __forceinline__ void copy_leaf_ids(const TreeView& t, uint64_t m, uint32_t lc, uint32_t pos, uint32_t slot,
                                               uint64_t o, uint64_t lim, uint32_t* __restrict__ out) {
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_id(), hl = lane & 31u;
     while (m) {
-        const int x = __builtin_ctzll(m);
+        const uint32_t xa = (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
-        const uint32_t cx = (uint32_t)__builtin_amdgcn_readlane((int)lc, x);
-        const uint32_t px = (uint32_t)__builtin_amdgcn_readlane((int)pos, x);
-        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)slot, x);
-        const uint32_t* s = t.slots + (uint64_t)sx * (D + 1) * t.C + D * t.C;
-        for (uint32_t e = lane; e < cx; e += 64) {
-            const uint64_t dst = o + px + e;
+        uint32_t xb = 64u;  // no second leaf
+        if (m) {
+            xb = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+        }
+        const uint32_t mine = lane < 32u ? xa : xb;
+        const uint32_t c0 = shfl_u32(lc, (int)(mine & 63u)), p0 = shfl_u32(pos, (int)(mine & 63u)),
+                       s0 = shfl_u32(slot, (int)(mine & 63u));
+        const uint32_t cx = mine < 64u ? c0 : 0u;
+        const uint32_t* s = t.slots + (uint64_t)s0 * (D + 1) * t.C + D * t.C;
+        for (uint32_t e = hl; e < cx; e += 32) {
+            const uint64_t dst = o + p0 + e;
             if (dst < lim) out[dst] = s[e];
         }
     }
@@ -803,16 +810,27 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* 
             if (REPORT) o += tot;
             else cnt += tot;
         }
-        // straddling leaves, one entry per lane
+        // straddling leaves two at a time, one per half-wave (entry e of a
+        // leaf on lane e mod 32 of its half)
         uint64_t m = partial;
+        const uint32_t hl = lane & 31u;
         while (m) {
-            const uint32_t c = (uint32_t)__builtin_ctzll(m);
+            const uint32_t ca = (uint32_t)__builtin_ctzll(m);
             m &= m - 1;
-            const uint32_t rc = shfl_u32(r.cnt, (int)c);
-            const uint32_t rs = shfl_u32(r.slot, (int)c);
+            uint32_t cb = 64u;  // no second leaf
+            if (m) {
+                cb = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+            }
+            const uint32_t mine = lane < 32u ? ca : cb;
+            const uint32_t sc = shfl_u32(r.cnt, (int)(mine & 63u)), ss = shfl_u32(r.slot, (int)(mine & 63u));
+            const uint32_t rc = mine < 64u ? sc : 0u;
+            const uint32_t rs = mine < 64u ? ss : 0u;
+            const uint32_t rmax = max((uint32_t)__builtin_amdgcn_readlane((int)rc, 0),
+                                      (uint32_t)__builtin_amdgcn_readlane((int)rc, 32));
             const uint32_t* s = t.slots + (uint64_t)rs * (D + 1) * C;
-            for (uint32_t e0 = 0; e0 < rc; e0 += 64) {
-                const uint32_t e = e0 + lane;
+            for (uint32_t e0 = 0; e0 < rmax; e0 += 32) {
+                const uint32_t e = e0 + hl;
                 bool in = false;
                 if (e < rc) {
                     uint32_t p[D];

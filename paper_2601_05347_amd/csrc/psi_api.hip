@@ -111,9 +111,12 @@ constexpr uint64_t BUCKET_MIN_N = 1ull << 24;
 constexpr uint64_t XT_WORDS = 2 * XCD_CHUNKS * RADIX * 2 + XCD_CHUNKS * 4 + XCD_CHUNKS * 8 + 16;
 
 // counted: the chunk counts for these bucket bits are already in the buffer
-// (made while encoding).
+// (made while encoding). kmax (device, may be null): the largest key, read
+// back with the chunk tile counts; if its bucket bits differ from `top`,
+// *redo is set, *true_top receives them and nothing is sorted.
 psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uint64_t n, uint32_t top, bool counted,
-                       int* which) {
+                       int* which, const uint64_t* kmax = nullptr, uint32_t* true_top = nullptr,
+                       bool* redo = nullptr) {
     Sorter& S = ix->sorter;
     hipStream_t st = ix->st;
     psi_status s;
@@ -175,9 +178,23 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
         launch_chunk_offsets(st, cnt, n, off1, off2, tb1, tb2);
     }
     if ((s = last_launch()) != PSI_OK) return s;
-    if ((s = readback(ix, tb2.ntiles, XCD_CHUNKS * 4)) != PSI_OK) return s;
+    uint32_t* hq = static_cast<uint32_t*>(ix->pinned);
+    if ((s = hip_ok(hipMemcpyAsync(hq, tb2.ntiles, XCD_CHUNKS * 4, hipMemcpyDeviceToHost, st))) != PSI_OK) return s;
+    if (kmax && (s = hip_ok(hipMemcpyAsync(hq + XCD_CHUNKS, kmax, 8, hipMemcpyDeviceToHost, st))) != PSI_OK)
+        return s;
+    if ((s = hip_ok(hipStreamSynchronize(st))) != PSI_OK) return s;
+    if (kmax) {
+        uint64_t km;
+        std::memcpy(&km, hq + XCD_CHUNKS, 8);
+        const uint32_t bits = km ? 64u - (uint32_t)__builtin_clzll(km) : 0u;
+        *true_top = bits > 16 ? bits - 16 : 0u;
+        if (*true_top != top) {
+            *redo = true;
+            return PSI_OK;
+        }
+    }
     uint32_t max2 = 0;
-    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) max2 = std::max(max2, static_cast<const uint32_t*>(ix->pinned)[x]);
+    for (uint32_t x = 0; x < XCD_CHUNKS; ++x) max2 = std::max(max2, hq[x]);
     const XcdChunks xc1{tb1.first_tile, tb1.ntiles, tb1.pos_begin, tb1.pos_end};
     const XcdChunks xc2{tb2.first_tile, tb2.ntiles, tb2.pos_begin, tb2.pos_end};
     {
@@ -335,13 +352,13 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
             launch_encode_chunks(ix->st, ix->D, ix->curve, d_pts, n, keys, ix->err.as<uint32_t>(),
                                  S.kmax.as<uint64_t>(), guess, S.xt.as<uint32_t>());
         }
-        if ((s = last_launch()) != PSI_OK) return s;
-        if ((s = readback(ix, S.kmax.p, 8)) != PSI_OK) return s;
-        const uint64_t km = *static_cast<const uint64_t*>(ix->pinned);
-        const uint32_t bits = km ? 64u - (uint32_t)__builtin_clzll(km) : 0u;
-        const uint32_t top = bits > 16 ? bits - 16 : 0u;
+        // the sort starts on the guess; the largest key comes back with the
+        // first readback, and a wrong guess redoes the counts
+        uint32_t top = guess;
+        bool redo = false;
+        s = bucket_sort(ix, keys, id_base, n, guess, true, &w, S.kmax.as<uint64_t>(), &top, &redo);
+        if (s == PSI_OK && redo) s = bucket_sort(ix, keys, id_base, n, top, false, &w);
         ix->bucket_top = top;
-        s = bucket_sort(ix, keys, id_base, n, top, top == guess, &w);
     } else {
         {
             ProfScope ps(ix, "encode_hist", n * (4 * ix->D + 8));
