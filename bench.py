@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--ops", default="build,insert,delete,knn,range")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-sample", type=int, default=16_000_000, help="points in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=32_000_000, help="points in the oracle's timed sample")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests per stream")
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
