@@ -12,8 +12,8 @@ log-uniform in 2^8..2^18. Inputs are resident in HBM before timing starts.
 (n + m + m) / (t_build + t_insert + t_delete). kNN queries/s and range
 boxes/s of the same steps are reported under `phases`.
 
-Prints ONE JSON line. `--gpus N` with N > 1 is refused: this build runs on one
-GPU only.
+Prints ONE JSON line. `--gpus N` with N > 1 is refused: the library runs on
+one GPU (the sharded design is described but not built).
 """
 from __future__ import annotations
 
@@ -396,7 +396,7 @@ def _bench_multi(args, num, dev, stream, np, torch, psi, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":

@@ -28,7 +28,7 @@ def test_header_declares_the_paper_calls():
 def test_library_exports_every_declared_symbol():
     import paper_2601_05347_amd as psi
     if not os.path.exists(psi.LIB_PATH):
-        pytest.fail("libpsi.so is not built (run __graft_entry__.build())")
+        pytest.fail("libpsi.so is not built (python -m paper_2601_05347_amd.build)")
     lib = ctypes.CDLL(psi.LIB_PATH)
     missing = [n for n in declared_symbols() if not hasattr(lib, n)]
     assert not missing, missing
