@@ -77,14 +77,20 @@ def parse():
 
 
 def csrc_hash() -> str:
-    """SHA-256 over the library's kernel sources (names and contents, sorted)."""
+    """SHA-256 over the library's kernel sources (names and code, sorted),
+    with comments and blank space left out: counters taken on the code stay
+    valid across comment edits."""
     import hashlib
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2601_05347_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):
+            code = open(os.path.join(d, f)).read()
+            code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+            code = re.sub(r"//[^\n]*", " ", code)
             h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+            h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

@@ -687,8 +687,9 @@ __global__ __launch_bounds__(256) void k_range(TreeView t, const uint32_t* __res
 // One wave per box. Expanding a node tests all its children at once (one
 // lane per child); children that straddle the box are remembered in a
 // per-level mask (a stack of masks in LDS) and expanded depth first. Leaves
-// that straddle the box are scanned one entry per lane; whole subtrees inside
-// the box add their counts, or, for reports, are copied one leaf per lane.
+// that straddle the box are scanned two at a time, one per half-wave and one
+// entry per lane; whole subtrees inside the box add their counts, or, for
+// reports, have their leaves' ids copied two leaves at a time.
 constexpr int RW_WAVES = 4;
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
