@@ -337,6 +337,110 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     }
 }
 
+// Small batches: every LSD pass of pl inside one workgroup, one launch in
+// all. The pairs stay in registers; each pass ranks them (wave ballots, as
+// the global passes: stable, item order = position order), writes them to
+// their new positions in one LDS copy and reads back the items of the new
+// order. 16 waves; wave w owns positions [w * SMALL_PER_WAVE, ...), lane l
+// of item i position w * SMALL_PER_WAVE + i * 64 + l.
+constexpr int SMALL_WAVES = 16, SMALL_IPT = SORT_SMALL_MAX / (SMALL_WAVES * 64);
+constexpr uint32_t SMALL_PER_WAVE = SMALL_IPT * 64;
+static_assert(SMALL_IPT * SMALL_WAVES * 64 == SORT_SMALL_MAX, "whole items per thread");
+__global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ iin, uint32_t id_base,
+                                                     uint32_t n, PassList pl, uint64_t* __restrict__ kout,
+                                                     uint32_t* __restrict__ iout) {
+    __shared__ uint64_t s_k[SORT_SMALL_MAX];
+    __shared__ uint32_t s_i[SORT_SMALL_MAX];
+    __shared__ uint32_t s_cnt[SMALL_WAVES][RADIX];
+    __shared__ uint32_t s_ws[RADIX / 64];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const uint32_t lane = lane_id();
+    uint64_t k[SMALL_IPT];
+    uint32_t id[SMALL_IPT];
+#pragma unroll
+    for (int i = 0; i < SMALL_IPT; ++i) {
+        const uint32_t pos = w * SMALL_PER_WAVE + i * 64 + lane;
+        k[i] = pos < n ? kin[pos] : 0ull;
+        id[i] = pos < n ? (iin ? iin[pos] : id_base + pos) : 0u;
+    }
+    for (int p = 0; p < pl.n; ++p) {
+        for (int x = tid; x < SMALL_WAVES * RADIX; x += blockDim.x) (&s_cnt[0][0])[x] = 0;
+        __syncthreads();
+        const uint32_t shift = pl.shift[p];
+        const bool by_id = pl.src[p] == 1;
+        uint32_t rk[SMALL_IPT];
+#pragma unroll
+        for (int i = 0; i < SMALL_IPT; ++i) {
+            const bool ok = w * SMALL_PER_WAVE + i * 64 + lane < n;
+            const uint32_t d = (uint32_t)((by_id ? (uint64_t)id[i] : k[i]) >> shift) & (RADIX - 1);
+            uint64_t peers = ballot(ok);
+#pragma unroll
+            for (int b = 0; b < RADIX_BITS; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t below = count_below(peers);
+            const uint32_t base = s_cnt[w][d];
+            if (ok && below == 0) s_cnt[w][d] = base + (uint32_t)__popcll(peers);
+            rk[i] = base + below;
+        }
+        __syncthreads();
+        // thread d < 256: its digit's column becomes exclusive over the waves,
+        // then every slot gets the digit's start (exclusive prefix over digits)
+        uint32_t tot = 0;
+        if (tid < RADIX) {
+            for (int x = 0; x < SMALL_WAVES; ++x) {
+                const uint32_t c = s_cnt[x][tid];
+                s_cnt[x][tid] = tot;
+                tot += c;
+            }
+        }
+        uint32_t v = tot;  // inclusive scan inside each wave (all lanes take part)
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = shfl_u32(v, (int)lane - o);
+            if (lane >= (uint32_t)o) v += t;
+        }
+        if (tid < RADIX && lane == 63) s_ws[w] = v;
+        __syncthreads();
+        if (tid < RADIX) {
+            uint32_t add = 0;
+            for (int i = 0; i < w; ++i) add += s_ws[i];
+            const uint32_t excl = v + add - tot;
+            for (int x = 0; x < SMALL_WAVES; ++x) s_cnt[x][tid] += excl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SMALL_IPT; ++i) {
+            if (w * SMALL_PER_WAVE + i * 64 + lane < n) {
+                const uint32_t d = (uint32_t)((by_id ? (uint64_t)id[i] : k[i]) >> shift) & (RADIX - 1);
+                const uint32_t dst = s_cnt[w][d] + rk[i];
+                s_k[dst] = k[i];
+                s_i[dst] = id[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SMALL_IPT; ++i) {
+            const uint32_t pos = w * SMALL_PER_WAVE + i * 64 + lane;
+            if (pos < n) {
+                k[i] = s_k[pos];
+                id[i] = s_i[pos];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SMALL_IPT; ++i) {
+        const uint32_t pos = w * SMALL_PER_WAVE + i * 64 + lane;
+        if (pos < n) {
+            kout[pos] = k[i];
+            iout[pos] = id[i];
+        }
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -528,10 +632,44 @@ void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base) {
 
 uint64_t scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
+// Arrays of at most SCAN_SMALL words: one workgroup of 1024 threads scans
+// each in one launch (a thread owns 16 consecutive words).
+constexpr uint64_t SCAN_SMALL = 1024 * 16;
+__global__ __launch_bounds__(1024) void k_scan_small(ScanSet s) {
+    __shared__ uint32_t s_w[16];
+    if (s.gate && *s.gate == 0) return;
+    const int y = blockIdx.x;
+    const uint32_t* __restrict__ in = s.in[y];
+    uint32_t* __restrict__ out = s.out[y];
+    const uint64_t n = s.n[y];
+    const uint64_t base = (uint64_t)threadIdx.x * 16;
+    uint32_t v[16];
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0u;
+        t += v[i];
+    }
+    const uint32_t inc = block_incl_scan256(t, s_w);  // any block of up to 16 waves
+    uint32_t run = inc - t;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == blockDim.x - 1 && s.total[y]) *s.total[y] = inc;
+}
+
 void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp) {
     ScanSet z = s;
     uint64_t tiles = 0, stride = 0;
     for (int y = k; y < SCAN_MULTI; ++y) z.in[y] = nullptr, z.out[y] = nullptr, z.total[y] = nullptr, z.n[y] = 0;
+    bool small = true;
+    for (int y = 0; y < k; ++y) small = small && z.n[y] <= SCAN_SMALL;
+    if (small) {
+        hipLaunchKernelGGL(k_scan_small, dim3(k), dim3(1024), 0, st, z);
+        return;
+    }
     for (int y = 0; y < k; ++y) {
         tiles = std::max<uint64_t>(tiles, (z.n[y] + SCAN_TILE - 1) / SCAN_TILE);
         stride = std::max<uint64_t>(stride, scan_tmp_words(z.n[y]));
@@ -539,6 +677,11 @@ void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp) {
     if (tiles) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles, k), dim3(SCAN_WG), 0, st, z, tmp, stride);
     hipLaunchKernelGGL(k_scan_sums, dim3(k), dim3(SCAN_WG), 0, st, z, tmp, stride);
     if (tiles) hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles, k), dim3(SCAN_WG), 0, st, z, tmp, stride);
+}
+
+void launch_sort_small(hipStream_t st, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint32_t n,
+                       const PassList& pl, uint64_t* kout, uint32_t* iout) {
+    if (n) hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, kin, iin, id_base, n, pl, kout, iout);
 }
 
 void launch_scan_u32(hipStream_t st, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,

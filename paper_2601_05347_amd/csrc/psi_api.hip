@@ -52,6 +52,14 @@ psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, ui
     psi_status s;
     hipStream_t st = ix->st;
     const bool cap = capturing(st);
+    if (n <= SORT_SMALL_MAX) {  // every pass in one workgroup's LDS, one launch
+        if ((s = ensure_q(S.k[0], std::max<uint64_t>(n, 1) * 8, st)) != PSI_OK) return s;
+        if ((s = ensure_q(S.i[0], std::max<uint64_t>(n, 1) * 4, st)) != PSI_OK) return s;
+        ProfScope ps(ix, fam, n * 24 * pl.n);
+        launch_sort_small(st, kin, iin, id_base, (uint32_t)n, pl, S.k[0].as<uint64_t>(), S.i[0].as<uint32_t>());
+        *which = 0;
+        return last_launch();
+    }
     if ((s = ensure_q(S.hist, MAX_PASSES * RADIX * 4, st)) != PSI_OK) return s;
     if ((s = ensure_q(S.off, MAX_PASSES * RADIX * 4, st)) != PSI_OK) return s;
     if ((s = ensure_q(S.ctr, MAX_PASSES * 4, st)) != PSI_OK) return s;

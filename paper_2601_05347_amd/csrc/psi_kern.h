@@ -23,6 +23,13 @@ struct PassList {
     uint8_t shift[MAX_PASSES];
 };
 
+// Up to SORT_SMALL_MAX pairs: all passes of pl (src 0: key byte at shift,
+// 1: id byte) in one launch of one workgroup; stable, like the global passes.
+// iin == nullptr: id = id_base + position.
+constexpr uint32_t SORT_SMALL_MAX = 10240;
+void launch_sort_small(hipStream_t st, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint32_t n,
+                       const PassList& pl, uint64_t* kout, uint32_t* iout);
+
 // Histograms of every pass's digit over the input pairs; ids == nullptr means
 // id = id_base + position. hist must be zeroed ([pl.n][256] u32).
 void launch_hist_pairs(hipStream_t st, const uint64_t* keys, const uint32_t* ids, uint32_t id_base,
