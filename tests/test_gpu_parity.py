@@ -66,7 +66,7 @@ def test_encode_rejects_out_of_range(psi, dim):
 
 
 # -------------------------------------------------------------------- sort
-@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 300_007])
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 10_240, 10_241, 300_007])  # 10240: the one-workgroup sort's limit
 def test_sort_pairs_parity(psi, n):
     say(f"sort n={n}")
     r = synth.draws(synth.stream_key(n, 9), 0, 2 * n)

@@ -192,3 +192,20 @@ def test_small_config_end_to_end(psi):
     P.insert(ins)
     P.delete(synth.delete_ids(np.arange(1_100_000, dtype=np.uint32), 100_000, seed=1))
     P.verify(q, 10)
+
+
+@pytest.mark.parametrize("m", [10_240, 10_241, 16_384, 16_385])
+def test_batch_sizes_at_the_one_launch_limits(psi, m):
+    """Batches at the limits of the one-workgroup sort (10240 pairs) and scan
+    (16384 words), on both sides, with random delete order and repeats."""
+    say(f"batch limits m={m}")
+    data, ins, q = synth.workload("uniform", 3, 21, seed=91, n=60_000, n_insert=m, n_query=300)
+    P = Pair(psi, 3, 1)
+    P.build(data)
+    P.insert(ins)
+    P.verify(queries=q)
+    live = np.arange(P.r.next_id(), dtype=np.uint32)
+    dels = synth.delete_ids(live, m - 5, seed=92)
+    dels = np.concatenate([dels, dels[:5]])  # five repeated ids: m in all
+    P.delete(dels[np.argsort(synth.draws(synth.stream_key(93, synth.P_AUX), 0, m), kind="stable")])
+    P.verify(queries=q)
