@@ -1,0 +1,158 @@
+"""Pins of the P-Orth oracle (Sec. 3, Alg. 1) against definitions it must meet.
+
+The oracle walks Alg. 1's steps (a lambda-level skeleton from region
+midpoints, a sieve, recursion, merge-up). These tests check its result
+against what an orth-tree is by definition, computed a different way: the
+cells of a regular grid hierarchy taken straight from coordinate bits, one
+level at a time, over all points (brute force). A wrong midpoint, a dropped
+merge, a child order slip or a box error fails one of them.
+"""
+import numpy as np
+import pytest
+
+from oracle import orth
+
+from synth import points
+
+
+def cells(pts, dim, level):
+    """Cell of every point at a level: low corner, from the coordinate bits."""
+    W = orth.domain_bits(dim)
+    sh = W - level
+    return (pts >> sh) << sh
+
+
+def brute_force_nodes(pts, dim, phi):
+    """{(level, corner): (count, leaf)} of the canonical orth-tree: the root,
+    and every non-empty cell whose parent cell holds more than phi points;
+    a node is a leaf when it holds at most phi points or is a single grid
+    point."""
+    W = orth.domain_bits(dim)
+    pts = np.asarray(pts, dtype=np.int64)
+    out = {}
+    if len(pts) == 0:
+        return out
+    out[(0, (0,) * dim)] = (len(pts), len(pts) <= phi)
+    for level in range(1, W + 1):
+        par = cells(pts, dim, level - 1)
+        pu, pc = np.unique(par, axis=0, return_counts=True)
+        big = {tuple(r) for r, c in zip(pu, pc) if c > phi}
+        if not big:
+            break
+        cu, cc = np.unique(cells(pts, dim, level), axis=0, return_counts=True)
+        pcell = cells(cu, dim, level - 1)
+        for r, c, p in zip(cu, cc, pcell):
+            if tuple(p) in big:
+                out[(level, tuple(int(x) for x in r))] = (int(c), bool(c <= phi or level == W))
+    return out
+
+
+def tree_nodes(root):
+    out = {}
+
+    def walk(nd):
+        out[(nd.level, tuple(int(x) for x in nd.corner))] = (nd.count, nd.leaf)
+        for c in nd.children:
+            walk(c)
+
+    if root is not None:
+        walk(root)
+    return out
+
+
+def inputs():
+    yield "uniform2", 2, points("uniform", 3000, 2, bits=31, seed=1)
+    yield "uniform3", 3, points("uniform", 3000, 3, bits=21, seed=2)
+    yield "varden3", 3, points("varden", 3000, 3, bits=21, seed=3)
+    yield "small-domain2", 2, points("uniform", 2000, 2, bits=6, seed=4)  # many equal points
+    yield "sweepline2", 2, points("sweepline", 2000, 2, bits=31, seed=5)
+
+
+@pytest.mark.parametrize("name,dim,pts", list(inputs()), ids=[x[0] for x in inputs()])
+@pytest.mark.parametrize("phi", [2, 8, 32])
+def test_tree_is_the_canonical_orth_tree(name, dim, pts, phi):
+    root = orth.build(pts, dim, phi)
+    assert tree_nodes(root) == brute_force_nodes(pts, dim, phi)
+
+
+@pytest.mark.parametrize("name,dim,pts", list(inputs())[:3], ids=[x[0] for x in inputs()][:3])
+def test_skeleton_height_does_not_change_the_tree(name, dim, pts):
+    ref = orth.preorder(orth.build(pts, dim, 8, lam=1), dim)
+    for lam in (2, 3, 5):
+        got = orth.preorder(orth.build(pts, dim, 8, lam=lam), dim)
+        for k in ("level", "corner", "leaf", "count", "lo", "hi", "end", "first"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"lam={lam} {k}")
+        for a, b in zip(got["leaf_ids"], ref["leaf_ids"]):
+            np.testing.assert_array_equal(np.sort(a), np.sort(b))
+
+
+@pytest.mark.parametrize("name,dim,pts", list(inputs()), ids=[x[0] for x in inputs()])
+def test_boxes_regions_and_leaves(name, dim, pts):
+    phi = 8
+    pts = np.asarray(pts, dtype=np.int64)
+    W = orth.domain_bits(dim)
+    pre = orth.preorder(orth.build(pts, dim, phi), dim)
+    # every point in exactly one leaf; leaves cover the points in preorder
+    all_ids = np.concatenate(pre["leaf_ids"])
+    np.testing.assert_array_equal(np.sort(all_ids), np.arange(len(pts)))
+    N = len(pre["level"])
+    li = 0
+    for v in range(N):
+        side = 1 << (W - pre["level"][v])
+        lo_r, hi_r = pre["corner"][v], pre["corner"][v] + side - 1
+        # the subtree's points: the leaves between v and its end
+        nl = int(pre["leaf"][v:pre["end"][v]].sum())
+        ids = np.concatenate(pre["leaf_ids"][li:li + nl]) if pre["leaf"][v] or nl else np.zeros(0, np.int64)
+        p = pts[ids]
+        assert len(ids) == pre["count"][v]
+        np.testing.assert_array_equal(pre["lo"][v], p.min(axis=0))
+        np.testing.assert_array_equal(pre["hi"][v], p.max(axis=0))
+        assert (p >= lo_r).all() and (p <= hi_r).all()  # inside the region
+        if pre["leaf"][v]:
+            assert pre["count"][v] <= phi or pre["level"][v] == W
+            li += 1
+        else:
+            assert pre["count"][v] > phi
+            # children: consecutive regions one level down, increasing index
+            c, kids = v + 1, []
+            while c < pre["end"][v]:
+                kids.append(c)
+                c = pre["end"][c]
+            assert all(pre["level"][k] == pre["level"][v] + 1 for k in kids)
+            half = side // 2
+            idx = [sum(((pre["corner"][k][d] - pre["corner"][v][d]) // half) << d for d in range(dim)) for k in kids]
+            assert idx == sorted(set(idx))
+            assert pre["end"][kids[-1]] == pre["end"][v]
+
+
+def test_empty_and_single_leaf():
+    assert orth.build(np.zeros((0, 3), np.uint32), 3, 32) is None
+    root = orth.build(points("uniform", 32, 3, bits=21, seed=9), 3, 32)
+    assert root.leaf and root.level == 0 and root.count == 32
+
+
+def test_equal_points_make_a_chain_to_one_grid_point():
+    # phi + 5 copies of one point: every level splits off a single child down
+    # to the grid point, which holds them all
+    for dim in (2, 3):
+        W = orth.domain_bits(dim)
+        p = np.tile(np.array([[5, 9, 1][:dim]], dtype=np.uint32), (13, 1))
+        pre = orth.preorder(orth.build(p, dim, 8), dim)
+        assert len(pre["level"]) == W + 1
+        np.testing.assert_array_equal(pre["level"], np.arange(W + 1))
+        assert pre["leaf"].tolist() == [False] * W + [True]
+        assert (pre["count"] == 13).all()
+        assert (pre["end"] == W + 1).all()
+
+
+def test_four_quadrants_by_hand():
+    # 2D, phi = 2: three points in three quadrants of the domain -> the root
+    # splits once; children in index order (x upper = bit 0, y upper = bit 1)
+    h = 1 << 30
+    p = np.array([[h + 1, 3], [2, h + 7], [h + 5, h + 5]], dtype=np.uint32)
+    pre = orth.preorder(orth.build(p, 2, 2), 2)
+    assert pre["leaf"].tolist() == [False, True, True, True]
+    assert [tuple(c) for c in pre["corner"][1:]] == [(h, 0), (0, h), (h, h)]
+    assert [a.tolist() for a in pre["leaf_ids"]] == [[0], [1], [2]]
+    assert pre["end"].tolist() == [4, 2, 3, 4]
+    assert pre["first"].tolist() == [-1, 0, 1, 2]
