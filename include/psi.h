@@ -231,6 +231,68 @@ psi_status psi_graph_end(void* hip_stream, psi_graph* out);
 psi_status psi_graph_launch(psi_graph g, void* hip_stream);
 psi_status psi_graph_destroy(psi_graph g);
 
+/* --- P-Orth tree (Sec. 3) ---------------------------------------------- */
+
+/* A second index kind: the parallel orth-tree of Sec. 3 (a quadtree in 2D,
+ * an octree in 3D). Every node is a cell of the regular grid hierarchy over
+ * the coordinate domain [0, 2^W)^D (W = 31 in 2D, 21 in 3D; the same
+ * coordinate limits as psi_build): a cell is split at its midpoint on every
+ * axis (the spatial median), so it has up to 2^D children, one per non-empty
+ * sub-cell. A cell with more than leaf_size points is an interior node; a
+ * cell with at most leaf_size points is a leaf, and so is a one-point cell
+ * holding more (equal points cannot be split). This is the tree Alg. 1
+ * builds after merging every subtree of at most leaf_size points into a
+ * leaf; its shape does not depend on the skeleton height of Alg. 1. Boxes are
+ * the exact bounding boxes of the points below each node. Static: no
+ * updates (Alg. 2 is not provided). */
+typedef struct psi_orth_s* psi_orth;
+
+/* prm: dim 2 or 3, curve must be PSI_MORTON (the tree's child order),
+ * leaf_size 2..32, fanout ignored, flags a subset of PSI_FLAG_INPUT_ORDER,
+ * PSI_FLAG_SORT_BUCKETS, PSI_FLAG_SORT_LSD (as for psi_create). Queries and
+ * builds run on hip_stream. */
+psi_status psi_orth_create(const psi_params* prm, void* hip_stream, psi_orth* out);
+psi_status psi_orth_destroy(psi_orth o);
+
+/* Builds the tree over n points (device, n x dim u32, row major; ids are
+ * positions 0..n-1), replacing the previous tree. n < 2^31. Waits for the
+ * stream twice (leaf and node counts). PSI_E_RANGE (and an empty tree) if a
+ * coordinate is out of range. Not under graph capture (PSI_E_STATE). */
+psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n);
+
+/* Exact k nearest neighbours (k = 1..16), output as psi_knn. */
+psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids,
+                        uint64_t* d_d2);
+/* Points inside closed boxes (nb x [lo[dim], hi[dim]]), as psi_range_count
+ * and psi_range_report; a report lists each box's ids in the tree's
+ * depth-first order. */
+psi_status psi_orth_range_count(psi_orth o, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts);
+psi_status psi_orth_range_report(psi_orth o, const uint32_t* d_boxes, uint64_t nb, const uint64_t* d_offsets,
+                                 uint32_t* d_ids);
+
+/* Waits for the stream; returns and clears a latched error as psi_sync. */
+psi_status psi_orth_sync(psi_orth o);
+
+/* Node count, leaf count and height (levels of the deepest leaf + 1; 0 for
+ * an empty tree). */
+psi_status psi_orth_shape(psi_orth o, uint64_t* h_nodes, uint64_t* h_leaves, uint32_t* h_height);
+
+/* Copies the tree out (either pointer may be null). d_nodes: nodes x 8 u32 in
+ * depth-first preorder, children in Morton order: lo[3], hi[3] (the third
+ * axis 0 in 2D), then for an interior node (index one past its subtree,
+ * points below it) and for a leaf (first point, count | 0x80000000).
+ * d_pts: n x 4 u32 {x, y, z or 0, id}, leaves' points contiguous, in the
+ * order leaves appear. */
+psi_status psi_orth_export(psi_orth o, uint32_t* d_nodes, uint32_t* d_pts);
+
+/* Timing of the tree's kernels, as psi_prof_* (families "orth_marks",
+ * "orth_nodes", "orth_boxes", "orth_knn", "orth_range_count",
+ * "orth_range_report", plus the sort's). */
+psi_status psi_orth_prof_enable(psi_orth o, int on);
+psi_status psi_orth_prof_reset(psi_orth o);
+psi_status psi_orth_prof_get(psi_orth o, const char* family, double* h_ms, uint64_t* h_launches,
+                             uint64_t* h_bytes);
+
 /* --- kernel timing ------------------------------------------------------ */
 
 /* When enabled, every kernel launch of the index is bracketed by HIP events

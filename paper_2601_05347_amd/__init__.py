@@ -63,6 +63,18 @@ SIGNATURES = {
     "psi_graph_end": (_i, [_P, _P]),
     "psi_graph_launch": (_i, [_P, _P]),
     "psi_graph_destroy": (_i, [_P]),
+    "psi_orth_create": (_i, [_P, _P, _P]),
+    "psi_orth_destroy": (_i, [_P]),
+    "psi_orth_build": (_i, [_P, _P, _u64]),
+    "psi_orth_knn": (_i, [_P, _P, _u64, _u32, _P, _P]),
+    "psi_orth_range_count": (_i, [_P, _P, _u64, _P]),
+    "psi_orth_range_report": (_i, [_P, _P, _u64, _P, _P]),
+    "psi_orth_sync": (_i, [_P]),
+    "psi_orth_shape": (_i, [_P, _P, _P, _P]),
+    "psi_orth_export": (_i, [_P, _P, _P]),
+    "psi_orth_prof_enable": (_i, [_P, _i]),
+    "psi_orth_prof_reset": (_i, [_P]),
+    "psi_orth_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
     "psi_prof_enable": (_i, [_P, _i]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
@@ -320,6 +332,66 @@ def psi_prof_get(h, family: str):
     return ms.value, n.value, b.value
 
 
+def psi_orth_create(dim: int, leaf_size: int = 32, flags: int = 0, stream=None):
+    h = C.c_void_p()
+    prm = psi_params(dim, MORTON, leaf_size, 8, flags)
+    _check(lib().psi_orth_create(C.byref(prm), _stream_ptr(stream), C.byref(h)), "psi_orth_create")
+    return h
+
+
+def psi_orth_destroy(h):
+    _check(lib().psi_orth_destroy(h), "psi_orth_destroy")
+
+
+def psi_orth_build(h, pts, n: int):
+    _check(lib().psi_orth_build(h, _dev_ptr(pts), n), "psi_orth_build")
+
+
+def psi_orth_knn(h, q, nq: int, k: int, ids, d2):
+    _check(lib().psi_orth_knn(h, _dev_ptr(q), nq, k, _dev_ptr(ids), _dev_ptr(d2)), "psi_orth_knn")
+
+
+def psi_orth_range_count(h, boxes, nb: int, counts):
+    _check(lib().psi_orth_range_count(h, _dev_ptr(boxes), nb, _dev_ptr(counts)), "psi_orth_range_count")
+
+
+def psi_orth_range_report(h, boxes, nb: int, offsets, ids):
+    _check(lib().psi_orth_range_report(h, _dev_ptr(boxes), nb, _dev_ptr(offsets), _dev_ptr(ids)),
+           "psi_orth_range_report")
+
+
+def psi_orth_sync(h):
+    _check(lib().psi_orth_sync(h), "psi_orth_sync")
+
+
+def psi_orth_shape(h):
+    nn = C.c_uint64()
+    nl = C.c_uint64()
+    hh = C.c_uint32()
+    _check(lib().psi_orth_shape(h, C.byref(nn), C.byref(nl), C.byref(hh)), "psi_orth_shape")
+    return nn.value, nl.value, hh.value
+
+
+def psi_orth_export(h, nodes, pts):
+    _check(lib().psi_orth_export(h, _dev_ptr(nodes), _dev_ptr(pts)), "psi_orth_export")
+
+
+def psi_orth_prof_enable(h, on: bool):
+    _check(lib().psi_orth_prof_enable(h, 1 if on else 0), "psi_orth_prof_enable")
+
+
+def psi_orth_prof_reset(h):
+    _check(lib().psi_orth_prof_reset(h), "psi_orth_prof_reset")
+
+
+def psi_orth_prof_get(h, family: str):
+    ms = C.c_double()
+    n = C.c_uint64()
+    b = C.c_uint64()
+    _check(lib().psi_orth_prof_get(h, family.encode(), C.byref(ms), C.byref(n), C.byref(b)), "psi_orth_prof_get")
+    return ms.value, n.value, b.value
+
+
 # ------------------------------------------------------------ convenience
 
 class Index:
@@ -459,6 +531,95 @@ class Index:
 
     def prof_get(self, family: str):
         return psi_prof_get(self._h, family)
+
+
+ORTH_LEAF = 0x80000000
+
+
+class Orth:
+    """A P-Orth tree (quadtree / octree) on the current ROCm device."""
+
+    def __init__(self, dim: int, leaf_size: int = 32, device="cuda", stream=None, flags: int = 0):
+        torch = _torch()
+        self.dim, self.leaf_size = dim, leaf_size
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = psi_orth_create(dim, leaf_size, flags, self.stream)
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            psi_orth_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pts(self, pts):
+        return _as_u32(pts, self.device).reshape(-1, self.dim).contiguous()
+
+    def build(self, pts):
+        t = self._pts(pts)
+        self.n = 0
+        psi_orth_build(self._h, t, t.shape[0])
+        self.n = t.shape[0]
+        return self
+
+    def knn(self, q, k: int):
+        torch = _torch()
+        t = self._pts(q)
+        nq = t.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        psi_orth_knn(self._h, t, nq, k, ids, d2)
+        return ids, d2
+
+    def range_count(self, boxes):
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = torch.empty(b.shape[0], dtype=torch.int64, device=self.device)
+        psi_orth_range_count(self._h, b, b.shape[0], cnt)
+        return cnt
+
+    def range_report(self, boxes, counts=None):
+        """Returns (offsets[nb+1], ids); ids of a box in the tree's preorder."""
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = self.range_count(b) if counts is None else counts
+        off = torch.zeros(b.shape[0] + 1, dtype=torch.int64, device=self.device)
+        torch.cumsum(cnt, 0, out=off[1:])
+        total = int(off[-1].item())
+        ids = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
+        psi_orth_range_report(self._h, b, b.shape[0], off, ids)
+        return off, ids[:total]
+
+    def sync(self):
+        psi_orth_sync(self._h)
+
+    def shape(self):
+        """(nodes, leaves, height)"""
+        return psi_orth_shape(self._h)
+
+    def export(self):
+        """(nodes u32[N, 8], pts u32[n, 4]) as numpy; layout in include/psi.h."""
+        torch = _torch()
+        N = self.shape()[0]
+        nodes = torch.empty((max(N, 1), 8), dtype=torch.int32, device=self.device)
+        pts = torch.empty((max(self.n, 1), 4), dtype=torch.int32, device=self.device)
+        psi_orth_export(self._h, nodes, pts)
+        return to_u32(nodes[:N]), to_u32(pts[:self.n])
+
+    def prof_enable(self, on=True):
+        psi_orth_prof_enable(self._h, on)
+
+    def prof_reset(self):
+        psi_orth_prof_reset(self._h)
+
+    def prof_get(self, family: str):
+        return psi_orth_prof_get(self._h, family)
 
 
 class MultiIndex:

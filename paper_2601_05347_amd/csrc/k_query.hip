@@ -33,35 +33,8 @@ __device__ __forceinline__ uint64_t box_dist(const uint32_t* q, const NodeRec& r
     return r.cnt ? s : PAD_D2;
 }
 
-template <int D>
-__device__ __forceinline__ uint64_t pt_dist(const uint32_t* q, const uint32_t* p) {
-    uint64_t s = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const uint64_t x = q[d] > p[d] ? q[d] - p[d] : p[d] - q[d];
-        s += x * x;
-    }
-    return s;
-}
-
 __device__ __forceinline__ NodeRec fetch(const TreeView& t, const LevelInfo* lv, uint32_t l, uint64_t i) {
     return l == t.h ? t.leaf[i] : t.inner[lv[l].off + i];
-}
-
-// Insert (d, id) into an ascending list of K pairs held in registers.
-template <int K>
-__device__ __forceinline__ void topk_insert(uint64_t (&bd)[K], uint32_t (&bi)[K], uint64_t d, uint32_t id) {
-#pragma unroll
-    for (int j = K - 1; j > 0; --j) {
-        const bool shift = pair_less(d, id, bd[j - 1], bi[j - 1]);
-        const bool here = !shift && pair_less(d, id, bd[j], bi[j]);
-        bd[j] = shift ? bd[j - 1] : (here ? d : bd[j]);
-        bi[j] = shift ? bi[j - 1] : (here ? id : bi[j]);
-    }
-    if (pair_less(d, id, bd[0], bi[0])) {
-        bd[0] = d;
-        bi[0] = id;
-    }
 }
 
 // ------------------------------------------------------- kNN, lane per query

@@ -324,18 +324,11 @@ psi_status build_nodes(psi_index ix) {
     return last_launch();
 }
 
-// Fresh build of n points whose ids are id_base .. id_base + n - 1 (Alg. 3).
-psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base) {
+// Curve keys of n points (written to the id table at id_base) and the pairs
+// (key, id_base + position) sorted by key, then id, into sorter.k/i[*which]
+// (Alg. 3's sort step). Requires n > 0 and the id table sized for them.
+psi_status encode_sort(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base, int* which) {
     psi_status s;
-    const uint64_t idn = (uint64_t)id_base + n;
-    if ((s = ix->idkey.grow_keep(idn * 8, (uint64_t)id_base * 8, ix->st)) != PSI_OK) return s;
-    ix->L = 0;
-    ix->slot_top = 0;
-    ix->n_free = 0;
-    if (n == 0) {
-        ix->n_live = 0;
-        return build_nodes(ix);
-    }
     Sorter& S = ix->sorter;
     if ((s = S.hist.ensure(MAX_PASSES * RADIX * 4)) != PSI_OK) return s;
     launch_fill_u32(ix->st, S.hist.as<uint32_t>(), 8 * RADIX, 0u);
@@ -375,7 +368,25 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
         }
         s = sort_pairs(ix, keys, nullptr, id_base, n, false, true, &w, "radix_pass");
     }
-    if (s != PSI_OK) return s;
+    *which = w;
+    return s;
+}
+
+// Fresh build of n points whose ids are id_base .. id_base + n - 1 (Alg. 3).
+psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base) {
+    psi_status s;
+    const uint64_t idn = (uint64_t)id_base + n;
+    if ((s = ix->idkey.grow_keep(idn * 8, (uint64_t)id_base * 8, ix->st)) != PSI_OK) return s;
+    ix->L = 0;
+    ix->slot_top = 0;
+    ix->n_free = 0;
+    if (n == 0) {
+        ix->n_live = 0;
+        return build_nodes(ix);
+    }
+    int w = 0;
+    if ((s = encode_sort(ix, d_pts, n, id_base, &w)) != PSI_OK) return s;
+    Sorter& S = ix->sorter;
     const uint64_t L = (n + ix->phi - 1) / ix->phi;
     const int c = ix->cur;
     if ((s = ix->slots.ensure(L * ix->slot_words() * 4)) != PSI_OK) return s;
@@ -401,7 +412,7 @@ psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id
 // Query points are also range-checked here (errors are latched).
 static const uint64_t ORDER_MIN = 4096;
 
-static psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool boxes, const uint32_t** order) {
+psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool boxes, const uint32_t** order) {
     *order = nullptr;
     const bool sort = n >= ORDER_MIN && !(ix->flags & PSI_FLAG_INPUT_ORDER);
     if (boxes && !sort) return PSI_OK;

@@ -14,6 +14,7 @@ enum : uint32_t {
     ERR_SPIN = 2u,      // a bounded wait in the radix look-back gave up
     ERR_DELETE = 4u,    // a routed delete did not find its id in the leaf
     ERR_CAPACITY = 8u,  // a leaf slot overflowed (internal check)
+    ERR_ORTH = 16u,     // a consistency check of the P-Orth build failed
 };
 
 constexpr uint32_t PAD_ID = 0xFFFFFFFFu;
@@ -191,6 +192,35 @@ template <int D> PSI_HD bool coord_ok(const uint32_t* p) {
 // (key, id) order used everywhere: lexicographic.
 PSI_HD bool pair_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
     return ka < kb || (ka == kb && ia < ib);
+}
+
+// Squared Euclidean distance of two points (exact in u64 for coordinates in
+// range: Sec. 2.2's metric, squared to stay in integers).
+template <int D>
+__device__ __forceinline__ uint64_t pt_dist(const uint32_t* q, const uint32_t* p) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint64_t x = q[d] > p[d] ? q[d] - p[d] : p[d] - q[d];
+        s += x * x;
+    }
+    return s;
+}
+
+// Insert (d, id) into an ascending list of K pairs held in registers.
+template <int K>
+__device__ __forceinline__ void topk_insert(uint64_t (&bd)[K], uint32_t (&bi)[K], uint64_t d, uint32_t id) {
+#pragma unroll
+    for (int j = K - 1; j > 0; --j) {
+        const bool shift = pair_less(d, id, bd[j - 1], bi[j - 1]);
+        const bool here = !shift && pair_less(d, id, bd[j], bi[j]);
+        bd[j] = shift ? bd[j - 1] : (here ? d : bd[j]);
+        bi[j] = shift ? bi[j - 1] : (here ? id : bi[j]);
+    }
+    if (pair_less(d, id, bd[0], bi[0])) {
+        bd[0] = d;
+        bi[0] = id;
+    }
 }
 
 // ---------------------------------------------------------------- wave64

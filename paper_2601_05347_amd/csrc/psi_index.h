@@ -214,5 +214,10 @@ psi_status readback(psi_index ix, const void* dev, size_t bytes);  // into ix->p
 psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
 psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
 psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base);
+psi_status encode_sort(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base, int* which);
+// Processing order of a query batch (curve keys of the points or box centres
+// in scr.c, input order; *order null or the positions sorted by key); latches
+// ERR_RANGE for out-of-range query points.
+psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool boxes, const uint32_t** order);
 
 }  // namespace psi

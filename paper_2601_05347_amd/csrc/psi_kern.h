@@ -201,6 +201,54 @@ void launch_range_report(hipStream_t st, int dim, const TreeView& t, const uint3
 void launch_range_count_lane(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,
                              uint64_t* counts);
 
+// ---------------------------------------------------------- P-Orth tree
+// Node of the P-Orth tree (Sec. 3) in depth-first preorder, children in
+// Morton order (32 bytes). Interior: a = index one past its subtree, b = points
+// below it. Leaf: a = first of its points in the point array, b = count | ORTH_LEAF.
+// A node's box is the exact bounding box of its points.
+struct alignas(16) OrthNode {
+    uint32_t lo[3];
+    uint32_t hi[3];
+    uint32_t a;
+    uint32_t b;
+};
+constexpr uint32_t ORTH_LEAF = 0x80000000u;
+constexpr uint32_t ORTH_TILE = 2048;  // sorted positions per block of the leaf marking
+
+struct OrthView {
+    const OrthNode* node;
+    const uint4* pts;          // {x, y, z or 0, id} in Morton order
+    const uint32_t* lstart;    // first point of each leaf, in leaf order
+    const uint64_t* fkey;      // Morton key of each leaf's first point
+    uint64_t N;                // nodes
+    uint32_t L;                // leaves
+    uint32_t n;                // points
+};
+// Leaf cut of the sorted keys. write = false: the number of leaf starts of
+// each ORTH_TILE tile into tile_cnt. write = true: with tile_off the exclusive
+// scan of those counts, the leaves' first positions, levels and first keys,
+// and every point {coords decoded from its key, id}.
+void launch_orth_marks(hipStream_t st, int dim, bool write, const uint64_t* sk, const uint32_t* sid, uint64_t n,
+                       uint32_t phi, uint32_t* tile_cnt, const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev,
+                       uint64_t* fkey, uint4* pts);
+// Interior nodes that open at each leaf, plus one (cnt1, L words), and the
+// largest leaf level (atomic max into *maxlev, zeroed first).
+void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
+                        uint32_t* cnt1, uint32_t* maxlev, uint32_t* err);
+// Node records in preorder from base = exclusive scan of cnt1 (N nodes in
+// all); leaf boxes from the points, interior boxes left empty; lev[v] = level
+// of interior node v, 0xFF for a leaf.
+void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
+                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, OrthNode* node,
+                       uint8_t* lev);
+// Boxes of the interior nodes of one level from their children.
+void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, OrthNode* node);
+// Queries over a P-Orth tree (k <= 16; order and qkeys as for launch_knn).
+void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t* q, const uint64_t* qkeys,
+                     uint64_t nq, const uint32_t* order, uint32_t k, uint32_t* ids, uint64_t* d2);
+void launch_orth_range(hipStream_t st, int dim, const OrthView& t, const uint32_t* boxes, uint64_t nb,
+                       const uint32_t* order, uint64_t* counts, const uint64_t* offsets, uint32_t* ids);
+
 // ----------------------------------------------------------------- export
 // Prefix sums of leaf counts -> entry offsets (u64, L+1 entries).
 void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp);

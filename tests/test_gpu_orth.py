@@ -1,0 +1,245 @@
+"""GPU parity of the P-Orth tree (Sec. 3) against the oracle.
+
+Structure: the exported preorder nodes and points against the oracle's
+Alg. 1 tree, exactly (a leaf's points carry no order, so each leaf's ids are
+compared as a set). Queries: kNN against brute force, range counts and
+reports against the oracle (a box's ids compared sorted). Sizes span several
+2048-point leaf-marking tiles with ragged tails; the edge cases are the empty
+tree, a root leaf, leaves at the size limit, equal points that no split can
+separate, and out-of-range input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import orth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def psi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2601_05347_amd as psi
+    psi.lib()
+    return psi
+
+
+def segment_sort(ids, first, count):
+    """ids of each segment [first, first + count) sorted, segments in order."""
+    seg = np.repeat(np.arange(len(first)), count)
+    idx = np.concatenate([np.arange(f, f + c) for f, c in zip(first, count)]) if len(first) else np.zeros(0, int)
+    v = ids[idx]
+    return v[np.lexsort((v, seg))]
+
+
+def check_structure(o, pts, dim, phi):
+    nodes, gp = o.export()
+    ref = orth.preorder(orth.build(pts, dim, phi), dim)
+    N = len(ref["level"])
+    nn, nl, h = o.shape()
+    assert nn == N and nl == int(ref["leaf"].sum())
+    assert h == (int(ref["level"].max()) + 1 if N else 0)
+    assert nodes.shape[0] == N
+    if N == 0:
+        return
+    leaf = (nodes[:, 7] & 0x80000000) != 0
+    np.testing.assert_array_equal(leaf, ref["leaf"])
+    np.testing.assert_array_equal(nodes[:, 7] & 0x7FFFFFFF, ref["count"])
+    np.testing.assert_array_equal(nodes[:, 0:dim], ref["lo"])
+    np.testing.assert_array_equal(nodes[:, 3:3 + dim], ref["hi"])
+    if dim == 2:
+        assert (nodes[:, 2] == 0).all() and (nodes[:, 5] == 0).all()
+    np.testing.assert_array_equal(nodes[~leaf, 6], ref["end"][~leaf])
+    np.testing.assert_array_equal(nodes[leaf, 6], ref["first"][leaf])
+    ids = gp[:, 3].astype(np.int64)
+    np.testing.assert_array_equal(np.sort(ids), np.arange(len(pts)))
+    np.testing.assert_array_equal(gp[:, :dim], np.asarray(pts)[ids])
+    if dim == 2:
+        assert (gp[:, 2] == 0).all()
+    first = nodes[leaf, 6].astype(np.int64)
+    cnt = (nodes[leaf, 7] & 0x7FFFFFFF).astype(np.int64)
+    got = segment_sort(ids, first, cnt)
+    want = np.concatenate([np.sort(a) for a in ref["leaf_ids"]])
+    np.testing.assert_array_equal(got, want)
+
+
+def check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 10, 16)):
+    for k in ks:
+        ids, d2 = o.knn(q, k)
+        o.sync()
+        eid, ed2 = oracle.knn_points(pts, q, k)
+        np.testing.assert_array_equal(psi.to_u64(d2), ed2, err_msg=f"kNN d2 k={k}")
+        np.testing.assert_array_equal(psi.to_u32(ids), eid, err_msg=f"kNN ids k={k}")
+    cnt = o.range_count(bx)
+    o.sync()
+    np.testing.assert_array_equal(psi.to_u64(cnt), oracle.range_count_points(pts, bx))
+    off, rid = o.range_report(bx)
+    o.sync()
+    ref = oracle.RefIndex(dim, 0, phi)
+    ref.build(pts)
+    eoff, eids = ref.range_report(bx)
+    off = psi.to_u64(off).astype(np.int64)
+    np.testing.assert_array_equal(off, eoff.astype(np.int64))
+    got = segment_sort(psi.to_u32(rid), off[:-1], np.diff(off))
+    np.testing.assert_array_equal(got, eids)
+
+
+def bits_of(dim):
+    return 31 if dim == 2 else 21
+
+
+def queries(dim, n, seed, data, bits):
+    """half near data points, half uniform over the domain"""
+    u = synth.uniform(n - n // 2, dim, bits, seed, synth.P_QUERY)
+    if len(data) == 0:
+        return synth.uniform(n, dim, bits, seed, synth.P_QUERY)
+    pick = data[synth.draws(synth.stream_key(seed, synth.P_AUX), 0, n // 2) % np.uint64(len(data))]
+    return np.concatenate([pick, u]).astype(np.uint32)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 2047, 2048, 2049, 5000, 100_003])
+def test_structure_and_queries_uniform(psi, dim, n):
+    say(f"orth uniform dim={dim} n={n}")
+    bits = bits_of(dim)
+    pts = synth.uniform(n, dim, bits, 11 + n)
+    o = psi.Orth(dim, 32).build(pts)
+    o.sync()
+    check_structure(o, pts, dim, 32)
+    q = queries(dim, 300, 5 + n, pts, bits)
+    bx = synth.boxes(q[:200], bits, 7, side_lo=bits - 8, side_hi=bits - 3)
+    check_queries(psi, o, pts, dim, 32, q, bx)
+
+
+@pytest.mark.parametrize("dist,dim,bits", [("varden", 3, 21), ("varden", 2, 31), ("sweepline", 2, 31),
+                                           ("uniform", 2, 6), ("uniform", 3, 4)])
+@pytest.mark.parametrize("phi", [2, 8, 32])
+def test_structure_and_queries_skewed(psi, dist, dim, bits, phi):
+    say(f"orth {dist} dim={dim} bits={bits} phi={phi}")
+    pts = synth.points(dist, 20_000, dim, bits, 21)
+    o = psi.Orth(dim, phi).build(pts)
+    o.sync()
+    check_structure(o, pts, dim, phi)
+    q = queries(dim, 400, 23, pts, bits)
+    bx = synth.boxes(q[:300], bits, 9, side_lo=max(bits - 8, 1), side_hi=max(bits - 2, 2))
+    check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 16))
+
+
+def test_many_queries_take_the_sorted_order(psi):
+    say("orth 3D 200k, 6000 queries")
+    pts = synth.uniform(200_000, 3, 21, 31)
+    o = psi.Orth(3, 32).build(pts)
+    q = queries(3, 6000, 33, pts, 21)
+    bx = synth.boxes(q[:5000], 21, 3, side_lo=12, side_hi=17)
+    check_queries(psi, o, pts, 3, 32, q, bx, ks=(10,))
+
+
+def test_equal_points_only(psi):
+    for dim in (2, 3):
+        say(f"orth equal points dim={dim}")
+        pts = np.tile(np.array([[7, 1 << 20, 3][:dim]], dtype=np.uint32), (100, 1))
+        o = psi.Orth(dim, 8).build(pts)
+        o.sync()
+        check_structure(o, pts, dim, 8)
+        assert o.shape() == (bits_of(dim) + 1, 1, bits_of(dim) + 1)
+        q = np.array([[7, 1 << 20, 3][:dim], [0, 0, 0][:dim]], dtype=np.uint32)
+        ids, d2 = o.knn(q, 16)
+        eid, ed2 = oracle.knn_points(pts, q, 16)
+        np.testing.assert_array_equal(psi.to_u32(ids), eid)
+        np.testing.assert_array_equal(psi.to_u64(d2), ed2)
+
+
+def test_empty_tree_and_rebuild(psi):
+    say("orth empty")
+    o = psi.Orth(3, 32).build(np.zeros((0, 3), np.uint32))
+    assert o.shape() == (0, 0, 0)
+    q = synth.uniform(50, 3, 21, 3)
+    ids, d2 = o.knn(q, 4)
+    assert (psi.to_u32(ids) == psi.PAD_ID).all() and (psi.to_u64(d2) == psi.PAD_D2).all()
+    bx = synth.boxes(q, 21, 1)
+    assert (psi.to_u64(o.range_count(bx)) == 0).all()
+    pts = synth.uniform(3000, 3, 21, 4)
+    o.build(pts)
+    check_structure(o, pts, 3, 32)
+    o.build(pts[:10])
+    check_structure(o, pts[:10], 3, 32)
+
+
+def test_out_of_range_points_and_bad_arguments(psi):
+    say("orth errors")
+    pts = synth.uniform(1000, 3, 21, 5)
+    pts[17, 1] = 1 << 21
+    o = psi.Orth(3, 32)
+    with pytest.raises(psi.PsiError) as e:
+        o.build(pts)
+    assert e.value.code == 2
+    assert o.shape() == (0, 0, 0)
+    o.sync()  # the error was cleared by the failed build
+    with pytest.raises(psi.PsiError) as e:
+        o.knn(pts[:5] & np.uint32(0xFFFF), 17)
+    assert e.value.code == 1
+    with pytest.raises(psi.PsiError) as e:
+        psi.psi_orth_create(3, 32, psi.FLAG_KNN_NEAREST_FIRST)
+    assert e.value.code == 1
+    ok = pts & np.uint32((1 << 21) - 1)
+    o.build(ok)
+    check_structure(o, ok, 3, 32)
+
+
+@pytest.mark.slow
+def test_fullsize_1e8_3d(psi):
+    """The 3D, 1e8-point uniform configuration: invariants over the whole
+    exported tree, queries on a sample against brute force."""
+    n, dim, phi = 100_000_000, 3, 32
+    say("orth full size 1e8 3D: build")
+    pts = synth.uniform(n, dim, 21, 1)
+    o = psi.Orth(dim, phi).build(pts)
+    o.sync()
+    nodes, gp = o.export()
+    N = nodes.shape[0]
+    say(f"orth full size: {N} nodes")
+    leaf = (nodes[:, 7] & 0x80000000) != 0
+    cnt = (nodes[:, 7] & 0x7FFFFFFF).astype(np.int64)
+    assert cnt[0] == n and int(cnt[leaf].sum()) == n
+    assert (cnt[~leaf] > phi).all()
+    small = cnt[leaf] <= phi
+    assert small.all() or (nodes[leaf][~small, 0:3] == nodes[leaf][~small, 3:6]).all()
+    ends = nodes[~leaf, 6].astype(np.int64)
+    assert ((ends > np.nonzero(~leaf)[0]) & (ends <= N)).all()
+    # an interior node's count = the points of the leaves in [v, end)
+    pre = np.concatenate([[0], np.cumsum(np.where(leaf, cnt, 0))])
+    iv = np.nonzero(~leaf)[0]
+    np.testing.assert_array_equal(pre[ends] - pre[iv], cnt[~leaf])
+    # leaves tile the point array in order
+    first = nodes[leaf, 6].astype(np.int64)
+    np.testing.assert_array_equal(first, np.concatenate([[0], np.cumsum(cnt[leaf])[:-1]]))
+    seen = np.zeros(n, dtype=bool)
+    seen[gp[:, 3]] = True
+    assert seen.all()
+    np.testing.assert_array_equal(gp[:, :3], pts[gp[:, 3]])
+    del seen
+    # sampled leaf boxes
+    li = np.nonzero(leaf)[0]
+    for v in li[:: max(1, len(li) // 2000)]:
+        p = gp[nodes[v, 6]: nodes[v, 6] + cnt[v], :3]
+        np.testing.assert_array_equal(nodes[v, 0:3], p.min(axis=0))
+        np.testing.assert_array_equal(nodes[v, 3:6], p.max(axis=0))
+    del gp
+    say("orth full size: queries")
+    q = queries(dim, 200, 3, pts, 21)
+    bx = synth.boxes(q[:100], 21, 5, side_lo=10, side_hi=14)
+    ids, d2 = o.knn(q, 10)
+    eid, ed2 = oracle.knn_points(pts, q, 10)
+    np.testing.assert_array_equal(psi.to_u64(d2), ed2)
+    np.testing.assert_array_equal(psi.to_u32(ids), eid)
+    np.testing.assert_array_equal(psi.to_u64(o.range_count(bx)), oracle.range_count_points(pts, bx))
