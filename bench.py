@@ -41,6 +41,9 @@ WORKLOADS = {
     "serve": dict(dim=3, bits=21, n=50_000_000, m=0, nq=0, k=10, nb=0),
     # 4096 independent 2D SPaC-Z indexes (sizes log-uniform 1e3..1e6), kNN k = 8
     "multi": dict(dim=2, bits=30, n=0, m=0, nq=0, k=8, nb=0),
+    # P-Orth tree (Sec. 3) beside the SPaC-H tree on the 3d-1e8 inputs: static
+    # build, 1e7 10-NN queries, 1e6 range counts and reports
+    "orth": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=1_000_000),
     # incremental workload: 3D, 1e8 points inserted into an empty index in n/b
     # batches, then deleted in n/b batches; 1e7 10-NN queries at the halfway points
     "incr": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=0),
@@ -307,6 +310,103 @@ def bench_incr(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_orth(args):
+    """P-Orth tree (Sec. 3) and SPaC-H tree on the same inputs (those of the
+    3d-1e8 workload): per step, a build of each, then kNN, range count and
+    range report on each. Every phase is timed with HIP events on the
+    stream; the builds include their readbacks."""
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+    cfg = dict(WORKLOADS["orth"])
+    if args.n:
+        cfg["n"] = args.n
+    dim, bits, n, nq, k, nb = (cfg[x] for x in ("dim", "bits", "n", "nq", "k", "nb"))
+    k = args.k or k
+    nq = min(nq, max(1000, n // 10))
+    nb = min(nb, max(1000, n // 100))
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    data, _, q = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=0, n_query=nq)
+    boxes = synth.boxes(q[:nb], bits, args.seed)
+    log(f"orth: inputs generated in {time.perf_counter() - t:.1f} s")
+    d_data = torch.from_numpy(data.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(q.view(np.int32)).to(dev)
+    d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
+    del data, q
+    stream = torch.cuda.current_stream(dev)
+    trees = {"orth": psi.Orth(dim, args.leaf, device=dev, stream=stream),
+             "spac_h": psi.Index(dim, psi.HILBERT, args.leaf, args.fanout, device=dev, stream=stream)}
+    api = {"orth": (psi.psi_orth_build, psi.psi_orth_knn, psi.psi_orth_range_count, psi.psi_orth_range_report),
+           "spac_h": (psi.psi_build, psi.psi_knn, psi.psi_range_count, psi.psi_range_report)}
+    k_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    k_d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    cnt = torch.empty(nb, dtype=torch.int64, device=dev)
+    off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+    rids, res, outs = {}, {}, {}
+    for name, tr in trees.items():
+        build, knn, rcount, rreport = api[name]
+        h = tr._h
+        ms = {p: [] for p in ("build", "knn", "range_count", "range_report")}
+        for it in range(args.warmup + args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            build(h, d_data, n)
+            ev[1].record(stream)
+            knn(h, d_q, nq, k, k_ids, k_d2)
+            ev[2].record(stream)
+            rcount(h, d_boxes, nb, cnt)
+            ev[3].record(stream)
+            if name not in rids:
+                torch.cumsum(cnt, 0, out=off[1:])
+                rids[name] = torch.empty(max(int(off[-1].item()), 1), dtype=torch.int32, device=dev)
+                ev[3].record(stream)
+            rreport(h, d_boxes, nb, off, rids[name])
+            ev[4].record(stream)
+            ev[4].synchronize()
+            if it >= args.warmup:
+                for j, p in enumerate(ms):
+                    ms[p].append(ev[j].elapsed_time(ev[j + 1]))
+        tr.sync()
+        outs[name] = (k_ids.clone(), k_d2.clone(), cnt.clone())
+        med = {p: round(float(np.median(v)), 3) for p, v in ms.items()}
+        res[name] = {"ms": med, "build_mpts_s": round(n / med["build"] / 1e3, 1),
+                     "knn_mq_s": round(nq / med["knn"] / 1e3, 1),
+                     "range_count_mbox_s": round(nb / med["range_count"] / 1e3, 2),
+                     "range_report_mbox_s": round(nb / med["range_report"] / 1e3, 2)}
+        if name == "orth":
+            nn, nl, hh = tr.shape()
+            res[name]["shape"] = {"nodes": nn, "leaves": nl, "height": hh}
+            tr.prof_enable(True)
+            tr.prof_reset()
+            build(h, d_data, n)
+            knn(h, d_q, nq, k, k_ids, k_d2)
+            fam = {}
+            for f in ("encode_hist", "radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide",
+                      "orth_marks", "orth_nodes", "orth_boxes", "orth_knn", "order", "radix_order"):
+                fms, nl_, _ = tr.prof_get(f)
+                if nl_:
+                    fam[f] = round(fms, 3)
+            tr.prof_enable(False)
+            res[name]["families_ms"] = fam
+        log(f"{name}: {res[name]}")
+    o, sp = res["orth"], res["spac_h"]
+    a, b = outs["orth"], outs["spac_h"]
+    identical = all(bool(torch.equal(x, y)) for x, y in zip(a, b))
+    out = {"metric": "P-Orth static build Mpoints/s (1e8 pts, 3D); kNN queries/s", "value": o["build_mpts_s"],
+           "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(sum(o["ms"].values()), 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+           "config": {"workload": f"orth: {dim}D {args.dist} P-Orth vs SPaC-H", "n": n, "queries": nq, "k": k,
+                      "boxes": nb, "leaf_size": args.leaf},
+           "orth": o, "spac_h": sp,
+           "orth_over_spac_h": {p: round(sp["ms"][p] / o["ms"][p], 3) for p in o["ms"]},
+           "knn_and_counts_identical": identical}
+    print(json.dumps(out), flush=True)
+
+
 def bench_multi(args):
     """Batched small indexes: one segmented build + one persistent kNN launch
     vs per-index builds and launches (and those launches replayed as a graph)."""
@@ -411,6 +511,8 @@ def main():
         return bench_multi(args)
     if args.workload == "incr":
         return bench_incr(args)
+    if args.workload == "orth":
+        return bench_orth(args)
     import numpy as np
     import torch
 

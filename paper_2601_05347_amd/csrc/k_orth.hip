@@ -48,15 +48,53 @@ template <int D> __device__ __forceinline__ uint32_t common_levels(uint64_t a, u
     return ((uint32_t)__builtin_clzll(x) - (64u - OrthBits<D>::KB)) / D;
 }
 
+// ------------------------------------------------------------ packed boxes
+__device__ __forceinline__ bool box_leaf(uint4 v) { return (v.y >> 31) != 0; }
+
+template <int D> __device__ __forceinline__ void box_unpack(uint4 v, uint32_t* lo, uint32_t* hi) {
+    const uint64_t a = ((uint64_t)v.y << 32) | v.x, b = ((uint64_t)v.w << 32) | v.z;
+    constexpr int W = BoxBits<D>::W;
+    constexpr uint64_t M = (1ull << W) - 1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = (uint32_t)((a >> (d * W)) & M);
+        hi[d] = (uint32_t)((b >> (d * W)) & M);
+    }
+}
+
+template <int D> __device__ __forceinline__ uint4 box_pack(const uint32_t* lo, const uint32_t* hi, bool leaf) {
+    constexpr int W = BoxBits<D>::W;
+    uint64_t a = leaf ? 1ull << 63 : 0ull, b = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        a |= (uint64_t)lo[d] << (d * W);
+        b |= (uint64_t)hi[d] << (d * W);
+    }
+    return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
+
+template <int D> __device__ __forceinline__ uint64_t box_dist2(const uint32_t* q, uint4 v) {
+    uint32_t lo[D], hi[D];
+    box_unpack<D>(v, lo, hi);
+    uint64_t s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t x = q[d] < lo[d] ? lo[d] - q[d] : (q[d] > hi[d] ? q[d] - hi[d] : 0u);
+        s += (uint64_t)x * x;
+    }
+    return s;
+}
+
+// --------------------------------------------------------------- leaf cut
 constexpr uint32_t OM_HALO = 32;  // keys loaded beyond each side of a tile (leaf size <= 32)
 constexpr uint32_t OM_PER = ORTH_TILE / 256;
+static_assert(OM_PER == 8, "a thread's marks are stored as one 8-byte word");
 
-template <int D, bool WRITE>
-__global__ __launch_bounds__(256) void k_orth_marks(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sid,
-                                                    uint64_t n, uint32_t phi, uint32_t* __restrict__ tile_cnt,
-                                                    const uint32_t* __restrict__ tile_off,
-                                                    uint32_t* __restrict__ lstart, uint8_t* __restrict__ llev,
-                                                    uint64_t* __restrict__ fkey, uint4* __restrict__ pts) {
+template <int D>
+__global__ __launch_bounds__(256) void k_orth_mark(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sid,
+                                                   uint64_t n, uint32_t phi, uint8_t* __restrict__ mark,
+                                                   uint32_t* __restrict__ tile_cnt, uint4* __restrict__ pts,
+                                                   uint32_t* __restrict__ ids) {
     __shared__ uint64_t s_k[ORTH_TILE + 2 * OM_HALO];  // key at position base - OM_HALO + x
     __shared__ uint8_t s_cp[ORTH_TILE + OM_HALO];      // 1 + levels shared by keys j and j + phi
     __shared__ uint32_t s_w[4];
@@ -74,48 +112,85 @@ __global__ __launch_bounds__(256) void k_orth_marks(const uint64_t* __restrict__
         s_cp[x] = (uint8_t)v;
     }
     __syncthreads();
-    // positions y = OM_PER * thread .. + OM_PER - 1 of the tile, in order
-    uint32_t lvl[OM_PER];
-    bool st[OM_PER];
+    // positions y0 + u of the tile; position y's windows j in [y - phi, y]
+    // are s_cp[y + OM_HALO - phi .. y + OM_HALO]. For phi >= 7 the eight
+    // windows share [y0 + 39 - phi, y0 + 32]; the rest is a suffix maximum on
+    // the left and a prefix maximum on the right.
+    const uint32_t y0 = threadIdx.x * OM_PER;
+    uint32_t m1[OM_PER];
+    if (phi >= 7) {
+        uint32_t core = 0;
+        for (uint32_t x = y0 + 39 - phi; x <= y0 + 32; ++x) core = max(core, (uint32_t)s_cp[x]);
+        uint32_t lf = 0, rg = 0;
+        m1[OM_PER - 1] = core;
+#pragma unroll
+        for (int u = OM_PER - 2; u >= 0; --u) {
+            lf = max(lf, (uint32_t)s_cp[y0 + u + 32 - phi]);
+            m1[u] = max(core, lf);
+        }
+#pragma unroll
+        for (uint32_t u = 1; u < OM_PER; ++u) {
+            rg = max(rg, (uint32_t)s_cp[y0 + u + 32]);
+            m1[u] = max(m1[u], rg);
+        }
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < OM_PER; ++u) {
+            uint32_t m = 0;
+            for (uint32_t x = y0 + u + OM_HALO - phi; x <= y0 + u + OM_HALO; ++x) m = max(m, (uint32_t)s_cp[x]);
+            m1[u] = m;
+        }
+    }
+    uint64_t word = 0;
     uint32_t c = 0;
 #pragma unroll
     for (uint32_t u = 0; u < OM_PER; ++u) {
-        const uint32_t y = threadIdx.x * OM_PER + u;
-        const uint64_t i = base + y;
-        lvl[u] = 0;
-        st[u] = false;
+        const uint64_t i = base + y0 + u;
         if (i < n) {
-            uint32_t m1 = 0;  // windows j in [i - phi, i]
-            for (uint32_t x = y + OM_HALO - phi; x <= y + OM_HALO; ++x) m1 = max(m1, (uint32_t)s_cp[x]);
-            const uint32_t l = min(m1, OrthBits<D>::W);
-            lvl[u] = l;
-            st[u] = i == 0 || common_levels<D>(s_k[y + OM_HALO - 1], s_k[y + OM_HALO]) < l;
-            c += st[u] ? 1u : 0u;
+            const uint32_t l = min(m1[u], OrthBits<D>::W);
+            const bool st = i == 0 || common_levels<D>(s_k[y0 + u + OM_HALO - 1], s_k[y0 + u + OM_HALO]) < l;
+            word |= (uint64_t)(l | (st ? 0x80u : 0u)) << (8 * u);
+            c += st ? 1u : 0u;
         }
     }
+    *reinterpret_cast<uint2*>(mark + base + y0) = make_uint2((uint32_t)word, (uint32_t)(word >> 32));
     const uint32_t incl = block_incl_scan256(c, s_w);
-    if (!WRITE) {
-        if (threadIdx.x == 255) tile_cnt[blockIdx.x] = incl;
-        return;
-    }
-    uint32_t leaf = tile_off[blockIdx.x] + incl - c;
-#pragma unroll
-    for (uint32_t u = 0; u < OM_PER; ++u) {
-        if (st[u]) {
-            const uint32_t y = threadIdx.x * OM_PER + u;
-            lstart[leaf] = (uint32_t)(base + y);
-            llev[leaf] = (uint8_t)lvl[u];
-            fkey[leaf] = s_k[y + OM_HALO];
-            ++leaf;
-        }
-    }
+    if (threadIdx.x == 255) tile_cnt[blockIdx.x] = incl;
     // the points in key order, coordinates decoded from the keys
     for (uint32_t y = threadIdx.x; y < ORTH_TILE; y += 256) {
         const uint64_t i = base + y;
         if (i >= n) break;
         uint32_t p[3] = {0u, 0u, 0u};
         morton_point<D>(s_k[y + OM_HALO], p);
-        pts[i] = make_uint4(p[0], p[1], D == 3 ? p[2] : 0u, sid[i]);
+        const uint32_t id = sid[i];
+        pts[i] = make_uint4(p[0], p[1], D == 3 ? p[2] : 0u, id);
+        ids[i] = id;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_orth_leaves(const uint64_t* __restrict__ sk, uint64_t n,
+                                                     const uint8_t* __restrict__ mark,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     uint32_t* __restrict__ lstart, uint8_t* __restrict__ llev,
+                                                     uint64_t* __restrict__ fkey) {
+    __shared__ uint32_t s_w[4];
+    const uint64_t base = (uint64_t)blockIdx.x * ORTH_TILE;
+    const uint32_t y0 = threadIdx.x * OM_PER;
+    const uint2 mm = *reinterpret_cast<const uint2*>(mark + base + y0);
+    const uint64_t word = ((uint64_t)mm.y << 32) | mm.x;
+    const uint32_t c = (uint32_t)__popcll(word & 0x8080808080808080ull);
+    const uint32_t incl = block_incl_scan256(c, s_w);
+    uint32_t leaf = tile_off[blockIdx.x] + incl - c;
+#pragma unroll
+    for (uint32_t u = 0; u < OM_PER; ++u) {
+        const uint32_t b = (uint32_t)(word >> (8 * u)) & 0xFFu;
+        if (b & 0x80u) {
+            const uint64_t i = base + y0 + u;
+            lstart[leaf] = (uint32_t)i;
+            llev[leaf] = (uint8_t)(b & 0x7Fu);
+            fkey[leaf] = sk[i];
+            ++leaf;
+        }
     }
 }
 
@@ -141,7 +216,10 @@ __global__ __launch_bounds__(256) void k_orth_counts(const uint8_t* __restrict__
     lv = wave_max_u32(lv);
     if (lane_id() == 0) s_m[threadIdx.x >> 6] = lv;
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(maxlev, max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3])));
+    if (threadIdx.x == 0) {  // one atomic only where the block raises the maximum seen so far
+        const uint32_t m = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        if (m > __hip_atomic_load(maxlev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxlev, m);
+    }
 }
 
 template <int D>
@@ -149,7 +227,8 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
                                                     const uint32_t* __restrict__ lstart,
                                                     const uint32_t* __restrict__ base, uint32_t L, uint32_t n,
                                                     uint64_t N, const uint4* __restrict__ pts,
-                                                    OrthNode* __restrict__ node, uint8_t* __restrict__ lev) {
+                                                    uint4* __restrict__ box, uint2* __restrict__ link,
+                                                    uint8_t* __restrict__ lev) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= L) return;
     const uint32_t lv = llev[t];
@@ -160,82 +239,96 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
     for (uint32_t l = s; l < lv; ++l) {
         const uint32_t sh = OrthBits<D>::KB - l * D;
         const uint64_t cell = key >> sh;
-        uint32_t lo = t + 1, hi = L;  // first later leaf outside the cell
-        while (lo < hi) {
-            const uint32_t mid = lo + ((hi - lo) >> 1);
-            if ((fkey[mid] >> sh) == cell) lo = mid + 1;
-            else hi = mid;
+        // first later leaf outside the cell: doubling steps, then bisection
+        uint32_t in = t, out = L;
+        for (uint32_t step = 1;; step <<= 1) {
+            const uint64_t pr = (uint64_t)t + step;
+            if (pr >= L) break;
+            if ((fkey[pr] >> sh) != cell) {
+                out = (uint32_t)pr;
+                break;
+            }
+            in = (uint32_t)pr;
         }
-        OrthNode r;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            r.lo[d] = 0xFFFFFFFFu;
-            r.hi[d] = 0u;
+        while (out - in > 1) {
+            const uint32_t mid = in + ((out - in) >> 1);
+            if ((fkey[mid] >> sh) == cell) in = mid;
+            else out = mid;
         }
-        r.a = lo < L ? base[lo] : (uint32_t)N;
-        r.b = (lo < L ? lstart[lo] : n) - pb;
-        node[b + (l - s)] = r;
-        lev[b + (l - s)] = (uint8_t)l;
+        const uint64_t v = b + (l - s);
+        link[v] = make_uint2(out < L ? base[out] : (uint32_t)N, (out < L ? lstart[out] : n) - pb);
+        box[v] = make_uint4(0u, 0u, 0u, 0u);
+        lev[v] = (uint8_t)l;
     }
-    OrthNode r;
+    uint32_t lo[D], hi[D];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        r.lo[d] = d < D ? 0xFFFFFFFFu : 0u;
-        r.hi[d] = 0u;
+    for (int d = 0; d < D; ++d) {
+        lo[d] = 0xFFFFFFFFu;
+        hi[d] = 0u;
     }
     for (uint32_t x = pb; x < pe; ++x) {
         const uint4 P = pts[x];
         const uint32_t p[3] = {P.x, P.y, P.z};
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            r.lo[d] = min(r.lo[d], p[d]);
-            r.hi[d] = max(r.hi[d], p[d]);
+            lo[d] = min(lo[d], p[d]);
+            hi[d] = max(hi[d], p[d]);
         }
     }
-    r.a = pb;
-    r.b = (pe - pb) | ORTH_LEAF;
     const uint64_t v = b + (s <= lv ? lv - s : 0u);
-    node[v] = r;
+    box[v] = box_pack<D>(lo, hi, true);
+    link[v] = make_uint2(pb, pe - pb);
     lev[v] = 0xFF;
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_orth_boxes(uint32_t level, uint64_t N, const uint8_t* __restrict__ lev,
-                                                    OrthNode* __restrict__ node) {
+                                                    uint4* __restrict__ box, const uint2* __restrict__ link) {
     const uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= N || lev[v] != level) return;
-    const uint64_t end = min<uint64_t>(node[v].a, N);
-    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
-    if (D == 2) lo[2] = 0u;
+    const uint64_t end = min<uint64_t>(link[v].x, N);
+    uint32_t lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = 0xFFFFFFFFu;
+        hi[d] = 0u;
+    }
     uint64_t c = v + 1;
     while (c < end) {  // the children: first child v + 1, then each one's end
-        const OrthNode r = node[c];
+        const uint4 bx = box[c];
+        uint32_t a[D], z[D];
+        box_unpack<D>(bx, a, z);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            lo[d] = min(lo[d], r.lo[d]);
-            hi[d] = max(hi[d], r.hi[d]);
+            lo[d] = min(lo[d], a[d]);
+            hi[d] = max(hi[d], z[d]);
         }
-        const uint64_t nx = (r.b & ORTH_LEAF) ? c + 1 : (uint64_t)r.a;
+        const uint64_t nx = box_leaf(bx) ? c + 1 : (uint64_t)link[c].x;
         c = nx > c ? nx : c + 1;
     }
+    box[v] = box_pack<D>(lo, hi, false);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_orth_export(const uint4* __restrict__ box, const uint2* __restrict__ link,
+                                                     uint64_t N, uint32_t* __restrict__ out) {
+    const uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= N) return;
+    const uint4 bx = box[v];
+    uint32_t lo[D], hi[D];
+    box_unpack<D>(bx, lo, hi);
+    const uint2 lk = link[v];
+    uint32_t* o = out + v * 8;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        node[v].lo[d] = lo[d];
-        node[v].hi[d] = hi[d];
+        o[d] = d < D ? lo[d] : 0u;
+        o[3 + d] = d < D ? hi[d] : 0u;
     }
+    o[6] = lk.x;
+    o[7] = lk.y | (box_leaf(bx) ? 0x80000000u : 0u);
 }
 
 // ------------------------------------------------------------------ queries
-template <int D> __device__ __forceinline__ uint64_t orth_box_dist(const uint32_t* q, const OrthNode& r) {
-    uint64_t s = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const uint32_t x = q[d] < r.lo[d] ? r.lo[d] - q[d] : (q[d] > r.hi[d] ? q[d] - r.hi[d] : 0u);
-        s += (uint64_t)x * x;
-    }
-    return s;
-}
-
 template <int D, int K>
 __device__ __forceinline__ void orth_scan(const uint4* __restrict__ pts, uint32_t b, uint32_t e, const uint32_t* q,
                                           uint64_t (&bd)[K], uint32_t (&bi)[K]) {
@@ -247,10 +340,12 @@ __device__ __forceinline__ void orth_scan(const uint4* __restrict__ pts, uint32_
     }
 }
 
-// Lane per query. The leaf holding the query's own Morton position and its
-// two neighbours in key order are scanned first (one contiguous run of
-// points) to start with a small k-th distance; the preorder walk then skips
-// them.
+constexpr uint32_t ORTH_SEED = 64;  // points scanned around the query's key before the walk
+
+// Lane per query. The leaves around the query's own Morton position (the
+// one holding it, then its neighbours in key order until they hold
+// ORTH_SEED points: one contiguous run of the point array) are scanned first
+// to start with a small k-th distance; the preorder walk then skips them.
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_orth_knn(OrthView t, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
@@ -278,18 +373,28 @@ __global__ __launch_bounds__(256) void k_orth_knn(OrthView t, const uint32_t* __
             else hi = mid;
         }
         const uint32_t j = lo ? lo - 1 : 0u;
-        const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, t.L - 1);
-        const uint32_t p0 = t.lstart[ja], p1 = jb + 1 < t.L ? t.lstart[jb + 1] : t.n;
+        uint32_t ja = j, jb = j;
+        uint32_t p0 = t.lstart[j], p1 = j + 1 < t.L ? t.lstart[j + 1] : t.n;
+        while (p1 - p0 < ORTH_SEED && (ja > 0 || jb + 1 < t.L)) {
+            if (ja > 0) p0 = t.lstart[--ja];
+            if (jb + 1 < t.L) {
+                ++jb;
+                p1 = jb + 1 < t.L ? t.lstart[jb + 1] : t.n;
+            }
+        }
         orth_scan<D, K>(t.pts, p0, p1, q, bd, bi);
         uint64_t v = 0;
         while (v < t.N) {
-            const OrthNode r = t.node[v];
-            const bool leaf = (r.b & ORTH_LEAF) != 0;
-            if (orth_box_dist<D>(q, r) <= bd[K - 1]) {
-                if (leaf && (r.a < p0 || r.a >= p1)) orth_scan<D, K>(t.pts, r.a, r.a + (r.b & ~ORTH_LEAF), q, bd, bi);
+            const uint4 bx = t.box[v];
+            const bool leaf = box_leaf(bx);
+            if (box_dist2<D>(q, bx) <= bd[K - 1]) {
+                if (leaf) {
+                    const uint2 lk = t.link[v];
+                    if (lk.x < p0 || lk.x >= p1) orth_scan<D, K>(t.pts, lk.x, lk.x + lk.y, q, bd, bi);
+                }
                 ++v;
             } else {
-                v = leaf ? v + 1 : max<uint64_t>(r.a, v + 1);
+                v = leaf ? v + 1 : max<uint64_t>(t.link[v].x, v + 1);
             }
         }
     }
@@ -324,30 +429,36 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
     }
     uint64_t v = empty ? t.N : 0;
     while (v < t.N) {
-        const OrthNode r = t.node[v];
-        const bool leaf = (r.b & ORTH_LEAF) != 0;
-        const uint32_t c = r.b & ~ORTH_LEAF;
-        const uint64_t next = leaf ? v + 1 : max<uint64_t>(r.a, v + 1);
+        const uint4 nb4 = t.box[v];
+        const bool leaf = box_leaf(nb4);
+        uint32_t rl[D], rh[D];
+        box_unpack<D>(nb4, rl, rh);
         bool inside = true, apart = false;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            apart = apart || r.hi[d] < lo[d] || r.lo[d] > hi[d];
-            inside = inside && lo[d] <= r.lo[d] && r.hi[d] <= hi[d];
+            apart = apart || rh[d] < lo[d] || rl[d] > hi[d];
+            inside = inside && lo[d] <= rl[d] && rh[d] <= hi[d];
         }
-        if (apart) {
-            v = next;
-        } else if (inside) {
+        if (!apart && !inside && !leaf) {
+            ++v;  // straddling interior node: its first child
+            continue;
+        }
+        const uint2 lk = t.link[v];
+        const uint64_t next = leaf ? v + 1 : max<uint64_t>(lk.x, v + 1);
+        if (inside) {
             if (!REPORT) {
-                cnt += c;
+                cnt += lk.y;
             } else {
-                uint64_t u = v;  // the subtree's points start at its first leaf's
-                while (u < t.N && !(t.node[u].b & ORTH_LEAF)) ++u;
-                const uint32_t pb = u < t.N ? t.node[u].a : 0u;
-                for (uint32_t e = 0; e < c && o < lim; ++e) out[o++] = t.pts[pb + e].w;
+                uint32_t pb = lk.x;
+                if (!leaf) {  // the subtree's points start at its first leaf's
+                    uint64_t u = v + 1;
+                    while (u < t.N && !box_leaf(t.box[u])) ++u;
+                    pb = u < t.N ? t.link[u].x : 0u;
+                }
+                for (uint32_t e = 0; e < lk.y && o < lim; ++e) out[o++] = t.ids[pb + e];
             }
-            v = next;
-        } else if (leaf) {
-            for (uint32_t x = r.a; x < r.a + c; ++x) {
+        } else if (!apart) {  // straddling leaf
+            for (uint32_t x = lk.x; x < lk.x + lk.y; ++x) {
                 const uint4 P = t.pts[x];
                 const uint32_t p[3] = {P.x, P.y, P.z};
                 bool in = true;
@@ -358,30 +469,27 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
                     else if (o < lim) out[o++] = P.w;
                 }
             }
-            v = next;
-        } else {
-            ++v;
         }
+        v = next;
     }
     if (!REPORT) counts[b] = cnt;
 }
 
 }  // namespace
 
-void launch_orth_marks(hipStream_t st, int dim, bool write, const uint64_t* sk, const uint32_t* sid, uint64_t n,
-                       uint32_t phi, uint32_t* tile_cnt, const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev,
-                       uint64_t* fkey, uint4* pts) {
+void launch_orth_mark(hipStream_t st, int dim, const uint64_t* sk, const uint32_t* sid, uint64_t n, uint32_t phi,
+                      uint8_t* mark, uint32_t* tile_cnt, uint4* pts, uint32_t* ids) {
     if (n == 0) return;
     const dim3 g(blocks_for(n, ORTH_TILE));
-#define PSI_OM(D, WR) hipLaunchKernelGGL((k_orth_marks<D, WR>), g, dim3(256), 0, st, sk, sid, n, phi, tile_cnt, tile_off, lstart, llev, fkey, pts)
-    if (dim == 2) {
-        if (write) PSI_OM(2, true);
-        else PSI_OM(2, false);
-    } else {
-        if (write) PSI_OM(3, true);
-        else PSI_OM(3, false);
-    }
-#undef PSI_OM
+    if (dim == 2) hipLaunchKernelGGL((k_orth_mark<2>), g, dim3(256), 0, st, sk, sid, n, phi, mark, tile_cnt, pts, ids);
+    else hipLaunchKernelGGL((k_orth_mark<3>), g, dim3(256), 0, st, sk, sid, n, phi, mark, tile_cnt, pts, ids);
+}
+
+void launch_orth_leaves(hipStream_t st, const uint64_t* sk, uint64_t n, const uint8_t* mark,
+                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_orth_leaves, dim3(blocks_for(n, ORTH_TILE)), dim3(256), 0, st, sk, n, mark, tile_off, lstart,
+                       llev, fkey);
 }
 
 void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
@@ -393,19 +501,27 @@ void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint
 }
 
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
-                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, OrthNode* node,
-                       uint8_t* lev) {
+                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
+                       uint2* link, uint8_t* lev) {
     if (L == 0) return;
     const dim3 g(blocks_for(L, 256));
-    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, node, lev);
-    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, node, lev);
+    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, lev);
+    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, lev);
 }
 
-void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, OrthNode* node) {
+void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,
+                       const uint2* link) {
     if (N == 0) return;
     const dim3 g(blocks_for(N, 256));
-    if (dim == 2) hipLaunchKernelGGL((k_orth_boxes<2>), g, dim3(256), 0, st, level, N, lev, node);
-    else hipLaunchKernelGGL((k_orth_boxes<3>), g, dim3(256), 0, st, level, N, lev, node);
+    if (dim == 2) hipLaunchKernelGGL((k_orth_boxes<2>), g, dim3(256), 0, st, level, N, lev, box, link);
+    else hipLaunchKernelGGL((k_orth_boxes<3>), g, dim3(256), 0, st, level, N, lev, box, link);
+}
+
+void launch_orth_export(hipStream_t st, int dim, const uint4* box, const uint2* link, uint64_t N, uint32_t* out) {
+    if (N == 0) return;
+    const dim3 g(blocks_for(N, 256));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_export<2>), g, dim3(256), 0, st, box, link, N, out);
+    else hipLaunchKernelGGL((k_orth_export<3>), g, dim3(256), 0, st, box, link, N, out);
 }
 
 void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t* q, const uint64_t* qkeys,

@@ -202,50 +202,57 @@ void launch_range_count_lane(hipStream_t st, int dim, const TreeView& t, const u
                              uint64_t* counts);
 
 // ---------------------------------------------------------- P-Orth tree
-// Node of the P-Orth tree (Sec. 3) in depth-first preorder, children in
-// Morton order (32 bytes). Interior: a = index one past its subtree, b = points
-// below it. Leaf: a = first of its points in the point array, b = count | ORTH_LEAF.
-// A node's box is the exact bounding box of its points.
-struct alignas(16) OrthNode {
-    uint32_t lo[3];
-    uint32_t hi[3];
-    uint32_t a;
-    uint32_t b;
-};
-constexpr uint32_t ORTH_LEAF = 0x80000000u;
+// Nodes of the P-Orth tree (Sec. 3) in depth-first preorder, children in
+// Morton order, as two arrays:
+//   box[v]  (16 bytes): the exact bounding box of the node's points, packed
+//           as for the kNN box tests (BoxBits: low corner in the first 64-bit
+//           word, high corner in the second); bit 63 of the first word is set
+//           for a leaf;
+//   link[v] (8 bytes): interior {index one past its subtree, points below};
+//           leaf {first of its points in the point array, count}.
 constexpr uint32_t ORTH_TILE = 2048;  // sorted positions per block of the leaf marking
 
 struct OrthView {
-    const OrthNode* node;
+    const uint4* box;
+    const uint2* link;
     const uint4* pts;          // {x, y, z or 0, id} in Morton order
+    const uint32_t* ids;       // the same ids, alone
     const uint32_t* lstart;    // first point of each leaf, in leaf order
     const uint64_t* fkey;      // Morton key of each leaf's first point
     uint64_t N;                // nodes
     uint32_t L;                // leaves
     uint32_t n;                // points
 };
-// Leaf cut of the sorted keys. write = false: the number of leaf starts of
-// each ORTH_TILE tile into tile_cnt. write = true: with tile_off the exclusive
-// scan of those counts, the leaves' first positions, levels and first keys,
-// and every point {coords decoded from its key, id}.
-void launch_orth_marks(hipStream_t st, int dim, bool write, const uint64_t* sk, const uint32_t* sid, uint64_t n,
-                       uint32_t phi, uint32_t* tile_cnt, const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev,
-                       uint64_t* fkey, uint4* pts);
+// Leaf cut of the sorted keys, first pass: per position a mark byte (leaf
+// level, bit 7 = a leaf starts here; mark holds a whole number of tiles),
+// the number of leaf starts of each ORTH_TILE tile, and every point {coords
+// decoded from its key, id} (pts) and its id (ids).
+void launch_orth_mark(hipStream_t st, int dim, const uint64_t* sk, const uint32_t* sid, uint64_t n, uint32_t phi,
+                      uint8_t* mark, uint32_t* tile_cnt, uint4* pts, uint32_t* ids);
+// Second pass, with tile_off the exclusive scan of the tile counts: each
+// leaf's first position, level and first key.
+void launch_orth_leaves(hipStream_t st, const uint64_t* sk, uint64_t n, const uint8_t* mark,
+                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey);
 // Interior nodes that open at each leaf, plus one (cnt1, L words), and the
 // largest leaf level (atomic max into *maxlev, zeroed first).
 void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
                         uint32_t* cnt1, uint32_t* maxlev, uint32_t* err);
-// Node records in preorder from base = exclusive scan of cnt1 (N nodes in
-// all); leaf boxes from the points, interior boxes left empty; lev[v] = level
+// Nodes in preorder from base = exclusive scan of cnt1 (N nodes in all):
+// links of every node, boxes of the leaves (from the points); lev[v] = level
 // of interior node v, 0xFF for a leaf.
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
-                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, OrthNode* node,
-                       uint8_t* lev);
+                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
+                       uint2* link, uint8_t* lev);
 // Boxes of the interior nodes of one level from their children.
-void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, OrthNode* node);
+void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,
+                       const uint2* link);
+// Nodes as 8 words each: lo[3], hi[3], then link.x and link.y | 0x80000000
+// for a leaf.
+void launch_orth_export(hipStream_t st, int dim, const uint4* box, const uint2* link, uint64_t N, uint32_t* out);
 // Queries over a P-Orth tree (k <= 16; order and qkeys as for launch_knn).
 void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t* q, const uint64_t* qkeys,
                      uint64_t nq, const uint32_t* order, uint32_t k, uint32_t* ids, uint64_t* d2);
+// counts (ids null) or reports into ids[offsets[b] .. offsets[b + 1]).
 void launch_orth_range(hipStream_t st, int dim, const OrthView& t, const uint32_t* boxes, uint64_t nb,
                        const uint32_t* order, uint64_t* counts, const uint64_t* offsets, uint32_t* ids);
 

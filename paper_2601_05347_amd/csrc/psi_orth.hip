@@ -9,14 +9,16 @@ using namespace psi;
 
 struct psi_orth_s {
     psi_index ix = nullptr;  // stream, sort workspace, error word, timing
-    psi::Buf node, pts, lev, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
+    psi::Buf box, link, pts, ids, lev, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
     uint64_t n = 0, N = 0, L = 0;
     uint32_t height = 0;
 
     psi::OrthView view() const {
         psi::OrthView v{};
-        v.node = node.as<psi::OrthNode>();
+        v.box = box.as<uint4>();
+        v.link = link.as<uint2>();
         v.pts = pts.as<uint4>();
+        v.ids = ids.as<uint32_t>();
         v.lstart = lstart.as<uint32_t>();
         v.fkey = fkey.as<uint64_t>();
         v.N = N;
@@ -58,12 +60,14 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     if ((s = o->tmp.ensure(scan_tmp_words(n) * 4)) != PSI_OK) return s;  // scans of tiles, then of L <= n leaves
     if ((s = o->small.ensure(64)) != PSI_OK) return s;
     if ((s = o->pts.ensure(n * 16)) != PSI_OK) return s;
-    // leaf cut: count, scan, then write leaves and points
+    if ((s = o->ids.ensure(n * 4)) != PSI_OK) return s;
+    if ((s = o->mark.ensure(tiles * ORTH_TILE)) != PSI_OK) return s;
+    // leaf cut: marks, points and tile counts; scan; then the leaves
     uint32_t* small = o->small.as<uint32_t>();
     {
-        ProfScope ps(ix, "orth_marks", n * 8);
-        launch_orth_marks(st, ix->D, false, sk, sid, n, ix->phi, o->tcnt.as<uint32_t>(), nullptr, nullptr, nullptr,
-                          nullptr, nullptr);
+        ProfScope ps(ix, "orth_marks", n * 30 + tiles * 4);
+        launch_orth_mark(st, ix->D, sk, sid, n, ix->phi, o->mark.as<uint8_t>(), o->tcnt.as<uint32_t>(),
+                         o->pts.as<uint4>(), o->ids.as<uint32_t>());
     }
     launch_scan_u32(st, o->tcnt.as<uint32_t>(), o->toff.as<uint32_t>(), tiles, small, o->tmp.as<uint32_t>());
     if ((s = last_launch()) != PSI_OK) return s;
@@ -83,9 +87,9 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     if ((s = o->cnt1.ensure(L * 4)) != PSI_OK) return s;
     if ((s = o->base.ensure(L * 4)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_marks", n * 28 + L * 13);
-        launch_orth_marks(st, ix->D, true, sk, sid, n, ix->phi, nullptr, o->toff.as<uint32_t>(),
-                          o->lstart.as<uint32_t>(), o->llev.as<uint8_t>(), o->fkey.as<uint64_t>(), o->pts.as<uint4>());
+        ProfScope ps(ix, "orth_marks", n + L * 21);
+        launch_orth_leaves(st, sk, n, o->mark.as<uint8_t>(), o->toff.as<uint32_t>(), o->lstart.as<uint32_t>(),
+                           o->llev.as<uint8_t>(), o->fkey.as<uint64_t>());
     }
     // nodes opened per leaf -> preorder positions
     launch_fill_u32(st, small, 2, 0u);
@@ -103,18 +107,19 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     // N is a 32-bit sum: it cannot have wrapped while L (maxlev + 1) < 2^32
     if (L * (maxlev + 1ull) >= (1ull << 32)) return PSI_E_CAPACITY;
     if (N < L) return PSI_E_INTERNAL;
-    if ((s = o->node.ensure(N * sizeof(OrthNode))) != PSI_OK) return s;
+    if ((s = o->box.ensure(N * 16)) != PSI_OK) return s;
+    if ((s = o->link.ensure(N * 8)) != PSI_OK) return s;
     if ((s = o->lev.ensure(N)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_nodes", L * 21 + N * 33 + n * 16);
+        ProfScope ps(ix, "orth_nodes", L * 21 + N * 25 + n * 16);
         launch_orth_nodes(st, ix->D, o->llev.as<uint8_t>(), o->fkey.as<uint64_t>(), o->lstart.as<uint32_t>(),
                           o->base.as<uint32_t>(), (uint32_t)L, (uint32_t)n, N, o->pts.as<uint4>(),
-                          o->node.as<OrthNode>(), o->lev.as<uint8_t>());
+                          o->box.as<uint4>(), o->link.as<uint2>(), o->lev.as<uint8_t>());
     }
     {
-        ProfScope ps(ix, "orth_boxes", N * 33 * (uint64_t)maxlev);
+        ProfScope ps(ix, "orth_boxes", N * (uint64_t)maxlev + (N - L) * 48);
         for (uint32_t l = maxlev; l-- > 0;)
-            launch_orth_boxes(st, ix->D, l, N, o->lev.as<uint8_t>(), o->node.as<OrthNode>());
+            launch_orth_boxes(st, ix->D, l, N, o->lev.as<uint8_t>(), o->box.as<uint4>(), o->link.as<uint2>());
     }
     if ((s = last_launch()) != PSI_OK) return s;
     o->n = n;
@@ -223,8 +228,10 @@ psi_status psi_orth_export(psi_orth o, uint32_t* d_nodes, uint32_t* d_pts) {
     if (!o) return PSI_E_ARG;
     hipStream_t st = o->ix->st;
     psi_status s = PSI_OK;
-    if (d_nodes && o->N)
-        s = hip_ok(hipMemcpyAsync(d_nodes, o->node.p, o->N * sizeof(OrthNode), hipMemcpyDeviceToDevice, st));
+    if (d_nodes && o->N) {
+        launch_orth_export(st, o->ix->D, o->box.as<uint4>(), o->link.as<uint2>(), o->N, d_nodes);
+        s = last_launch();
+    }
     if (s == PSI_OK && d_pts && o->n)
         s = hip_ok(hipMemcpyAsync(d_pts, o->pts.p, o->n * 16, hipMemcpyDeviceToDevice, st));
     if (s != PSI_OK) return s;
