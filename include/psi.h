@@ -264,8 +264,8 @@ psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n);
 psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids,
                         uint64_t* d_d2);
 /* Points inside closed boxes (nb x [lo[dim], hi[dim]]), as psi_range_count
- * and psi_range_report; a report lists each box's ids in the tree's
- * depth-first order. */
+ * and psi_range_report; a report lists each box's ids in no particular
+ * order. */
 psi_status psi_orth_range_count(psi_orth o, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts);
 psi_status psi_orth_range_report(psi_orth o, const uint32_t* d_boxes, uint64_t nb, const uint64_t* d_offsets,
                                  uint32_t* d_ids);

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
                                                     const uint32_t* __restrict__ base, uint32_t L, uint32_t n,
                                                     uint64_t N, const uint4* __restrict__ pts,
                                                     uint4* __restrict__ box, uint2* __restrict__ link,
-                                                    uint8_t* __restrict__ lev) {
+                                                    uint32_t* __restrict__ first, uint8_t* __restrict__ lev) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= L) return;
     const uint32_t lv = llev[t];
@@ -258,6 +258,7 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
         const uint64_t v = b + (l - s);
         link[v] = make_uint2(out < L ? base[out] : (uint32_t)N, (out < L ? lstart[out] : n) - pb);
         box[v] = make_uint4(0u, 0u, 0u, 0u);
+        first[v] = pb;
         lev[v] = (uint8_t)l;
     }
     uint32_t lo[D], hi[D];
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
     const uint64_t v = b + (s <= lv ? lv - s : 0u);
     box[v] = box_pack<D>(lo, hi, true);
     link[v] = make_uint2(pb, pe - pb);
+    first[v] = pb;
     lev[v] = 0xFF;
 }
 
@@ -405,13 +407,26 @@ __global__ __launch_bounds__(256) void k_orth_knn(OrthView t, const uint32_t* __
     }
 }
 
-// Lane per box; REPORT writes the ids in preorder to out[offsets[b] ..
-// offsets[b + 1]).
+// Wave per box. The wave takes the preorder nodes 64 at a time from the
+// current position v (one node per lane, coalesced). A node is on the walk
+// unless an earlier node of the window is an interior node whose subtree is
+// decided by its box alone (apart from the query box, or inside it) and whose
+// subtree reaches past it: subtrees nest, so an exclusive prefix maximum of
+// those subtree ends over the lanes tells every lane whether it is skipped.
+// The next window starts at v + 64 or past the farthest such subtree. On the
+// walk: nodes inside the box add their counts (reports copy their ids, whole
+// subtrees being contiguous in the point array, one node at a time by the
+// whole wave); leaves straddling the box are scanned two at a time, one per
+// half-wave.
+constexpr int ORW_WAVES = 4;
+
 template <int D, bool REPORT>
 __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* __restrict__ boxes, uint64_t nb,
                                                     const uint32_t* __restrict__ order, uint64_t* __restrict__ counts,
                                                     const uint64_t* __restrict__ offsets, uint32_t* __restrict__ out) {
-    const uint64_t bx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = lane_id(), hl = lane & 31u;
+    const uint64_t bx = (uint64_t)blockIdx.x * ORW_WAVES + w;
     if (bx >= nb) return;
     const uint64_t b = order ? order[bx] : bx;
     uint32_t lo[D], hi[D];
@@ -422,57 +437,101 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
         hi[d] = boxes[b * 2 * D + D + d];
         empty = empty || lo[d] > hi[d];
     }
-    uint64_t cnt = 0, o = 0, lim = 0;
+    uint64_t cnt_lane = 0, cnt = 0, o = 0, lim = 0;
     if (REPORT) {
         o = offsets[b];
         lim = offsets[b + 1];
     }
     uint64_t v = empty ? t.N : 0;
     while (v < t.N) {
-        const uint4 nb4 = t.box[v];
+        const uint64_t i = v + lane;
+        const bool valid = i < t.N;
+        uint4 nb4 = make_uint4(0u, 0u, 0u, 0u);
+        uint2 lk = make_uint2(0u, 0u);
+        if (valid) {
+            nb4 = t.box[i];
+            lk = t.link[i];
+        }
         const bool leaf = box_leaf(nb4);
         uint32_t rl[D], rh[D];
         box_unpack<D>(nb4, rl, rh);
-        bool inside = true, apart = false;
+        bool inside = valid, apart = !valid;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             apart = apart || rh[d] < lo[d] || rl[d] > hi[d];
             inside = inside && lo[d] <= rl[d] && rh[d] <= hi[d];
         }
-        if (!apart && !inside && !leaf) {
-            ++v;  // straddling interior node: its first child
-            continue;
-        }
-        const uint2 lk = t.link[v];
-        const uint64_t next = leaf ? v + 1 : max<uint64_t>(lk.x, v + 1);
-        if (inside) {
-            if (!REPORT) {
-                cnt += lk.y;
-            } else {
-                uint32_t pb = lk.x;
-                if (!leaf) {  // the subtree's points start at its first leaf's
-                    uint64_t u = v + 1;
-                    while (u < t.N && !box_leaf(t.box[u])) ++u;
-                    pb = u < t.N ? t.link[u].x : 0u;
-                }
-                for (uint32_t e = 0; e < lk.y && o < lim; ++e) out[o++] = t.ids[pb + e];
-            }
-        } else if (!apart) {  // straddling leaf
-            for (uint32_t x = lk.x; x < lk.x + lk.y; ++x) {
-                const uint4 P = t.pts[x];
-                const uint32_t p[3] = {P.x, P.y, P.z};
-                bool in = true;
+        const uint32_t jend = (valid && !leaf && (apart || inside)) ? lk.x : 0u;
+        uint32_t incl = jend;  // inclusive prefix maximum over the lanes
 #pragma unroll
-                for (int d = 0; d < D; ++d) in = in && lo[d] <= p[d] && p[d] <= hi[d];
-                if (in) {
-                    if (!REPORT) ++cnt;
-                    else if (o < lim) out[o++] = P.w;
+        for (int s = 1; s < 64; s <<= 1) {
+            const uint32_t y = shfl_u32(incl, (int)lane - s);
+            if (lane >= (uint32_t)s) incl = max(incl, y);
+        }
+        uint32_t excl = shfl_u32(incl, (int)lane - 1);
+        if (lane == 0) excl = 0;
+        const bool on = valid && (uint64_t)excl <= i;
+        const uint32_t far = __builtin_amdgcn_readlane((int)incl, 63);
+        // whole subtrees inside the box
+        const bool take = on && inside && !apart;
+        if (!REPORT) {
+            cnt_lane += take ? lk.y : 0u;
+        } else {
+            uint64_t m = ballot(take);
+            while (m) {
+                const uint32_t x = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)lk.y, (int)x);
+                const uint32_t pb = t.first[v + x];
+                for (uint32_t e = lane; e < c; e += 64) {
+                    const uint64_t dst = o + e;
+                    if (dst < lim) out[dst] = t.ids[pb + e];
                 }
+                o += c;
             }
         }
-        v = next;
+        // leaves straddling the box, two at a time (one per half-wave)
+        uint64_t m = ballot(on && leaf && !inside && !apart);
+        while (m) {
+            const uint32_t xa = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            uint32_t xb = 64u;  // no second leaf
+            if (m) {
+                xb = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+            }
+            const uint32_t mine = lane < 32u ? xa : xb;
+            const uint32_t sp = shfl_u32(lk.x, (int)(mine & 63u)), sc = shfl_u32(lk.y, (int)(mine & 63u));
+            const uint32_t rc = mine < 64u ? sc : 0u;
+            const uint32_t rmax = max((uint32_t)__builtin_amdgcn_readlane((int)rc, 0),
+                                      (uint32_t)__builtin_amdgcn_readlane((int)rc, 32));
+            for (uint32_t e0 = 0; e0 < rmax; e0 += 32) {
+                const uint32_t e = e0 + hl;
+                bool in = false;
+                uint32_t id = 0;
+                if (e < rc) {
+                    const uint4 P = t.pts[sp + e];
+                    const uint32_t p[3] = {P.x, P.y, P.z};
+                    in = true;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) in = in && lo[d] <= p[d] && p[d] <= hi[d];
+                    id = P.w;
+                }
+                const uint64_t hit = ballot(in);
+                if (REPORT && in) {
+                    const uint64_t dst = o + count_below(hit);
+                    if (dst < lim) out[dst] = id;
+                }
+                if (REPORT) o += (uint32_t)__popcll(hit);
+                else cnt += (uint32_t)__popcll(hit);
+            }
+        }
+        v = max<uint64_t>(v + 64, (uint64_t)far);
     }
-    if (!REPORT) counts[b] = cnt;
+    if (!REPORT) {
+        for (int s = 32; s >= 1; s >>= 1) cnt_lane += shfl_u64(cnt_lane, (int)(lane ^ (uint32_t)s));
+        if (lane == 0) counts[b] = cnt + cnt_lane;
+    }
 }
 
 }  // namespace
@@ -502,11 +561,11 @@ void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint
 
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
                        const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
-                       uint2* link, uint8_t* lev) {
+                       uint2* link, uint32_t* first, uint8_t* lev) {
     if (L == 0) return;
     const dim3 g(blocks_for(L, 256));
-    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, lev);
-    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, lev);
+    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, first, lev);
+    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, first, lev);
 }
 
 void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,
@@ -546,7 +605,7 @@ void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t*
 void launch_orth_range(hipStream_t st, int dim, const OrthView& t, const uint32_t* boxes, uint64_t nb,
                        const uint32_t* order, uint64_t* counts, const uint64_t* offsets, uint32_t* ids) {
     if (nb == 0) return;
-    const dim3 g(blocks_for(nb, 256));
+    const dim3 g(blocks_for(nb, ORW_WAVES));
     const bool rep = ids != nullptr;
     if (dim == 2) {
         if (rep) hipLaunchKernelGGL((k_orth_range<2, true>), g, dim3(256), 0, st, t, boxes, nb, order, counts, offsets, ids);

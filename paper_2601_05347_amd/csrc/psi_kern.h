@@ -215,6 +215,7 @@ constexpr uint32_t ORTH_TILE = 2048;  // sorted positions per block of the leaf 
 struct OrthView {
     const uint4* box;
     const uint2* link;
+    const uint32_t* first;     // first point of each node's subtree
     const uint4* pts;          // {x, y, z or 0, id} in Morton order
     const uint32_t* ids;       // the same ids, alone
     const uint32_t* lstart;    // first point of each leaf, in leaf order
@@ -238,11 +239,11 @@ void launch_orth_leaves(hipStream_t st, const uint64_t* sk, uint64_t n, const ui
 void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
                         uint32_t* cnt1, uint32_t* maxlev, uint32_t* err);
 // Nodes in preorder from base = exclusive scan of cnt1 (N nodes in all):
-// links of every node, boxes of the leaves (from the points); lev[v] = level
-// of interior node v, 0xFF for a leaf.
+// links and first points of every node, boxes of the leaves (from the
+// points); lev[v] = level of interior node v, 0xFF for a leaf.
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
                        const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
-                       uint2* link, uint8_t* lev);
+                       uint2* link, uint32_t* first, uint8_t* lev);
 // Boxes of the interior nodes of one level from their children.
 void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,
                        const uint2* link);

@@ -9,7 +9,7 @@ using namespace psi;
 
 struct psi_orth_s {
     psi_index ix = nullptr;  // stream, sort workspace, error word, timing
-    psi::Buf box, link, pts, ids, lev, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
+    psi::Buf box, link, first, pts, ids, lev, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
     uint64_t n = 0, N = 0, L = 0;
     uint32_t height = 0;
 
@@ -17,6 +17,7 @@ struct psi_orth_s {
         psi::OrthView v{};
         v.box = box.as<uint4>();
         v.link = link.as<uint2>();
+        v.first = first.as<uint32_t>();
         v.pts = pts.as<uint4>();
         v.ids = ids.as<uint32_t>();
         v.lstart = lstart.as<uint32_t>();
@@ -109,12 +110,14 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     if (N < L) return PSI_E_INTERNAL;
     if ((s = o->box.ensure(N * 16)) != PSI_OK) return s;
     if ((s = o->link.ensure(N * 8)) != PSI_OK) return s;
+    if ((s = o->first.ensure(N * 4)) != PSI_OK) return s;
     if ((s = o->lev.ensure(N)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_nodes", L * 21 + N * 25 + n * 16);
+        ProfScope ps(ix, "orth_nodes", L * 21 + N * 29 + n * 16);
         launch_orth_nodes(st, ix->D, o->llev.as<uint8_t>(), o->fkey.as<uint64_t>(), o->lstart.as<uint32_t>(),
                           o->base.as<uint32_t>(), (uint32_t)L, (uint32_t)n, N, o->pts.as<uint4>(),
-                          o->box.as<uint4>(), o->link.as<uint2>(), o->lev.as<uint8_t>());
+                          o->box.as<uint4>(), o->link.as<uint2>(), o->first.as<uint32_t>(),
+                          o->lev.as<uint8_t>());
     }
     {
         ProfScope ps(ix, "orth_boxes", N * (uint64_t)maxlev + (N - L) * 48);
