@@ -243,8 +243,12 @@ psi_status psi_graph_destroy(psi_graph g);
  * holding more (equal points cannot be split). This is the tree Alg. 1
  * builds after merging every subtree of at most leaf_size points into a
  * leaf; its shape does not depend on the skeleton height of Alg. 1. Boxes are
- * the exact bounding boxes of the points below each node. Static: no
- * updates (Alg. 2 is not provided). */
+ * the exact bounding boxes of the points below each node.
+ * Batch updates give the tree of the new point set (the tree is canonical, so
+ * this is what Alg. 2's insertion and its deletion with flattening produce);
+ * they reach it by merging the sorted batch into the sorted order of the old
+ * points (or compacting that order) and cutting the tree again, in time
+ * linear in the tree's size, not by Alg. 2's local sieve. */
 typedef struct psi_orth_s* psi_orth;
 
 /* prm: dim 2 or 3, curve must be PSI_MORTON (the tree's child order),
@@ -259,6 +263,19 @@ psi_status psi_orth_destroy(psi_orth o);
  * stream twice (leaf and node counts). PSI_E_RANGE (and an empty tree) if a
  * coordinate is out of range. Not under graph capture (PSI_E_STATE). */
 psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n);
+
+/* Inserts m points (device, m x dim u32); they get ids next_id ..
+ * next_id + m - 1 in input order, written to d_new_ids (device, m u32) if
+ * not null. PSI_E_RANGE (nothing inserted, tree unchanged) if a coordinate is
+ * out of range; PSI_E_CAPACITY past 2^32 - 1 ids or 2^31 points. Waits for the
+ * stream. Any other failure leaves the tree empty. */
+psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
+/* Deletes the points with the given ids (device, m u32, any order); unknown,
+ * deleted and repeated ids are ignored. *d_ndeleted (device u64, may be null)
+ * receives the number removed. Waits for the stream. */
+psi_status psi_orth_batch_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
+/* Live points and the next id an insert hands out. */
+psi_status psi_orth_size(psi_orth o, uint64_t* h_n_live, uint32_t* h_next_id);
 
 /* Exact k nearest neighbours (k = 1..16), output as psi_knn. */
 psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids,
@@ -286,7 +303,7 @@ psi_status psi_orth_shape(psi_orth o, uint64_t* h_nodes, uint64_t* h_leaves, uin
 psi_status psi_orth_export(psi_orth o, uint32_t* d_nodes, uint32_t* d_pts);
 
 /* Timing of the tree's kernels, as psi_prof_* (families "orth_marks",
- * "orth_nodes", "orth_boxes", "orth_knn", "orth_range_count",
+ * "orth_nodes", "orth_boxes", "orth_merge", "orth_knn", "orth_range_count",
  * "orth_range_report", plus the sort's). */
 psi_status psi_orth_prof_enable(psi_orth o, int on);
 psi_status psi_orth_prof_reset(psi_orth o);

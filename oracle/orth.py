@@ -134,10 +134,11 @@ def build(pts, dim: int, phi: int, lam: int | None = None):
     return build_orth(np.arange(len(pts), dtype=np.int64), tuple([0] * dim), 0)
 
 
-def preorder(root, dim: int) -> dict:
+def preorder(root, dim: int, ids=None) -> dict:
     """Depth-first preorder arrays of a tree (children in index order):
     level, corner, leaf flag, count, lo, hi, end (index one past the subtree),
-    first (first point of a leaf in leaf order) and the leaves' id arrays."""
+    first (first point of a leaf in leaf order) and the leaves' id arrays
+    (row numbers of the built points, or ids[row] when ids is given)."""
     out = dict(level=[], corner=[], leaf=[], count=[], lo=[], hi=[], end=[], first=[], leaf_ids=[])
     if root is None:
         for k in ("level", "count", "end", "first"):
@@ -159,7 +160,7 @@ def preorder(root, dim: int) -> dict:
         out["end"].append(-1)
         out["first"].append(pos[0] if nd.leaf else -1)
         if nd.leaf:
-            out["leaf_ids"].append(nd.ids)
+            out["leaf_ids"].append(nd.ids if ids is None else np.asarray(ids, dtype=np.int64)[nd.ids])
             pos[0] += nd.count
         else:
             for c in nd.children:

@@ -66,6 +66,9 @@ SIGNATURES = {
     "psi_orth_create": (_i, [_P, _P, _P]),
     "psi_orth_destroy": (_i, [_P]),
     "psi_orth_build": (_i, [_P, _P, _u64]),
+    "psi_orth_batch_insert": (_i, [_P, _P, _u64, _P]),
+    "psi_orth_batch_delete": (_i, [_P, _P, _u64, _P]),
+    "psi_orth_size": (_i, [_P, _P, _P]),
     "psi_orth_knn": (_i, [_P, _P, _u64, _u32, _P, _P]),
     "psi_orth_range_count": (_i, [_P, _P, _u64, _P]),
     "psi_orth_range_report": (_i, [_P, _P, _u64, _P, _P]),
@@ -347,6 +350,21 @@ def psi_orth_build(h, pts, n: int):
     _check(lib().psi_orth_build(h, _dev_ptr(pts), n), "psi_orth_build")
 
 
+def psi_orth_batch_insert(h, pts, m: int, new_ids=None):
+    _check(lib().psi_orth_batch_insert(h, _dev_ptr(pts), m, _dev_ptr(new_ids)), "psi_orth_batch_insert")
+
+
+def psi_orth_batch_delete(h, ids, m: int, ndeleted=None):
+    _check(lib().psi_orth_batch_delete(h, _dev_ptr(ids), m, _dev_ptr(ndeleted)), "psi_orth_batch_delete")
+
+
+def psi_orth_size(h):
+    n = C.c_uint64()
+    nid = C.c_uint32()
+    _check(lib().psi_orth_size(h, C.byref(n), C.byref(nid)), "psi_orth_size")
+    return n.value, nid.value
+
+
 def psi_orth_knn(h, q, nq: int, k: int, ids, d2):
     _check(lib().psi_orth_knn(h, _dev_ptr(q), nq, k, _dev_ptr(ids), _dev_ptr(d2)), "psi_orth_knn")
 
@@ -563,10 +581,35 @@ class Orth:
 
     def build(self, pts):
         t = self._pts(pts)
-        self.n = 0
-        psi_orth_build(self._h, t, t.shape[0])
-        self.n = t.shape[0]
+        try:
+            psi_orth_build(self._h, t, t.shape[0])
+        finally:
+            self.n = psi_orth_size(self._h)[0]
         return self
+
+    def batch_insert(self, pts):
+        torch = _torch()
+        t = self._pts(pts)
+        ids = torch.empty(max(t.shape[0], 1), dtype=torch.int32, device=self.device)
+        try:
+            psi_orth_batch_insert(self._h, t, t.shape[0], ids)
+        finally:
+            self.n = psi_orth_size(self._h)[0]
+        return ids[:t.shape[0]]
+
+    def batch_delete(self, ids) -> int:
+        torch = _torch()
+        t = _as_u32(ids, self.device).reshape(-1)
+        nd = torch.zeros(1, dtype=torch.int64, device=self.device)
+        try:
+            psi_orth_batch_delete(self._h, t, t.numel(), nd)
+        finally:
+            self.n = psi_orth_size(self._h)[0]
+        return int(nd.item())
+
+    def size(self):
+        """(live points, next id)"""
+        return psi_orth_size(self._h)
 
     def knn(self, q, k: int):
         torch = _torch()

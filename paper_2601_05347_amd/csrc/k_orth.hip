@@ -534,6 +534,118 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
     }
 }
 
+// ------------------------------------------------------------------ updates
+// The tree is canonical (its shape depends only on the point set), so a batch
+// update produces the new set's sorted (key, id) pairs by a merge or a
+// compaction of the old order, and the tree is cut again from them.
+
+// Place of each new pair among the old points: the number of old keys <= its
+// key (every old id is smaller than every new one, so an old point with an
+// equal key comes first); hist[place] counts them.
+template <int D>
+__global__ __launch_bounds__(256) void k_orth_place(const uint4* __restrict__ pts, uint64_t n,
+                                                    const uint64_t* __restrict__ bk, uint64_t m,
+                                                    uint32_t* __restrict__ place, uint32_t* __restrict__ hist) {
+    const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t key = bk[j];
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        const uint4 P = pts[mid];
+        const uint32_t p[3] = {P.x, P.y, P.z};
+        if (morton_key<D>(p) <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    place[j] = (uint32_t)lo;
+    atomicAdd(&hist[lo], 1u);
+}
+
+// Merged order: old point i moves up by the new pairs placed at or before it
+// (hscan[i] + hist[i]), new pair j lands after place[j] old points and j new
+// ones.
+template <int D>
+__global__ __launch_bounds__(256) void k_orth_merge(const uint4* __restrict__ pts, uint64_t n,
+                                                    const uint32_t* __restrict__ hist,
+                                                    const uint32_t* __restrict__ hscan,
+                                                    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bid,
+                                                    const uint32_t* __restrict__ place, uint64_t m,
+                                                    uint64_t* __restrict__ mk, uint32_t* __restrict__ mi) {
+    const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x < n) {
+        const uint64_t dst = x + hscan[x] + hist[x];
+        const uint4 P = pts[x];
+        const uint32_t p[3] = {P.x, P.y, P.z};
+        mk[dst] = morton_key<D>(p);
+        mi[dst] = P.w;
+    } else if (x < n + m) {
+        const uint64_t j = x - n, dst = place[j] + j;
+        mk[dst] = bk[j];
+        mi[dst] = bid[j];
+    }
+}
+
+// Clears the live bits of the batch's ids; counts the bits that were set.
+__global__ __launch_bounds__(256) void k_orth_kill(const uint32_t* __restrict__ dids, uint64_t m, uint32_t next_id,
+                                                   uint32_t* __restrict__ alive,
+                                                   unsigned long long* __restrict__ removed) {
+    const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    bool hit = false;
+    if (j < m) {
+        const uint32_t id = dids[j];
+        if (id < next_id) {
+            const uint32_t bit = 1u << (id & 31u);
+            hit = (atomicAnd(&alive[id >> 5], ~bit) & bit) != 0;
+        }
+    }
+    const uint64_t b = ballot(hit);
+    if (lane_id() == 0 && b) atomicAdd(removed, (unsigned long long)__popcll(b));
+}
+
+__global__ __launch_bounds__(256) void k_orth_keep(const uint32_t* __restrict__ ids, uint64_t n,
+                                                   const uint32_t* __restrict__ alive, uint32_t* __restrict__ flag) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t id = ids[i];
+    flag[i] = (alive[id >> 5] >> (id & 31u)) & 1u;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_orth_compact(const uint4* __restrict__ pts, uint64_t n,
+                                                      const uint32_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ pos, uint64_t* __restrict__ mk,
+                                                      uint32_t* __restrict__ mi) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const uint4 P = pts[i];
+    const uint32_t p[3] = {P.x, P.y, P.z};
+    mk[pos[i]] = morton_key<D>(p);
+    mi[pos[i]] = P.w;
+}
+
+// Sets the live bits of ids [lo, hi): one thread per bitmap word; a word that
+// starts at or after lo is written whole (its bits at or above hi cleared),
+// the word holding older ids below lo is or-ed.
+__global__ __launch_bounds__(256) void k_orth_alive(uint32_t* __restrict__ alive, uint32_t lo, uint32_t hi) {
+    const uint64_t w = (uint64_t)(lo >> 5) + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t ws = w * 32;
+    if (ws >= hi) return;
+    const uint64_t a = ws > lo ? ws : lo, b = ws + 32 < hi ? ws + 32 : hi;
+    const uint32_t nb = (uint32_t)(b - a);
+    const uint32_t mask = (nb >= 32 ? 0xFFFFFFFFu : ((1u << nb) - 1u)) << (uint32_t)(a - ws);
+    if (ws >= lo) alive[w] = mask;
+    else alive[w] |= mask;
+}
+
+__global__ __launch_bounds__(256) void k_orth_iota(uint32_t* __restrict__ out, uint64_t m, uint32_t base) {
+    const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < m) out[j] = base + (uint32_t)j;
+}
+
+__global__ void k_orth_put64(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 }  // namespace
 
 void launch_orth_mark(hipStream_t st, int dim, const uint64_t* sk, const uint32_t* sid, uint64_t n, uint32_t phi,
@@ -614,6 +726,57 @@ void launch_orth_range(hipStream_t st, int dim, const OrthView& t, const uint32_
         if (rep) hipLaunchKernelGGL((k_orth_range<3, true>), g, dim3(256), 0, st, t, boxes, nb, order, counts, offsets, ids);
         else hipLaunchKernelGGL((k_orth_range<3, false>), g, dim3(256), 0, st, t, boxes, nb, order, counts, offsets, ids);
     }
+}
+
+void launch_orth_place(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint64_t* bk, uint64_t m,
+                       uint32_t* place, uint32_t* hist) {
+    if (m == 0) return;
+    const dim3 g(blocks_for(m, 256));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_place<2>), g, dim3(256), 0, st, pts, n, bk, m, place, hist);
+    else hipLaunchKernelGGL((k_orth_place<3>), g, dim3(256), 0, st, pts, n, bk, m, place, hist);
+}
+
+void launch_orth_merge(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* hist,
+                       const uint32_t* hscan, const uint64_t* bk, const uint32_t* bid, const uint32_t* place,
+                       uint64_t m, uint64_t* mk, uint32_t* mi) {
+    if (n + m == 0) return;
+    const dim3 g(blocks_for(n + m, 256));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_merge<2>), g, dim3(256), 0, st, pts, n, hist, hscan, bk, bid, place, m, mk, mi);
+    else hipLaunchKernelGGL((k_orth_merge<3>), g, dim3(256), 0, st, pts, n, hist, hscan, bk, bid, place, m, mk, mi);
+}
+
+void launch_orth_kill(hipStream_t st, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
+                      unsigned long long* removed) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_orth_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, dids, m, next_id, alive, removed);
+}
+
+void launch_orth_keep(hipStream_t st, const uint32_t* ids, uint64_t n, const uint32_t* alive, uint32_t* flag) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_orth_keep, dim3(blocks_for(n, 256)), dim3(256), 0, st, ids, n, alive, flag);
+}
+
+void launch_orth_compact(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* flag,
+                         const uint32_t* pos, uint64_t* mk, uint32_t* mi) {
+    if (n == 0) return;
+    const dim3 g(blocks_for(n, 256));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_compact<2>), g, dim3(256), 0, st, pts, n, flag, pos, mk, mi);
+    else hipLaunchKernelGGL((k_orth_compact<3>), g, dim3(256), 0, st, pts, n, flag, pos, mk, mi);
+}
+
+void launch_orth_alive(hipStream_t st, uint32_t* alive, uint32_t lo, uint32_t hi) {
+    if (hi <= lo) return;
+    const uint64_t words = (((uint64_t)hi + 31) >> 5) - (lo >> 5);
+    hipLaunchKernelGGL(k_orth_alive, dim3(blocks_for(words, 256)), dim3(256), 0, st, alive, lo, hi);
+}
+
+void launch_orth_iota(hipStream_t st, uint32_t* out, uint64_t m, uint32_t base) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_orth_iota, dim3(blocks_for(m, 256)), dim3(256), 0, st, out, m, base);
+}
+
+void launch_orth_put64(hipStream_t st, unsigned long long* p, unsigned long long v) {
+    hipLaunchKernelGGL(k_orth_put64, dim3(1), dim3(64), 0, st, p, v);
 }
 
 }  // namespace psi

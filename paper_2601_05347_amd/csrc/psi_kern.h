@@ -257,6 +257,32 @@ void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t*
 void launch_orth_range(hipStream_t st, int dim, const OrthView& t, const uint32_t* boxes, uint64_t nb,
                        const uint32_t* order, uint64_t* counts, const uint64_t* offsets, uint32_t* ids);
 
+// P-Orth batch updates (the tree is canonical: the new set's sorted pairs are
+// made from the old order, then the tree is cut again).
+// place[j] = old points whose key is <= new key bk[j]; hist[place[j]] += 1
+// (hist: n + 1 words, zeroed).
+void launch_orth_place(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint64_t* bk, uint64_t m,
+                       uint32_t* place, uint32_t* hist);
+// Merged (key, id) pairs of the old points and the sorted batch into mk/mi
+// (n + m); hscan = exclusive scan of hist over its first n words.
+void launch_orth_merge(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* hist,
+                       const uint32_t* hscan, const uint64_t* bk, const uint32_t* bid, const uint32_t* place,
+                       uint64_t m, uint64_t* mk, uint32_t* mi);
+// Clears the live bits of the batch's ids below next_id; *removed += bits
+// that were set.
+void launch_orth_kill(hipStream_t st, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
+                      unsigned long long* removed);
+// flag[i] = live bit of point i's id.
+void launch_orth_keep(hipStream_t st, const uint32_t* ids, uint64_t n, const uint32_t* alive, uint32_t* flag);
+// Flagged points' (key, id) to mk/mi[pos[i]] (pos = exclusive scan of flag).
+void launch_orth_compact(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* flag,
+                         const uint32_t* pos, uint64_t* mk, uint32_t* mi);
+// Sets the live bits of ids [lo, hi) (words past the one holding lo - 1 are
+// written whole).
+void launch_orth_alive(hipStream_t st, uint32_t* alive, uint32_t lo, uint32_t hi);
+void launch_orth_iota(hipStream_t st, uint32_t* out, uint64_t m, uint32_t base);
+void launch_orth_put64(hipStream_t st, unsigned long long* p, unsigned long long v);
+
 // ----------------------------------------------------------------- export
 // Prefix sums of leaf counts -> entry offsets (u64, L+1 entries).
 void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp);

@@ -10,8 +10,11 @@ using namespace psi;
 struct psi_orth_s {
     psi_index ix = nullptr;  // stream, sort workspace, error word, timing
     psi::Buf box, link, first, pts, ids, lev, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
+    psi::Buf alive;             // live bit per id ever handed out
+    psi::Buf mk, mi, place, hist, hscan, flag;  // batch updates: the new set's sorted pairs
     uint64_t n = 0, N = 0, L = 0;
     uint32_t height = 0;
+    uint32_t next_id = 0;
 
     psi::OrthView view() const {
         psi::OrthView v{};
@@ -43,18 +46,16 @@ psi_status read2(psi_index ix, const uint32_t* a, uint32_t na, const uint32_t* b
     return hip_ok(hipStreamSynchronize(ix->st));
 }
 
-psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
+// The tree of the n pairs (sk, sid) sorted by (Morton key, id): leaf cut,
+// points, nodes and boxes. Reports PSI_E_RANGE (no tree) if an encode of the
+// pairs' points latched a range error.
+psi_status orth_cut(psi_orth o, const uint64_t* sk, const uint32_t* sid, uint64_t n) {
     psi_index ix = o->ix;
     hipStream_t st = ix->st;
     psi_status s;
     o->n = o->N = o->L = 0;
     o->height = 0;
     if (n == 0) return PSI_OK;
-    if ((s = ix->idkey.ensure(n * 8)) != PSI_OK) return s;
-    int w = 0;
-    if ((s = encode_sort(ix, d_pts, n, 0, &w)) != PSI_OK) return s;
-    const uint64_t* sk = ix->sorter.k[w].as<uint64_t>();
-    const uint32_t* sid = ix->sorter.i[w].as<uint32_t>();
     const uint64_t tiles = (n + ORTH_TILE - 1) / ORTH_TILE;
     if ((s = o->tcnt.ensure(tiles * 4)) != PSI_OK) return s;
     if ((s = o->toff.ensure(tiles * 4 + 4)) != PSI_OK) return s;
@@ -132,6 +133,99 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     return PSI_OK;
 }
 
+psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
+    psi_index ix = o->ix;
+    psi_status s;
+    o->n = o->N = o->L = 0;
+    o->height = 0;
+    o->next_id = 0;
+    if (n == 0) return PSI_OK;
+    if ((s = ix->idkey.ensure(n * 8)) != PSI_OK) return s;
+    int w = 0;
+    if ((s = encode_sort(ix, d_pts, n, 0, &w)) != PSI_OK) return s;
+    if ((s = o->alive.ensure((n + 31) / 32 * 4)) != PSI_OK) return s;
+    launch_orth_alive(ix->st, o->alive.as<uint32_t>(), 0, (uint32_t)n);
+    if ((s = orth_cut(o, ix->sorter.k[w].as<uint64_t>(), ix->sorter.i[w].as<uint32_t>(), n)) != PSI_OK) return s;
+    o->next_id = (uint32_t)n;
+    return PSI_OK;
+}
+
+// Insert: sort the batch, merge it into the old order, cut the tree again.
+psi_status orth_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids) {
+    psi_index ix = o->ix;
+    hipStream_t st = ix->st;
+    psi_status s;
+    const uint64_t n = o->n, id0 = o->next_id;
+    if ((s = ix->idkey.ensure((id0 + m) * 8)) != PSI_OK) return s;
+    int w = 0;
+    if ((s = encode_sort(ix, d_pts, m, (uint32_t)id0, &w)) != PSI_OK) return s;
+    if ((s = read2(ix, ix->err.as<uint32_t>(), 1, nullptr, 0)) != PSI_OK) return s;
+    uint32_t e = 0;
+    std::memcpy(&e, ix->pinned, 4);
+    if (e & ERR_RANGE) {  // nothing inserted, the tree unchanged
+        launch_fill_u32(st, ix->err.as<uint32_t>(), 1, 0u);
+        (void)hipStreamSynchronize(st);
+        return PSI_E_RANGE;
+    }
+    const uint64_t* bk = ix->sorter.k[w].as<uint64_t>();
+    const uint32_t* bid = ix->sorter.i[w].as<uint32_t>();
+    if ((s = o->mk.ensure((n + m) * 8)) != PSI_OK) return s;
+    if ((s = o->mi.ensure((n + m) * 4)) != PSI_OK) return s;
+    if ((s = o->place.ensure(m * 4)) != PSI_OK) return s;
+    if ((s = o->hist.ensure((n + 1) * 4)) != PSI_OK) return s;
+    if ((s = o->hscan.ensure((n + 1) * 4)) != PSI_OK) return s;
+    if ((s = o->tmp.ensure(scan_tmp_words(n + m + 1) * 4)) != PSI_OK) return s;
+    {
+        ProfScope ps(ix, "orth_merge", m * 16 * 20 + n * 44);
+        launch_fill_u32(st, o->hist.as<uint32_t>(), n + 1, 0u);
+        launch_orth_place(st, ix->D, o->pts.as<uint4>(), n, bk, m, o->place.as<uint32_t>(), o->hist.as<uint32_t>());
+        launch_scan_u32(st, o->hist.as<uint32_t>(), o->hscan.as<uint32_t>(), n, nullptr, o->tmp.as<uint32_t>());
+        launch_orth_merge(st, ix->D, o->pts.as<uint4>(), n, o->hist.as<uint32_t>(), o->hscan.as<uint32_t>(), bk, bid,
+                          o->place.as<uint32_t>(), m, o->mk.as<uint64_t>(), o->mi.as<uint32_t>());
+    }
+    if (d_new_ids) launch_orth_iota(st, d_new_ids, m, (uint32_t)id0);
+    if ((s = o->alive.grow_keep((id0 + m + 31) / 32 * 4, (id0 + 31) / 32 * 4, st)) != PSI_OK) return s;
+    launch_orth_alive(st, o->alive.as<uint32_t>(), (uint32_t)id0, (uint32_t)(id0 + m));
+    if ((s = last_launch()) != PSI_OK) return s;
+    o->next_id = (uint32_t)(id0 + m);
+    // the cut may grow the point arrays the merge read: let the merge finish
+    if ((s = hip_ok(hipStreamSynchronize(st))) != PSI_OK) return s;
+    return orth_cut(o, o->mk.as<uint64_t>(), o->mi.as<uint32_t>(), n + m);
+}
+
+// Delete: clear the ids' live bits, compact the old order, cut the tree again.
+psi_status orth_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
+    psi_index ix = o->ix;
+    hipStream_t st = ix->st;
+    psi_status s;
+    const uint64_t n = o->n;
+    if ((s = o->small.ensure(64)) != PSI_OK) return s;
+    unsigned long long* removed = reinterpret_cast<unsigned long long*>(o->small.as<uint32_t>() + 8);
+    launch_orth_put64(st, removed, 0ull);
+    if (m && o->next_id) launch_orth_kill(st, d_ids, m, o->next_id, o->alive.as<uint32_t>(), removed);
+    if ((s = last_launch()) != PSI_OK) return s;
+    if ((s = read2(ix, reinterpret_cast<const uint32_t*>(removed), 2, nullptr, 0)) != PSI_OK) return s;
+    uint64_t r = 0;
+    std::memcpy(&r, ix->pinned, 8);
+    if (d_ndeleted) launch_orth_put64(st, reinterpret_cast<unsigned long long*>(d_ndeleted), r);
+    if (r == 0) return last_launch();
+    if (r > n) return PSI_E_INTERNAL;
+    if ((s = o->mk.ensure((n - r) * 8 + 8)) != PSI_OK) return s;
+    if ((s = o->mi.ensure((n - r) * 4 + 4)) != PSI_OK) return s;
+    if ((s = o->flag.ensure(n * 4)) != PSI_OK) return s;
+    if ((s = o->hscan.ensure(n * 4)) != PSI_OK) return s;
+    if ((s = o->tmp.ensure(scan_tmp_words(n) * 4)) != PSI_OK) return s;
+    {
+        ProfScope ps(ix, "orth_merge", n * 36);
+        launch_orth_keep(st, o->ids.as<uint32_t>(), n, o->alive.as<uint32_t>(), o->flag.as<uint32_t>());
+        launch_scan_u32(st, o->flag.as<uint32_t>(), o->hscan.as<uint32_t>(), n, nullptr, o->tmp.as<uint32_t>());
+        launch_orth_compact(st, ix->D, o->pts.as<uint4>(), n, o->flag.as<uint32_t>(), o->hscan.as<uint32_t>(),
+                            o->mk.as<uint64_t>(), o->mi.as<uint32_t>());
+    }
+    if ((s = last_launch()) != PSI_OK) return s;
+    return orth_cut(o, o->mk.as<uint64_t>(), o->mi.as<uint32_t>(), n - r);
+}
+
 }  // namespace
 
 extern "C" {
@@ -173,6 +267,37 @@ psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
         o->height = 0;
     }
     return s;
+}
+
+psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids) {
+    if (!o || (m && !d_pts)) return PSI_E_ARG;
+    if (capturing(o->ix->st)) return PSI_E_STATE;
+    if ((uint64_t)o->next_id + m > 0xFFFFFFFFull || o->n + m >= (1ull << 31)) return PSI_E_CAPACITY;
+    if (m == 0) return PSI_OK;
+    psi_status s = orth_insert(o, d_pts, m, d_new_ids);
+    if (s != PSI_OK && s != PSI_E_RANGE) {
+        o->n = o->N = o->L = 0;
+        o->height = 0;
+    }
+    return s;
+}
+
+psi_status psi_orth_batch_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
+    if (!o || (m && !d_ids)) return PSI_E_ARG;
+    if (capturing(o->ix->st)) return PSI_E_STATE;
+    psi_status s = orth_delete(o, d_ids, m, d_ndeleted);
+    if (s != PSI_OK) {
+        o->n = o->N = o->L = 0;
+        o->height = 0;
+    }
+    return s;
+}
+
+psi_status psi_orth_size(psi_orth o, uint64_t* h_n_live, uint32_t* h_next_id) {
+    if (!o) return PSI_E_ARG;
+    if (h_n_live) *h_n_live = o->n;
+    if (h_next_id) *h_next_id = o->next_id;
+    return PSI_OK;
 }
 
 psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids, uint64_t* d_d2) {

@@ -42,9 +42,11 @@ def segment_sort(ids, first, count):
     return v[np.lexsort((v, seg))]
 
 
-def check_structure(o, pts, dim, phi):
+def check_structure(o, pts, dim, phi, live=None):
+    """live: the ids of the rows of pts (ascending; default 0 .. n-1)."""
+    live = np.arange(len(pts), dtype=np.int64) if live is None else np.asarray(live, dtype=np.int64)
     nodes, gp = o.export()
-    ref = orth.preorder(orth.build(pts, dim, phi), dim)
+    ref = orth.preorder(orth.build(pts, dim, phi), dim, ids=live)
     N = len(ref["level"])
     nn, nl, h = o.shape()
     assert nn == N and nl == int(ref["leaf"].sum())
@@ -62,8 +64,8 @@ def check_structure(o, pts, dim, phi):
     np.testing.assert_array_equal(nodes[~leaf, 6], ref["end"][~leaf])
     np.testing.assert_array_equal(nodes[leaf, 6], ref["first"][leaf])
     ids = gp[:, 3].astype(np.int64)
-    np.testing.assert_array_equal(np.sort(ids), np.arange(len(pts)))
-    np.testing.assert_array_equal(gp[:, :dim], np.asarray(pts)[ids])
+    np.testing.assert_array_equal(np.sort(ids), live)
+    np.testing.assert_array_equal(gp[:, :dim], np.asarray(pts)[np.searchsorted(live, ids)])
     if dim == 2:
         assert (gp[:, 2] == 0).all()
     first = nodes[leaf, 6].astype(np.int64)
@@ -73,15 +75,31 @@ def check_structure(o, pts, dim, phi):
     np.testing.assert_array_equal(got, want)
 
 
-def check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 10, 16)):
+def rows_to_ids(rows, live):
+    rows = np.asarray(rows)
+    out = np.full(rows.shape, 0xFFFFFFFF, dtype=np.uint32)
+    ok = rows != 0xFFFFFFFF
+    out[ok] = np.asarray(live)[rows[ok].astype(np.int64)]
+    return out
+
+
+def check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 10, 16), live=None):
+    live = np.arange(len(pts), dtype=np.int64) if live is None else np.asarray(live, dtype=np.int64)
     for k in ks:
         ids, d2 = o.knn(q, k)
         o.sync()
-        eid, ed2 = oracle.knn_points(pts, q, k)
+        if len(pts):
+            eid, ed2 = oracle.knn_points(pts, q, k)
+        else:
+            eid = np.full((len(q), k), 0xFFFFFFFF, np.uint32)
+            ed2 = np.full((len(q), k), 0xFFFFFFFFFFFFFFFF, np.uint64)
         np.testing.assert_array_equal(psi.to_u64(d2), ed2, err_msg=f"kNN d2 k={k}")
-        np.testing.assert_array_equal(psi.to_u32(ids), eid, err_msg=f"kNN ids k={k}")
+        np.testing.assert_array_equal(psi.to_u32(ids), rows_to_ids(eid, live), err_msg=f"kNN ids k={k}")
     cnt = o.range_count(bx)
     o.sync()
+    if len(pts) == 0:
+        assert (psi.to_u64(cnt) == 0).all()
+        return
     np.testing.assert_array_equal(psi.to_u64(cnt), oracle.range_count_points(pts, bx))
     off, rid = o.range_report(bx)
     o.sync()
@@ -91,7 +109,7 @@ def check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 10, 16)):
     off = psi.to_u64(off).astype(np.int64)
     np.testing.assert_array_equal(off, eoff.astype(np.int64))
     got = segment_sort(psi.to_u32(rid), off[:-1], np.diff(off))
-    np.testing.assert_array_equal(got, eids)
+    np.testing.assert_array_equal(got, rows_to_ids(eids, live))
 
 
 def bits_of(dim):
@@ -194,6 +212,93 @@ def test_out_of_range_points_and_bad_arguments(psi):
     ok = pts & np.uint32((1 << 21) - 1)
     o.build(ok)
     check_structure(o, ok, 3, 32)
+
+
+@pytest.mark.parametrize("dim,phi", [(2, 8), (3, 32), (3, 2)])
+def test_batch_updates_match_the_oracle(psi, dim, phi):
+    """build -> insert (with points equal to live ones) -> delete (live, dead,
+    unknown and repeated ids) -> insert -> delete nearly all -> delete all ->
+    insert into the empty tree; after each step the tree equals the oracle's
+    tree of the live set, and queries match brute force."""
+    bits = bits_of(dim) if dim == 3 else 20
+    rng = synth.draws(synth.stream_key(41 + dim + phi, synth.P_AUX), 0, 10_000)
+    pts = synth.uniform(3000, dim, bits, 42)
+    extra = np.concatenate([synth.uniform(1700, dim, bits, 43, synth.P_INSERT), pts[:300]])  # 300 repeats
+    allp = np.concatenate([pts, extra])
+    o = psi.Orth(dim, phi).build(pts)
+    live = np.arange(3000)
+    q = queries(dim, 200, 44, pts, bits)
+    bx = synth.boxes(q[:150], bits, 45, side_lo=bits - 8, side_hi=bits - 3)
+
+    def check(step):
+        say(f"orth updates dim={dim} phi={phi}: {step}, {len(live)} live")
+        assert o.size()[0] == len(live)
+        check_structure(o, allp[live], dim, phi, live)
+        check_queries(psi, o, allp[live], dim, phi, q, bx, ks=(1, 10), live=live)
+
+    check("build")
+    new = psi.to_u32(o.batch_insert(extra))
+    np.testing.assert_array_equal(new, np.arange(3000, 5000))
+    live = np.arange(5000)
+    check("insert")
+    dels = live[rng[:5000] % 3 == 0]
+    batch = np.concatenate([dels, dels[:50], [6000, 7000, 0xFFFFFFF0]]).astype(np.uint32)
+    assert o.batch_delete(batch) == len(dels)
+    live = np.setdiff1d(live, dels)
+    assert o.batch_delete(dels[:10]) == 0  # already deleted
+    check("delete")
+    more = synth.uniform(500, dim, bits, 46, synth.P_INSERT)
+    allp = np.concatenate([allp, more])
+    np.testing.assert_array_equal(psi.to_u32(o.batch_insert(more)), np.arange(5000, 5500))
+    live = np.concatenate([live, np.arange(5000, 5500)])
+    check("insert 2")
+    keep = live[:: max(1, len(live) // 10)][:10]
+    assert o.batch_delete(np.setdiff1d(live, keep).astype(np.uint32)) == len(live) - len(keep)
+    live = keep
+    check("delete nearly all")
+    assert o.batch_delete(live.astype(np.uint32)) == len(live)
+    live = live[:0]
+    check("delete all")
+    assert o.shape() == (0, 0, 0)
+    last = synth.uniform(40, dim, bits, 47, synth.P_INSERT)
+    allp = np.concatenate([allp, last])
+    np.testing.assert_array_equal(psi.to_u32(o.batch_insert(last)), np.arange(5500, 5540))
+    live = np.arange(5500, 5540)
+    check("insert into the empty tree")
+
+
+def test_insert_without_build_and_rejected_batches(psi):
+    say("orth insert into a fresh tree")
+    o = psi.Orth(3, 16)
+    pts = synth.uniform(5000, 3, 21, 51)
+    np.testing.assert_array_equal(psi.to_u32(o.batch_insert(pts[:3000])), np.arange(3000))
+    np.testing.assert_array_equal(psi.to_u32(o.batch_insert(pts[3000:])), np.arange(3000, 5000))
+    check_structure(o, pts, 3, 16)
+    bad = synth.uniform(10, 3, 21, 52, synth.P_INSERT)
+    bad[3, 2] = 1 << 21
+    with pytest.raises(psi.PsiError) as e:
+        o.batch_insert(bad)
+    assert e.value.code == 2
+    assert o.size() == (5000, 5000)
+    check_structure(o, pts, 3, 16)  # unchanged
+    assert o.batch_delete(np.zeros(0, np.uint32)) == 0
+    check_structure(o, pts, 3, 16)
+
+
+def test_large_batches(psi):
+    say("orth 300k build, 100k insert, 120k delete")
+    pts = synth.uniform(300_000, 3, 21, 61)
+    ins = synth.points("varden", 100_000, 3, 21, 62, synth.P_INSERT)
+    o = psi.Orth(3, 32).build(pts)
+    o.batch_insert(ins)
+    allp = np.concatenate([pts, ins])
+    dels = synth.delete_ids(np.arange(400_000, dtype=np.uint32), 120_000, 63)
+    assert o.batch_delete(dels) == 120_000
+    live = np.setdiff1d(np.arange(400_000), dels.astype(np.int64))
+    check_structure(o, allp[live], 3, 32, live)
+    q = queries(3, 2000, 64, allp[live], 21)
+    bx = synth.boxes(q[:1000], 21, 65, side_lo=12, side_hi=17)
+    check_queries(psi, o, allp[live], 3, 32, q, bx, ks=(10,), live=live)
 
 
 @pytest.mark.slow
