@@ -41,9 +41,9 @@ WORKLOADS = {
     "serve": dict(dim=3, bits=21, n=50_000_000, m=0, nq=0, k=10, nb=0),
     # 4096 independent 2D SPaC-Z indexes (sizes log-uniform 1e3..1e6), kNN k = 8
     "multi": dict(dim=2, bits=30, n=0, m=0, nq=0, k=8, nb=0),
-    # P-Orth tree (Sec. 3) beside the SPaC-H tree on the 3d-1e8 inputs: static
-    # build, 1e7 10-NN queries, 1e6 range counts and reports
-    "orth": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=1_000_000),
+    # P-Orth tree (Sec. 3) beside the SPaC-H tree on the 3d-1e8 inputs: build,
+    # insert 1e6, delete 1e6, 1e7 10-NN queries, 1e6 range counts and reports
+    "orth": dict(dim=3, bits=21, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
     # incremental workload: 3D, 1e8 points inserted into an empty index in n/b
     # batches, then deleted in n/b batches; 1e7 10-NN queries at the halfway points
     "incr": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=0),
@@ -312,8 +312,8 @@ def bench_incr(args):
 
 def bench_orth(args):
     """P-Orth tree (Sec. 3) and SPaC-H tree on the same inputs (those of the
-    3d-1e8 workload): per step, a build of each, then kNN, range count and
-    range report on each. Every phase is timed with HIP events on the
+    3d-1e8 workload): per step, a build of each, a batch insert and a batch
+    delete, then kNN, range count and range report on each. Every phase is timed with HIP events on the
     stream; the builds include their readbacks."""
     import numpy as np
     import torch
@@ -329,43 +329,55 @@ def bench_orth(args):
     nb = min(nb, max(1000, n // 100))
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    data, _, q = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=0, n_query=nq)
+    m = cfg["m"]
+    data, ins, q = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=m, n_query=nq)
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, args.seed)
     boxes = synth.boxes(q[:nb], bits, args.seed)
     log(f"orth: inputs generated in {time.perf_counter() - t:.1f} s")
     d_data = torch.from_numpy(data.view(np.int32)).to(dev)
+    d_ins = torch.from_numpy(ins.view(np.int32)).to(dev)
+    d_dels = torch.from_numpy(dels.view(np.int32)).to(dev)
     d_q = torch.from_numpy(q.view(np.int32)).to(dev)
     d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
-    del data, q
+    del data, q, ins
     stream = torch.cuda.current_stream(dev)
     trees = {"orth": psi.Orth(dim, args.leaf, device=dev, stream=stream),
              "spac_h": psi.Index(dim, psi.HILBERT, args.leaf, args.fanout, device=dev, stream=stream)}
-    api = {"orth": (psi.psi_orth_build, psi.psi_orth_knn, psi.psi_orth_range_count, psi.psi_orth_range_report),
-           "spac_h": (psi.psi_build, psi.psi_knn, psi.psi_range_count, psi.psi_range_report)}
+    api = {"orth": (psi.psi_orth_build, psi.psi_orth_batch_insert, psi.psi_orth_batch_delete, psi.psi_orth_knn,
+                    psi.psi_orth_range_count, psi.psi_orth_range_report),
+           "spac_h": (psi.psi_build, psi.psi_batch_insert, psi.psi_batch_delete, psi.psi_knn, psi.psi_range_count,
+                      psi.psi_range_report)}
+    new_ids = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
     k_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     k_d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
     cnt = torch.empty(nb, dtype=torch.int64, device=dev)
     off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
     rids, res, outs = {}, {}, {}
     for name, tr in trees.items():
-        build, knn, rcount, rreport = api[name]
+        build, insert, delete, knn, rcount, rreport = api[name]
         h = tr._h
-        ms = {p: [] for p in ("build", "knn", "range_count", "range_report")}
+        ms = {p: [] for p in ("build", "insert", "delete", "knn", "range_count", "range_report")}
         for it in range(args.warmup + args.steps):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
             ev[0].record(stream)
             build(h, d_data, n)
             ev[1].record(stream)
-            knn(h, d_q, nq, k, k_ids, k_d2)
+            insert(h, d_ins, m, new_ids)
             ev[2].record(stream)
-            rcount(h, d_boxes, nb, cnt)
+            delete(h, d_dels, m, nd)
             ev[3].record(stream)
+            knn(h, d_q, nq, k, k_ids, k_d2)
+            ev[4].record(stream)
+            rcount(h, d_boxes, nb, cnt)
+            ev[5].record(stream)
             if name not in rids:
                 torch.cumsum(cnt, 0, out=off[1:])
                 rids[name] = torch.empty(max(int(off[-1].item()), 1), dtype=torch.int32, device=dev)
-                ev[3].record(stream)
+                ev[5].record(stream)
             rreport(h, d_boxes, nb, off, rids[name])
-            ev[4].record(stream)
-            ev[4].synchronize()
+            ev[6].record(stream)
+            ev[6].synchronize()
             if it >= args.warmup:
                 for j, p in enumerate(ms):
                     ms[p].append(ev[j].elapsed_time(ev[j + 1]))
@@ -373,6 +385,8 @@ def bench_orth(args):
         outs[name] = (k_ids.clone(), k_d2.clone(), cnt.clone())
         med = {p: round(float(np.median(v)), 3) for p, v in ms.items()}
         res[name] = {"ms": med, "build_mpts_s": round(n / med["build"] / 1e3, 1),
+                     "insert_mpts_s": round(m / med["insert"] / 1e3, 1),
+                     "delete_mpts_s": round(m / med["delete"] / 1e3, 1),
                      "knn_mq_s": round(nq / med["knn"] / 1e3, 1),
                      "range_count_mbox_s": round(nb / med["range_count"] / 1e3, 2),
                      "range_report_mbox_s": round(nb / med["range_report"] / 1e3, 2)}
@@ -382,10 +396,12 @@ def bench_orth(args):
             tr.prof_enable(True)
             tr.prof_reset()
             build(h, d_data, n)
+            insert(h, d_ins, m, new_ids)
+            delete(h, d_dels, m, nd)
             knn(h, d_q, nq, k, k_ids, k_d2)
             fam = {}
             for f in ("encode_hist", "radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide",
-                      "orth_marks", "orth_nodes", "orth_boxes", "orth_knn", "order", "radix_order"):
+                      "orth_marks", "orth_nodes", "orth_boxes", "orth_merge", "orth_knn", "order", "radix_order"):
                 fms, nl_, _ = tr.prof_get(f)
                 if nl_:
                     fam[f] = round(fms, 3)
@@ -395,7 +411,7 @@ def bench_orth(args):
     o, sp = res["orth"], res["spac_h"]
     a, b = outs["orth"], outs["spac_h"]
     identical = all(bool(torch.equal(x, y)) for x, y in zip(a, b))
-    out = {"metric": "P-Orth static build Mpoints/s (1e8 pts, 3D); kNN queries/s", "value": o["build_mpts_s"],
+    out = {"metric": "P-Orth build Mpoints/s (1e8 pts, 3D); updates, kNN and range beside SPaC-H", "value": o["build_mpts_s"],
            "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(sum(o["ms"].values()), 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",

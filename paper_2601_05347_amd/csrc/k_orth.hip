@@ -585,10 +585,16 @@ __global__ __launch_bounds__(256) void k_orth_merge(const uint4* __restrict__ pt
     }
 }
 
-// Clears the live bits of the batch's ids; counts the bits that were set.
+// Clears the live bits of the batch's ids and counts the bits that were set.
+// The entry that cleared a bit finds its point in the key order (binary
+// search for (key, id), the key from the id's key table) and clears that
+// position's keep flag.
+template <int D>
 __global__ __launch_bounds__(256) void k_orth_kill(const uint32_t* __restrict__ dids, uint64_t m, uint32_t next_id,
-                                                   uint32_t* __restrict__ alive,
-                                                   unsigned long long* __restrict__ removed) {
+                                                   uint32_t* __restrict__ alive, const uint64_t* __restrict__ idkey,
+                                                   const uint4* __restrict__ pts, uint64_t n,
+                                                   uint32_t* __restrict__ keep, unsigned long long* __restrict__ removed,
+                                                   uint32_t* __restrict__ err) {
     const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     bool hit = false;
     if (j < m) {
@@ -596,18 +602,23 @@ __global__ __launch_bounds__(256) void k_orth_kill(const uint32_t* __restrict__ 
         if (id < next_id) {
             const uint32_t bit = 1u << (id & 31u);
             hit = (atomicAnd(&alive[id >> 5], ~bit) & bit) != 0;
+            if (hit) {
+                const uint64_t key = idkey[id];
+                uint64_t lo = 0, hi = n;
+                while (lo < hi) {
+                    const uint64_t mid = lo + ((hi - lo) >> 1);
+                    const uint4 P = pts[mid];
+                    const uint32_t p[3] = {P.x, P.y, P.z};
+                    if (pair_less(morton_key<D>(p), P.w, key, id)) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < n && pts[lo].w == id) keep[lo] = 0u;
+                else atomicOr(err, ERR_ORTH);
+            }
         }
     }
     const uint64_t b = ballot(hit);
     if (lane_id() == 0 && b) atomicAdd(removed, (unsigned long long)__popcll(b));
-}
-
-__global__ __launch_bounds__(256) void k_orth_keep(const uint32_t* __restrict__ ids, uint64_t n,
-                                                   const uint32_t* __restrict__ alive, uint32_t* __restrict__ flag) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t id = ids[i];
-    flag[i] = (alive[id >> 5] >> (id & 31u)) & 1u;
 }
 
 template <int D>
@@ -635,11 +646,6 @@ __global__ __launch_bounds__(256) void k_orth_alive(uint32_t* __restrict__ alive
     const uint32_t mask = (nb >= 32 ? 0xFFFFFFFFu : ((1u << nb) - 1u)) << (uint32_t)(a - ws);
     if (ws >= lo) alive[w] = mask;
     else alive[w] |= mask;
-}
-
-__global__ __launch_bounds__(256) void k_orth_iota(uint32_t* __restrict__ out, uint64_t m, uint32_t base) {
-    const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < m) out[j] = base + (uint32_t)j;
 }
 
 __global__ void k_orth_put64(unsigned long long* p, unsigned long long v) {
@@ -745,15 +751,13 @@ void launch_orth_merge(hipStream_t st, int dim, const uint4* pts, uint64_t n, co
     else hipLaunchKernelGGL((k_orth_merge<3>), g, dim3(256), 0, st, pts, n, hist, hscan, bk, bid, place, m, mk, mi);
 }
 
-void launch_orth_kill(hipStream_t st, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
-                      unsigned long long* removed) {
+void launch_orth_kill(hipStream_t st, int dim, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
+                      const uint64_t* idkey, const uint4* pts, uint64_t n, uint32_t* keep,
+                      unsigned long long* removed, uint32_t* err) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_orth_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, dids, m, next_id, alive, removed);
-}
-
-void launch_orth_keep(hipStream_t st, const uint32_t* ids, uint64_t n, const uint32_t* alive, uint32_t* flag) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_orth_keep, dim3(blocks_for(n, 256)), dim3(256), 0, st, ids, n, alive, flag);
+    const dim3 g(blocks_for(m, 256));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_kill<2>), g, dim3(256), 0, st, dids, m, next_id, alive, idkey, pts, n, keep, removed, err);
+    else hipLaunchKernelGGL((k_orth_kill<3>), g, dim3(256), 0, st, dids, m, next_id, alive, idkey, pts, n, keep, removed, err);
 }
 
 void launch_orth_compact(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* flag,
@@ -768,11 +772,6 @@ void launch_orth_alive(hipStream_t st, uint32_t* alive, uint32_t lo, uint32_t hi
     if (hi <= lo) return;
     const uint64_t words = (((uint64_t)hi + 31) >> 5) - (lo >> 5);
     hipLaunchKernelGGL(k_orth_alive, dim3(blocks_for(words, 256)), dim3(256), 0, st, alive, lo, hi);
-}
-
-void launch_orth_iota(hipStream_t st, uint32_t* out, uint64_t m, uint32_t base) {
-    if (m == 0) return;
-    hipLaunchKernelGGL(k_orth_iota, dim3(blocks_for(m, 256)), dim3(256), 0, st, out, m, base);
 }
 
 void launch_orth_put64(hipStream_t st, unsigned long long* p, unsigned long long v) {

@@ -269,18 +269,18 @@ void launch_orth_merge(hipStream_t st, int dim, const uint4* pts, uint64_t n, co
                        const uint32_t* hscan, const uint64_t* bk, const uint32_t* bid, const uint32_t* place,
                        uint64_t m, uint64_t* mk, uint32_t* mi);
 // Clears the live bits of the batch's ids below next_id; *removed += bits
-// that were set.
-void launch_orth_kill(hipStream_t st, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
-                      unsigned long long* removed);
-// flag[i] = live bit of point i's id.
-void launch_orth_keep(hipStream_t st, const uint32_t* ids, uint64_t n, const uint32_t* alive, uint32_t* flag);
+// that were set; keep[position of each removed point] = 0 (keep: n words,
+// filled with 1 first; idkey: Morton key per id). A removed id not found in
+// the point array latches ERR_ORTH.
+void launch_orth_kill(hipStream_t st, int dim, const uint32_t* dids, uint64_t m, uint32_t next_id, uint32_t* alive,
+                      const uint64_t* idkey, const uint4* pts, uint64_t n, uint32_t* keep,
+                      unsigned long long* removed, uint32_t* err);
 // Flagged points' (key, id) to mk/mi[pos[i]] (pos = exclusive scan of flag).
 void launch_orth_compact(hipStream_t st, int dim, const uint4* pts, uint64_t n, const uint32_t* flag,
                          const uint32_t* pos, uint64_t* mk, uint32_t* mi);
 // Sets the live bits of ids [lo, hi) (words past the one holding lo - 1 are
 // written whole).
 void launch_orth_alive(hipStream_t st, uint32_t* alive, uint32_t lo, uint32_t hi);
-void launch_orth_iota(hipStream_t st, uint32_t* out, uint64_t m, uint32_t base);
 void launch_orth_put64(hipStream_t st, unsigned long long* p, unsigned long long v);
 
 // ----------------------------------------------------------------- export

@@ -156,7 +156,8 @@ psi_status orth_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* 
     hipStream_t st = ix->st;
     psi_status s;
     const uint64_t n = o->n, id0 = o->next_id;
-    if ((s = ix->idkey.ensure((id0 + m) * 8)) != PSI_OK) return s;
+    // the id table keeps every id's key (deletes look points up by it)
+    if ((s = ix->idkey.grow_keep((id0 + m) * 8, id0 * 8, st)) != PSI_OK) return s;
     int w = 0;
     if ((s = encode_sort(ix, d_pts, m, (uint32_t)id0, &w)) != PSI_OK) return s;
     if ((s = read2(ix, ix->err.as<uint32_t>(), 1, nullptr, 0)) != PSI_OK) return s;
@@ -183,7 +184,7 @@ psi_status orth_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* 
         launch_orth_merge(st, ix->D, o->pts.as<uint4>(), n, o->hist.as<uint32_t>(), o->hscan.as<uint32_t>(), bk, bid,
                           o->place.as<uint32_t>(), m, o->mk.as<uint64_t>(), o->mi.as<uint32_t>());
     }
-    if (d_new_ids) launch_orth_iota(st, d_new_ids, m, (uint32_t)id0);
+    if (d_new_ids) launch_iota_u32(st, d_new_ids, m, (uint32_t)id0);
     if ((s = o->alive.grow_keep((id0 + m + 31) / 32 * 4, (id0 + 31) / 32 * 4, st)) != PSI_OK) return s;
     launch_orth_alive(st, o->alive.as<uint32_t>(), (uint32_t)id0, (uint32_t)(id0 + m));
     if ((s = last_launch()) != PSI_OK) return s;
@@ -193,16 +194,21 @@ psi_status orth_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* 
     return orth_cut(o, o->mk.as<uint64_t>(), o->mi.as<uint32_t>(), n + m);
 }
 
-// Delete: clear the ids' live bits, compact the old order, cut the tree again.
+// Delete: clear the ids' live bits and the keep flags of their points,
+// compact the old order, cut the tree again.
 psi_status orth_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
     psi_index ix = o->ix;
     hipStream_t st = ix->st;
     psi_status s;
     const uint64_t n = o->n;
     if ((s = o->small.ensure(64)) != PSI_OK) return s;
+    if ((s = o->flag.ensure(std::max<uint64_t>(n, 1) * 4)) != PSI_OK) return s;
     unsigned long long* removed = reinterpret_cast<unsigned long long*>(o->small.as<uint32_t>() + 8);
     launch_orth_put64(st, removed, 0ull);
-    if (m && o->next_id) launch_orth_kill(st, d_ids, m, o->next_id, o->alive.as<uint32_t>(), removed);
+    launch_fill_u32(st, o->flag.as<uint32_t>(), n, 1u);
+    if (m && o->next_id)
+        launch_orth_kill(st, ix->D, d_ids, m, o->next_id, o->alive.as<uint32_t>(), ix->idkey.as<uint64_t>(),
+                         o->pts.as<uint4>(), n, o->flag.as<uint32_t>(), removed, ix->err.as<uint32_t>());
     if ((s = last_launch()) != PSI_OK) return s;
     if ((s = read2(ix, reinterpret_cast<const uint32_t*>(removed), 2, nullptr, 0)) != PSI_OK) return s;
     uint64_t r = 0;
@@ -212,12 +218,10 @@ psi_status orth_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* 
     if (r > n) return PSI_E_INTERNAL;
     if ((s = o->mk.ensure((n - r) * 8 + 8)) != PSI_OK) return s;
     if ((s = o->mi.ensure((n - r) * 4 + 4)) != PSI_OK) return s;
-    if ((s = o->flag.ensure(n * 4)) != PSI_OK) return s;
     if ((s = o->hscan.ensure(n * 4)) != PSI_OK) return s;
     if ((s = o->tmp.ensure(scan_tmp_words(n) * 4)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_merge", n * 36);
-        launch_orth_keep(st, o->ids.as<uint32_t>(), n, o->alive.as<uint32_t>(), o->flag.as<uint32_t>());
+        ProfScope ps(ix, "orth_merge", n * 32);
         launch_scan_u32(st, o->flag.as<uint32_t>(), o->hscan.as<uint32_t>(), n, nullptr, o->tmp.as<uint32_t>());
         launch_orth_compact(st, ix->D, o->pts.as<uint4>(), n, o->flag.as<uint32_t>(), o->hscan.as<uint32_t>(),
                             o->mk.as<uint64_t>(), o->mi.as<uint32_t>());
