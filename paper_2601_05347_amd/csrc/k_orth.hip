@@ -286,29 +286,44 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
 template <int D>
 __global__ __launch_bounds__(256) void k_orth_boxes(uint32_t level, uint64_t N, const uint8_t* __restrict__ lev,
                                                     uint4* __restrict__ box, const uint2* __restrict__ link) {
-    const uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (v >= N || lev[v] != level) return;
-    const uint64_t end = min<uint64_t>(link[v].x, N);
-    uint32_t lo[D], hi[D];
+    // sixteen nodes per thread: one 16-byte read of their levels
+    const uint64_t v0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (v0 >= N) return;
+    uint32_t match = 0;  // bit u: node v0 + u is an interior node of this level
+    if (v0 + 16 <= N) {
+        const uint4 w = *reinterpret_cast<const uint4*>(lev + v0);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        lo[d] = 0xFFFFFFFFu;
-        hi[d] = 0u;
+        for (int u = 0; u < 16; ++u) match |= (((ws[u >> 2] >> (8 * (u & 3))) & 0xFFu) == level ? 1u : 0u) << u;
+    } else {
+        for (int u = 0; v0 + u < N; ++u) match |= (lev[v0 + u] == level ? 1u : 0u) << u;
     }
-    uint64_t c = v + 1;
-    while (c < end) {  // the children: first child v + 1, then each one's end
-        const uint4 bx = box[c];
-        uint32_t a[D], z[D];
-        box_unpack<D>(bx, a, z);
+    while (match) {
+        const int u = __builtin_ctz(match);
+        match &= match - 1;
+        const uint64_t v = v0 + u;
+        const uint64_t end = min<uint64_t>(link[v].x, N);
+        uint32_t lo[D], hi[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            lo[d] = min(lo[d], a[d]);
-            hi[d] = max(hi[d], z[d]);
+            lo[d] = 0xFFFFFFFFu;
+            hi[d] = 0u;
         }
-        const uint64_t nx = box_leaf(bx) ? c + 1 : (uint64_t)link[c].x;
-        c = nx > c ? nx : c + 1;
+        uint64_t c = v + 1;
+        while (c < end) {  // the children: first child v + 1, then each one's end
+            const uint4 bx = box[c];
+            uint32_t a[D], z[D];
+            box_unpack<D>(bx, a, z);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                lo[d] = min(lo[d], a[d]);
+                hi[d] = max(hi[d], z[d]);
+            }
+            const uint64_t nx = box_leaf(bx) ? c + 1 : (uint64_t)link[c].x;
+            c = nx > c ? nx : c + 1;
+        }
+        box[v] = box_pack<D>(lo, hi, false);
     }
-    box[v] = box_pack<D>(lo, hi, false);
 }
 
 template <int D>
@@ -689,7 +704,7 @@ void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint6
 void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,
                        const uint2* link) {
     if (N == 0) return;
-    const dim3 g(blocks_for(N, 256));
+    const dim3 g(blocks_for((N + 15) / 16, 256));
     if (dim == 2) hipLaunchKernelGGL((k_orth_boxes<2>), g, dim3(256), 0, st, level, N, lev, box, link);
     else hipLaunchKernelGGL((k_orth_boxes<3>), g, dim3(256), 0, st, level, N, lev, box, link);
 }
