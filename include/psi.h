@@ -277,7 +277,7 @@ psi_status psi_orth_batch_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, 
 /* Live points and the next id an insert hands out. */
 psi_status psi_orth_size(psi_orth o, uint64_t* h_n_live, uint32_t* h_next_id);
 
-/* Exact k nearest neighbours (k = 1..16), output as psi_knn. */
+/* Exact k nearest neighbours (k = 1..128), output as psi_knn. */
 psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids,
                         uint64_t* d_d2);
 /* Points inside closed boxes (nb x [lo[dim], hi[dim]]), as psi_range_count

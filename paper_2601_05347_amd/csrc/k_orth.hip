@@ -422,6 +422,181 @@ __global__ __launch_bounds__(256) void k_orth_knn(OrthView t, const uint32_t* __
     }
 }
 
+// ----------------------------------------------------- kNN, wave per query
+// For k > 16: the k best pairs of a query live in LDS, ascending, in two
+// copies (the merge writes the other one). A batch of up to 64 points (one per
+// lane) is merged in: the points that beat the current k-th pair are ranked
+// among themselves, each list entry and each candidate finds its new place by
+// binary search in the other sequence.
+constexpr int OKW_WAVES = 4;
+
+template <int KMAX>
+struct OrthKList {
+    uint64_t (*d)[KMAX];  // [2][KMAX]
+    uint32_t (*i)[KMAX];
+    uint64_t* cd;         // [64] candidates
+    uint32_t* ci;
+};
+
+template <int D, int KMAX>
+__device__ __forceinline__ void orth_merge64(const OrthKList<KMAX>& L, int& cur, uint32_t k, bool valid, uint4 P,
+                                             const uint32_t* q) {
+    const uint32_t lane = lane_id();
+    uint64_t dd = PAD_D2;
+    uint32_t id = PAD_ID;
+    bool cand = false;
+    if (valid) {
+        const uint32_t p[3] = {P.x, P.y, P.z};
+        dd = pt_dist<D>(q, p);
+        id = P.w;
+        cand = pair_less(dd, id, L.d[cur][k - 1], L.i[cur][k - 1]);
+    }
+    const uint64_t cm = ballot(cand);
+    if (cm == 0) return;
+    const uint32_t nc = (uint32_t)__popcll(cm);
+    if (cand) {
+        const uint32_t slot = count_below(cm);
+        L.cd[slot] = dd;
+        L.ci[slot] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t cpos = 0, rank = 0;
+    if (cand) {
+        for (uint32_t x = 0; x < nc; ++x) rank += pair_less(L.cd[x], L.ci[x], dd, id) ? 1u : 0u;
+        uint32_t lo = 0, hi = k;  // list entries below the candidate
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pair_less(L.d[cur][mid], L.i[cur][mid], dd, id)) lo = mid + 1;
+            else hi = mid;
+        }
+        cpos = rank + lo;
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane has read the unsorted candidates
+    if (cand) {
+        L.cd[rank] = dd;
+        L.ci[rank] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int nxt = cur ^ 1;
+    for (uint32_t x = lane; x < k; x += 64) {
+        const uint64_t ld = L.d[cur][x];
+        const uint32_t li = L.i[cur][x];
+        uint32_t lo = 0, hi = nc;  // candidates below list entry x
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pair_less(L.cd[mid], L.ci[mid], ld, li)) lo = mid + 1;
+            else hi = mid;
+        }
+        if (x + lo < k) {
+            L.d[nxt][x + lo] = ld;
+            L.i[nxt][x + lo] = li;
+        }
+    }
+    if (cand && cpos < k) {
+        L.d[nxt][cpos] = dd;
+        L.i[nxt][cpos] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    cur = nxt;
+}
+
+// The walk takes 64 preorder nodes per step, as the range kernel does: a
+// node is skipped when an earlier pruned interior node's subtree covers it;
+// the leaves left within the k-th distance are scanned in order, 64 points
+// at a time, each rechecked against the k-th distance of the moment.
+template <int D, int KMAX>
+__global__ __launch_bounds__(256) void k_orth_knn_wave(OrthView t, const uint32_t* __restrict__ qp,
+                                                       const uint64_t* __restrict__ qkeys, uint64_t nq,
+                                                       const uint32_t* __restrict__ order, uint32_t k,
+                                                       uint32_t* __restrict__ out_ids,
+                                                       uint64_t* __restrict__ out_d2) {
+    __shared__ uint64_t s_d[OKW_WAVES][2][KMAX];
+    __shared__ uint32_t s_i[OKW_WAVES][2][KMAX];
+    __shared__ uint64_t s_cd[OKW_WAVES][64];
+    __shared__ uint32_t s_ci[OKW_WAVES][64];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = lane_id();
+    const uint64_t tq = (uint64_t)blockIdx.x * OKW_WAVES + w;
+    if (tq >= nq) return;
+    const uint64_t qi = order ? order[tq] : tq;
+    uint32_t q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+    for (uint32_t x = lane; x < KMAX; x += 64) {
+        s_d[w][0][x] = PAD_D2;
+        s_i[w][0][x] = PAD_ID;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const OrthKList<KMAX> Lst{s_d[w], s_i[w], s_cd[w], s_ci[w]};
+    int cur = 0;
+    if (t.N > 0 && t.L > 0) {
+        const uint64_t key = qkeys[qi];
+        uint32_t lo = 0, hi = t.L;
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if (t.fkey[mid] <= key) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t j = lo ? lo - 1 : 0u;
+        const uint32_t want = max(ORTH_SEED, 2 * k);
+        uint32_t ja = j, jb = j;
+        uint32_t p0 = t.lstart[j], p1 = j + 1 < t.L ? t.lstart[j + 1] : t.n;
+        while (p1 - p0 < want && (ja > 0 || jb + 1 < t.L)) {
+            if (ja > 0) p0 = t.lstart[--ja];
+            if (jb + 1 < t.L) {
+                ++jb;
+                p1 = jb + 1 < t.L ? t.lstart[jb + 1] : t.n;
+            }
+        }
+        for (uint32_t e0 = p0; e0 < p1; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            const bool ok = e < p1;
+            orth_merge64<D, KMAX>(Lst, cur, k, ok, ok ? t.pts[e] : make_uint4(0u, 0u, 0u, 0u), q);
+        }
+        uint64_t v = 0;
+        while (v < t.N) {
+            const uint64_t kth = s_d[w][cur][k - 1];
+            const uint64_t i = v + lane;
+            const bool valid = i < t.N;
+            const uint4 bx = valid ? t.box[i] : make_uint4(0u, 0u, 0u, 0u);
+            const bool leaf = box_leaf(bx);
+            const uint64_t bd = valid ? box_dist2<D>(q, bx) : PAD_D2;
+            const bool pruned = valid && bd > kth;
+            const uint32_t jend = (pruned && !leaf) ? t.link[i].x : 0u;
+            uint32_t incl = jend;  // inclusive prefix maximum of pruned subtree ends
+#pragma unroll
+            for (int sft = 1; sft < 64; sft <<= 1) {
+                const uint32_t y = shfl_u32(incl, (int)lane - sft);
+                if (lane >= (uint32_t)sft) incl = max(incl, y);
+            }
+            uint32_t excl = shfl_u32(incl, (int)lane - 1);
+            if (lane == 0) excl = 0;
+            const bool on = valid && (uint64_t)excl <= i;
+            const uint32_t far = __builtin_amdgcn_readlane((int)incl, 63);
+            uint64_t m = ballot(on && leaf && !pruned);
+            while (m) {
+                const uint32_t x = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                const uint64_t dx = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(bd >> 32), (int)x) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bd, (int)x);
+                if (dx > s_d[w][cur][k - 1]) continue;
+                const uint2 lk = t.link[v + x];
+                if (lk.x >= p0 && lk.x < p1) continue;  // a seed leaf
+                for (uint32_t e0 = lk.x; e0 < lk.x + lk.y; e0 += 64) {
+                    const uint32_t e = e0 + lane;
+                    const bool ok = e < lk.x + lk.y;
+                    orth_merge64<D, KMAX>(Lst, cur, k, ok, ok ? t.pts[e] : make_uint4(0u, 0u, 0u, 0u), q);
+                }
+            }
+            v = max<uint64_t>(v + 64, (uint64_t)far);
+        }
+    }
+    for (uint32_t x = lane; x < k; x += 64) {
+        out_ids[qi * k + x] = s_i[w][cur][x];
+        out_d2[qi * k + x] = s_d[w][cur][x];
+    }
+}
+
 // Wave per box. The wave takes the preorder nodes 64 at a time from the
 // current position v (one node per lane, coalesced). A node is on the walk
 // unless an earlier node of the window is an interior node whose subtree is
@@ -728,7 +903,13 @@ void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t*
         case 7: PSI_OK_(D, 7); break;   case 8: PSI_OK_(D, 8); break;   case 9: PSI_OK_(D, 9); break;    \
         case 10: PSI_OK_(D, 10); break; case 11: PSI_OK_(D, 11); break; case 12: PSI_OK_(D, 12); break;  \
         case 13: PSI_OK_(D, 13); break; case 14: PSI_OK_(D, 14); break; case 15: PSI_OK_(D, 15); break;  \
-        case 16: PSI_OK_(D, 16); break; default: break;                                                  \
+        case 16: PSI_OK_(D, 16); break;                                                                  \
+        default: {                                                                                       \
+            const dim3 gw(blocks_for(nq, OKW_WAVES));                                                    \
+            if (k <= 32) hipLaunchKernelGGL((k_orth_knn_wave<D, 32>), gw, dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+            else if (k <= 64) hipLaunchKernelGGL((k_orth_knn_wave<D, 64>), gw, dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+            else hipLaunchKernelGGL((k_orth_knn_wave<D, 128>), gw, dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+        }                                                                                                \
     }
     if (dim == 2) { PSI_OK_ALL(2) } else { PSI_OK_ALL(3) }
 #undef PSI_OK_ALL

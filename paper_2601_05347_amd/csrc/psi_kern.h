@@ -250,7 +250,8 @@ void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, cons
 // Nodes as 8 words each: lo[3], hi[3], then link.x and link.y | 0x80000000
 // for a leaf.
 void launch_orth_export(hipStream_t st, int dim, const uint4* box, const uint2* link, uint64_t N, uint32_t* out);
-// Queries over a P-Orth tree (k <= 16; order and qkeys as for launch_knn).
+// Queries over a P-Orth tree (k <= 128: a lane per query up to 16, else a
+// wave; order and qkeys as for launch_knn).
 void launch_orth_knn(hipStream_t st, int dim, const OrthView& t, const uint32_t* q, const uint64_t* qkeys,
                      uint64_t nq, const uint32_t* order, uint32_t k, uint32_t* ids, uint64_t* d2);
 // counts (ids null) or reports into ids[offsets[b] .. offsets[b + 1]).

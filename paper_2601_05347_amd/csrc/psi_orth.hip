@@ -305,7 +305,7 @@ psi_status psi_orth_size(psi_orth o, uint64_t* h_n_live, uint32_t* h_next_id) {
 }
 
 psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids, uint64_t* d_d2) {
-    if (!o || k == 0 || k > 16 || (nq && (!d_q || !d_ids || !d_d2))) return PSI_E_ARG;
+    if (!o || k == 0 || k > 128 || (nq && (!d_q || !d_ids || !d_d2))) return PSI_E_ARG;
     if (nq == 0) return PSI_OK;
     psi_index ix = o->ix;
     const uint32_t* order = nullptr;

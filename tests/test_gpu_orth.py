@@ -153,6 +153,23 @@ def test_structure_and_queries_skewed(psi, dist, dim, bits, phi):
     check_queries(psi, o, pts, dim, phi, q, bx, ks=(1, 16))
 
 
+@pytest.mark.parametrize("dist,dim,bits,n", [("uniform", 3, 21, 100_003), ("uniform", 2, 31, 5000),
+                                             ("uniform", 3, 4, 20_000), ("varden", 2, 31, 20_000),
+                                             ("uniform", 3, 21, 33)])
+def test_knn_large_k(psi, dist, dim, bits, n):
+    """k > 16 takes a wave per query (k up to 128, more than the points: padding)."""
+    say(f"orth large k {dist} dim={dim} bits={bits} n={n}")
+    pts = synth.points(dist, n, dim, bits, 71)
+    o = psi.Orth(dim, 32).build(pts)
+    q = queries(dim, 300, 72, pts, bits)
+    for k in (17, 32, 33, 64, 100, 128):
+        ids, d2 = o.knn(q, k)
+        o.sync()
+        eid, ed2 = oracle.knn_points(pts, q, k)
+        np.testing.assert_array_equal(psi.to_u64(d2), ed2, err_msg=f"k={k}")
+        np.testing.assert_array_equal(psi.to_u32(ids), eid, err_msg=f"k={k}")
+
+
 def test_many_queries_take_the_sorted_order(psi):
     say("orth 3D 200k, 6000 queries")
     pts = synth.uniform(200_000, 3, 21, 31)
@@ -182,8 +199,9 @@ def test_empty_tree_and_rebuild(psi):
     o = psi.Orth(3, 32).build(np.zeros((0, 3), np.uint32))
     assert o.shape() == (0, 0, 0)
     q = synth.uniform(50, 3, 21, 3)
-    ids, d2 = o.knn(q, 4)
-    assert (psi.to_u32(ids) == psi.PAD_ID).all() and (psi.to_u64(d2) == psi.PAD_D2).all()
+    for k in (4, 40):
+        ids, d2 = o.knn(q, k)
+        assert (psi.to_u32(ids) == psi.PAD_ID).all() and (psi.to_u64(d2) == psi.PAD_D2).all()
     bx = synth.boxes(q, 21, 1)
     assert (psi.to_u64(o.range_count(bx)) == 0).all()
     pts = synth.uniform(3000, 3, 21, 4)
@@ -204,7 +222,7 @@ def test_out_of_range_points_and_bad_arguments(psi):
     assert o.shape() == (0, 0, 0)
     o.sync()  # the error was cleared by the failed build
     with pytest.raises(psi.PsiError) as e:
-        o.knn(pts[:5] & np.uint32(0xFFFF), 17)
+        o.knn(pts[:5] & np.uint32(0xFFFF), 129)
     assert e.value.code == 1
     with pytest.raises(psi.PsiError) as e:
         psi.psi_orth_create(3, 32, psi.FLAG_KNN_NEAREST_FIRST)
