@@ -261,7 +261,9 @@ psi_status psi_orth_destroy(psi_orth o);
 /* Builds the tree over n points (device, n x dim u32, row major; ids are
  * positions 0..n-1), replacing the previous tree. n < 2^31. Waits for the
  * stream twice (leaf and node counts). PSI_E_RANGE (and an empty tree) if a
- * coordinate is out of range. Not under graph capture (PSI_E_STATE). */
+ * coordinate is out of range. Not under graph capture (PSI_E_STATE).
+ * Builds, inserts and deletes first return (and clear) an error latched by
+ * an earlier call, as psi_orth_sync would, leaving the tree unchanged. */
 psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n);
 
 /* Inserts m points (device, m x dim u32); they get ids next_id ..

@@ -265,7 +265,11 @@ psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     if (!o || (n && !d_pts)) return PSI_E_ARG;
     if (n >= (1ull << 31)) return PSI_E_CAPACITY;
     if (capturing(o->ix->st)) return PSI_E_STATE;
-    psi_status s = orth_build(o, d_pts, n);
+    // an error latched by an earlier call (a query's out-of-range point) is
+    // reported here, not taken for this build's
+    psi_status s = psi_sync(o->ix);
+    if (s != PSI_OK) return s;
+    s = orth_build(o, d_pts, n);
     if (s != PSI_OK) {
         o->n = o->N = o->L = 0;
         o->height = 0;
@@ -278,7 +282,9 @@ psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, 
     if (capturing(o->ix->st)) return PSI_E_STATE;
     if ((uint64_t)o->next_id + m > 0xFFFFFFFFull || o->n + m >= (1ull << 31)) return PSI_E_CAPACITY;
     if (m == 0) return PSI_OK;
-    psi_status s = orth_insert(o, d_pts, m, d_new_ids);
+    psi_status s = psi_sync(o->ix);
+    if (s != PSI_OK) return s;
+    s = orth_insert(o, d_pts, m, d_new_ids);
     if (s != PSI_OK && s != PSI_E_RANGE) {
         o->n = o->N = o->L = 0;
         o->height = 0;
@@ -289,7 +295,9 @@ psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, 
 psi_status psi_orth_batch_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
     if (!o || (m && !d_ids)) return PSI_E_ARG;
     if (capturing(o->ix->st)) return PSI_E_STATE;
-    psi_status s = orth_delete(o, d_ids, m, d_ndeleted);
+    psi_status s = psi_sync(o->ix);
+    if (s != PSI_OK) return s;
+    s = orth_delete(o, d_ids, m, d_ndeleted);
     if (s != PSI_OK) {
         o->n = o->N = o->L = 0;
         o->height = 0;

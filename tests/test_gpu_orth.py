@@ -230,6 +230,15 @@ def test_out_of_range_points_and_bad_arguments(psi):
     ok = pts & np.uint32((1 << 21) - 1)
     o.build(ok)
     check_structure(o, ok, 3, 32)
+    # a query's out-of-range point is reported by the next build, which then
+    # leaves the tree unchanged; the build after it goes through
+    o.knn(pts[10:20], 4)
+    with pytest.raises(psi.PsiError) as e:
+        o.build(ok[:100])
+    assert e.value.code == 2
+    check_structure(o, ok, 3, 32)
+    o.build(ok[:100])
+    check_structure(o, ok[:100], 3, 32)
 
 
 @pytest.mark.parametrize("dim,phi", [(2, 8), (3, 32), (3, 2)])
