@@ -607,8 +607,50 @@ __global__ __launch_bounds__(256) void k_orth_knn_wave(OrthView t, const uint32_
 // walk: nodes inside the box add their counts (reports copy their ids, whole
 // subtrees being contiguous in the point array, one node at a time by the
 // whole wave); leaves straddling the box are scanned two at a time, one per
-// half-wave.
+// half-wave. The walk starts at the deepest node whose cell holds the whole
+// box (the cell of the levels the Morton keys of the two corners share): every
+// point in the box is below it.
 constexpr int ORW_WAVES = 4;
+
+// Preorder range [v0, v1) of the node whose cell is the level-ls cell holding
+// key kl, or an empty range if that cell holds no point. A leaf whose cell
+// contains it stands for it.
+template <int D>
+__device__ __forceinline__ void orth_cell_node(const OrthView& t, uint64_t kl, uint32_t ls, uint64_t& v0,
+                                               uint64_t& v1) {
+    v0 = v1 = 0;
+    const uint32_t sh = OrthBits<D>::KB - ls * D;
+    const uint64_t cell = kl >> sh, cstart = cell << sh;
+    uint32_t lo = 0, hi = t.L;  // first leaf whose first key is >= the cell's start
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (t.fkey[mid] < cstart) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t t1 = lo;
+    if (t1 > 0) {  // the leaf before it may hold the whole cell
+        const uint32_t tp = t1 - 1, lvp = t.llev[tp], shp = OrthBits<D>::KB - lvp * D;
+        if (lvp <= ls && (t.fkey[tp] >> shp) == (cstart >> shp)) {
+            const uint32_t s = open_from<D>(t.fkey, tp);
+            v0 = (uint64_t)t.base[tp] + (s <= lvp ? lvp - s : 0u);
+            v1 = v0 + 1;
+            return;
+        }
+    }
+    if (t1 < t.L && (t.fkey[t1] >> sh) == cell) {
+        const uint32_t lv = t.llev[t1], s = open_from<D>(t.fkey, t1);
+        if (lv <= ls) {  // leaf t1 holds the cell
+            v0 = (uint64_t)t.base[t1] + (s <= lv ? lv - s : 0u);
+            v1 = v0 + 1;
+        } else if (s <= ls) {  // the interior node of level ls opened at t1
+            v0 = (uint64_t)t.base[t1] + (ls - s);
+            v1 = t.link[v0].x;
+        } else {  // not reached for a consistent tree: walk everything
+            v0 = 0;
+            v1 = t.N;
+        }
+    }
+}
 
 template <int D, bool REPORT>
 __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* __restrict__ boxes, uint64_t nb,
@@ -632,10 +674,23 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
         o = offsets[b];
         lim = offsets[b + 1];
     }
-    uint64_t v = empty ? t.N : 0;
-    while (v < t.N) {
+    // corners clamped to the coordinate domain (no point lies outside it)
+    uint32_t clo[3] = {0u, 0u, 0u}, chi[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        constexpr uint32_t top = (1u << OrthBits<D>::W) - 1u;
+        empty = empty || lo[d] > top;
+        clo[d] = lo[d];
+        chi[d] = min(hi[d], top);
+    }
+    uint64_t v = 0, vend = 0;
+    if (!empty && t.N > 0) {
+        const uint64_t kl = morton_key<D>(clo), kh = morton_key<D>(chi);
+        orth_cell_node<D>(t, kl, common_levels<D>(kl, kh), v, vend);
+    }
+    while (v < vend) {
         const uint64_t i = v + lane;
-        const bool valid = i < t.N;
+        const bool valid = i < vend;
         uint4 nb4 = make_uint4(0u, 0u, 0u, 0u);
         uint2 lk = make_uint2(0u, 0u);
         if (valid) {

@@ -220,6 +220,8 @@ struct OrthView {
     const uint32_t* ids;       // the same ids, alone
     const uint32_t* lstart;    // first point of each leaf, in leaf order
     const uint64_t* fkey;      // Morton key of each leaf's first point
+    const uint8_t* llev;       // level of each leaf
+    const uint32_t* base;      // preorder index of the first node each leaf opens
     uint64_t N;                // nodes
     uint32_t L;                // leaves
     uint32_t n;                // points

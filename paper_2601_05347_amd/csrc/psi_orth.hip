@@ -25,6 +25,8 @@ struct psi_orth_s {
         v.ids = ids.as<uint32_t>();
         v.lstart = lstart.as<uint32_t>();
         v.fkey = fkey.as<uint64_t>();
+        v.llev = llev.as<uint8_t>();
+        v.base = base.as<uint32_t>();
         v.N = N;
         v.L = (uint32_t)L;
         v.n = (uint32_t)n;

@@ -170,6 +170,52 @@ def test_knn_large_k(psi, dist, dim, bits, n):
         np.testing.assert_array_equal(psi.to_u32(ids), eid, err_msg=f"k={k}")
 
 
+@pytest.mark.parametrize("dist,dim,bits", [("uniform", 3, 21), ("uniform", 2, 31), ("uniform", 3, 5),
+                                           ("varden", 3, 21)])
+def test_range_boxes_of_every_size_and_edge(psi, dist, dim, bits):
+    """Boxes from one grid point to the whole domain, boxes that are exactly
+    one cell of some level, boxes past the domain's edge (clamped when the walk
+    looks for the cell holding the box), empty boxes."""
+    say(f"orth range edges {dist} dim={dim} bits={bits}")
+    W = bits_of(dim)
+    pts = synth.points(dist, 30_000, dim, bits, 81)
+    o = psi.Orth(dim, 8).build(pts)
+    q = queries(dim, 400, 82, pts, bits)
+    r = synth.draws(synth.stream_key(83, synth.P_AUX), 0, 4 * len(q))
+    boxes = []
+    for j, c in enumerate(q[:200]):  # cells of random levels around points
+        lev = int(r[j] % np.uint64(W + 1))
+        side = 1 << (W - lev)
+        lo = (c.astype(np.int64) // side) * side
+        boxes.append(np.stack([lo, lo + side - 1]))
+    for j, c in enumerate(q[200:300]):  # small boxes, sides 1 .. 64
+        sd = 1 + (r[200 + j] % np.uint64(64)).astype(np.int64)
+        lo = np.maximum(c.astype(np.int64) - sd // 2, 0)
+        boxes.append(np.stack([lo, lo + sd - 1]))
+    for j, c in enumerate(q[300:340]):  # past the domain's upper edge
+        lo = c.astype(np.int64)
+        boxes.append(np.stack([lo, np.full(dim, 0xFFFFFFFF, np.int64)]))
+    full = np.stack([np.zeros(dim, np.int64), np.full(dim, 0xFFFFFFFF, np.int64)])
+    beyond = np.stack([np.full(dim, 1 << W, np.int64), np.full(dim, 0xFFFFFFFF, np.int64)])
+    emptyb = np.stack([np.full(dim, 9, np.int64), np.full(dim, 3, np.int64)])
+    one = np.stack([pts[5].astype(np.int64), pts[5].astype(np.int64)])
+    boxes += [full, beyond, emptyb, one]
+    bx = np.asarray(boxes, dtype=np.int64).astype(np.uint32)
+    cnt = psi.to_u64(o.range_count(bx))
+    o.sync()
+    p = pts.astype(np.int64)
+    want = np.array([((p >= b[0].astype(np.int64)) & (p <= b[1].astype(np.int64))).all(axis=1).sum()
+                     for b in bx], dtype=np.uint64)
+    np.testing.assert_array_equal(cnt, want)
+    off, rid = o.range_report(bx)
+    o.sync()
+    off = psi.to_u64(off).astype(np.int64)
+    got = segment_sort(psi.to_u32(rid), off[:-1], np.diff(off))
+    exp = np.concatenate([np.nonzero(((p >= b[0].astype(np.int64)) & (p <= b[1].astype(np.int64))).all(axis=1))[0]
+                          for b in bx]).astype(np.uint32)
+    np.testing.assert_array_equal(got, exp)
+
+
 def test_many_queries_take_the_sorted_order(psi):
     say("orth 3D 200k, 6000 queries")
     pts = synth.uniform(200_000, 3, 21, 31)
