@@ -606,8 +606,8 @@ __global__ __launch_bounds__(256) void k_orth_knn_wave(OrthView t, const uint32_
 // The next window starts at v + 64 or past the farthest such subtree. On the
 // walk: nodes inside the box add their counts (reports copy their ids, whole
 // subtrees being contiguous in the point array, one node at a time by the
-// whole wave); leaves straddling the box are scanned two at a time, one per
-// half-wave. The walk starts at the deepest node whose cell holds the whole
+// whole wave); the points of the window's leaves that straddle the box are
+// scanned one per lane, concatenated across leaves. The walk starts at the deepest node whose cell holds the whole
 // box (the cell of the levels the Morton keys of the two corners share): every
 // point in the box is below it.
 constexpr int ORW_WAVES = 4;
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
                                                     const uint32_t* __restrict__ order, uint64_t* __restrict__ counts,
                                                     const uint64_t* __restrict__ offsets, uint32_t* __restrict__ out) {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t lane = lane_id(), hl = lane & 31u;
+    const uint32_t lane = lane_id();
     const uint64_t bx = (uint64_t)blockIdx.x * ORW_WAVES + w;
     if (bx >= nb) return;
     const uint64_t b = order ? order[bx] : bx;
@@ -735,41 +735,47 @@ __global__ __launch_bounds__(256) void k_orth_range(OrthView t, const uint32_t* 
                 o += c;
             }
         }
-        // leaves straddling the box, two at a time (one per half-wave)
-        uint64_t m = ballot(on && leaf && !inside && !apart);
-        while (m) {
-            const uint32_t xa = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1;
-            uint32_t xb = 64u;  // no second leaf
-            if (m) {
-                xb = (uint32_t)__builtin_ctzll(m);
-                m &= m - 1;
-            }
-            const uint32_t mine = lane < 32u ? xa : xb;
-            const uint32_t sp = shfl_u32(lk.x, (int)(mine & 63u)), sc = shfl_u32(lk.y, (int)(mine & 63u));
-            const uint32_t rc = mine < 64u ? sc : 0u;
-            const uint32_t rmax = max((uint32_t)__builtin_amdgcn_readlane((int)rc, 0),
-                                      (uint32_t)__builtin_amdgcn_readlane((int)rc, 32));
-            for (uint32_t e0 = 0; e0 < rmax; e0 += 32) {
-                const uint32_t e = e0 + hl;
-                bool in = false;
-                uint32_t id = 0;
-                if (e < rc) {
-                    const uint4 P = t.pts[sp + e];
-                    const uint32_t p[3] = {P.x, P.y, P.z};
-                    in = true;
+        // leaves straddling the box: their points, concatenated in lane
+        // order, one point per lane per step
+        const bool strad = on && leaf && !inside && !apart;
+        const uint32_t lc = strad ? lk.y : 0u;
+        uint32_t run = lc;  // inclusive scan of the counts over the lanes
 #pragma unroll
-                    for (int d = 0; d < D; ++d) in = in && lo[d] <= p[d] && p[d] <= hi[d];
-                    id = P.w;
+        for (int sft = 1; sft < 64; sft <<= 1) {
+            const uint32_t y = shfl_u32(run, (int)lane - sft);
+            if (lane >= (uint32_t)sft) run += y;
+        }
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)run, 63);
+        for (uint32_t e0 = 0; e0 < tot; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            uint32_t a = 0, z = 63;  // the first lane whose run end passes e
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const uint32_t mid = (a + z) >> 1;
+                const uint32_t ev = shfl_u32(run, (int)mid);
+                if (a < z) {
+                    if (ev > e) z = mid;
+                    else a = mid + 1;
                 }
-                const uint64_t hit = ballot(in);
-                if (REPORT && in) {
-                    const uint64_t dst = o + count_below(hit);
-                    if (dst < lim) out[dst] = id;
-                }
-                if (REPORT) o += (uint32_t)__popcll(hit);
-                else cnt += (uint32_t)__popcll(hit);
             }
+            const uint32_t src = shfl_u32(lk.x, (int)a), p0 = shfl_u32(run - lc, (int)a);
+            bool in = false;
+            uint32_t id = 0;
+            if (e < tot) {
+                const uint4 P = t.pts[src + (e - p0)];
+                const uint32_t p[3] = {P.x, P.y, P.z};
+                in = true;
+#pragma unroll
+                for (int d = 0; d < D; ++d) in = in && lo[d] <= p[d] && p[d] <= hi[d];
+                id = P.w;
+            }
+            const uint64_t hit = ballot(in);
+            if (REPORT && in) {
+                const uint64_t dst = o + count_below(hit);
+                if (dst < lim) out[dst] = id;
+            }
+            if (REPORT) o += (uint32_t)__popcll(hit);
+            else cnt += (uint32_t)__popcll(hit);
         }
         v = max<uint64_t>(v + 64, (uint64_t)far);
     }
