@@ -168,29 +168,89 @@ __global__ __launch_bounds__(256) void k_orth_mark(const uint64_t* __restrict__ 
     }
 }
 
+// Second pass over a tile: the leaves' first positions, levels and keys,
+// then their boxes. The tile's points, with OM_HALO positions beyond it, are
+// decoded from the keys into LDS (three words per position: no bank
+// conflicts); a thread per leaf reduces its run of points there. Only the
+// tile's last leaf can end past the tile; if it is a leaf of equal points
+// running past the staged positions, its thread reads on from global memory.
+template <int D>
 __global__ __launch_bounds__(256) void k_orth_leaves(const uint64_t* __restrict__ sk, uint64_t n,
                                                      const uint8_t* __restrict__ mark,
                                                      const uint32_t* __restrict__ tile_off,
                                                      uint32_t* __restrict__ lstart, uint8_t* __restrict__ llev,
-                                                     uint64_t* __restrict__ fkey) {
+                                                     uint64_t* __restrict__ fkey, uint4* __restrict__ lbox) {
+    constexpr uint32_t SPAN = ORTH_TILE + OM_HALO;
+    __shared__ uint32_t s_p[SPAN * 3];
+    __shared__ uint16_t s_st[ORTH_TILE];  // tile position of the tile's k-th leaf start
     __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_nl;
     const uint64_t base = (uint64_t)blockIdx.x * ORTH_TILE;
+    for (uint32_t x = threadIdx.x; x < SPAN; x += 256) {
+        const uint64_t g = base + x;
+        uint32_t p[3] = {0u, 0u, 0u};
+        if (g < n) morton_point<D>(sk[g], p);
+        s_p[3 * x] = p[0];
+        s_p[3 * x + 1] = p[1];
+        s_p[3 * x + 2] = p[2];
+    }
     const uint32_t y0 = threadIdx.x * OM_PER;
     const uint2 mm = *reinterpret_cast<const uint2*>(mark + base + y0);
     const uint64_t word = ((uint64_t)mm.y << 32) | mm.x;
     const uint32_t c = (uint32_t)__popcll(word & 0x8080808080808080ull);
     const uint32_t incl = block_incl_scan256(c, s_w);
-    uint32_t leaf = tile_off[blockIdx.x] + incl - c;
+    if (threadIdx.x == 255) s_nl = incl;
+    const uint32_t t0 = tile_off[blockIdx.x];
+    uint32_t k = incl - c;
 #pragma unroll
     for (uint32_t u = 0; u < OM_PER; ++u) {
         const uint32_t b = (uint32_t)(word >> (8 * u)) & 0xFFu;
         if (b & 0x80u) {
             const uint64_t i = base + y0 + u;
-            lstart[leaf] = (uint32_t)i;
-            llev[leaf] = (uint8_t)(b & 0x7Fu);
-            fkey[leaf] = sk[i];
-            ++leaf;
+            lstart[t0 + k] = (uint32_t)i;
+            llev[t0 + k] = (uint8_t)(b & 0x7Fu);
+            fkey[t0 + k] = sk[i];
+            s_st[k] = (uint16_t)(y0 + u);
+            ++k;
         }
+    }
+    __syncthreads();
+    const uint32_t nl = s_nl;
+    const uint64_t tile_end = min<uint64_t>(ORTH_TILE, n - base);
+    for (uint32_t j = threadIdx.x; j < nl; j += 256) {
+        const uint32_t y = s_st[j];
+        uint32_t lo[D], hi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) lo[d] = hi[d] = s_p[3 * y + d];
+        if (j + 1 < nl) {
+            const uint32_t ye = s_st[j + 1];
+            for (uint32_t x = y + 1; x < ye; ++x) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    lo[d] = min(lo[d], s_p[3 * x + d]);
+                    hi[d] = max(hi[d], s_p[3 * x + d]);
+                }
+            }
+        } else {  // the tile's last leaf: up to the next start, which may lie past the tile
+            uint64_t g = base + y + 1;
+            for (; g < n && (g < base + tile_end || !(mark[g] & 0x80u)); ++g) {
+                const uint64_t x = g - base;
+                uint32_t p[3];
+                if (x < SPAN) {
+                    p[0] = s_p[3 * x];
+                    p[1] = s_p[3 * x + 1];
+                    p[2] = s_p[3 * x + 2];
+                } else {
+                    morton_point<D>(sk[g], p);
+                }
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    lo[d] = min(lo[d], p[d]);
+                    hi[d] = max(hi[d], p[d]);
+                }
+            }
+        }
+        lbox[t0 + j] = box_pack<D>(lo, hi, true);
     }
 }
 
@@ -226,7 +286,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ llev, const uint64_t* __restrict__ fkey,
                                                     const uint32_t* __restrict__ lstart,
                                                     const uint32_t* __restrict__ base, uint32_t L, uint32_t n,
-                                                    uint64_t N, const uint4* __restrict__ pts,
+                                                    uint64_t N, const uint4* __restrict__ lbox,
                                                     uint4* __restrict__ box, uint2* __restrict__ link,
                                                     uint32_t* __restrict__ first, uint8_t* __restrict__ lev) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
@@ -261,23 +321,8 @@ __global__ __launch_bounds__(256) void k_orth_nodes(const uint8_t* __restrict__ 
         first[v] = pb;
         lev[v] = (uint8_t)l;
     }
-    uint32_t lo[D], hi[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        lo[d] = 0xFFFFFFFFu;
-        hi[d] = 0u;
-    }
-    for (uint32_t x = pb; x < pe; ++x) {
-        const uint4 P = pts[x];
-        const uint32_t p[3] = {P.x, P.y, P.z};
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            lo[d] = min(lo[d], p[d]);
-            hi[d] = max(hi[d], p[d]);
-        }
-    }
     const uint64_t v = b + (s <= lv ? lv - s : 0u);
-    box[v] = box_pack<D>(lo, hi, true);
+    box[v] = lbox[t];
     link[v] = make_uint2(pb, pe - pb);
     first[v] = pb;
     lev[v] = 0xFF;
@@ -913,11 +958,12 @@ void launch_orth_mark(hipStream_t st, int dim, const uint64_t* sk, const uint32_
     else hipLaunchKernelGGL((k_orth_mark<3>), g, dim3(256), 0, st, sk, sid, n, phi, mark, tile_cnt, pts, ids);
 }
 
-void launch_orth_leaves(hipStream_t st, const uint64_t* sk, uint64_t n, const uint8_t* mark,
-                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey) {
+void launch_orth_leaves(hipStream_t st, int dim, const uint64_t* sk, uint64_t n, const uint8_t* mark,
+                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey, uint4* lbox) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_orth_leaves, dim3(blocks_for(n, ORTH_TILE)), dim3(256), 0, st, sk, n, mark, tile_off, lstart,
-                       llev, fkey);
+    const dim3 g(blocks_for(n, ORTH_TILE));
+    if (dim == 2) hipLaunchKernelGGL((k_orth_leaves<2>), g, dim3(256), 0, st, sk, n, mark, tile_off, lstart, llev, fkey, lbox);
+    else hipLaunchKernelGGL((k_orth_leaves<3>), g, dim3(256), 0, st, sk, n, mark, tile_off, lstart, llev, fkey, lbox);
 }
 
 void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
@@ -929,12 +975,12 @@ void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint
 }
 
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
-                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
+                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* lbox, uint4* box,
                        uint2* link, uint32_t* first, uint8_t* lev) {
     if (L == 0) return;
     const dim3 g(blocks_for(L, 256));
-    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, first, lev);
-    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, pts, box, link, first, lev);
+    if (dim == 2) hipLaunchKernelGGL((k_orth_nodes<2>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, lbox, box, link, first, lev);
+    else hipLaunchKernelGGL((k_orth_nodes<3>), g, dim3(256), 0, st, llev, fkey, lstart, base, L, n, N, lbox, box, link, first, lev);
 }
 
 void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,

@@ -233,18 +233,18 @@ struct OrthView {
 void launch_orth_mark(hipStream_t st, int dim, const uint64_t* sk, const uint32_t* sid, uint64_t n, uint32_t phi,
                       uint8_t* mark, uint32_t* tile_cnt, uint4* pts, uint32_t* ids);
 // Second pass, with tile_off the exclusive scan of the tile counts: each
-// leaf's first position, level and first key.
-void launch_orth_leaves(hipStream_t st, const uint64_t* sk, uint64_t n, const uint8_t* mark,
-                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey);
+// leaf's first position, level, first key and box (packed, leaf bit set).
+void launch_orth_leaves(hipStream_t st, int dim, const uint64_t* sk, uint64_t n, const uint8_t* mark,
+                        const uint32_t* tile_off, uint32_t* lstart, uint8_t* llev, uint64_t* fkey, uint4* lbox);
 // Interior nodes that open at each leaf, plus one (cnt1, L words), and the
 // largest leaf level (atomic max into *maxlev, zeroed first).
 void launch_orth_counts(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, uint32_t L,
                         uint32_t* cnt1, uint32_t* maxlev, uint32_t* err);
 // Nodes in preorder from base = exclusive scan of cnt1 (N nodes in all):
-// links and first points of every node, boxes of the leaves (from the
-// points); lev[v] = level of interior node v, 0xFF for a leaf.
+// links and first points of every node, boxes of the leaves (lbox, in leaf
+// order); lev[v] = level of interior node v, 0xFF for a leaf.
 void launch_orth_nodes(hipStream_t st, int dim, const uint8_t* llev, const uint64_t* fkey, const uint32_t* lstart,
-                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* pts, uint4* box,
+                       const uint32_t* base, uint32_t L, uint32_t n, uint64_t N, const uint4* lbox, uint4* box,
                        uint2* link, uint32_t* first, uint8_t* lev);
 // Boxes of the interior nodes of one level from their children.
 void launch_orth_boxes(hipStream_t st, int dim, uint32_t level, uint64_t N, const uint8_t* lev, uint4* box,

@@ -9,7 +9,7 @@ using namespace psi;
 
 struct psi_orth_s {
     psi_index ix = nullptr;  // stream, sort workspace, error word, timing
-    psi::Buf box, link, first, pts, ids, lev, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
+    psi::Buf box, link, first, pts, ids, lev, lbox, mark, lstart, llev, fkey, tcnt, toff, cnt1, base, tmp, small;
     psi::Buf alive;             // live bit per id ever handed out
     psi::Buf mk, mi, place, hist, hscan, flag;  // batch updates: the new set's sorted pairs
     uint64_t n = 0, N = 0, L = 0;
@@ -90,10 +90,11 @@ psi_status orth_cut(psi_orth o, const uint64_t* sk, const uint32_t* sid, uint64_
     if ((s = o->fkey.ensure(L * 8)) != PSI_OK) return s;
     if ((s = o->cnt1.ensure(L * 4)) != PSI_OK) return s;
     if ((s = o->base.ensure(L * 4)) != PSI_OK) return s;
+    if ((s = o->lbox.ensure(L * 16)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_marks", n + L * 21);
-        launch_orth_leaves(st, sk, n, o->mark.as<uint8_t>(), o->toff.as<uint32_t>(), o->lstart.as<uint32_t>(),
-                           o->llev.as<uint8_t>(), o->fkey.as<uint64_t>());
+        ProfScope ps(ix, "orth_marks", n * 9 + L * 37);
+        launch_orth_leaves(st, ix->D, sk, n, o->mark.as<uint8_t>(), o->toff.as<uint32_t>(), o->lstart.as<uint32_t>(),
+                           o->llev.as<uint8_t>(), o->fkey.as<uint64_t>(), o->lbox.as<uint4>());
     }
     // nodes opened per leaf -> preorder positions
     launch_fill_u32(st, small, 2, 0u);
@@ -116,9 +117,9 @@ psi_status orth_cut(psi_orth o, const uint64_t* sk, const uint32_t* sid, uint64_
     if ((s = o->first.ensure(N * 4)) != PSI_OK) return s;
     if ((s = o->lev.ensure(N)) != PSI_OK) return s;
     {
-        ProfScope ps(ix, "orth_nodes", L * 21 + N * 29 + n * 16);
+        ProfScope ps(ix, "orth_nodes", L * 37 + N * 29);
         launch_orth_nodes(st, ix->D, o->llev.as<uint8_t>(), o->fkey.as<uint64_t>(), o->lstart.as<uint32_t>(),
-                          o->base.as<uint32_t>(), (uint32_t)L, (uint32_t)n, N, o->pts.as<uint4>(),
+                          o->base.as<uint32_t>(), (uint32_t)L, (uint32_t)n, N, o->lbox.as<uint4>(),
                           o->box.as<uint4>(), o->link.as<uint2>(), o->first.as<uint32_t>(),
                           o->lev.as<uint8_t>());
     }
