@@ -186,13 +186,24 @@ __global__ __launch_bounds__(256) void k_orth_leaves(const uint64_t* __restrict_
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_nl;
     const uint64_t base = (uint64_t)blockIdx.x * ORTH_TILE;
-    for (uint32_t x = threadIdx.x; x < SPAN; x += 256) {
+    constexpr uint32_t NLD = (SPAN + 255) / 256;
+    uint64_t kk[NLD];  // all of a thread's loads in flight before any decode
+#pragma unroll
+    for (uint32_t r = 0; r < NLD; ++r) {
+        const uint32_t x = threadIdx.x + 256 * r;
         const uint64_t g = base + x;
-        uint32_t p[3] = {0u, 0u, 0u};
-        if (g < n) morton_point<D>(sk[g], p);
-        s_p[3 * x] = p[0];
-        s_p[3 * x + 1] = p[1];
-        s_p[3 * x + 2] = p[2];
+        kk[r] = (x < SPAN && g < n) ? sk[g] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < NLD; ++r) {
+        const uint32_t x = threadIdx.x + 256 * r;
+        if (x < SPAN) {
+            uint32_t p[3] = {0u, 0u, 0u};
+            morton_point<D>(kk[r], p);
+            s_p[3 * x] = p[0];
+            s_p[3 * x + 1] = p[1];
+            s_p[3 * x + 2] = p[2];
+        }
     }
     const uint32_t y0 = threadIdx.x * OM_PER;
     const uint2 mm = *reinterpret_cast<const uint2*>(mark + base + y0);
