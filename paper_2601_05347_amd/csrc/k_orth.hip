@@ -99,9 +99,20 @@ __global__ __launch_bounds__(256) void k_orth_mark(const uint64_t* __restrict__ 
     __shared__ uint8_t s_cp[ORTH_TILE + OM_HALO];      // 1 + levels shared by keys j and j + phi
     __shared__ uint32_t s_w[4];
     const uint64_t base = (uint64_t)blockIdx.x * ORTH_TILE;
-    for (uint32_t x = threadIdx.x; x < ORTH_TILE + 2 * OM_HALO; x += 256) {
-        const int64_t g = (int64_t)base - (int64_t)OM_HALO + x;
-        s_k[x] = (g >= 0 && (uint64_t)g < n) ? sk[g] : 0ull;
+    {
+        constexpr uint32_t SPAN = ORTH_TILE + 2 * OM_HALO, NLD = (SPAN + 255) / 256;
+        uint64_t kk[NLD];  // all of a thread's loads in flight at once
+#pragma unroll
+        for (uint32_t r = 0; r < NLD; ++r) {
+            const uint32_t x = threadIdx.x + 256 * r;
+            const int64_t g = (int64_t)base - (int64_t)OM_HALO + x;
+            kk[r] = (x < SPAN && g >= 0 && (uint64_t)g < n) ? sk[g] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < NLD; ++r) {
+            const uint32_t x = threadIdx.x + 256 * r;
+            if (x < SPAN) s_k[x] = kk[r];
+        }
     }
     __syncthreads();
     // j = base - OM_HALO + x; 0 when keys j or j + phi fall outside [0, n)
@@ -157,14 +168,22 @@ __global__ __launch_bounds__(256) void k_orth_mark(const uint64_t* __restrict__ 
     const uint32_t incl = block_incl_scan256(c, s_w);
     if (threadIdx.x == 255) tile_cnt[blockIdx.x] = incl;
     // the points in key order, coordinates decoded from the keys
-    for (uint32_t y = threadIdx.x; y < ORTH_TILE; y += 256) {
+    uint32_t idv[OM_PER];
+#pragma unroll
+    for (uint32_t r = 0; r < OM_PER; ++r) {
+        const uint64_t i = base + threadIdx.x + 256 * r;
+        idv[r] = i < n ? sid[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < OM_PER; ++r) {
+        const uint32_t y = threadIdx.x + 256 * r;
         const uint64_t i = base + y;
-        if (i >= n) break;
-        uint32_t p[3] = {0u, 0u, 0u};
-        morton_point<D>(s_k[y + OM_HALO], p);
-        const uint32_t id = sid[i];
-        pts[i] = make_uint4(p[0], p[1], D == 3 ? p[2] : 0u, id);
-        ids[i] = id;
+        if (i < n) {
+            uint32_t p[3] = {0u, 0u, 0u};
+            morton_point<D>(s_k[y + OM_HALO], p);
+            pts[i] = make_uint4(p[0], p[1], D == 3 ? p[2] : 0u, idv[r]);
+            ids[i] = idv[r];
+        }
     }
 }
 
