@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
     ap.add_argument("--batch-frac", default="0.1,0.01,0.001,0.0001", help="incr: batch sizes as fractions of n")
+    ap.add_argument("--tree", default="spac", choices=["spac", "orth"],
+                    help="incr: the SPaC tree (curve from --curve) or the P-Orth tree")
     ap.add_argument("--sorted-leaves", action="store_true",
                     help="keep every leaf in (key, id) order after updates (the total-order ablation)")
     return ap.parse_args()
@@ -218,6 +220,14 @@ def bench_incr(args):
     d_q = {"ind": torch.from_numpy(ind.view(np.int32)).to(dev), "ood": torch.from_numpy(ood.view(np.int32)).to(dev)}
     d_ids = torch.arange(n, dtype=torch.int32, device=dev)
     half = n // 2
+    orth = args.tree == "orth"
+    if orth:
+        new_tree = lambda flags=0: psi.Orth(dim, args.leaf, device=dev)  # noqa: E731
+        build, insert, delete, knn = (psi.psi_orth_build, psi.psi_orth_batch_insert, psi.psi_orth_batch_delete,
+                                      psi.psi_orth_knn)
+    else:
+        new_tree = lambda flags=0: psi.Index(dim, curve, args.leaf, args.fanout, device=dev, flags=flags)  # noqa: E731
+        build, insert, delete, knn = psi.psi_build, psi.psi_batch_insert, psi.psi_batch_delete, psi.psi_knn
 
     def ev():
         e = torch.cuda.Event(enable_timing=True)
@@ -230,7 +240,7 @@ def bench_incr(args):
             ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
             d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
             a = ev()
-            psi.psi_knn(ix._h, q, nq, k, ids, d2)
+            knn(ix._h, q, nq, k, ids, d2)
             b = ev()
             b.synchronize()
             out[name], ms[name] = (ids, d2), round(a.elapsed_time(b), 3)
@@ -238,27 +248,26 @@ def bench_incr(args):
 
     # static references: the first half (ids 0 .. n/2 - 1) and the second half
     # (built alone its ids are 0 .. n/2 - 1: the incremental ids minus n/2)
-    st1 = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
-    psi.psi_build(st1._h, d_data[:half], half)
+    st1 = new_tree()
+    build(st1._h, d_data[:half], half)
     ref1, ms1 = queries(st1)
     del st1
-    st2 = psi.Index(dim, curve, args.leaf, args.fanout, device=dev)
-    psi.psi_build(st2._h, d_data[half:], n - half)
+    st2 = new_tree()
+    build(st2._h, d_data[half:], n - half)
     ref2, ms2 = queries(st2)
     del st2
     runs = {}
     for frac in [float(x) for x in args.batch_frac.split(",")]:
         s = max(1, int(round(n * frac)))
         nbat = n // s
-        ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev,
-                       flags=psi.FLAG_SORTED_LEAVES if args.sorted_leaves else 0)
-        psi.psi_build(ix._h, d_data[:0], 0)
+        ix = new_tree(psi.FLAG_SORTED_LEAVES if args.sorted_leaves else 0)
+        build(ix._h, d_data[:0], 0)
         torch.cuda.synchronize()
         ins_ms = del_ms = 0.0
         same = True
         a = ev()
         for i in range(nbat):
-            psi.psi_batch_insert(ix._h, d_data[i * s:(i + 1) * s], s, None)
+            insert(ix._h, d_data[i * s:(i + 1) * s], s, None)
             if i == nbat // 2 - 1:
                 b = ev()
                 b.synchronize()
@@ -273,7 +282,7 @@ def bench_incr(args):
         ins_ms += a.elapsed_time(b)
         a = ev()
         for i in range(nbat):
-            psi.psi_batch_delete(ix._h, d_ids[i * s:(i + 1) * s], s, None)
+            delete(ix._h, d_ids[i * s:(i + 1) * s], s, None)
             if i == nbat // 2 - 1:
                 b = ev()
                 b.synchronize()
@@ -289,7 +298,7 @@ def bench_incr(args):
         b.synchronize()
         del_ms += a.elapsed_time(b)
         ix.sync()
-        left = ix.size()
+        left = ix.size()[0] if orth else ix.size()
         del ix
         runs[f"b={frac}"] = {"batch": s, "batches": nbat, "insert_ms": round(ins_ms, 3), "delete_ms": round(del_ms, 3),
                              "insert_mpts_s": round(nbat * s / ins_ms / 1e3, 1),
@@ -304,7 +313,8 @@ def bench_incr(args):
            "value": round(2 * small["batches"] * small["batch"] / tot / 1e3, 2), "unit": "Mpoints/s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": round(tot, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
-           "config": {"workload": f"incremental: {dim}D {dist} {args.curve}", "n": n, "queries": nq, "k": k,
+           "config": {"workload": f"incremental: {dim}D {dist} {'P-Orth' if orth else args.curve}", "n": n,
+                      "queries": nq, "k": k,
                       "leaf_size": args.leaf, "fanout": args.fanout, "sorted_leaves": args.sorted_leaves},
            "static_knn_ms": {"first_half": ms1, "second_half": ms2}, "runs": runs}
     print(json.dumps(out), flush=True)
