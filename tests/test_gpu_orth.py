@@ -374,18 +374,14 @@ def test_large_batches(psi):
     check_queries(psi, o, allp[live], 3, 32, q, bx, ks=(10,), live=live)
 
 
-@pytest.mark.slow
-def test_fullsize_1e8_3d(psi):
-    """The 3D, 1e8-point uniform configuration: invariants over the whole
-    exported tree, queries on a sample against brute force."""
-    n, dim, phi = 100_000_000, 3, 32
-    say("orth full size 1e8 3D: build")
-    pts = synth.uniform(n, dim, 21, 1)
-    o = psi.Orth(dim, phi).build(pts)
-    o.sync()
+def check_fullsize(o, allp, live, phi):
+    """Invariants over a whole exported tree of the points allp[live] (ids =
+    live, ascending): counts, subtree ends, leaves tiling the points, every id
+    once with its coordinates, sampled leaf boxes."""
+    n = len(live)
     nodes, gp = o.export()
     N = nodes.shape[0]
-    say(f"orth full size: {N} nodes")
+    say(f"orth full size: {N} nodes, {n} points")
     leaf = (nodes[:, 7] & 0x80000000) != 0
     cnt = (nodes[:, 7] & 0x7FFFFFFF).astype(np.int64)
     assert cnt[0] == n and int(cnt[leaf].sum()) == n
@@ -401,18 +397,28 @@ def test_fullsize_1e8_3d(psi):
     # leaves tile the point array in order
     first = nodes[leaf, 6].astype(np.int64)
     np.testing.assert_array_equal(first, np.concatenate([[0], np.cumsum(cnt[leaf])[:-1]]))
-    seen = np.zeros(n, dtype=bool)
-    seen[gp[:, 3]] = True
-    assert seen.all()
-    np.testing.assert_array_equal(gp[:, :3], pts[gp[:, 3]])
-    del seen
+    ids = gp[:, 3].astype(np.int64)
+    np.testing.assert_array_equal(np.sort(ids), live)
+    np.testing.assert_array_equal(gp[:, :3], allp[ids])
     # sampled leaf boxes
     li = np.nonzero(leaf)[0]
     for v in li[:: max(1, len(li) // 2000)]:
         p = gp[nodes[v, 6]: nodes[v, 6] + cnt[v], :3]
         np.testing.assert_array_equal(nodes[v, 0:3], p.min(axis=0))
         np.testing.assert_array_equal(nodes[v, 3:6], p.max(axis=0))
-    del gp
+
+
+@pytest.mark.slow
+def test_fullsize_1e8_3d(psi):
+    """The 3D, 1e8-point uniform configuration of the benchmark (build, insert
+    1e6, delete 1e6): invariants over the whole exported tree after each step,
+    queries on a sample against brute force."""
+    n, m, dim, phi = 100_000_000, 1_000_000, 3, 32
+    say("orth full size 1e8 3D: build")
+    pts = synth.uniform(n, dim, 21, 1)
+    o = psi.Orth(dim, phi).build(pts)
+    o.sync()
+    check_fullsize(o, pts, np.arange(n, dtype=np.int64), phi)
     say("orth full size: queries")
     q = queries(dim, 200, 3, pts, 21)
     bx = synth.boxes(q[:100], 21, 5, side_lo=10, side_hi=14)
@@ -421,3 +427,21 @@ def test_fullsize_1e8_3d(psi):
     np.testing.assert_array_equal(psi.to_u64(d2), ed2)
     np.testing.assert_array_equal(psi.to_u32(ids), eid)
     np.testing.assert_array_equal(psi.to_u64(o.range_count(bx)), oracle.range_count_points(pts, bx))
+    say("orth full size: insert 1e6, delete 1e6")
+    ins = synth.uniform(m, dim, 21, 1, synth.P_INSERT)
+    np.testing.assert_array_equal(psi.to_u32(o.batch_insert(ins)), np.arange(n, n + m))
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, 1)
+    assert o.batch_delete(dels) == m
+    o.sync()
+    allp = np.concatenate([pts, ins])
+    del pts
+    keep = np.ones(n + m, dtype=bool)
+    keep[dels.astype(np.int64)] = False
+    live = np.nonzero(keep)[0]
+    check_fullsize(o, allp, live, phi)
+    say("orth full size: queries after the updates")
+    ids, d2 = o.knn(q, 10)
+    eid, ed2 = oracle.knn_points(allp[live], q, 10)
+    np.testing.assert_array_equal(psi.to_u64(d2), ed2)
+    np.testing.assert_array_equal(psi.to_u32(ids), rows_to_ids(eid, live))
+    np.testing.assert_array_equal(psi.to_u64(o.range_count(bx)), oracle.range_count_points(allp[live], bx))
