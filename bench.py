@@ -44,6 +44,8 @@ WORKLOADS = {
     # P-Orth tree (Sec. 3) beside the SPaC-H tree on the 3d-1e8 inputs: build,
     # insert 1e6, delete 1e6, 1e7 10-NN queries, 1e6 range counts and reports
     "orth": dict(dim=3, bits=21, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
+    # the same in 2D, coordinates in [0, 2^30)^2
+    "orth2d": dict(dim=2, bits=30, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
     # incremental workload: 3D, 1e8 points inserted into an empty index in n/b
     # batches, then deleted in n/b batches; 1e7 10-NN queries at the halfway points
     "incr": dict(dim=3, bits=21, n=100_000_000, m=0, nq=10_000_000, k=10, nb=0),
@@ -330,7 +332,7 @@ def bench_orth(args):
 
     import paper_2601_05347_amd as psi
     import synth
-    cfg = dict(WORKLOADS["orth"])
+    cfg = dict(WORKLOADS[args.workload])
     if args.n:
         cfg["n"] = args.n
     dim, bits, n, nq, k, nb = (cfg[x] for x in ("dim", "bits", "n", "nq", "k", "nb"))
@@ -537,7 +539,7 @@ def main():
         return bench_multi(args)
     if args.workload == "incr":
         return bench_incr(args)
-    if args.workload == "orth":
+    if args.workload in ("orth", "orth2d"):
         return bench_orth(args)
     import numpy as np
     import torch
