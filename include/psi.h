@@ -270,7 +270,8 @@ psi_status psi_orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n);
  * next_id + m - 1 in input order, written to d_new_ids (device, m u32) if
  * not null. PSI_E_RANGE (nothing inserted, tree unchanged) if a coordinate is
  * out of range; PSI_E_CAPACITY past 2^32 - 1 ids or 2^31 points. Waits for the
- * stream. Any other failure leaves the tree empty. */
+ * stream. Any other failure leaves the tree empty, with ids restarting at 0
+ * (as does a failed delete). */
 psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
 /* Deletes the points with the given ids (device, m u32, any order); unknown,
  * deleted and repeated ids are ignored. *d_ndeleted (device u64, may be null)

@@ -288,9 +288,10 @@ psi_status psi_orth_batch_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, 
     psi_status s = psi_sync(o->ix);
     if (s != PSI_OK) return s;
     s = orth_insert(o, d_pts, m, d_new_ids);
-    if (s != PSI_OK && s != PSI_E_RANGE) {
+    if (s != PSI_OK && s != PSI_E_RANGE) {  // an empty tree, ids from 0 again
         o->n = o->N = o->L = 0;
         o->height = 0;
+        o->next_id = 0;
     }
     return s;
 }
@@ -301,9 +302,10 @@ psi_status psi_orth_batch_delete(psi_orth o, const uint32_t* d_ids, uint64_t m, 
     psi_status s = psi_sync(o->ix);
     if (s != PSI_OK) return s;
     s = orth_delete(o, d_ids, m, d_ndeleted);
-    if (s != PSI_OK) {
+    if (s != PSI_OK) {  // an empty tree, ids from 0 again
         o->n = o->N = o->L = 0;
         o->height = 0;
+        o->next_id = 0;
     }
     return s;
 }
