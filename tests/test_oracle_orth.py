@@ -156,3 +156,47 @@ def test_four_quadrants_by_hand():
     assert [a.tolist() for a in pre["leaf_ids"]] == [[0], [1], [2]]
     assert pre["end"].tolist() == [4, 2, 3, 4]
     assert pre["first"].tolist() == [-1, 0, 1, 2]
+
+
+MUTANTS = [
+    ("merge keeps subtrees of exactly phi points", "if nd.count <= phi:", "if nd.count < phi:"),
+    ("a point on the midpoint goes low", "upper = p >= c + half", "upper = p > c + half"),
+    ("children ordered with the axes swapped", "child |= upper[:, d].astype(np.int64) << d",
+     "child |= upper[:, d].astype(np.int64) << (dim - 1 - d)"),
+    ("box from the region, not the points", "nd.lo = p.min(axis=0)", "nd.lo = np.asarray(corner, dtype=np.int64)"),
+    ("one-point cells split", "if len(ids) < phi or level == W:", "if len(ids) < phi or level == W + 1:"),
+]
+
+
+@pytest.mark.parametrize("what,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_a_planted_mistake(what, old, new):
+    """Each plausible slip, planted in a copy of the oracle, fails a pin."""
+    import types
+    src = open(orth.__file__).read()
+    assert old in src
+    mod = types.ModuleType("orth_mutant")
+    exec(compile(src.replace(old, new), "orth_mutant", "exec"), mod.__dict__)
+    caught = False
+    for name, dim, pts in inputs():
+        for phi in (2, 8, 32):
+            try:
+                root = mod.build(pts, dim, phi)
+                if tree_nodes(root) != brute_force_nodes(pts, dim, phi):
+                    caught = True
+                    break
+                pre = mod.preorder(root, dim)
+                p = np.asarray(pts, dtype=np.int64)
+                for v in range(len(pre["level"])):
+                    if pre["leaf"][v]:
+                        j = int(pre["leaf"][:v].sum())
+                        q = p[pre["leaf_ids"][j]]
+                        if (pre["lo"][v] != q.min(axis=0)).any():
+                            caught = True
+                            break
+            except Exception:
+                caught = True
+            if caught:
+                break
+        if caught:
+            break
+    assert caught, what
