@@ -36,9 +36,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build_lib(force=True)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("PSI_ORACLE_LIB")  # a test's planted-mistake copy
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build_lib(force=True)
+        L = C.CDLL(path)
         P = C.c_void_p
         u64, u32, i32 = C.c_uint64, C.c_uint32, C.c_int
         sig = {

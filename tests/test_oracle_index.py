@@ -173,6 +173,25 @@ def test_knn_lattice_ties(ora):
     ring2 = sorted(pos[p] for p in [(20, 10), (22, 10), (20, 12), (22, 12)])
     assert ids[0].tolist() == [centre] + ring1 + ring2
     assert d2[0].tolist() == [0, 1, 1, 1, 1, 2, 2, 2, 2]
+    # k cutting through a ring keeps its smallest ids, whatever the key order
+    for k in range(1, 9):
+        ids, d2 = R.knn(np.array([[21, 11]], np.uint32), k)
+        assert ids[0].tolist() == ([centre] + ring1 + ring2)[:k], k
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_knn_ties_at_the_kth_distance(ora, dim):
+    # a tiny domain: many equal points and equal distances, so the k-th
+    # distance is shared by several points; the smallest ids among them win
+    pts = synth.uniform(800, dim, 3, seed=7 + dim)
+    q = synth.uniform(40, dim, 3, seed=8 + dim, purpose=synth.P_QUERY)
+    R = ora.RefIndex(dim, 1)
+    R.build(pts)
+    for k in (3, 10, 33):
+        a = R.knn(q, k)
+        c = _np_knn(pts, np.arange(len(pts), dtype=np.uint32), q, k)
+        np.testing.assert_array_equal(a[0], c[0])
+        np.testing.assert_array_equal(a[1], c[1])
 
 
 def test_knn_padding_when_k_exceeds_n(ora):
