@@ -15,8 +15,17 @@
  *     (or psi_set_stream). Argument errors are returned at once. Errors that
  *     only the device can see (coordinate out of range, an internal check)
  *     are latched and returned by the next psi_sync / psi_size.
- *     Update calls (insert, delete) wait once on their stream to size their
- *     output; query calls never wait.
+ *   - Build, insert, delete and the queries only enqueue work: none of them
+ *     waits for the stream. The sizes of the tree (leaf count, current
+ *     directory, slots, next id, node layout) live in device memory and are
+ *     planned, checked and committed by kernels; the host sizes buffers and
+ *     grids by upper bounds (an update's worst case for its batch size), which
+ *     it tightens from a copy of the device state taken after each update
+ *     without waiting for it. A call may still wait when more than 64 updates
+ *     are queued, or when a replayed graph left the sizes unknown. Growing a
+ *     buffer never waits either (the replaced block is freed once the stream
+ *     is idle). The inspection calls (psi_sync, psi_size, psi_next_id,
+ *     psi_shape, the exports) wait for the stream.
  *   - Points are row-major uint32 [n][dim]. 2D coordinates must be < 2^31 and
  *     3D coordinates < 2^21: the key has 32 (2D) or 21 (3D) bits per axis
  *     (Sec. 3, the precision a 64-bit code allows), and 2D squared distances
@@ -42,7 +51,8 @@ typedef enum {
     PSI_E_ARG = 1,       /* bad argument (null pointer, bad size or parameter) */
     PSI_E_RANGE = 2,     /* a coordinate exceeds the key's bits per axis */
     PSI_E_NOMEM = 3,     /* device allocation failed */
-    PSI_E_CAPACITY = 4,  /* id space (2^32 - 1 ids) exhausted */
+    PSI_E_CAPACITY = 4,  /* id space (2^32 - 1 ids) exhausted, or an update did not fit
+                            the buffers a captured graph was sized with */
     PSI_E_HIP = 5,       /* a HIP runtime call failed */
     PSI_E_STATE = 6,     /* call not valid in the index's current state */
     PSI_E_INTERNAL = 7   /* a device-side consistency check failed */
@@ -113,7 +123,10 @@ psi_status psi_build(psi_index ix, const uint32_t* d_pts, uint64_t n);
 /* Batch insert (Alg. 4): add m points; their ids are the next m unused ids
  * in input order, written to d_new_ids (may be NULL). Each sorted run of new
  * points is appended, unsorted, to the leaf whose key range holds it; a leaf
- * that would exceed 2*phi entries is re-cut into balanced leaves. */
+ * that would exceed 2*phi entries is re-cut into balanced leaves. A batch with
+ * a coordinate out of range is rejected whole on the device before any leaf
+ * changes: nothing is inserted, no id is used, d_new_ids reads 0xFFFFFFFF and
+ * the next psi_sync returns PSI_E_RANGE. */
 psi_status psi_batch_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
 
 /* Batch delete (Sec. 4.2): remove the live points whose ids are listed.
@@ -143,11 +156,13 @@ psi_status psi_range_count(psi_index ix, const uint32_t* d_boxes, uint64_t nb, u
 psi_status psi_range_report(psi_index ix, const uint32_t* d_boxes, uint64_t nb,
                             const uint64_t* d_offsets, uint32_t* d_ids);
 
-/* Waits for the stream; returns the first latched device error, if any. */
+/* Waits for the stream; returns the first latched device error, if any
+ * (PSI_E_RANGE; PSI_E_CAPACITY for an update a replayed graph could not fit
+ * into the buffers it was captured with; PSI_E_INTERNAL), and clears it. */
 psi_status psi_sync(psi_index ix);
 /* Number of live points (waits for the stream, like psi_sync). */
 psi_status psi_size(psi_index ix, uint64_t* h_n_live);
-/* Next id that an insert would assign. */
+/* Next id that an insert would assign (waits for the stream). */
 psi_status psi_next_id(psi_index ix, uint32_t* h_next_id);
 
 /* --- inspection (tests, checkpoints) ------------------------------------ */
@@ -219,13 +234,26 @@ psi_status psi_multi_export(psi_multi mx, uint64_t* d_keys, uint32_t* d_ids, uin
 
 /* --- graph capture of query steps ----------------------------------------- */
 
-/* Capture the query calls (psi_knn, psi_range_count, psi_range_report,
- * psi_multi_knn) issued on `hip_stream` between psi_graph_begin and
- * psi_graph_end into a hipGraph; psi_graph_launch replays them with the same
- * buffers and sizes. Inside a capture no memory is allocated: run each call
- * once with the same sizes before capturing (a call that would need a larger
- * buffer returns PSI_E_STATE). Build and updates wait on the host and return
- * PSI_E_STATE while their stream is being captured. */
+/* Capture the calls (psi_build, psi_batch_insert, psi_batch_delete,
+ * psi_knn, psi_range_count, psi_range_report, psi_multi_knn) issued on
+ * `hip_stream` between psi_graph_begin and psi_graph_end into a hipGraph;
+ * psi_graph_launch replays them with the same buffers and sizes.
+ *   - Inside a capture no memory is allocated: run the same calls once with
+ *     the same sizes before capturing (a call that would need a larger buffer
+ *     returns PSI_E_STATE).
+ *   - Every replay starts from the index's state at that moment: a captured
+ *     insert hands out fresh ids on each replay (the next id is device
+ *     state), a captured build resets the index. The per-leaf launches of a
+ *     captured update cover as many leaves as the buffers hold; a replay
+ *     that would exceed the buffers (or find more leaves than that) is
+ *     refused on the device before it changes anything (the next psi_sync
+ *     returns PSI_E_CAPACITY).
+ *   - A graph records the indexes it touches. Any later eager build, update,
+ *     or buffer growth of such an index stales the graph: psi_graph_launch
+ *     then returns PSI_E_STATE and launches nothing (the graph would read a
+ *     stale directory or freed memory). Replays themselves do not stale it.
+ *   - After a replay that ran updates, the next call that needs the sizes
+ *     (an update, an inspection call) waits for the stream once. */
 psi_status psi_graph_begin(void* hip_stream);
 psi_status psi_graph_end(void* hip_stream, psi_graph* out);
 psi_status psi_graph_launch(psi_graph g, void* hip_stream);

@@ -21,10 +21,11 @@ inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + pe
 
 // bstart[t] = first position whose top bits (key >> shift) are >= t, for
 // t in [0, nb]; the keys are already ordered by those bits.
-__global__ void k_bucket_starts(const uint64_t* __restrict__ keys, uint64_t n, uint32_t shift, uint32_t nb,
-                                uint32_t* __restrict__ bstart) {
+__global__ void k_bucket_starts(const uint64_t* __restrict__ keys, uint64_t n, const uint32_t* __restrict__ top,
+                                uint32_t nb, uint32_t* __restrict__ bstart) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > nb) return;
+    const uint32_t shift = *top;
     uint64_t lo = 0, hi = n;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
@@ -126,8 +127,10 @@ __device__ __forceinline__ void rank_runs(uint64_t* s_k, uint32_t* s_i, uint32_t
 // alone.
 template <int BMAX>
 __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
-                                                    const uint32_t* __restrict__ bstart, uint32_t lo_bits,
-                                                    uint32_t* __restrict__ big, uint32_t* __restrict__ err) {
+                                                    const uint32_t* __restrict__ bstart,
+                                                    const uint32_t* __restrict__ top, uint32_t* __restrict__ big,
+                                                    uint32_t* __restrict__ err) {
+    const uint32_t lo_bits = *top;
     constexpr int IPT = BMAX / 256;  // items per thread at the largest bucket
     __shared__ uint64_t s_k[BMAX];
     __shared__ uint32_t s_i[BMAX];
@@ -337,8 +340,17 @@ __global__ __launch_bounds__(256) void k_hist_keys2(const uint64_t* __restrict__
 // x (tiles T x / 8 .. T (x + 1) / 8), cnt[1][g][d1] over the keys whose d0
 // lies in [32 g, 32 g + 32) (the g-th group of the first pass's output).
 // Each workgroup reads one contiguous range, eight loads in flight per thread.
+// With `redo` set (device word), the kernel counts only if *redo is nonzero,
+// and the digits sit at bits *top and *top + 8 instead.
 __global__ __launch_bounds__(256) void k_hist_chunks(const uint64_t* __restrict__ keys, uint64_t n, uint32_t s0,
-                                                     uint32_t s1, uint64_t T, uint32_t* __restrict__ cnt) {
+                                                     uint32_t s1, uint64_t T, uint32_t* __restrict__ cnt,
+                                                     const uint32_t* __restrict__ redo,
+                                                     const uint32_t* __restrict__ top) {
+    if (redo) {
+        if (*redo == 0) return;
+        s0 = *top;
+        s1 = s0 + 8;
+    }
     __shared__ uint32_t h[2][XCD_CHUNKS][RADIX];
     for (int i = threadIdx.x; i < 2 * (int)XCD_CHUNKS * RADIX; i += blockDim.x) (&h[0][0][0])[i] = 0;
     __syncthreads();
@@ -451,40 +463,78 @@ __global__ void k_big_tables(const uint32_t* __restrict__ bstart, const uint32_t
     }
 }
 
-// Per-segment histograms of the low six digits, one block per tile.
+// Per-segment histograms of the low six digits, tile by tile (the block
+// takes tiles blockIdx.x, + gridDim.x, ... below *ntiles).
 __global__ __launch_bounds__(256) void k_seg_hist_keys(const uint64_t* __restrict__ keys, SegTiles sg,
+                                                       const uint32_t* __restrict__ ntiles,
                                                        uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[6][RADIX];
-    for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t s = sg.tile_seg[blockIdx.x];
-    const uint64_t beg = sg.tile_beg[blockIdx.x];
-    const uint64_t end = min<uint64_t>(beg + SORT_TILE, sg.seg_end[s]);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const uint64_t k = keys[i];
+    const uint32_t nt = *ntiles;
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) (&h[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t s = sg.tile_seg[tile];
+        const uint64_t beg = sg.tile_beg[tile];
+        const uint64_t end = min<uint64_t>(beg + SORT_TILE, sg.seg_end[s]);
+        for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+            const uint64_t k = keys[i];
 #pragma unroll
-        for (int p = 0; p < 6; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+            for (int p = 0; p < 6; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+        }
+        __syncthreads();
+        uint32_t* hs = hist + (uint64_t)s * 8 * RADIX;
+        for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) {
+            const uint32_t v = (&h[0][0])[i];
+            if (v) atomicAdd(&hs[i], v);
+        }
     }
-    __syncthreads();
-    uint32_t* hs = hist + (uint64_t)s * 8 * RADIX;
-    for (int i = threadIdx.x; i < 6 * RADIX; i += blockDim.x) {
-        const uint32_t v = (&h[0][0])[i];
-        if (v) atomicAdd(&hs[i], v);
-    }
+}
+
+// The bucket bits: the 16 below the largest key's leading bit (0 if it has
+// at most 16 bits); redo = they differ from the guess the counts were taken
+// for while encoding.
+__global__ void k_fix_top(const uint64_t* __restrict__ kmax, uint32_t guess, uint32_t* __restrict__ top,
+                          uint32_t* __restrict__ redo) {
+    if (threadIdx.x | blockIdx.x) return;
+    const uint64_t km = *kmax;
+    const uint32_t bits = km ? 64u - (uint32_t)__clzll((long long)km) : 0u;
+    const uint32_t t = bits > 16 ? bits - 16 : 0u;
+    *top = t;
+    *redo = t != guess ? 1u : 0u;
+}
+
+// p[0 .. words_per * *count) = 0.
+__global__ void k_zero_counted(uint32_t* __restrict__ p, uint64_t words_per, const uint32_t* __restrict__ count) {
+    const uint64_t n = words_per * *count;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 }  // namespace
 
-void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
+void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, const uint32_t* top, uint32_t* bstart,
                           uint32_t nb) {
-    hipLaunchKernelGGL(k_bucket_starts, dim3(blocks_for((uint64_t)nb + 1, 256)), dim3(256), 0, st, keys, n, shift,
+    hipLaunchKernelGGL(k_bucket_starts, dim3(blocks_for((uint64_t)nb + 1, 256)), dim3(256), 0, st, keys, n, top,
                        nb, bstart);
 }
 
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t* big, uint32_t* err, bool wide) {
-    if (wide) hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
-    else hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, lo_bits, big, err);
+                       const uint32_t* top, uint32_t* big, uint32_t* err, bool wide) {
+    if (wide) hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, top, big, err);
+    else hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, top, big, err);
+}
+
+void launch_fix_top(hipStream_t st, const uint64_t* kmax, uint32_t guess, uint32_t* top, uint32_t* redo) {
+    hipLaunchKernelGGL(k_fix_top, dim3(1), dim3(64), 0, st, kmax, guess, top, redo);
+}
+
+void launch_zero_counted(hipStream_t st, uint32_t* p, uint64_t words_per, const uint32_t* count, uint64_t max_count) {
+    const uint64_t n = words_per * max_count;
+    if (!n) return;
+    unsigned g = blocks_for(n, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_zero_counted, dim3(g), dim3(256), 0, st, p, words_per, count);
 }
 
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,
@@ -508,11 +558,13 @@ void launch_hist_keys2(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_
     hipLaunchKernelGGL(k_hist_keys2, dim3(g), dim3(256), 0, st, keys, n, s0, s1, hist);
 }
 
-void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt) {
+void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt,
+                        const uint32_t* redo, const uint32_t* top) {
     if (n == 0) return;
     unsigned g = blocks_for(n, 256 * 64);
     if (g > 512) g = 512;
-    hipLaunchKernelGGL(k_hist_chunks, dim3(g), dim3(256), 0, st, keys, n, s0, s1, (n + SORT_TILE - 1) / SORT_TILE, cnt);
+    hipLaunchKernelGGL(k_hist_chunks, dim3(g), dim3(256), 0, st, keys, n, s0, s1, (n + SORT_TILE - 1) / SORT_TILE, cnt,
+                       redo, top);
 }
 
 void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint32_t* off1, uint32_t* off2,
@@ -522,8 +574,11 @@ void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint3
                        tb2.pos_begin, tb2.pos_end);
 }
 
-void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist) {
-    if (ntiles) hipLaunchKernelGGL(k_seg_hist_keys, dim3((unsigned)ntiles), dim3(256), 0, st, keys, sg, hist);
+void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t max_tiles, const uint32_t* ntiles,
+                          const SegTiles& sg, uint32_t* hist) {
+    if (!max_tiles) return;
+    const unsigned g = max_tiles > 2048 ? 2048u : (unsigned)max_tiles;
+    hipLaunchKernelGGL(k_seg_hist_keys, dim3(g), dim3(256), 0, st, keys, sg, ntiles, hist);
 }
 
 }  // namespace psi

@@ -41,7 +41,10 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
                                                       const uint32_t* __restrict__ sid, uint64_t n, uint64_t L,
                                                       uint32_t C, uint32_t* __restrict__ slots,
                                                       uint64_t* __restrict__ piv_key, uint32_t* __restrict__ piv_id,
-                                                      NodeRec* __restrict__ leafrec) {
+                                                      NodeRec* __restrict__ leafrec, const uint64_t* __restrict__ skip) {
+    // skip (may be null): a nonzero word there cancels the fill (an insert
+    // into an index that turned out not to be empty)
+    if (skip && *skip != 0) return;
     // Hilbert keys decode through the curve's state tables, staged once per
     // workgroup (the grid is sized to the chip; half-waves stride over leaves)
     __shared__ uint16_t s_h[CURVE ? HilbertFsm<D>::ENTRIES : 1];
@@ -118,22 +121,28 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
 // One node level: parent i = union of children [B i, B i + B) one level down.
 // G = B rounded up to a power of two lanes per parent: every lane loads one
 // child record (a parent's children are one contiguous run of records) and the
-// group reduces counts and boxes by xor shuffles.
-// cchild (may be null) and cparent receive the packed boxes of the children
-// and of the parents (the kNN's box tests read those).
+// group reduces counts and boxes by xor shuffles. The level is the u-th above
+// the leaves in the layout the device state holds (nothing to do if the tree
+// is lower than that).
 template <int D, int G>
-__global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ child, uint64_t n_child,
-                                                    NodeRec* __restrict__ parent, uint64_t n_parent, uint32_t B,
-                                                    uint4* __restrict__ cchild, uint4* __restrict__ cparent) {
-    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+__global__ __launch_bounds__(256) void k_node_level(const DevTree* __restrict__ dt, uint32_t u,
+                                                    NodeRec* __restrict__ inner, uint32_t B, Dirs dirs) {
+    const uint32_t h = dt->h;
+    if (u > h || dt->L == 0) return;
+    const uint32_t l = h - u;  // parent level
+    const uint64_t n_parent = dt->lv[l].n, n_child = dt->lv[l + 1].n;
+    const NodeRec* child = u == 1 ? dirs.leaf[dt->cur] : inner + dt->lv[l + 1].off;
+    NodeRec* parent = inner + dt->lv[l].off;
     const uint32_t g = threadIdx.x % G;
+    // a group of G lanes per parent, striding over the level (the grid is
+    // sized by a bound of the level's size); the loop bound is uniform per
+    // group, so all of a group's lanes stay for the shuffles
+    const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) / G;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n_parent; i += stride) {
     const uint64_t c = i * B + g;
     const bool on = i < n_parent && g < B && c < n_child;  // all lanes stay for the shuffles
     NodeRec x = {};
-    if (on) {
-        x = child[c];
-        if (cchild) cchild[c] = packed_box<D>(x);
-    }
+    if (on) x = child[c];
     uint32_t cnt = on ? x.cnt : 0u;
     uint32_t lo[D], hi[D];
 #pragma unroll
@@ -161,15 +170,19 @@ __global__ __launch_bounds__(256) void k_node_level(const NodeRec* __restrict__ 
         r.cnt = cnt;
         r.slot = 0xFFFFFFFFu;
         parent[i] = r;
-        if (cparent) cparent[i] = packed_box<D>(r);
+    }
     }
 }
 
-// Packed boxes of n records (a tree whose root is a leaf).
+// Packed boxes of the current leaves (leaves = true) or of the inner nodes,
+// as many as the device state holds; grid-stride over at most `cap` records.
 template <int D>
-__global__ void k_pack_boxes(const NodeRec* __restrict__ rec, uint64_t n, uint4* __restrict__ out) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = packed_box<D>(rec[i]);
+__global__ void k_pack_tree(const DevTree* __restrict__ dt, bool leaves, const NodeRec* __restrict__ inner,
+                            uint4* __restrict__ out, Dirs dirs) {
+    const uint64_t n = leaves ? dt->L : dt->n_inner;
+    const NodeRec* rec = leaves ? dirs.leaf[dt->cur] : inner;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = packed_box<D>(rec[i]);
 }
 
 __global__ void k_leaf_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t* __restrict__ cnt) {
@@ -288,11 +301,11 @@ __global__ void k_export_structure(TreeView t, uint64_t n_inner, const uint64_t*
 
 void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
                          uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
-                         uint32_t* piv_id, NodeRec* leafrec) {
+                         uint32_t* piv_id, NodeRec* leafrec, const uint64_t* skip) {
     if (L == 0) return;
     unsigned g = blocks_for(L, 256 / 32);
     if (g > 2048) g = 2048;  // 8 workgroups per CU; half-waves stride over the leaves
-#define PSI_BL(D, CV) hipLaunchKernelGGL((k_build_leaves<D, CV>), dim3(g), dim3(256), 0, st, sk, sid, n, L, C, slots, piv_key, piv_id, leafrec)
+#define PSI_BL(D, CV) hipLaunchKernelGGL((k_build_leaves<D, CV>), dim3(g), dim3(256), 0, st, sk, sid, n, L, C, slots, piv_key, piv_id, leafrec, skip)
     if (dim == 2 && curve == 0) PSI_BL(2, 0);
     if (dim == 2 && curve == 1) PSI_BL(2, 1);
     if (dim == 3 && curve == 0) PSI_BL(3, 0);
@@ -300,19 +313,23 @@ void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk,
 #undef PSI_BL
 }
 
-void launch_pack_boxes(hipStream_t st, int dim, const NodeRec* rec, uint64_t n, uint4* out) {
-    if (!n) return;
-    if (dim == 2) hipLaunchKernelGGL(k_pack_boxes<2>, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, n, out);
-    else hipLaunchKernelGGL(k_pack_boxes<3>, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, n, out);
+void launch_pack_tree(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, bool leaves,
+                      const NodeRec* inner, uint4* out, uint64_t cap) {
+    if (!cap) return;
+    unsigned g = blocks_for(cap, 256);
+    if (g > 4096) g = 4096;
+    if (dim == 2) hipLaunchKernelGGL(k_pack_tree<2>, dim3(g), dim3(256), 0, st, dt, leaves, inner, out, dirs);
+    else hipLaunchKernelGGL(k_pack_tree<3>, dim3(g), dim3(256), 0, st, dt, leaves, inner, out, dirs);
 }
 
-void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
-                       uint64_t n_parent, uint32_t B, uint4* cchild, uint4* cparent) {
-    if (n_parent == 0) return;
+void launch_node_level(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint32_t u,
+                       uint64_t n_parent_cap, NodeRec* inner, uint32_t B) {
+    if (n_parent_cap == 0) return;
     uint32_t G = 2;
     while (G < B) G <<= 1;
-    const unsigned g = blocks_for(n_parent * G, 256);
-#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, child, n_child, parent, n_parent, B, cchild, cparent)
+    unsigned g = blocks_for(n_parent_cap * G, 256);
+    if (g > 4096) g = 4096;
+#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, dt, u, inner, B, dirs)
 #define PSI_NL2(GG)              \
     do {                         \
         if (dim == 2) PSI_NL(2, GG); \

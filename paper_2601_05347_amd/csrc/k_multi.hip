@@ -52,11 +52,16 @@ __global__ __launch_bounds__(256) void k_encode_hist_seg(const uint32_t* __restr
     }
 }
 
+// Segments blockIdx.x, + gridDim.x, ... below num (or *num_dev).
 __global__ __launch_bounds__(256) void k_seg_digit_offsets(const uint32_t* __restrict__ hist,
                                                            const uint64_t* __restrict__ seg_begin,
-                                                           uint32_t* __restrict__ off) {
+                                                           uint32_t* __restrict__ off, uint32_t num,
+                                                           const uint32_t* __restrict__ num_dev) {
     __shared__ uint32_t s_w[4];
-    const uint32_t s = blockIdx.x, p = blockIdx.y;
+    const uint32_t ns = num_dev ? *num_dev : num;
+    const uint32_t p = blockIdx.y;
+    for (uint32_t s = blockIdx.x; s < ns; s += gridDim.x) {
+    __syncthreads();
     const uint64_t base = ((uint64_t)s * 8 + p) * RADIX;
     const uint32_t v = hist[base + threadIdx.x];
     const uint32_t lane = lane_id();
@@ -70,6 +75,7 @@ __global__ __launch_bounds__(256) void k_seg_digit_offsets(const uint32_t* __res
     uint32_t add = 0;
     for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) add += s_w[w];
     off[base + threadIdx.x] = (uint32_t)seg_begin[s] + add + x - v;
+    }
 }
 
 template <int D, int CURVE>
@@ -183,8 +189,11 @@ void launch_encode_hist_seg(hipStream_t st, int dim, int curve, const uint32_t* 
 }
 
 void launch_seg_digit_offsets(hipStream_t st, uint32_t num, const uint32_t* hist, const uint64_t* seg_begin,
-                              uint32_t* off) {
-    if (num) hipLaunchKernelGGL(k_seg_digit_offsets, dim3(num, 8), dim3(256), 0, st, hist, seg_begin, off);
+                              uint32_t* off, const uint32_t* num_dev) {
+    if (num) {
+        const unsigned g = num > 1024 ? 1024u : num;
+        hipLaunchKernelGGL(k_seg_digit_offsets, dim3(g, 8), dim3(256), 0, st, hist, seg_begin, off, num, num_dev);
+    }
 }
 
 void launch_build_leaves_seg(hipStream_t st, int dim, int curve, uint32_t num, uint64_t total_leaves,

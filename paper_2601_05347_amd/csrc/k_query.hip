@@ -39,11 +39,12 @@ __device__ __forceinline__ NodeRec fetch(const TreeView& t, const LevelInfo* lv,
 
 // ------------------------------------------------------- kNN, lane per query
 template <int D, int K>
-__global__ __launch_bounds__(256) void k_knn_lane(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
+__global__ __launch_bounds__(256) void k_knn_lane(TreeView tv, const uint32_t* __restrict__ qp, uint64_t nq,
                                                   const uint32_t* __restrict__ order,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
-    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    const TreeView t = resolve_tree(tv);
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tq >= nq) return;
@@ -272,12 +273,13 @@ struct SingleTree {
 };
 
 template <int D, int K>
-__global__ __launch_bounds__(256) void k_knn_seed(TreeView t, const uint32_t* __restrict__ qp,
+__global__ __launch_bounds__(256) void k_knn_seed(TreeView tv, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
                                                   const uint32_t* __restrict__ order,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
-    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    const TreeView t = resolve_tree(tv);
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tq >= nq) return;
@@ -404,7 +406,7 @@ __device__ __forceinline__ bool wave_argmin(bool on, uint64_t d, uint64_t& best_
 }
 
 template <int D, int KMAX>
-__global__ __launch_bounds__(256) void k_knn_wave(TreeView t, const uint32_t* __restrict__ qp, uint64_t nq,
+__global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* __restrict__ qp, uint64_t nq,
                                                   const uint32_t* __restrict__ order, uint32_t k,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
@@ -412,7 +414,8 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView t, const uint32_t* __
     __shared__ uint32_t s_i[KW_WAVES][2][KMAX];
     __shared__ uint64_t s_cd[KW_WAVES][64];
     __shared__ uint32_t s_ci[KW_WAVES][64];
-    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    const TreeView t = resolve_tree(tv);
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
@@ -572,11 +575,12 @@ __device__ __forceinline__ bool in_box(const uint32_t* p, const uint32_t* lo, co
 
 // REPORT = false: count; REPORT = true: write ids to out[0 .. lim).
 template <int D, bool REPORT>
-__global__ __launch_bounds__(256) void k_range(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
+__global__ __launch_bounds__(256) void k_range(TreeView tv, const uint32_t* __restrict__ boxes, uint64_t nb,
                                                uint64_t* __restrict__ counts, const uint64_t* __restrict__ offsets,
                                                uint32_t* __restrict__ out_ids) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
-    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    const TreeView t = resolve_tree(tv);
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
@@ -706,7 +710,7 @@ __device__ __forceinline__ void copy_leaf_ids(const TreeView& t, uint64_t m, uin
 }
 
 template <int D, bool REPORT>
-__global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* __restrict__ boxes, uint64_t nb,
+__global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t* __restrict__ boxes, uint64_t nb,
                                                     const uint32_t* __restrict__ order,
                                                     uint64_t* __restrict__ counts,
                                                     const uint64_t* __restrict__ offsets,
@@ -714,7 +718,8 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView t, const uint32_t* 
     __shared__ LevelInfo s_lv[MAX_LEVELS];
     __shared__ uint64_t s_mask[RW_WAVES][MAX_LEVELS];
     __shared__ uint64_t s_base[RW_WAVES][MAX_LEVELS];
-    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = t.lv[threadIdx.x];
+    const TreeView t = resolve_tree(tv);
+    if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = lane_id();

@@ -178,12 +178,19 @@ __global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restric
 // a look-back that stops at the chunk's first tile. Consecutive tiles then
 // write their digit runs through the same L2, which merges the partial lines.
 // Correctness does not depend on the placement.
-template <bool IMPLICIT_ID, bool DIGIT_ID, bool SEG, bool XCD = false>
+// LOOP: a workgroup keeps taking tiles (of its chunk, for an XCD pass; below
+// *ntiles_dev for a segmented pass) until none is left, so the grid need not
+// match the data-dependent tile count; a tile is always processed by the
+// workgroup that took it, so every look-back ends. Otherwise a workgroup
+// takes one tile (an XCD workgroup finding its chunk exhausted exits).
+// shift_dev (may be null): the digit's bit position is shift + *shift_dev.
+template <bool IMPLICIT_ID, bool DIGIT_ID, bool SEG, bool XCD = false, bool LOOP = false>
 __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin, uint32_t id_base,
-    uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n, uint32_t shift,
-    const uint32_t* __restrict__ dig_off, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
-    uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg, XcdChunks xc) {
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n, uint32_t shift_arg,
+    const uint32_t* __restrict__ dig_off_arg, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
+    uint32_t epoch, uint32_t* __restrict__ err, SegTiles sg, XcdChunks xc, const uint32_t* __restrict__ shift_dev,
+    const uint32_t* __restrict__ ntiles_dev) {
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_id[SORT_TILE];
     // running counts per wave, then each wave's first LDS slot per digit; once
@@ -196,6 +203,15 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const uint32_t lane = lane_id();
+    constexpr bool loop = LOOP;
+    if (LOOP && SEG && *ntiles_dev == 0) return;  // no tile at all (the usual case of the big-bucket passes)
+    const uint32_t shift = shift_arg + (shift_dev ? *shift_dev : 0u);
+    for (bool first_round = true;; first_round = false) {
+    if (!first_round) {
+        if (!loop) break;
+        __syncthreads();  // the previous tile's LDS readers are done
+    }
+    const uint32_t* dig_off = dig_off_arg;
     for (int i = tid; i < WAVES * RADIX; i += SORT_WG) (&s_wcnt[0][0])[i] = 0;
     if (tid == 0) {
         if (XCD) {
@@ -203,14 +219,17 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
             const uint32_t t = atomicAdd(tile_ctr + x, 1u);
             s_nth = t;
             s_tile = t < xc.ntiles[x] ? xc.first_tile[x] + t : ~0u;
+        } else if (loop) {
+            const uint32_t t = atomicAdd(tile_ctr, 1u);
+            s_tile = t < *ntiles_dev ? t : ~0u;
         } else {
             s_tile = atomicAdd(tile_ctr, 1u);
         }
     }
     __syncthreads();
     const uint32_t tile = s_tile;
-    if (XCD) {
-        if (tile == ~0u) return;  // every tile of this chunk is taken
+    if (XCD || loop) {
+        if (tile == ~0u) break;  // every tile (of the chunk) is taken
     } else if (tile >= gridDim.x) {  // counter not reset: never index past the status array
         if (tid == 0) atomicOr(err, ERR_SPIN);
         return;
@@ -334,6 +353,7 @@ __global__ __launch_bounds__(SORT_WG) void k_onesweep(
         } else {
             atomicOr(err, ERR_CAPACITY);
         }
+    }
     }
 }
 
@@ -592,14 +612,25 @@ void launch_digit_offsets(hipStream_t st, int npass, const uint32_t* hist, uint3
 void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
                      const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
                      uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
-                     uint32_t epoch, uint32_t* err, const SegTiles* seg, uint64_t seg_tiles) {
+                     uint32_t epoch, uint32_t* err, const SegTiles* seg, uint64_t seg_tiles,
+                     const uint32_t* ntiles_dev) {
     if (n == 0) return;
     SegTiles sg{};
     if (seg) sg = *seg;
     const unsigned g = seg ? (unsigned)seg_tiles : blocks_for(n, SORT_TILE);
     if (g == 0) return;
-#define PSI_OS(I, Dg, S) hipLaunchKernelGGL((k_onesweep<I, Dg, S>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg, XcdChunks{})
-    if (seg) {
+    const uint32_t* nt = seg ? ntiles_dev : nullptr;
+#define PSI_OS(I, Dg, S) hipLaunchKernelGGL((k_onesweep<I, Dg, S>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg, XcdChunks{}, (const uint32_t*)nullptr, nt)
+    if (seg && nt) {
+        if (implicit_ids)
+            hipLaunchKernelGGL((k_onesweep<true, false, true, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin,
+                               id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg, XcdChunks{},
+                               (const uint32_t*)nullptr, nt);
+        else
+            hipLaunchKernelGGL((k_onesweep<false, false, true, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin,
+                               id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, sg, XcdChunks{},
+                               (const uint32_t*)nullptr, nt);
+    } else if (seg) {
         if (implicit_ids) PSI_OS(true, false, true);
         else PSI_OS(false, false, true);
     } else if (implicit_ids && !digit_from_id) PSI_OS(true, false, false);
@@ -612,15 +643,30 @@ void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, cons
 void launch_onesweep_xcd(hipStream_t st, bool implicit_ids, const uint64_t* kin, const uint32_t* iin,
                          uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n, uint32_t shift,
                          const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, uint32_t* err,
-                         const XcdChunks& xc, uint32_t max_chunk_tiles) {
-    if (n == 0 || max_chunk_tiles == 0) return;
-    const unsigned g = XCD_CHUNKS * max_chunk_tiles;
-    if (implicit_ids)
+                         const XcdChunks& xc, uint32_t wg_per_chunk, const uint32_t* shift_dev, bool overflow) {
+    if (n == 0 || wg_per_chunk == 0) return;
+    // one tile per workgroup; then, for chunks holding more tiles than
+    // wg_per_chunk, a small launch whose workgroups take the rest (it finds
+    // nothing to do when the chunks are balanced)
+    const unsigned g = XCD_CHUNKS * wg_per_chunk;
+    const unsigned g2 = XCD_CHUNKS * 32;
+    if (implicit_ids) {
         hipLaunchKernelGGL((k_onesweep<true, false, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base,
-                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc);
-    else
+                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc, shift_dev,
+                           (const uint32_t*)nullptr);
+        if (overflow)
+            hipLaunchKernelGGL((k_onesweep<true, false, false, true, true>), dim3(g2), dim3(SORT_WG), 0, st, kin, iin,
+                               id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc,
+                               shift_dev, (const uint32_t*)nullptr);
+    } else {
         hipLaunchKernelGGL((k_onesweep<false, false, false, true>), dim3(g), dim3(SORT_WG), 0, st, kin, iin, id_base,
-                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc);
+                           kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc, shift_dev,
+                           (const uint32_t*)nullptr);
+        if (overflow)
+            hipLaunchKernelGGL((k_onesweep<false, false, false, true, true>), dim3(g2), dim3(SORT_WG), 0, st, kin, iin,
+                               id_base, kout, iout, n, shift, dig_off, status, tile_ctr, epoch, err, SegTiles{}, xc,
+                               shift_dev, (const uint32_t*)nullptr);
+    }
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {

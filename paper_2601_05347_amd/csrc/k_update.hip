@@ -18,7 +18,14 @@
 //   ctr[0] valid batch entries, [1] runs, [2] new leaf count, [3] slots to
 //   allocate, [4] output chunks, [5] slots freed, [6] groups, [7] 1 + index
 //   of the last full-enough leaf, [8] nonzero if a delete left a leaf below
-//   the minimum (only then do leaves regroup).
+//   the minimum (only then do leaves regroup), [9] range error of the
+//   inserted batch, [10] outcome of the plan check (0 apply, 1 rejected,
+//   2 the index was empty: the batch is built as a fresh tree), and the
+//   64-bit word at [12] is nonzero unless that fresh build runs.
+// Every size an update depends on (leaf count, slots, the free stack, the
+// current directory buffer) is read from the index's device state (DevTree)
+// and from these counters: the host sizes grids and buffers by upper bounds
+// only, and the last kernel of the update commits the new state.
 #include "psi_hilbert.h"
 #include "psi_kern.h"
 #include "psi_update.h"
@@ -41,11 +48,15 @@ __device__ __forceinline__ uint32_t find_owner(const uint32_t* off, uint32_t R, 
 }
 
 __global__ void k_route(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi, uint64_t n,
-                        const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ pk,
-                        const uint32_t* __restrict__ pi, uint64_t L, uint32_t* __restrict__ leaf_of) {
+                        const uint32_t* __restrict__ n_dev, const DevTree* __restrict__ dt,
+                        uint32_t* __restrict__ leaf_of, Dirs dirs) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t ne = n_dev ? *n_dev : n;
     if (e >= ne) return;
+    const uint32_t c = dt->cur;
+    const uint64_t* pk = dirs.pkey[c];
+    const uint32_t* pi = dirs.pid[c];
+    const uint64_t L = dt->L;
     const uint64_t k = bk[e];
     const uint32_t i = bi[e];
     uint64_t lo = 0, hi = L;  // first pivot greater than (k, i)
@@ -78,13 +89,17 @@ __device__ __forceinline__ uint32_t run_end(const uint32_t* run_beg, uint32_t r,
     return r + 1 < R ? run_beg[r + 1] : n;
 }
 
+// A run fits its leaf while the leaf stays within 2 phi entries (the slot
+// capacity C is 2 phi rounded up to a multiple of four: only a stride).
 __global__ void k_ins_plan(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
-                           const uint32_t* __restrict__ ctr, uint64_t m, const NodeRec* __restrict__ leaf,
-                           uint32_t C, uint32_t phi, uint32_t* __restrict__ rpieces,
-                           uint32_t* __restrict__ rchunks, uint32_t* __restrict__ rsplit) {
+                           const uint32_t* __restrict__ ctr, uint64_t m, const DevTree* __restrict__ dt,
+                           uint32_t phi, uint32_t* __restrict__ rpieces,
+                           uint32_t* __restrict__ rchunks, uint32_t* __restrict__ rsplit, Dirs dirs) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
-    const uint32_t R = ctr[1];
+    const NodeRec* leaf = dirs.leaf[dt->cur];
+    const uint32_t C = 2 * phi;
+    const uint32_t R = dt->L ? ctr[1] : 0u;  // an empty index takes the batch as a fresh build
     if (r >= R) {
         rpieces[r] = rchunks[r] = rsplit[r] = 0u;
         return;
@@ -112,48 +127,65 @@ __global__ void k_ins_pieces(const uint32_t* __restrict__ run_leaf, const uint32
     pieces[run_leaf[r]] = rpieces[r];
 }
 
-__global__ void k_alloc(uint32_t* __restrict__ slot_alloc, uint64_t A, const uint32_t* __restrict__ free_stack,
-                        uint64_t n_free, uint64_t slot_top, Caps cap) {
-    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= A) return;
-    const uint64_t v = a < n_free ? free_stack[n_free - 1 - a] : slot_top + (a - n_free);
-    if (v >= cap.slots) {
-        atomicOr(cap.err, ERR_CAPACITY);
-        slot_alloc[a] = 0;  // never used: the update is reported as failed
-        return;
+// Slots for the A = ctr[3] new leaves: the top of the free stack first, then
+// fresh ones past the bump pointer (both read from the device state).
+__global__ void k_alloc(uint32_t* __restrict__ slot_alloc, const uint32_t* __restrict__ ctr,
+                        const uint32_t* __restrict__ free_stack, const DevTree* __restrict__ dt, Caps cap) {
+    const uint64_t A = ctr[3], n_free = dt->n_free, slot_top = dt->slot_top;
+    for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = a < n_free ? free_stack[n_free - 1 - a] : slot_top + (a - n_free);
+        if (v >= cap.slots) {
+            atomicOr(cap.err, ERR_CAPACITY);
+            slot_alloc[a] = 0;  // never used: the plan check rejects such an update first
+            continue;
+        }
+        slot_alloc[a] = (uint32_t)v;
     }
-    slot_alloc[a] = (uint32_t)v;
 }
 
-__global__ void k_dir_copy(const NodeRec* __restrict__ src, const uint64_t* __restrict__ spk,
-                           const uint32_t* __restrict__ spi, const uint32_t* __restrict__ pieces,
-                           const uint32_t* __restrict__ newpos, uint64_t L, NodeRec* __restrict__ dst,
-                           uint64_t* __restrict__ dpk, uint32_t* __restrict__ dpi, Caps cap) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L || pieces[j] != 1u) return;
+// Untouched leaves move to the other directory buffer when the insert re-cuts
+// leaves (ctr[3] > 0); otherwise the directory is updated in place.
+__global__ void k_dir_copy(const DevTree* __restrict__ dt, const uint32_t* __restrict__ ctr,
+                           const uint32_t* __restrict__ pieces, const uint32_t* __restrict__ newpos, Caps cap) {
+    if (ctr[3] == 0) return;  // nothing re-cut: the directory is updated in place
+    const uint64_t L = dt->L;
+    const uint32_t c = dt->cur;
+    const NodeRec* src = cap.dirs.leaf[c];
+    const uint64_t* spk = cap.dirs.pkey[c];
+    const uint32_t* spi = cap.dirs.pid[c];
+    NodeRec* dst = cap.dirs.leaf[1 - c];
+    uint64_t* dpk = cap.dirs.pkey[1 - c];
+    uint32_t* dpi = cap.dirs.pid[1 - c];
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < L; j += (uint64_t)gridDim.x * blockDim.x) {
+    if (pieces[j] != 1u) continue;
     const uint32_t q = newpos[j];
     if (q >= cap.leaves) {
         atomicOr(cap.err, ERR_CAPACITY);
-        return;
+        continue;
     }
     dst[q] = src[j];
     dpk[q] = spk[j];
     dpi[q] = spi[j];
+    }
 }
 
 template <int D, int CURVE>
 __global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi,
                              const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
                              const uint32_t* __restrict__ ctr, uint64_t m, const uint32_t* __restrict__ rsplit,
-                             const uint32_t* __restrict__ newpos, NodeRec* __restrict__ dleaf,
-                             uint64_t* __restrict__ dpk, uint32_t* __restrict__ dpi, uint32_t* __restrict__ slots,
-                             uint32_t C, uint32_t* __restrict__ err, Caps cap) {
+                             const uint32_t* __restrict__ newpos, const DevTree* __restrict__ dt,
+                             uint32_t* __restrict__ slots, uint32_t C, uint32_t* __restrict__ err, Caps cap) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t R = ctr[1];
     if (r >= R || rsplit[r]) return;
+    const bool recut = ctr[3] != 0;
+    const uint32_t dc = recut ? 1 - dt->cur : dt->cur;
+    NodeRec* dleaf = cap.dirs.leaf[dc];
+    uint64_t* dpk = cap.dirs.pkey[dc];
+    uint32_t* dpi = cap.dirs.pid[dc];
     const uint32_t j = run_leaf[r];
     const uint32_t beg = run_beg[r], end = run_end(run_beg, (uint32_t)r, R, (uint32_t)m);
-    const uint32_t q = newpos ? newpos[j] : j;  // no re-cut leaves: the directory keeps its order
+    const uint32_t q = recut ? newpos[j] : j;  // no re-cut leaves: the directory keeps its order
     if (q >= cap.leaves) {
         atomicOr(err, ERR_CAPACITY);
         return;
@@ -185,9 +217,11 @@ __global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __
 }
 
 // Merge of a leaf (sorted in LDS) with its sorted run, cut into P balanced
-// pieces written to fresh slots. One block handles UPD_CHUNK outputs.
+// pieces written to fresh slots. A block handles output chunk c (UPD_CHUNK
+// outputs); the LDS arrays belong to the caller's loop over chunks.
 template <int D, int CURVE>
-__global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
+__device__ __forceinline__ void ins_split_chunk(
+    uint32_t c, uint64_t* s_uk, uint64_t* s_ak, uint32_t* s_ui, uint32_t* s_ai, uint32_t (*s_ap)[64],
     const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi, const uint32_t* __restrict__ run_leaf,
     const uint32_t* __restrict__ run_beg, const uint32_t* __restrict__ ctr, uint64_t m,
     const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ piece_off,
@@ -195,11 +229,7 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
     const NodeRec* __restrict__ sleaf, NodeRec* __restrict__ dleaf, uint64_t* __restrict__ dpk,
     uint32_t* __restrict__ dpi, uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C,
     uint32_t phi, Caps cap) {
-    __shared__ uint64_t s_uk[64], s_ak[64];
-    __shared__ uint32_t s_ui[64], s_ai[64];
-    __shared__ uint32_t s_ap[D][64];
     const uint32_t R = ctr[1];
-    const uint32_t c = blockIdx.x;
     const uint32_t r = find_owner(chunk_off, R, c);
     const uint32_t j = run_leaf[r];
     const uint32_t beg = run_beg[r], end = run_end(run_beg, r, R, (uint32_t)m);
@@ -293,18 +323,43 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
     }
 }
 
+// Persistent over the output chunks of the re-cut leaves (ctr[4] of them):
+// the grid is sized by an upper bound, the count is read on the device.
+template <int D, int CURVE>
+__global__ __launch_bounds__(UPD_CHUNK) void k_ins_split(
+    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi, const uint32_t* __restrict__ run_leaf,
+    const uint32_t* __restrict__ run_beg, const uint32_t* __restrict__ ctr, uint64_t m,
+    const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ piece_off,
+    const uint32_t* __restrict__ newpos, const uint32_t* __restrict__ slot_alloc, const DevTree* __restrict__ dt,
+    uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C, uint32_t phi, Caps cap) {
+    __shared__ uint64_t s_uk[64], s_ak[64];
+    __shared__ uint32_t s_ui[64], s_ai[64];
+    __shared__ uint32_t s_ap[D][64];
+    const uint32_t nch = ctr[4];
+    const uint32_t c0 = dt->cur;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        __syncthreads();  // the previous chunk's LDS readers are done
+        ins_split_chunk<D, CURVE>(c, s_uk, s_ak, s_ui, s_ai, s_ap, bk, bi, run_leaf, run_beg, ctr, m, chunk_off,
+                                  piece_off, newpos, slot_alloc, cap.dirs.leaf[c0], cap.dirs.leaf[1 - c0], cap.dirs.pkey[1 - c0],
+                                  cap.dirs.pid[1 - c0], piece_pos, slots, C, phi, cap);
+    }
+}
+
 // Exact boxes of freshly cut pieces (half-wave per piece; pieces hold <= 32).
+// Pieces are written to the directory buffer that is not current yet.
 template <int D>
-__global__ __launch_bounds__(256) void k_piece_meta(const uint32_t* __restrict__ piece_pos, uint64_t A,
-                                                    NodeRec* __restrict__ leaf, const uint32_t* __restrict__ slots,
-                                                    uint32_t C, Caps cap) {
-    const uint64_t a = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+__global__ __launch_bounds__(256) void k_piece_meta(const uint32_t* __restrict__ piece_pos,
+                                                    const uint32_t* __restrict__ ctr, const DevTree* __restrict__ dt,
+                                                    const uint32_t* __restrict__ slots, uint32_t C, Caps cap) {
+    const uint64_t A = ctr[3];
+    NodeRec* leaf = cap.dirs.leaf[1 - dt->cur];
     const uint32_t t = threadIdx.x & 31;
-    if (a >= A) return;
+    const uint64_t step = ((uint64_t)gridDim.x * blockDim.x) >> 5;
+    for (uint64_t a = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; a < A; a += step) {
     const uint32_t q = piece_pos[a];
-    if (q >= cap.leaves) return;
+    if (q >= cap.leaves) continue;
     NodeRec rec = leaf[q];
-    if (rec.slot >= cap.slots || rec.cnt > C) return;
+    if (rec.slot >= cap.slots || rec.cnt > C) continue;
     const uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -326,13 +381,19 @@ __global__ __launch_bounds__(256) void k_piece_meta(const uint32_t* __restrict__
         rec.hi[2] = 0;
     }
     if (t == 0) leaf[q] = rec;
+    }
 }
 
+// The slots of the re-cut leaves go on the free stack above what this
+// update took from it.
 __global__ void k_ins_free(const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ ctr, uint64_t m,
                            const uint32_t* __restrict__ rsplit, const uint32_t* __restrict__ free_off,
-                           const NodeRec* __restrict__ sleaf, uint32_t* __restrict__ free_stack, uint64_t base, Caps cap) {
+                           const DevTree* __restrict__ dt, uint32_t* __restrict__ free_stack, Caps cap) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ctr[1] || !rsplit[r]) return;
+    const NodeRec* sleaf = cap.dirs.leaf[dt->cur];
+    const uint64_t n_free = dt->n_free, A = ctr[3];
+    const uint64_t base = n_free - (A < n_free ? A : n_free);
     const uint64_t x = base + free_off[r];
     if (x >= cap.frees) {
         atomicOr(cap.err, ERR_CAPACITY);
@@ -343,9 +404,10 @@ __global__ void k_ins_free(const uint32_t* __restrict__ run_leaf, const uint32_t
 
 // ------------------------------------------------------------------ delete
 __global__ void k_del_gather(const uint32_t* __restrict__ ids, uint64_t m, const uint64_t* __restrict__ idkey,
-                             uint32_t next_id, uint64_t* __restrict__ dk, uint32_t* __restrict__ di) {
+                             const DevTree* __restrict__ dt, uint64_t* __restrict__ dk, uint32_t* __restrict__ di) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
+    const uint32_t next_id = dt->next_id;
     const uint32_t id = ids[e];
     const uint64_t key = id < next_id ? idkey[id] : DEAD_KEY;
     dk[e] = key;
@@ -405,10 +467,11 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ run_leaf,
                                                     const uint32_t* __restrict__ run_beg,
                                                     const uint32_t* __restrict__ ctr, uint64_t m,
-                                                    NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
+                                                    const DevTree* __restrict__ dt, uint32_t* __restrict__ slots,
                                                     uint32_t C, uint32_t half, uint32_t* __restrict__ under,
                                                     uint32_t* __restrict__ err, Caps cap) {
     __shared__ uint32_t s_under;
+    NodeRec* leaf = cap.dirs.leaf[dt->cur];
     if (threadIdx.x == 0) s_under = 0;
     const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / DEL_G;
     const uint32_t lane = lane_id();
@@ -508,17 +571,23 @@ __global__ __launch_bounds__(256) void k_del_remove(const uint32_t* __restrict__
 
 // Per-leaf counts, and per workgroup 1 + its last leaf holding at least
 // `half` entries (0 if none) in bmax[blockIdx.x].
-__global__ __launch_bounds__(256) void k_del_counts(const NodeRec* __restrict__ leaf, uint64_t L, uint32_t half,
+// The arrays span an upper bound Lb of the leaf count: entries past the
+// device's L are zero, so the scans over Lb entries see only real leaves.
+__global__ __launch_bounds__(256) void k_del_counts(const DevTree* __restrict__ dt, uint64_t Lb, uint32_t half,
                                                     const uint32_t* __restrict__ ctr, uint32_t* __restrict__ cnt,
-                                                    uint32_t* __restrict__ bmax) {
+                                                    uint32_t* __restrict__ bmax, Dirs dirs) {
     __shared__ uint32_t s_w[4];
     if (ctr[8] == 0) return;  // no leaf below the minimum: no regrouping
+    const uint64_t L = dt->L;
+    const NodeRec* leaf = dirs.leaf[dt->cur];
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t last = 0;
     if (j < L) {
         const uint32_t c = leaf[j].cnt;
         cnt[j] = c;
         if (c >= half) last = (uint32_t)(j + 1);
+    } else if (j < Lb) {
+        cnt[j] = 0;
     }
     last = wave_max_u32(last);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = last;
@@ -539,27 +608,32 @@ __global__ __launch_bounds__(256) void k_del_last_full(const uint32_t* __restric
     if (threadIdx.x == 0) ctr[7] = max(max(s_w[0], s_w[1]), max(s_w[2], s_w[3]));
 }
 
-__global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t L, uint32_t half,
-                             const uint32_t* __restrict__ ctr, uint32_t* __restrict__ start) {
+__global__ void k_del_starts(const uint32_t* __restrict__ cnt, uint64_t Lb, uint32_t half,
+                             const uint32_t* __restrict__ ctr, const DevTree* __restrict__ dt,
+                             uint32_t* __restrict__ start) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L || ctr[8] == 0) return;
-    start[j] = (j == 0 || (cnt[j - 1] >= half && j < ctr[7])) ? 1u : 0u;
+    if (j >= Lb || ctr[8] == 0) return;
+    start[j] = j < dt->L && (j == 0 || (cnt[j - 1] >= half && j < ctr[7])) ? 1u : 0u;
 }
 
-__global__ void k_del_groups(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx, uint64_t L,
-                             const uint32_t* __restrict__ ctr, uint32_t* __restrict__ grp_first) {
+__global__ void k_del_groups(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx,
+                             const DevTree* __restrict__ dt, const uint32_t* __restrict__ ctr,
+                             uint32_t* __restrict__ grp_first) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (ctr[8] == 0) return;
+    const uint64_t L = dt->L;
     if (j < L && start[j]) grp_first[gidx[j]] = (uint32_t)j;
 }
 
-__global__ void k_del_gplan(const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr, uint64_t L,
-                            const uint32_t* __restrict__ cum, uint32_t phi, uint32_t* __restrict__ gpieces,
-                            uint32_t* __restrict__ gchunks, uint32_t* __restrict__ galloc,
-                            uint32_t* __restrict__ gfree, uint32_t* __restrict__ gchanged) {
+__global__ void k_del_gplan(const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr, uint64_t Lb,
+                            const DevTree* __restrict__ dt, const uint32_t* __restrict__ cum, uint32_t phi,
+                            uint32_t* __restrict__ gpieces, uint32_t* __restrict__ gchunks,
+                            uint32_t* __restrict__ galloc, uint32_t* __restrict__ gfree,
+                            uint32_t* __restrict__ gchanged) {
     if (ctr[8] == 0) return;
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= L) return;
+    if (g >= Lb) return;
+    const uint64_t L = dt->L;
     const uint32_t G = ctr[6];
     if (g >= G) {
         gpieces[g] = gchunks[g] = galloc[g] = gfree[g] = gchanged[g] = 0u;
@@ -579,11 +653,16 @@ __global__ void k_del_gplan(const uint32_t* __restrict__ grp_first, const uint32
 
 __global__ void k_del_gcopy(const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr,
                             const uint32_t* __restrict__ gchanged, const uint32_t* __restrict__ gpos,
-                            const NodeRec* __restrict__ src, const uint64_t* __restrict__ spk,
-                            const uint32_t* __restrict__ spi, NodeRec* __restrict__ dst, uint64_t* __restrict__ dpk,
-                            uint32_t* __restrict__ dpi, Caps cap) {
+                            const DevTree* __restrict__ dt, Caps cap) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ctr[6] || gchanged[g]) return;
+    if (g >= ctr[6] || gchanged[g] || ctr[5] == 0) return;
+    const uint32_t c = dt->cur;
+    const NodeRec* src = cap.dirs.leaf[c];
+    const uint64_t* spk = cap.dirs.pkey[c];
+    const uint32_t* spi = cap.dirs.pid[c];
+    NodeRec* dst = cap.dirs.leaf[1 - c];
+    uint64_t* dpk = cap.dirs.pkey[1 - c];
+    uint32_t* dpi = cap.dirs.pid[1 - c];
     const uint32_t j = grp_first[g], q = gpos[g];
     if (q >= cap.leaves) {
         atomicOr(cap.err, ERR_CAPACITY);
@@ -598,16 +677,20 @@ __global__ void k_del_gcopy(const uint32_t* __restrict__ grp_first, const uint32
 template <int D, int CURVE>
 __global__ __launch_bounds__(256) void k_sort_leaves(const uint32_t* __restrict__ start,
                                                      const uint32_t* __restrict__ gidx,
-                                                     const uint32_t* __restrict__ gchanged, uint64_t L,
-                                                     const NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
-                                                     uint32_t C) {
-    const uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+                                                     const uint32_t* __restrict__ gchanged,
+                                                     const uint32_t* __restrict__ ctr,
+                                                     const DevTree* __restrict__ dt, uint32_t* __restrict__ slots,
+                                                     uint32_t C, Dirs dirs) {
     const uint32_t lane = lane_id();
-    if (j >= L) return;
+    if (ctr[5] == 0) return;  // no regrouping
+    const uint64_t L = dt->L;
+    const NodeRec* leaf = dirs.leaf[dt->cur];
+    const uint64_t step = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; j < L; j += step) {
     const uint32_t g = gidx[j] + start[j] - 1u;
-    if (!gchanged[g]) return;
+    if (!gchanged[g]) continue;  // uniform over the wave
     const NodeRec rec = leaf[j];
-    if (rec.cnt <= 1 || rec.cnt > 64 || rec.cnt > C) return;
+    if (rec.cnt <= 1 || rec.cnt > 64 || rec.cnt > C) continue;
     uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
     const bool on = lane < rec.cnt;
     uint32_t p[D];
@@ -630,6 +713,7 @@ __global__ __launch_bounds__(256) void k_sort_leaves(const uint32_t* __restrict_
         for (int d = 0; d < D; ++d) s[d * C + rank] = p[d];
         s[D * C + rank] = id;
     }
+    }
 }
 
 // After appends, with leaves kept in total order: one wave per run whose
@@ -640,13 +724,15 @@ __global__ __launch_bounds__(256) void k_sort_appended(const uint32_t* __restric
                                                        const uint32_t* __restrict__ ctr, uint64_t m,
                                                        const uint32_t* __restrict__ rsplit,
                                                        const uint32_t* __restrict__ newpos,
-                                                       const NodeRec* __restrict__ leaf, uint32_t* __restrict__ slots,
+                                                       const DevTree* __restrict__ dt, uint32_t* __restrict__ slots,
                                                        uint32_t C, Caps cap) {
     const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t lane = lane_id();
     if (r >= m || r >= ctr[1] || rsplit[r]) return;  // uniform over the wave
+    const bool recut = ctr[3] != 0;
+    const NodeRec* leaf = cap.dirs.leaf[recut ? 1 - dt->cur : dt->cur];
     const uint32_t j = run_leaf[r];
-    const uint32_t q = newpos ? newpos[j] : j;
+    const uint32_t q = recut ? newpos[j] : j;
     if (q >= cap.leaves) return;
     const NodeRec rec = leaf[q];
     if (rec.cnt <= 1 || rec.cnt > 64 || rec.cnt > C || rec.slot >= cap.slots) return;
@@ -674,24 +760,31 @@ __global__ __launch_bounds__(256) void k_sort_appended(const uint32_t* __restric
     }
 }
 
-// Concatenate the (sorted) leaves of a changed group and cut into P pieces.
+// Concatenate the (sorted) leaves of a changed group and cut into P pieces;
+// persistent over the ctr[4] output chunks.
 template <int D, int CURVE>
 __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
-    const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr, uint64_t L,
+    const uint32_t* __restrict__ grp_first, const uint32_t* __restrict__ ctr,
     const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ alloc_off,
     const uint32_t* __restrict__ gpos, const uint32_t* __restrict__ cum, const uint32_t* __restrict__ slot_alloc,
-    const NodeRec* __restrict__ sleaf, NodeRec* __restrict__ dleaf, uint64_t* __restrict__ dpk,
-    uint32_t* __restrict__ dpi, uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C,
+    const DevTree* __restrict__ dt, uint32_t* __restrict__ piece_pos, uint32_t* __restrict__ slots, uint32_t C,
     uint32_t phi, Caps cap) {
     const uint32_t G = ctr[6];
-    const uint32_t c = blockIdx.x;
+    const uint32_t nch = ctr[4];
+    const uint64_t L = dt->L;
+    const uint32_t c0 = dt->cur;
+    const NodeRec* sleaf = cap.dirs.leaf[c0];
+    NodeRec* dleaf = cap.dirs.leaf[1 - c0];
+    uint64_t* dpk = cap.dirs.pkey[1 - c0];
+    uint32_t* dpi = cap.dirs.pid[1 - c0];
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
     const uint32_t g = find_owner(chunk_off, G, c);
     const uint32_t f = grp_first[g];
     const uint32_t e = g + 1 < G ? grp_first[g + 1] : (uint32_t)L;
     const uint32_t t = cum[e] - cum[f];
     const uint32_t P = (t + phi - 1) / phi;
     const uint64_t k = (uint64_t)(c - chunk_off[g]) * UPD_CHUNK + threadIdx.x;
-    if (k >= t) return;
+    if (k >= t) continue;
     const uint32_t gp = cum[f] + (uint32_t)k;
     uint32_t lo = f, hi = e;  // source leaf: last s in [f, e) with cum[s] <= gp
     while (hi - lo > 1) {
@@ -703,7 +796,7 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
     const uint32_t so = gp - cum[lo];
     if (src.slot >= cap.slots || so >= C) {
         atomicOr(cap.err, ERR_CAPACITY);
-        return;
+        continue;
     }
     const uint32_t* s = slots + (uint64_t)src.slot * (D + 1) * C;
     uint32_t p[D];
@@ -717,12 +810,12 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
     const uint64_t qq = (uint64_t)gpos[g] + pc;
     if (ai >= cap.alloc || qq >= cap.leaves) {
         atomicOr(cap.err, ERR_CAPACITY);
-        return;
+        continue;
     }
     const uint32_t slot = slot_alloc[ai];
     if (slot >= cap.slots || off >= C) {
         atomicOr(cap.err, ERR_CAPACITY);
-        return;
+        continue;
     }
     uint32_t* o = slots + (uint64_t)slot * (D + 1) * C;
 #pragma unroll
@@ -742,14 +835,18 @@ __global__ __launch_bounds__(UPD_CHUNK) void k_del_regroup(
         dleaf[q] = nr;
         piece_pos[ai] = q;
     }
+    }
 }
 
 __global__ void k_del_free(const uint32_t* __restrict__ start, const uint32_t* __restrict__ gidx,
                            const uint32_t* __restrict__ gchanged, const uint32_t* __restrict__ grp_first,
-                           const uint32_t* __restrict__ free_off, uint64_t L, const NodeRec* __restrict__ sleaf,
-                           uint32_t* __restrict__ free_stack, uint64_t base, Caps cap) {
+                           const uint32_t* __restrict__ free_off, const uint32_t* __restrict__ ctr,
+                           const DevTree* __restrict__ dt, uint32_t* __restrict__ free_stack, Caps cap) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L) return;
+    if (j >= dt->L || ctr[5] == 0) return;
+    const NodeRec* sleaf = cap.dirs.leaf[dt->cur];
+    const uint64_t n_free = dt->n_free, A = ctr[3];
+    const uint64_t base = n_free - (A < n_free ? A : n_free);
     const uint32_t g = gidx[j] + start[j] - 1u;
     if (!gchanged[g]) return;
     const uint64_t x = base + free_off[g] + (j - grp_first[g]);
@@ -775,9 +872,15 @@ __global__ void k_del_free(const uint32_t* __restrict__ start, const uint32_t* _
         else hipLaunchKernelGGL((F<3>), __VA_ARGS__);                     \
     } while (0)
 
+// Grid for a grid-stride loop over at most n items.
+inline unsigned stride_blocks(uint64_t n, unsigned per) {
+    const unsigned g = blocks_for(n, per);
+    return g < 1 ? 1u : (g > 8192 ? 8192u : g);
+}
+
 void upd_route(hipStream_t st, const uint64_t* bk, const uint32_t* bi, uint64_t n, const uint32_t* n_dev,
-               const uint64_t* pk, const uint32_t* pi, uint64_t L, uint32_t* leaf_of) {
-    if (n) hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, st, bk, bi, n, n_dev, pk, pi, L, leaf_of);
+               const DevTree* dt, const Dirs& dirs, uint32_t* leaf_of) {
+    if (n) hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, st, bk, bi, n, n_dev, dt, leaf_of, dirs);
 }
 void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_t* n_dev, uint32_t* flag,
               uint32_t* ridx, uint32_t* run_leaf, uint32_t* run_beg, uint32_t* R_dev, uint32_t* tmp) {
@@ -787,53 +890,53 @@ void upd_runs(hipStream_t st, const uint32_t* leaf_of, uint64_t n, const uint32_
     hipLaunchKernelGGL(k_run_write, dim3(blocks_for(n, 256)), dim3(256), 0, st, leaf_of, flag, ridx, n, run_leaf, run_beg);
 }
 void upd_ins_plan(hipStream_t st, const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
-                  const NodeRec* leaf, uint32_t C, uint32_t phi, uint32_t* rpieces, uint32_t* rchunks,
+                  const DevTree* dt, const Dirs& dirs, uint32_t phi, uint32_t* rpieces, uint32_t* rchunks,
                   uint32_t* rsplit) {
-    hipLaunchKernelGGL(k_ins_plan, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, run_beg, ctr, m, leaf, C, phi, rpieces, rchunks, rsplit);
+    hipLaunchKernelGGL(k_ins_plan, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, run_beg, ctr, m, dt, phi, rpieces, rchunks, rsplit, dirs);
 }
 void upd_ins_pieces(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rpieces,
                     const uint32_t* rsplit, uint32_t* pieces) {
     hipLaunchKernelGGL(k_ins_pieces, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rpieces, rsplit, pieces);
 }
-void upd_alloc(hipStream_t st, uint32_t* slot_alloc, uint64_t A, const uint32_t* free_stack, uint64_t n_free,
-               uint64_t slot_top, Caps cap) {
-    if (A) hipLaunchKernelGGL(k_alloc, dim3(blocks_for(A, 256)), dim3(256), 0, st, slot_alloc, A, free_stack, n_free, slot_top, cap);
+void upd_alloc(hipStream_t st, uint32_t* slot_alloc, uint64_t A_max, const uint32_t* ctr, const uint32_t* free_stack,
+               const DevTree* dt, Caps cap) {
+    if (A_max) hipLaunchKernelGGL(k_alloc, dim3(stride_blocks(A_max, 256)), dim3(256), 0, st, slot_alloc, ctr, free_stack, dt, cap);
 }
-void upd_dir_copy(hipStream_t st, const NodeRec* src, const uint64_t* spk, const uint32_t* spi, const uint32_t* pieces,
-                  const uint32_t* newpos, uint64_t L, NodeRec* dst, uint64_t* dpk, uint32_t* dpi, Caps cap) {
-    if (L) hipLaunchKernelGGL(k_dir_copy, dim3(blocks_for(L, 256)), dim3(256), 0, st, src, spk, spi, pieces, newpos, L, dst, dpk, dpi, cap);
+void upd_dir_copy(hipStream_t st, const DevTree* dt, const uint32_t* ctr, const uint32_t* pieces,
+                  const uint32_t* newpos, uint64_t Lb, Caps cap) {
+    if (Lb) hipLaunchKernelGGL(k_dir_copy, dim3(stride_blocks(Lb, 256)), dim3(256), 0, st, dt, ctr, pieces, newpos, cap);
 }
 void upd_ins_append(hipStream_t st, int dim, int curve, const uint64_t* bk, const uint32_t* bi,
                     const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
-                    const uint32_t* rsplit, const uint32_t* newpos, NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi,
-                    uint32_t* slots, uint32_t C, uint32_t* err, Caps cap) {
-    PSI_DC(k_ins_append, dim3(blocks_for(m, 256)), dim3(256), 0, st, bk, bi, run_leaf, run_beg, ctr, m, rsplit, newpos, dleaf, dpk, dpi, slots, C, err, cap);
+                    const uint32_t* rsplit, const uint32_t* newpos, const DevTree* dt, uint32_t* slots, uint32_t C,
+                    uint32_t* err, Caps cap) {
+    PSI_DC(k_ins_append, dim3(blocks_for(m, 256)), dim3(256), 0, st, bk, bi, run_leaf, run_beg, ctr, m, rsplit, newpos, dt, slots, C, err, cap);
 }
 void upd_sort_appended(hipStream_t st, int dim, int curve, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m,
-                       const uint32_t* rsplit, const uint32_t* newpos, const NodeRec* leaf, uint32_t* slots,
+                       const uint32_t* rsplit, const uint32_t* newpos, const DevTree* dt, uint32_t* slots,
                        uint32_t C, Caps cap) {
-    PSI_DC(k_sort_appended, dim3(blocks_for(m, 4)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, newpos, leaf, slots, C, cap);
+    PSI_DC(k_sort_appended, dim3(blocks_for(m, 4)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, newpos, dt, slots, C, cap);
 }
-void upd_ins_split(hipStream_t st, int dim, int curve, uint64_t nchunks, const uint64_t* bk, const uint32_t* bi,
+void upd_ins_split(hipStream_t st, int dim, int curve, uint64_t nch_max, const uint64_t* bk, const uint32_t* bi,
                    const uint32_t* run_leaf, const uint32_t* run_beg, const uint32_t* ctr, uint64_t m,
                    const uint32_t* chunk_off, const uint32_t* piece_off, const uint32_t* newpos,
-                   const uint32_t* slot_alloc, const NodeRec* sleaf, NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi,
-                   uint32_t* piece_pos, uint32_t* slots, uint32_t C, uint32_t phi, Caps cap) {
-    if (nchunks)
-        PSI_DC(k_ins_split, dim3((unsigned)nchunks), dim3(UPD_CHUNK), 0, st, bk, bi, run_leaf, run_beg, ctr, m, chunk_off, piece_off, newpos, slot_alloc, sleaf, dleaf, dpk, dpi, piece_pos, slots, C, phi, cap);
+                   const uint32_t* slot_alloc, const DevTree* dt, uint32_t* piece_pos, uint32_t* slots, uint32_t C,
+                   uint32_t phi, Caps cap) {
+    if (nch_max)
+        PSI_DC(k_ins_split, dim3(stride_blocks(nch_max, 1)), dim3(UPD_CHUNK), 0, st, bk, bi, run_leaf, run_beg, ctr, m, chunk_off, piece_off, newpos, slot_alloc, dt, piece_pos, slots, C, phi, cap);
 }
-void upd_piece_meta(hipStream_t st, int dim, const uint32_t* piece_pos, uint64_t A, NodeRec* leaf,
-                    const uint32_t* slots, uint32_t C, Caps cap) {
-    if (A) PSI_D(k_piece_meta, dim3(blocks_for(A, 8)), dim3(256), 0, st, piece_pos, A, leaf, slots, C, cap);
+void upd_piece_meta(hipStream_t st, int dim, const uint32_t* piece_pos, uint64_t A_max, const uint32_t* ctr,
+                    const DevTree* dt, const uint32_t* slots, uint32_t C, Caps cap) {
+    if (A_max) PSI_D(k_piece_meta, dim3(stride_blocks(A_max, 8)), dim3(256), 0, st, piece_pos, ctr, dt, slots, C, cap);
 }
 void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rsplit,
-                  const uint32_t* free_off, const NodeRec* sleaf, uint32_t* free_stack, uint64_t base, Caps cap) {
-    hipLaunchKernelGGL(k_ins_free, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, free_off, sleaf, free_stack, base, cap);
+                  const uint32_t* free_off, const DevTree* dt, uint32_t* free_stack, Caps cap) {
+    hipLaunchKernelGGL(k_ins_free, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, free_off, dt, free_stack, cap);
 }
 
-void upd_del_gather(hipStream_t st, const uint32_t* ids, uint64_t m, const uint64_t* idkey, uint32_t next_id,
+void upd_del_gather(hipStream_t st, const uint32_t* ids, uint64_t m, const uint64_t* idkey, const DevTree* dt,
                     uint64_t* dk, uint32_t* di) {
-    hipLaunchKernelGGL(k_del_gather, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, next_id, dk, di);
+    hipLaunchKernelGGL(k_del_gather, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, dt, dk, di);
 }
 void upd_del_compact(hipStream_t st, const uint64_t* sk, const uint32_t* si, uint64_t m, uint32_t* flag,
                      uint32_t* pos, uint32_t* V_dev, uint64_t* ck, uint32_t* ci, uint32_t* tmp) {
@@ -846,55 +949,54 @@ void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint6
     hipLaunchKernelGGL(k_del_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, ctr, m, idkey, ndel);
 }
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
-                    const uint32_t* ctr, uint64_t m, NodeRec* leaf, uint32_t* slots, uint32_t C, uint32_t phi,
+                    const uint32_t* ctr, uint64_t m, const DevTree* dt, uint32_t* slots, uint32_t C, uint32_t phi,
                     uint32_t* under, uint32_t* err, Caps cap) {
     const uint32_t half = (phi + 1) / 2;
-    PSI_D(k_del_remove, dim3(blocks_for(m, 256 / DEL_G)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, leaf, slots, C, half, under, err, cap);
+    PSI_D(k_del_remove, dim3(blocks_for(m, 256 / DEL_G)), dim3(256), 0, st, ci, run_leaf, run_beg, ctr, m, dt, slots, C, half, under, err, cap);
 }
-void upd_del_plan(hipStream_t st, const NodeRec* leaf, uint64_t L, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
+void upd_del_plan(hipStream_t st, const DevTree* dt, const Dirs& dirs, uint64_t Lb, uint32_t phi, uint32_t* ctr, uint32_t* cnt,
                   uint32_t* cum, uint32_t* start, uint32_t* gidx, uint32_t* grp_first, uint32_t* gpieces,
                   uint32_t* gchunks, uint32_t* galloc, uint32_t* gfree, uint32_t* gchanged, uint32_t* gpos,
                   uint32_t* chunk_off, uint32_t* alloc_off, uint32_t* free_off, uint32_t* tmp) {
     const uint32_t half = (phi + 1) / 2;
-    const unsigned g = blocks_for(L, 256);
+    const unsigned g = blocks_for(Lb, 256);
     // start[] holds the per-workgroup maxima until k_del_starts fills it
     // every launch below exits at once unless the delete left a leaf below
     // the minimum (ctr[8]); the totals then stay 0 and nothing regroups
-    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, leaf, L, half, ctr, cnt, start);
+    hipLaunchKernelGGL(k_del_counts, dim3(g), dim3(256), 0, st, dt, Lb, half, ctr, cnt, start, dirs);
     hipLaunchKernelGGL(k_del_last_full, dim3(1), dim3(256), 0, st, start, (uint64_t)g, ctr);
-    launch_scan_u32(st, cnt, cum, L, cum + L, tmp, ctr + 8);
-    hipLaunchKernelGGL(k_del_starts, dim3(g), dim3(256), 0, st, cnt, L, half, ctr, start);
-    launch_scan_u32(st, start, gidx, L, ctr + 6, tmp, ctr + 8);
-    hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, L, ctr, grp_first);
-    hipLaunchKernelGGL(k_del_gplan, dim3(g), dim3(256), 0, st, grp_first, ctr, L, cum, phi, gpieces, gchunks, galloc, gfree, gchanged);
+    launch_scan_u32(st, cnt, cum, Lb, cum + Lb, tmp, ctr + 8);
+    hipLaunchKernelGGL(k_del_starts, dim3(g), dim3(256), 0, st, cnt, Lb, half, ctr, dt, start);
+    launch_scan_u32(st, start, gidx, Lb, ctr + 6, tmp, ctr + 8);
+    hipLaunchKernelGGL(k_del_groups, dim3(g), dim3(256), 0, st, start, gidx, dt, ctr, grp_first);
+    hipLaunchKernelGGL(k_del_gplan, dim3(g), dim3(256), 0, st, grp_first, ctr, Lb, dt, cum, phi, gpieces, gchunks, galloc, gfree, gchanged);
     ScanSet sc{{gpieces, galloc, gchunks, gfree},
                {gpos, alloc_off, chunk_off, free_off},
                {ctr + 2, ctr + 3, ctr + 4, ctr + 5},
-               {L, L, L, L},
+               {Lb, Lb, Lb, Lb},
                ctr + 8};
     launch_scan_multi(st, sc, 4, tmp);
 }
-void upd_del_gcopy(hipStream_t st, const uint32_t* grp_first, const uint32_t* ctr, uint64_t L,
-                   const uint32_t* gchanged, const uint32_t* gpos, const NodeRec* src, const uint64_t* spk,
-                   const uint32_t* spi, NodeRec* dst, uint64_t* dpk, uint32_t* dpi, Caps cap) {
-    hipLaunchKernelGGL(k_del_gcopy, dim3(blocks_for(L, 256)), dim3(256), 0, st, grp_first, ctr, gchanged, gpos, src, spk, spi, dst, dpk, dpi, cap);
+void upd_del_gcopy(hipStream_t st, const uint32_t* grp_first, const uint32_t* ctr, uint64_t Lb,
+                   const uint32_t* gchanged, const uint32_t* gpos, const DevTree* dt, Caps cap) {
+    hipLaunchKernelGGL(k_del_gcopy, dim3(blocks_for(Lb, 256)), dim3(256), 0, st, grp_first, ctr, gchanged, gpos, dt, cap);
 }
 void upd_sort_leaves(hipStream_t st, int dim, int curve, const uint32_t* start, const uint32_t* gidx,
-                     const uint32_t* gchanged, uint64_t L, const NodeRec* leaf, uint32_t* slots, uint32_t C) {
-    PSI_DC(k_sort_leaves, dim3(blocks_for(L, 4)), dim3(256), 0, st, start, gidx, gchanged, L, leaf, slots, C);
+                     const uint32_t* gchanged, const uint32_t* ctr, uint64_t Lb, const DevTree* dt, const Dirs& dirs,
+                     uint32_t* slots, uint32_t C) {
+    PSI_DC(k_sort_leaves, dim3(stride_blocks(Lb, 4)), dim3(256), 0, st, start, gidx, gchanged, ctr, dt, slots, C, dirs);
 }
-void upd_del_regroup(hipStream_t st, int dim, int curve, uint64_t nchunks, const uint32_t* grp_first,
-                     const uint32_t* ctr, uint64_t L, const uint32_t* chunk_off, const uint32_t* alloc_off,
-                     const uint32_t* gpos, const uint32_t* cum, const uint32_t* slot_alloc, const NodeRec* sleaf,
-                     NodeRec* dleaf, uint64_t* dpk, uint32_t* dpi, uint32_t* piece_pos, uint32_t* slots, uint32_t C,
-                     uint32_t phi, Caps cap) {
-    if (nchunks)
-        PSI_DC(k_del_regroup, dim3((unsigned)nchunks), dim3(UPD_CHUNK), 0, st, grp_first, ctr, L, chunk_off, alloc_off, gpos, cum, slot_alloc, sleaf, dleaf, dpk, dpi, piece_pos, slots, C, phi, cap);
+void upd_del_regroup(hipStream_t st, int dim, int curve, uint64_t nch_max, const uint32_t* grp_first,
+                     const uint32_t* ctr, const uint32_t* chunk_off, const uint32_t* alloc_off,
+                     const uint32_t* gpos, const uint32_t* cum, const uint32_t* slot_alloc, const DevTree* dt,
+                     uint32_t* piece_pos, uint32_t* slots, uint32_t C, uint32_t phi, Caps cap) {
+    if (nch_max)
+        PSI_DC(k_del_regroup, dim3(stride_blocks(nch_max, 1)), dim3(UPD_CHUNK), 0, st, grp_first, ctr, chunk_off, alloc_off, gpos, cum, slot_alloc, dt, piece_pos, slots, C, phi, cap);
 }
 void upd_del_free(hipStream_t st, const uint32_t* start, const uint32_t* gidx, const uint32_t* gchanged,
-                  const uint32_t* grp_first, const uint32_t* free_off, uint64_t L, const NodeRec* sleaf,
-                  uint32_t* free_stack, uint64_t base, Caps cap) {
-    hipLaunchKernelGGL(k_del_free, dim3(blocks_for(L, 256)), dim3(256), 0, st, start, gidx, gchanged, grp_first, free_off, L, sleaf, free_stack, base, cap);
+                  const uint32_t* grp_first, const uint32_t* free_off, const uint32_t* ctr, uint64_t Lb,
+                  const DevTree* dt, uint32_t* free_stack, Caps cap) {
+    hipLaunchKernelGGL(k_del_free, dim3(blocks_for(Lb, 256)), dim3(256), 0, st, start, gidx, gchanged, grp_first, free_off, ctr, dt, free_stack, cap);
 }
 
 }  // namespace psi

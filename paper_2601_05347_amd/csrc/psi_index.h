@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <map>
 #include <string>
 #include <utility>
@@ -61,8 +62,68 @@ struct Buf {
         bytes = want;
         return PSI_OK;
     }
+    // Stream-ordered variants for the index's hot paths: the new block is
+    // allocated at once, the old one (its contents copied on `st` first by
+    // grow_keep_q) goes to `grave` and is freed once the stream is idle, so
+    // neither call waits for queued work. need <= bytes does nothing.
+    psi_status ensure_q(size_t need, std::vector<void*>& grave) {
+        if (need <= bytes) return PSI_OK;
+        void* q = nullptr;
+        size_t want = need + need / 4 + 256;
+        if (hipMalloc(&q, want) != hipSuccess) {
+            (void)hipGetLastError();
+            want = need;
+            if (hipMalloc(&q, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return PSI_E_NOMEM;
+            }
+        }
+        if (p) grave.push_back(p);
+        p = q;
+        bytes = want;
+        return PSI_OK;
+    }
+    psi_status grow_keep_q(size_t need, hipStream_t st, std::vector<void*>& grave) {
+        if (need <= bytes) return PSI_OK;
+        void* q = nullptr;
+        size_t want = need + need / 2 + 256;
+        if (hipMalloc(&q, want) != hipSuccess) {
+            (void)hipGetLastError();
+            want = need;
+            if (hipMalloc(&q, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return PSI_E_NOMEM;
+            }
+        }
+        if (p) {
+            if (hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipFree(q);
+                return PSI_E_HIP;
+            }
+            grave.push_back(p);
+        }
+        p = q;
+        bytes = want;
+        return PSI_OK;
+    }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
+
+// Upper bounds of the device state's sizes, as the host tracks them.
+struct Bounds {
+    uint64_t L = 0, slot_top = 0, n_free = 0, n_live = 0, next_id = 0;
+};
+// An update whose commit the host has not seen yet: its event, the pinned
+// slot its DevTree head is copied to, and how much it may have grown the
+// state. `stale`: a later build replaced the state it describes.
+struct Inflight {
+    hipEvent_t ev = nullptr;
+    uint32_t slot = 0;
+    Bounds delta;
+    bool stale = false;
+};
+constexpr uint32_t MIRROR_SLOTS = 64;  // updates in flight before a call waits
 
 // Per-family kernel timing with HIP events (enabled on demand).
 struct ProfFamily {
@@ -131,34 +192,43 @@ struct psi_index_s {
     int D = 2;
     int curve = 0;
     uint32_t phi = 32;
-    uint32_t C = 64;  // slot capacity (2 phi rounded up to a multiple of 4)
+    uint32_t C = 64;  // slot stride (2 phi rounded up to a multiple of 4)
     uint32_t B = 8;
     uint32_t flags = 0;
     hipStream_t st = nullptr;
 
+    // The sizes of the tree (leaf count, live points, next id, slot and
+    // free-stack tops, current directory buffer, node layout) live on the
+    // device in `dev` (a DevTree) and change only in stream order. The host
+    // keeps `base`, their exact values as of the last update it has seen
+    // complete (or the last wait), plus per-update growth bounds of the
+    // updates still in flight; buffers and grids are sized by base + those
+    // bounds, so no call needs the device's answer before it returns.
+    psi::Buf dev;
+    psi::Bounds base;
+    std::deque<psi::Inflight> inflight;
+    psi::DevTree* mirror = nullptr;  // pinned [MIRROR_SLOTS] DevTree heads
+    uint32_t mirror_next = 0;
+    std::vector<hipEvent_t> ev_pool;
+    bool unknown = false;   // a replayed graph changed the state: wait before sizing
+    uint64_t gen = 1;       // bumped by every change that stales a captured graph
+    std::vector<void*> grave;  // replaced device blocks, freed once the stream is idle
+
     // id -> key table (DEAD_KEY for deleted or never used ids)
     psi::Buf idkey;
-    uint32_t next_id = 0;
-    uint64_t n_live = 0;
 
     // leaf storage: slot s holds [D][C] coordinates then [C] ids (u32)
     psi::Buf slots;
-    uint64_t slot_top = 0;  // slots ever handed out (bump pointer)
     psi::Buf free_stack;    // freed slots, reused before bumping
-    uint64_t n_free = 0;
 
     // leaf directory (double-buffered for updates): records and pivots
     psi::Buf leaf[2], pkey[2], pid[2];
-    int cur = 0;
-    uint64_t L = 0;
 
     // node levels 0..h-1, level-major from the root
     psi::Buf inner;
     psi::Buf cinner, cleaf;  // packed boxes of the inner nodes and of the leaves
     bool boxes_fresh = false;  // packed boxes match the current tree
-    uint64_t n_inner = 0;
-    uint32_t h = 0;
-    std::vector<psi::LevelInfo> lv;
+    uint64_t L_cap = 0;        // leaves the node buffers and packed boxes are sized for
 
     uint32_t bucket_top = ~0u;  // bucket bits of the last two-level build sort
 
@@ -169,6 +239,8 @@ struct psi_index_s {
     psi::Prof prof;
 
     uint64_t slot_words() const { return (uint64_t)(D + 1) * C; }
+    psi::DevTree* dt() const { return dev.as<psi::DevTree>(); }
+    // View for query kernels: sizes and the directory come from dt at launch.
     psi::TreeView view() const;
 };
 
@@ -203,18 +275,46 @@ psi_status hip_ok(hipError_t e);
 bool capturing(hipStream_t st);
 // Buf::ensure for paths that may run under graph capture: growing a buffer
 // there is refused (PSI_E_STATE); a call outside capture sizes it first.
-psi_status ensure_q(Buf& b, size_t need, hipStream_t st);
+// Growth never waits (the old block is freed once the stream is idle) and
+// stales captured graphs.
+psi_status ensure_q(psi_index ix, Buf& b, size_t need);
+psi_status grow_keep_q(psi_index ix, Buf& b, size_t need);
+
+// Host view of the device state (psi_api.hip).
+// Retires the updates that have completed (non-blocking) and frees replaced
+// blocks once the stream is idle.
+void poll(psi_index ix);
+// Upper bounds of the state once every queued update has run (waits only if
+// a replayed graph left the state unknown).
+psi_status bounds(psi_index ix, Bounds* out);
+// Waits for the stream and makes `base` exact (no update left in flight).
+psi_status settle(psi_index ix);
+// After an update's kernels: mirror the DevTree head to pinned memory behind
+// an event, so a later call can take exact sizes without waiting.
+psi_status track_update(psi_index ix, const Bounds& delta);
+// Sizes the node buffers and packed boxes for up to L leaves, launches the
+// node levels of the layout in dt (at most the height of L leaves).
+psi_status build_nodes(psi_index ix, uint64_t L_bound);
+// Exact tree view for exports (after settle()): leaf count, height and the
+// current directory from the state.
+psi::TreeView exact_view(psi_index ix, std::vector<psi::LevelInfo>* lv = nullptr);
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
                       bool id_digits, bool hist_ready, int* which, const char* fam, uint32_t key_shift0 = 0,
                       int key_passes = 8);
-psi_status build_nodes(psi_index ix);
 psi_status readback(psi_index ix, const void* dev, size_t bytes);  // into ix->pinned, waits
 
 // updates (psi_update.hip)
 psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
 psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
-psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base);
-psi_status encode_sort(psi_index ix, const uint32_t* d_pts, uint64_t n, uint32_t id_base, int* which);
+psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n);
+// Curve keys of n points into keys[0 .. n) and the pairs (key, id_base + i)
+// sorted by (key, id) into sorter.k/i[*which]; requires n > 0.
+psi_status encode_sort(psi_index ix, const uint32_t* d_pts, uint64_t n, uint64_t* keys, uint32_t id_base,
+                       int* which);
+// Both directory buffers sized for `leaves` leaves (contents kept).
+psi_status ensure_dirs(psi_index ix, uint64_t leaves);
+// The directory buffers as kernel arguments take them.
+psi::Dirs dirs_of(psi_index ix);
 // Processing order of a query batch (curve keys of the points or box centres
 // in scr.c, input order; *order null or the positions sorted by key); latches
 // ERR_RANGE for out-of-range query points.

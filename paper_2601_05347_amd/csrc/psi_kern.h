@@ -4,9 +4,45 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stddef.h>
+
 #include "psi_dev.h"
 
 namespace psi {
+
+// The two directory buffers, passed to kernels by value: pointers that come
+// in as kernel arguments are known to address device memory (global loads),
+// while pointers read from memory would be loaded through the slower flat
+// path. DevTree::cur says which one is current.
+struct Dirs {
+    NodeRec* leaf[2];
+    uint64_t* pkey[2];
+    uint32_t* pid[2];
+};
+
+// The mutable state of one index, kept in device memory so that updates are
+// planned, applied and committed by kernels alone (the host never has to read
+// a count back to size the next launch). Kernels read the leaf count, the
+// current directory buffer and the node layout from here; the host sizes its
+// launches and buffers by upper bounds of these values.
+struct DevTree {
+    NodeRec* leaf[2];    // the two directory buffers; leaf[cur] is current
+    uint64_t* pkey[2];   // pivot keys, same buffers
+    uint32_t* pid[2];    // pivot ids
+    uint64_t L;          // leaves in the current directory
+    uint64_t n_inner;    // inner nodes (levels 0 .. h-1)
+    uint64_t n_live;     // live points
+    uint64_t slot_top;   // leaf slots ever handed out (bump pointer)
+    uint64_t n_free;     // entries of the free-slot stack
+    uint32_t cur;        // current directory buffer
+    uint32_t h;          // height: levels 0 .. h, level h = the leaves
+    uint32_t next_id;    // next id an insert hands out
+    uint32_t sort_top;   // bucket bits of the last two-level build sort (~0: none yet)
+    LevelInfo lv[MAX_LEVELS];  // levels 0 .. h
+};
+// Bytes of the DevTree head (everything before the level table): what the
+// host mirrors after each update to tighten its upper bounds.
+constexpr size_t DEVTREE_HEAD = offsetof(DevTree, lv);
 
 // ------------------------------------------------------------- radix sort
 constexpr int RADIX_BITS = 8;
@@ -76,17 +112,26 @@ struct XcdChunks {
     const uint64_t* pos_begin;
     const uint64_t* pos_end;
 };
+// A segmented pass with ntiles_dev (device word, may be null) takes tiles
+// while fewer than *ntiles_dev are taken, with seg_tiles workgroups that
+// each take as many as they can (else one workgroup per tile).
 void launch_onesweep(hipStream_t st, bool implicit_ids, bool digit_from_id, const uint64_t* kin,
                      const uint32_t* iin, uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n,
                      uint32_t shift, const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr,
-                     uint32_t epoch, uint32_t* err, const SegTiles* seg = nullptr, uint64_t seg_tiles = 0);
+                     uint32_t epoch, uint32_t* err, const SegTiles* seg = nullptr, uint64_t seg_tiles = 0,
+                     const uint32_t* ntiles_dev = nullptr);
 // Chunked pass: dig_off is [XCD_CHUNKS][256] (chunk x's destination of digit
-// d); tile_ctr holds XCD_CHUNKS zeroed counters; max_chunk_tiles bounds
-// ntiles[x] (XCD_CHUNKS * max_chunk_tiles workgroups are launched).
+// d); tile_ctr holds XCD_CHUNKS zeroed counters; XCD_CHUNKS * wg_per_chunk
+// workgroups take one tile each; with `overflow`, a second small launch
+// takes whatever tiles are left (chunks of data-dependent sizes: any
+// wg_per_chunk >= 1 is then correct); without it wg_per_chunk must bound
+// every chunk's tiles. The digit sits at bit shift (+ *shift_dev if
+// shift_dev is not null).
 void launch_onesweep_xcd(hipStream_t st, bool implicit_ids, const uint64_t* kin, const uint32_t* iin,
                          uint32_t id_base, uint64_t* kout, uint32_t* iout, uint64_t n, uint32_t shift,
                          const uint32_t* dig_off, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, uint32_t* err,
-                         const XcdChunks& xc, uint32_t max_chunk_tiles);
+                         const XcdChunks& xc, uint32_t wg_per_chunk, const uint32_t* shift_dev = nullptr,
+                         bool overflow = false);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 
@@ -111,18 +156,27 @@ struct ChunkTables {
     uint64_t* pos_begin;
     uint64_t* pos_end;
 };
-void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt);
+// With redo (device word, may be null): counts only if *redo != 0, on the
+// digits at bits *top and *top + 8.
+void launch_hist_chunks(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t s0, uint32_t s1, uint32_t* cnt,
+                        const uint32_t* redo = nullptr, const uint32_t* top = nullptr);
+// *top = bucket bits of the largest key *kmax (16 below its leading bit);
+// *redo = (*top != guess).
+void launch_fix_top(hipStream_t st, const uint64_t* kmax, uint32_t guess, uint32_t* top, uint32_t* redo);
+// Zeroes words_per * (*count) words (count <= max_count).
+void launch_zero_counted(hipStream_t st, uint32_t* p, uint64_t words_per, const uint32_t* count, uint64_t max_count);
 void launch_chunk_offsets(hipStream_t st, const uint32_t* cnt, uint64_t n, uint32_t* off1, uint32_t* off2,
                           ChunkTables tb1, ChunkTables tb2);
 // bstart[t] for t in [0, nb] (nb + 1 words): first position of bucket t.
-void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* bstart,
+// The bucket bits start at bit *top (device word).
+void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, const uint32_t* top, uint32_t* bstart,
                           uint32_t nb);
 // Sorts buckets by (key, id) in place, in two launches: wide = false takes
 // every bucket of at most BUCKET_SMALL pairs and sets big[t] = 1 for the
 // larger ones (else 0); wide = true then takes those of at most BUCKET_MAX
 // and clears their flag. Decreasing bucket starts latch ERR_SPIN.
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
-                       uint32_t lo_bits, uint32_t* big, uint32_t* err, bool wide);
+                       const uint32_t* top, uint32_t* big, uint32_t* err, bool wide);
 // Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
 // bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
 // big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).
@@ -132,7 +186,9 @@ void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* b
 void launch_big_fill(hipStream_t st, const uint32_t* bstart, const uint32_t* big, const uint32_t* big_idx,
                      const uint32_t* tile_off, uint32_t nb, const SegTiles& sg, uint64_t* seg_begin);
 // Per-segment histograms of the six low key digits: hist [num][8][256], zeroed.
-void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t ntiles, const SegTiles& sg, uint32_t* hist);
+// Over the first *ntiles tiles (at most max_tiles).
+void launch_seg_hist_keys(hipStream_t st, const uint64_t* keys, uint64_t max_tiles, const uint32_t* ntiles,
+                          const SegTiles& sg, uint32_t* hist);
 
 // ------------------------------------------------------------------ scans
 // Exclusive prefix sums; `total` (device, may be null) receives the sum.
@@ -160,30 +216,59 @@ void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp);
 // Fill leaves from sorted pairs: leaf j takes sorted positions
 // [floor(j n / L), floor((j+1) n / L)), its points decoded from the keys;
 // writes slot j, the pivot and the leaf record. Requires n / L <= 32.
+// skip (device, may be null): the fill does nothing if it holds nonzero.
 void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
                          uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
-                         uint32_t* piv_id, NodeRec* leafrec);
-// One node level: parent i = union of children [B i, B i + B) one level down;
-// packed boxes of the children (cchild, may be null) and of the parents.
-void launch_node_level(hipStream_t st, int dim, const NodeRec* child, uint64_t n_child, NodeRec* parent,
-                       uint64_t n_parent, uint32_t B, uint4* cchild, uint4* cparent);
-// Packed boxes of n records.
-void launch_pack_boxes(hipStream_t st, int dim, const NodeRec* rec, uint64_t n, uint4* out);
+                         uint32_t* piv_id, NodeRec* leafrec, const uint64_t* skip = nullptr);
+// Node level u (1 = the parents of the leaves) of the layout in dt: parent i
+// = union of children [B i, B i + B). n_parent_cap bounds the level's size
+// (the grid); a level above the tree's height does nothing.
+void launch_node_level(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint32_t u,
+                       uint64_t n_parent_cap, NodeRec* inner, uint32_t B);
+// Packed boxes of the current leaves (leaves = true) or inner nodes of dt;
+// cap bounds their number.
+void launch_pack_tree(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, bool leaves,
+                      const NodeRec* inner, uint4* out, uint64_t cap);
 
 // ---------------------------------------------------------------- queries
+
+
+// What a query kernel needs of a tree. For a resident index `dt` is set and
+// the kernels take leaf, pkey, L, h and the level table from it at launch
+// (resolve_tree); the other fields are fixed per index. With dt == nullptr
+// (many small indexes, exports after a sync) every field is taken as given.
 struct TreeView {
     const NodeRec* inner;   // levels 0..h-1
-    const NodeRec* leaf;    // level h (the directory)
+    const NodeRec* leaf;    // level h (the directory); with dt: directory buffer 0
+    const NodeRec* leaf_alt;  // with dt: directory buffer 1
     const uint4* cinner;    // packed boxes of inner (same positions)
     const uint4* cleaf;     // packed boxes of leaf
-    const uint64_t* pkey;   // leaf pivot keys (ascending)
+    const uint64_t* pkey;   // leaf pivot keys (ascending); with dt: buffer 0
+    const uint64_t* pkey_alt;  // with dt: buffer 1
     const uint32_t* slots;
     uint32_t h;
     uint32_t B;
     uint32_t C;
     uint64_t L;
-    LevelInfo lv[MAX_LEVELS];  // levels 0..h (passed by value with every launch)
+    const DevTree* dt;
 };
+#ifdef __HIPCC__
+// The directory buffers come in as kernel arguments (leaf / leaf_alt, pkey /
+// pkey_alt), so the compiler knows they are device memory and loads through
+// them are global loads; the device state only says which one is current.
+__device__ __forceinline__ TreeView resolve_tree(const TreeView& tv) {
+    TreeView t = tv;
+    if (tv.dt) {
+        const DevTree* d = tv.dt;
+        const bool c = d->cur != 0;
+        t.leaf = c ? tv.leaf_alt : tv.leaf;
+        t.pkey = c ? tv.pkey_alt : tv.pkey;
+        t.L = d->L;
+        t.h = d->h;
+    }
+    return t;
+}
+#endif
 // Queries are processed in the order `order` gives (nullptr: input order);
 // results always land in the query's own row.
 // qkeys: curve keys of the queries in input order (seeds the search with the
@@ -314,7 +399,7 @@ void launch_encode_hist_seg(hipStream_t st, int dim, int curve, const uint32_t* 
                             const SegTiles& sg, uint64_t* keys, uint32_t* hist, uint32_t* err);
 // off[s][p][d] = seg_begin[s] + exclusive prefix over digits of hist[s][p][.]
 void launch_seg_digit_offsets(hipStream_t st, uint32_t num, const uint32_t* hist, const uint64_t* seg_begin,
-                              uint32_t* off);
+                              uint32_t* off, const uint32_t* num_dev = nullptr);
 // Leaves of every index: global leaf g belongs to index s with
 // leaf_off[s] <= g < leaf_off[s+1]; ids stored are local (position - pt_base).
 void launch_build_leaves_seg(hipStream_t st, int dim, int curve, uint32_t num, uint64_t total_leaves,

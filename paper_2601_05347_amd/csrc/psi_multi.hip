@@ -40,10 +40,6 @@ struct psi_multi_s {
         t.pkey = pkey.as<uint64_t>() + m.leaf_base;
         t.L = m.L;
         t.h = m.h;
-        for (uint32_t l = 0; l <= m.h && l < (uint32_t)MAX_LEVELS; ++l) {
-            t.lv[l].off = l < m.h ? m.lvl_off[l] : 0;
-            t.lv[l].n = m.lvl_n[l];
-        }
         return t;
     }
 };
@@ -242,8 +238,11 @@ psi_status psi_multi_knn(psi_multi mx, const uint64_t* d_q_off, const uint32_t* 
     if (!mx || !d_q_off || !d_q || !d_ids || !d_d2) return PSI_E_ARG;
     if (k != 1 && k != 2 && k != 4 && k != 8 && k != 10 && k != 16) return PSI_E_ARG;
     psi_status s;
-    if ((s = ensure_q(mx->qtmp, ((uint64_t)mx->num + 1 + scan_tmp_words(mx->num) + 64) * 4, mx->st)) != PSI_OK)
-        return s;
+    const size_t need = ((uint64_t)mx->num + 1 + scan_tmp_words(mx->num) + 64) * 4;
+    if (need > mx->qtmp.bytes) {
+        if (capturing(mx->st)) return PSI_E_STATE;  // a captured call cannot allocate
+        if ((s = mx->qtmp.ensure(need)) != PSI_OK) return s;
+    }
     uint32_t* pref = mx->qtmp.as<uint32_t>();
     uint32_t* work = pref + mx->num + 1;
     uint32_t* tmp = work + 16;

@@ -78,6 +78,10 @@ psi_status orth_cut(psi_orth o, const uint64_t* sk, const uint32_t* sid, uint64_
     if ((s = read2(ix, small, 1, ix->err.as<uint32_t>(), 1)) != PSI_OK) return s;
     uint32_t h[2];
     std::memcpy(h, ix->pinned, 8);
+    // the sort's bucket bits, the next build's guess (the stream is idle)
+    uint32_t top = ~0u;
+    if (hipMemcpy(&top, &ix->dt()->sort_top, 4, hipMemcpyDeviceToHost) == hipSuccess) ix->bucket_top = top;
+    else (void)hipGetLastError();
     if (h[1] & ERR_RANGE) {  // keys of out-of-range points: no tree
         launch_fill_u32(st, ix->err.as<uint32_t>(), 1, 0u);
         (void)hipStreamSynchronize(st);
@@ -145,7 +149,7 @@ psi_status orth_build(psi_orth o, const uint32_t* d_pts, uint64_t n) {
     if (n == 0) return PSI_OK;
     if ((s = ix->idkey.ensure(n * 8)) != PSI_OK) return s;
     int w = 0;
-    if ((s = encode_sort(ix, d_pts, n, 0, &w)) != PSI_OK) return s;
+    if ((s = encode_sort(ix, d_pts, n, ix->idkey.as<uint64_t>(), 0, &w)) != PSI_OK) return s;
     if ((s = o->alive.ensure((n + 31) / 32 * 4)) != PSI_OK) return s;
     launch_orth_alive(ix->st, o->alive.as<uint32_t>(), 0, (uint32_t)n);
     if ((s = orth_cut(o, ix->sorter.k[w].as<uint64_t>(), ix->sorter.i[w].as<uint32_t>(), n)) != PSI_OK) return s;
@@ -162,7 +166,7 @@ psi_status orth_insert(psi_orth o, const uint32_t* d_pts, uint64_t m, uint32_t* 
     // the id table keeps every id's key (deletes look points up by it)
     if ((s = ix->idkey.grow_keep((id0 + m) * 8, id0 * 8, st)) != PSI_OK) return s;
     int w = 0;
-    if ((s = encode_sort(ix, d_pts, m, (uint32_t)id0, &w)) != PSI_OK) return s;
+    if ((s = encode_sort(ix, d_pts, m, ix->idkey.as<uint64_t>() + id0, (uint32_t)id0, &w)) != PSI_OK) return s;
     if ((s = read2(ix, ix->err.as<uint32_t>(), 1, nullptr, 0)) != PSI_OK) return s;
     uint32_t e = 0;
     std::memcpy(&e, ix->pinned, 4);

@@ -1,5 +1,6 @@
 """hipGraph capture of query steps: every replay equals the eager result,
-with the program's own eager work and synchronizations between replays."""
+with the program's own eager work and synchronizations between replays.
+(Captured builds and updates: test_gpu_enqueue.py.)"""
 import sys
 
 import numpy as np
@@ -51,8 +52,6 @@ def test_graph_replays_knn_and_range(psi, nq):
         psi.psi_knn(h, dq, nq, 10, ids, d2)
         psi.psi_range_count(h, db, nq, cnt)
         g = psi.psi_graph_end(stream)
-        # updates are refused while capturing
-        other = torch.cuda.Stream()
         for rep in range(4):
             ids.fill_(-1)
             d2.fill_(-1)
@@ -74,26 +73,6 @@ def test_graph_replays_knn_and_range(psi, nq):
         np.testing.assert_array_equal(psi.to_u32(e_ids)[rows], r_ids)
         np.testing.assert_array_equal(psi.to_u64(e_d2)[rows], r_d2)
         ix.sync()
-
-
-def test_updates_refused_under_capture(psi):
-    import torch
-    say("graph refuses updates")
-    stream = torch.cuda.Stream()
-    dev = torch.device("cuda")
-    with torch.cuda.stream(stream):
-        ix = psi.Index(2, 0, 32, 8, device=dev, stream=stream)
-        ix.build(synth.uniform(1000, 2, 30, seed=1))
-        pts = torch.from_numpy(synth.uniform(10, 2, 30, seed=2).view(np.int32)).to(dev)
-        stream.synchronize()
-        psi.psi_graph_begin(stream)
-        with pytest.raises(psi.PsiError) as e:
-            psi.psi_batch_insert(ix._h, pts, 10)
-        g = psi.psi_graph_end(stream)
-        psi.psi_graph_destroy(g)
-        assert e.value.code == 6
-        ix.sync()
-        assert ix.size() == 1000
 
 
 def test_graph_multi_knn(psi):
