@@ -201,6 +201,19 @@ psi_status psi_encode(uint32_t dim, uint32_t curve, const uint32_t* d_pts, uint6
 psi_status psi_sort_pairs(const uint64_t* d_keys, const uint32_t* d_ids, uint64_t n,
                           uint64_t* d_keys_out, uint32_t* d_ids_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * sort as psi_sort_pairs, with the same result, but no allocation and no
+ * wait. Its workspace is a fixed device array of about 25 MB inside the
+ * library, one per GPU, kept until the process ends; n above
+ * PSI_SORT_NOALLOC_MAX returns PSI_E_ARG and queues nothing. Every call on
+ * one GPU shares that GPU's workspace, so calls that may run at the same time
+ * on one GPU (on different streams) race; calls on one stream are safe. The
+ * outputs must not overlap the inputs. */
+#define PSI_SORT_NOALLOC_MAX (1u << 20)
+psi_status psi_sort_pairs_noalloc(const uint64_t* d_keys, const uint32_t* d_ids, uint64_t n,
+                                  uint64_t* d_keys_out, uint32_t* d_ids_out, void* hip_stream);
+
 /* --- many independent indexes (batched small indexes) -------------------- */
 
 /* Build `num` independent indexes from one CSR batch: index s holds the

@@ -52,6 +52,7 @@ SIGNATURES = {
     "psi_export_leaves": (_i, [_P, _P, _P]),
     "psi_encode": (_i, [_u32, _u32, _P, _u64, _P, _P]),
     "psi_sort_pairs": (_i, [_P, _P, _u64, _P, _P, _P]),
+    "psi_sort_pairs_noalloc": (_i, [_P, _P, _u64, _P, _P, _P]),
     "psi_multi_build": (_i, [_P, _P, _u32, _P, _P, _P]),
     "psi_multi_destroy": (_i, [_P]),
     "psi_multi_knn": (_i, [_P, _P, _P, _u32, _P, _P]),
@@ -260,6 +261,14 @@ def psi_encode(dim: int, curve: int, pts, n: int, keys, stream=None):
 def psi_sort_pairs(keys, ids, n: int, keys_out, ids_out, stream=None):
     _check(lib().psi_sort_pairs(_dev_ptr(keys), _dev_ptr(ids), n, _dev_ptr(keys_out), _dev_ptr(ids_out),
                                 _stream_ptr(stream)), "psi_sort_pairs")
+
+
+SORT_NOALLOC_MAX = 1 << 20
+
+
+def psi_sort_pairs_noalloc(keys, ids, n: int, keys_out, ids_out, stream=None):
+    _check(lib().psi_sort_pairs_noalloc(_dev_ptr(keys), _dev_ptr(ids), n, _dev_ptr(keys_out), _dev_ptr(ids_out),
+                                        _stream_ptr(stream)), "psi_sort_pairs_noalloc")
 
 
 def psi_multi_build(dim: int, curve: int, num: int, pt_off, pts, leaf_size: int = 32, fanout: int = 8,
