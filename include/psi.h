@@ -245,6 +245,65 @@ psi_status psi_multi_export_structure(psi_multi mx, uint32_t index, uint64_t* d_
  * ids); lengths follow the build's offsets. */
 psi_status psi_multi_export(psi_multi mx, uint64_t* d_keys, uint32_t* d_ids, uint32_t* d_pts);
 
+/* --- serving: continuous batching of mixed requests ----------------------- */
+
+/* A server takes over a resident index and serves a stream of requests by
+ * continuous batching (the paper's operations under a request load; the
+ * consistency rule is sequential consistency in submission order: every
+ * request sees exactly the updates submitted before it, as if the requests
+ * ran one at a time).
+ *   - Requests are grouped into epochs, maximal runs of updates or of
+ *     queries, admitted in submission order while the sum of their estimated
+ *     device footprints stays within budget_bytes (a request that could never
+ *     fit is refused with PSI_E_CAPACITY; when the budget is full, the
+ *     oldest epoch is waited for).
+ *   - Consecutive inserts run as one batch (ids in submission order, as
+ *     separate inserts would give them). kNN requests of one epoch with the
+ *     same k run as one launch.
+ *   - Updates run on one stream of the server's, queries on another. An
+ *     update's encode, sort, routing and planning overlap the queries of the
+ *     epoch before it; its first change to the tree waits for them. A query
+ *     epoch waits for the updates before it.
+ *   - psi_server_submit queues a request and returns a ticket at once;
+ *     psi_server_poll and psi_server_flush dispatch queued epochs (without
+ *     waiting for the device, unless the budget is full); psi_server_wait
+ *     dispatches and waits for one ticket.
+ *   - The index must not be used directly while the server exists; it gets
+ *     its stream back when the server is destroyed.
+ * Every d_* buffer is device memory owned by the caller and must stay valid,
+ * and the inputs unchanged, until the request's ticket is done. */
+enum {
+    PSI_REQ_INSERT = 0,        /* d_in: points [n][dim]; d_ids: new ids [n] (may be NULL) */
+    PSI_REQ_DELETE = 1,        /* d_in: ids [n]; d_out: number removed [1] (may be NULL) */
+    PSI_REQ_KNN = 2,           /* d_in: queries [n][dim]; k; d_ids [n][k], d_out: d2 [n][k] (as psi_knn) */
+    PSI_REQ_RANGE_COUNT = 3,   /* d_in: boxes [n][2][dim]; d_out: counts [n] */
+    PSI_REQ_RANGE_REPORT = 4   /* d_in: boxes; d_out: offsets [n+1] (exclusive scan of the counts);
+                                  d_ids: ids [ids_cap]; a box's ids past ids_cap are dropped (the
+                                  offsets still give the true counts) */
+};
+typedef struct {
+    uint32_t kind;          /* PSI_REQ_* */
+    uint32_t k;             /* kNN only: 1..128 */
+    uint64_t n;             /* points, ids, queries or boxes */
+    const uint32_t* d_in;
+    uint32_t* d_ids;
+    uint64_t* d_out;
+    uint64_t ids_cap;       /* range report only */
+    void* ready_event;      /* hipEvent_t the server waits for before reading d_in (may be NULL) */
+} psi_request;
+typedef struct psi_server_s* psi_server;
+
+psi_status psi_server_create(psi_index ix, uint64_t budget_bytes, psi_server* out);
+/* Dispatches what is queued, waits for everything, gives the index back. */
+psi_status psi_server_destroy(psi_server s);
+psi_status psi_server_submit(psi_server s, const psi_request* req, uint64_t* h_ticket);
+/* *h_done = 1 once the ticket's work has completed on the device; then
+ * *h_done_ms (may be NULL) is its completion time in ms after
+ * psi_server_create. Returns the ticket's status once done. */
+psi_status psi_server_poll(psi_server s, uint64_t ticket, int* h_done, double* h_done_ms);
+psi_status psi_server_wait(psi_server s, uint64_t ticket, double* h_done_ms);
+psi_status psi_server_flush(psi_server s);
+
 /* --- graph capture of query steps ----------------------------------------- */
 
 /* Capture the calls (psi_build, psi_batch_insert, psi_batch_delete,

@@ -60,6 +60,12 @@ SIGNATURES = {
     "psi_multi_shape": (_i, [_P, _u32, _P, _P, _P]),
     "psi_multi_export_structure": (_i, [_P, _u32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "psi_multi_export": (_i, [_P, _P, _P, _P]),
+    "psi_server_create": (_i, [_P, _u64, _P]),
+    "psi_server_destroy": (_i, [_P]),
+    "psi_server_submit": (_i, [_P, _P, _P]),
+    "psi_server_poll": (_i, [_P, _u64, _P, _P]),
+    "psi_server_wait": (_i, [_P, _u64, _P]),
+    "psi_server_flush": (_i, [_P]),
     "psi_graph_begin": (_i, [_P]),
     "psi_graph_end": (_i, [_P, _P]),
     "psi_graph_launch": (_i, [_P, _P]),
@@ -94,6 +100,15 @@ class PsiError(RuntimeError):
 class psi_params(C.Structure):
     _fields_ = [("dim", C.c_uint32), ("curve", C.c_uint32), ("leaf_size", C.c_uint32),
                 ("fanout", C.c_uint32), ("flags", C.c_uint32)]
+
+
+REQ_INSERT, REQ_DELETE, REQ_KNN, REQ_RANGE_COUNT, REQ_RANGE_REPORT = 0, 1, 2, 3, 4
+
+
+class psi_request(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("k", C.c_uint32), ("n", C.c_uint64), ("d_in", C.c_void_p),
+                ("d_ids", C.c_void_p), ("d_out", C.c_void_p), ("ids_cap", C.c_uint64),
+                ("ready_event", C.c_void_p)]
 
 
 _lib = None
@@ -308,6 +323,43 @@ def psi_multi_export_structure(h, index, piv_key, piv_id, leaf_cnt, leaf_lo, lea
 
 def psi_multi_export(h, keys, ids, pts):
     _check(lib().psi_multi_export(h, _dev_ptr(keys), _dev_ptr(ids), _dev_ptr(pts)), "psi_multi_export")
+
+
+def psi_server_create(h, budget_bytes: int):
+    s = C.c_void_p()
+    _check(lib().psi_server_create(h, budget_bytes, C.byref(s)), "psi_server_create")
+    return s
+
+
+def psi_server_destroy(s):
+    _check(lib().psi_server_destroy(s), "psi_server_destroy")
+
+
+def psi_server_submit(s, kind: int, n: int, d_in, d_ids=None, d_out=None, k: int = 0, ids_cap: int = 0,
+                      ready_event=None) -> int:
+    r = psi_request(kind, k, n, _dev_ptr(d_in), _dev_ptr(d_ids), _dev_ptr(d_out), ids_cap,
+                    C.c_void_p(ready_event.cuda_event) if ready_event is not None else None)
+    t = C.c_uint64()
+    _check(lib().psi_server_submit(s, C.byref(r), C.byref(t)), "psi_server_submit")
+    return t.value
+
+
+def psi_server_poll(s, ticket: int):
+    """(done, completion ms since the server was created or None)."""
+    d = C.c_int()
+    ms = C.c_double(-1.0)
+    _check(lib().psi_server_poll(s, ticket, C.byref(d), C.byref(ms)), "psi_server_poll")
+    return bool(d.value), (ms.value if d.value else None)
+
+
+def psi_server_wait(s, ticket: int) -> float:
+    ms = C.c_double(-1.0)
+    _check(lib().psi_server_wait(s, ticket, C.byref(ms)), "psi_server_wait")
+    return ms.value
+
+
+def psi_server_flush(s):
+    _check(lib().psi_server_flush(s), "psi_server_flush")
 
 
 def psi_graph_begin(stream=None):

@@ -75,7 +75,8 @@ void poll(psi_index ix) {
         ix->ev_pool.push_back(f.ev);
         ix->inflight.pop_front();
     }
-    if (!ix->grave.empty() && ix->inflight.empty() && hipStreamQuery(ix->st) == hipSuccess) {
+    if (!ix->grave.empty() && ix->inflight.empty() && hipStreamQuery(ix->st) == hipSuccess &&
+        (!ix->aux_st || hipStreamQuery(ix->aux_st) == hipSuccess)) {
         for (void* p : ix->grave) (void)hipFree(p);
         ix->grave.clear();
     }
@@ -85,6 +86,7 @@ psi_status settle(psi_index ix) {
     if (capturing(ix->st)) return PSI_E_STATE;
     psi_status s = hip_ok(hipStreamSynchronize(ix->st));
     if (s != PSI_OK) return s;
+    if (ix->aux_st && (s = hip_ok(hipStreamSynchronize(ix->aux_st))) != PSI_OK) return s;
     for (Inflight& f : ix->inflight) ix->ev_pool.push_back(f.ev);
     ix->inflight.clear();
     for (void* p : ix->grave) (void)hipFree(p);
@@ -151,8 +153,8 @@ psi_status readback(psi_index ix, const void* dev, size_t bytes) {
 // order whatever the input order), then the eight key bytes.
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
                       bool id_digits, bool hist_ready, int* which, const char* fam, uint32_t key_shift0,
-                      int key_passes) {
-    Sorter& S = ix->sorter;
+                      int key_passes, Sorter* sorter) {
+    Sorter& S = sorter ? *sorter : ix->sorter;
     PassList pl{};
     pl.n = 0;
     if (id_digits)
@@ -513,8 +515,8 @@ psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool b
     const bool sort = n >= ORDER_MIN && !(ix->flags & PSI_FLAG_INPUT_ORDER);
     if (boxes && !sort) return PSI_OK;
     psi_status s;
-    if ((s = ensure_q(ix, ix->scr.c, n * 8)) != PSI_OK) return s;
-    uint64_t* keys = ix->scr.c.as<uint64_t>();
+    if ((s = ensure_q(ix, ix->qkeys, n * 8)) != PSI_OK) return s;
+    uint64_t* keys = ix->qkeys.as<uint64_t>();
     {
         ProfScope ps(ix, "order", n * (boxes ? 8ull * ix->D : 4ull * ix->D) + n * 8);
         if (boxes) launch_encode_boxes(ix->st, ix->D, ix->curve, d_items, n, keys);
@@ -526,8 +528,10 @@ psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool b
     // passes instead of all 64 bits in eight.
     int w = 0;
     const uint32_t kb = ix->D == 2 ? 62u : 63u;
-    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order", kb - 24, 3)) != PSI_OK) return s;
-    *order = ix->sorter.i[w].as<uint32_t>();
+    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order", kb - 24, 3, &ix->qsorter)) !=
+        PSI_OK)
+        return s;
+    *order = ix->qsorter.i[w].as<uint32_t>();
     return last_launch();
 }
 
@@ -734,7 +738,7 @@ psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, u
         if (!cap) ix->boxes_fresh = true;
     }
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
-    launch_knn(ix->st, ix->D, ix->view(), d_q, ix->scr.c.as<uint64_t>(), nq, order, k,
+    launch_knn(ix->st, ix->D, ix->view(), d_q, ix->qkeys.as<uint64_t>(), nq, order, k,
                (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, d_ids, d_d2);
     return last_launch();
 }

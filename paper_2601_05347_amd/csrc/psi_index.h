@@ -234,8 +234,11 @@ struct psi_index_s {
 
     psi::Buf err;      // device u32 error bits
     void* pinned = nullptr;  // host readback area (4 KiB)
-    psi::Sorter sorter;
+    psi::Sorter sorter;    // builds and updates
+    psi::Sorter qsorter;   // query ordering: queries may run beside an update
+    psi::Buf qkeys;        // curve keys of a query batch
     psi::Scratch scr;
+    hipStream_t aux_st = nullptr;  // a second stream the index's queries run on (a server's)
     psi::Prof prof;
 
     uint64_t slot_words() const { return (uint64_t)(D + 1) * C; }
@@ -298,14 +301,20 @@ psi_status build_nodes(psi_index ix, uint64_t L_bound);
 // Exact tree view for exports (after settle()): leaf count, height and the
 // current directory from the state.
 psi::TreeView exact_view(psi_index ix, std::vector<psi::LevelInfo>* lv = nullptr);
+// sorter: the workspace (null: the index's update workspace).
 psi_status sort_pairs(psi_index ix, const uint64_t* kin, const uint32_t* iin, uint32_t id_base, uint64_t n,
                       bool id_digits, bool hist_ready, int* which, const char* fam, uint32_t key_shift0 = 0,
-                      int key_passes = 8);
+                      int key_passes = 8, Sorter* sorter = nullptr);
 psi_status readback(psi_index ix, const void* dev, size_t bytes);  // into ix->pinned, waits
 
 // updates (psi_update.hip)
-psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
-psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
+// before_apply (may be null): the stream waits for this event before the
+// first kernel that changes what queries read (leaves, directory, nodes);
+// the batch's encode, sort, routing and planning run before that.
+psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids,
+                     hipEvent_t before_apply = nullptr);
+psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted,
+                     hipEvent_t before_apply = nullptr);
 psi_status do_build(psi_index ix, const uint32_t* d_pts, uint64_t n);
 // Curve keys of n points into keys[0 .. n) and the pairs (key, id_base + i)
 // sorted by (key, id) into sorter.k/i[*which]; requires n > 0.

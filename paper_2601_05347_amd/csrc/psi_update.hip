@@ -194,7 +194,7 @@ psi_status reserve(psi_index ix, const Bounds& u, uint64_t L_cap, uint64_t A_max
 // device state and the counters, a one-thread check rejects a batch with an
 // out-of-range coordinate (or one that would not fit) before any leaf is
 // written, and a one-thread commit publishes the new state.
-psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids) {
+psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids, hipEvent_t before_apply) {
     psi_status s;
     hipStream_t st = ix->st;
     Bounds u;
@@ -254,6 +254,7 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
     st_ins_check(st, dt, a.ctr, m, phi, id_cap, cap);
     // new directory positions when leaves are re-cut (ctr[3] > 0): exclusive
     // scan of the per-leaf piece counts
+    if (before_apply && (s = hip_ok(hipStreamWaitEvent(st, before_apply, 0))) != PSI_OK) return s;
     st_fill_gated(st, a.pieces, Lg, 1u, a.ctr + 3);
     upd_ins_pieces(st, a.run_leaf, a.ctr, m, a.rpieces, a.rsplit, a.pieces);
     launch_scan_u32(st, a.pieces, a.newpos, Lg, a.ctr + 2, a.tmp, a.ctr + 3);
@@ -288,7 +289,7 @@ psi_status do_insert(psi_index ix, const uint32_t* d_pts, uint64_t m, uint32_t* 
 }
 
 // Batch delete, queued without waiting, in the same way.
-psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted) {
+psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted, hipEvent_t before_apply) {
     psi_status s;
     hipStream_t st = ix->st;
     if (m == 0) {
@@ -337,6 +338,7 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
     upd_del_kill(st, a.ci, a.ctr, m, ix->idkey.as<uint64_t>(), d_ndeleted);
     upd_route(st, a.ck, a.ci, m, a.ctr + 0, dt, cap.dirs, a.leaf_of);
     upd_runs(st, a.leaf_of, m, a.ctr + 0, a.flag, a.ridx, a.run_leaf, a.run_beg, a.ctr + 1, a.tmp);
+    if (before_apply && (s = hip_ok(hipStreamWaitEvent(st, before_apply, 0))) != PSI_OK) return s;
     upd_del_remove(st, ix->D, a.ci, a.run_leaf, a.run_beg, a.ctr, m, dt, slots, ix->C, phi, a.ctr + 8,
                    ix->err.as<uint32_t>(), cap);
     // Leaves below the minimum can only come from this delete (every update

@@ -17,6 +17,12 @@ continuous batching:
 * consistency: every request sees exactly the updates that arrived before
   it, as if the requests ran one by one in arrival order.
 
+`DeviceServer` does the same through the library's server (psi_server_*):
+admission, epochs and the fusion of updates and kNN batches happen in the
+C++ runtime, updates and queries run on two streams, and an update's batch
+sort and routing overlap the queries of the epoch before it. This module
+then only stages payloads and submits and polls requests.
+
 Latency of a request = completion (a HIP event after its epoch) minus its
 scheduled arrival. The index is the library's (all work runs in its HIP
 kernels); this module only schedules.
@@ -28,8 +34,9 @@ from collections import deque
 
 import numpy as np
 
-from . import (Index, psi_batch_delete, psi_batch_insert, psi_knn, psi_range_count, psi_range_report, to_u32,
-               to_u64)
+from . import (REQ_DELETE, REQ_INSERT, REQ_KNN, REQ_RANGE_REPORT, Index, PsiError, psi_batch_delete, psi_batch_insert,
+               psi_knn, psi_range_count, psi_range_report, psi_server_create, psi_server_destroy, psi_server_poll,
+               psi_server_submit, psi_server_wait, to_u32, to_u64)
 
 UPDATE, QUERY = 0, 1
 KIND_CLASS = {"insert": UPDATE, "delete": UPDATE, "knn": QUERY, "range": QUERY}
@@ -227,6 +234,7 @@ class BatchServer:
         pending = deque(reqs)
         queue = deque()
         in_flight = 0
+        self.max_in_flight = 0
         epochs = []  # (event, requests) awaiting completion times
 
         def admit():
@@ -238,11 +246,16 @@ class BatchServer:
                     pending.popleft()
                     r["rejected"] = True
                     continue
-                if in_flight + fp > self.budget and queue:
-                    break
+                if in_flight + fp > self.budget:
+                    if queue:  # serve what is admitted first
+                        break
+                    if epochs:  # wait for the oldest epoch to free its share, then retry
+                        finish([epochs.pop(0)])
+                        continue
                 pending.popleft()
                 r["fp"] = fp
                 in_flight += fp
+                self.max_in_flight = max(self.max_in_flight, in_flight)
                 self._stage(r)
                 queue.append(r)
 
@@ -343,3 +356,129 @@ class BatchServer:
                 n = len(r["boxes"])
                 r["result_dev"] = (off[o:o + n + 1], out)
                 o += n
+
+
+class DeviceServer:
+    """Continuous batching by the library's server (psi_server_*): this class
+    stages each request's payload on a copy stream, submits it with the
+    upload's event, and polls for completion; admission, epochs, fusion and
+    the overlap of updates with queries happen in the C++ runtime."""
+
+    def __init__(self, index: Index, budget_bytes: int = 32 << 30, staging_bytes: int = 64 << 20,
+                 report_slack: float = 4.0):
+        import torch
+        self.ix = index
+        self.budget = budget_bytes
+        self.copy_stream = torch.cuda.Stream(device=index.device)
+        self.ring = _PinnedRing(staging_bytes)
+        self.report_slack = report_slack
+        self.n_live = None
+
+    _stage = BatchServer._stage
+
+    def _report_capacity(self, boxes, n_live: int, bits: int) -> int:
+        """Output room for a range report: the expected hits of each box under
+        a uniform density (n_live points in [0, 2^bits)^dim), times a slack,
+        plus a margin; a box past the room is truncated and reported as such."""
+        b = np.asarray(boxes, dtype=np.float64).reshape(len(boxes), 2, -1)
+        vol = np.prod(np.maximum(b[:, 1] - b[:, 0] + 1, 0), axis=1) / float(1 << bits) ** b.shape[2]
+        return int(self.report_slack * float(vol.sum()) * n_live) + 1024 * len(boxes) + 1024
+
+    def run(self, reqs, realtime: bool = True, n_live: int = 0, bits: int = 21):
+        import torch
+        ix = self.ix
+        dev, D = ix.device, ix.dim
+        srv = psi_server_create(ix._h, self.budget)
+        t0 = time.perf_counter()  # the server's clock starts at creation (its base event has completed)
+        live = n_live
+        outstanding = deque()
+        try:
+            i = 0
+            while i < len(reqs) or outstanding:
+                now = time.perf_counter() - t0
+                while i < len(reqs) and (not realtime or reqs[i]["arrival"] <= now):
+                    r = reqs[i]
+                    i += 1
+                    self._stage(r)
+                    k = r["kind"]
+                    if k == "insert":
+                        n = len(r["points"])
+                        r["out"] = (torch.empty(max(n, 1), dtype=torch.int32, device=dev),)
+                        r["ticket"] = psi_server_submit(srv, REQ_INSERT, n, r["dev"], d_ids=r["out"][0],
+                                                        ready_event=r["ready"])
+                        live += n
+                    elif k == "delete":
+                        n = len(r["ids"])
+                        # written by the delete itself (a fill here would run on another
+                        # stream, unordered with the server's write)
+                        r["out"] = (torch.empty(1, dtype=torch.int64, device=dev),)
+                        r["ticket"] = psi_server_submit(srv, REQ_DELETE, n, r["dev"], d_out=r["out"][0],
+                                                        ready_event=r["ready"])
+                        live -= n
+                    elif k == "knn":
+                        n, kk = len(r["queries"]), r.get("k", 10)
+                        r["out"] = (torch.empty((max(n, 1), kk), dtype=torch.int32, device=dev),
+                                    torch.empty((max(n, 1), kk), dtype=torch.int64, device=dev))
+                        r["ticket"] = psi_server_submit(srv, REQ_KNN, n, r["dev"], d_ids=r["out"][0],
+                                                        d_out=r["out"][1], k=kk, ready_event=r["ready"])
+                    else:
+                        n = len(r["boxes"])
+                        cap = self._report_capacity(r["boxes"], max(live, 1), bits)
+                        r["out"] = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+                                    torch.empty(cap, dtype=torch.int32, device=dev))
+                        r["cap"] = cap
+                        r["ticket"] = psi_server_submit(srv, REQ_RANGE_REPORT, n, r["dev"], d_ids=r["out"][1],
+                                                        d_out=r["out"][0], ids_cap=cap, ready_event=r["ready"])
+                    outstanding.append(r)
+                # completions (each poll also dispatches what is queued)
+                still = deque()
+                for r in outstanding:
+                    try:
+                        done, ms = psi_server_poll(srv, r["ticket"])
+                    except PsiError as e:
+                        if e.code != 4:  # PSI_E_CAPACITY: a request larger than the whole budget
+                            raise
+                        r["rejected"] = True
+                        r.pop("out", None)
+                        continue
+                    if done:
+                        self._finish(r, ms)
+                    else:
+                        still.append(r)
+                outstanding = still
+                if outstanding or i < len(reqs):
+                    nxt = reqs[i]["arrival"] if i < len(reqs) and realtime else None
+                    if not outstanding and nxt is not None:
+                        time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 2e-4)))
+                    elif outstanding:
+                        time.sleep(5e-5)
+        finally:
+            for r in outstanding:
+                try:
+                    self._finish(r, psi_server_wait(srv, r["ticket"]))
+                except PsiError as e:
+                    if e.code != 4:
+                        raise
+                    r["rejected"] = True
+            psi_server_destroy(srv)
+        return reqs
+
+    def _finish(self, r, ms):
+        r["done_s"] = ms / 1e3
+        r["latency_ms"] = (r["done_s"] - r["arrival"]) * 1e3
+        out = r.pop("out")
+        k = r["kind"]
+        if k == "insert":
+            r["result"] = to_u32(out[0][:len(r["points"])])
+        elif k == "delete":
+            r["result"] = int(to_u64(out[0])[0])
+        elif k == "knn":
+            n = len(r["queries"])
+            r["result"] = (to_u32(out[0][:n]), to_u64(out[1][:n]))
+        else:
+            off = to_u64(out[0])
+            total = int(off[-1])
+            r["truncated"] = total > r["cap"]
+            r["result"] = (off, to_u32(out[1][:min(total, r["cap"])]))
+        r.pop("dev", None)
+        r.pop("_host", None)
