@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=32_000_000, help="points in the oracle's timed sample")
+    ap.add_argument("--cpu-queries", type=int, default=512, help="queries and boxes in the oracle's timed sample")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving block of the default line")
+    ap.add_argument("--serve-requests", type=int, default=600, help="requests in the default line's serving block")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests per stream")
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
@@ -116,8 +119,25 @@ def profiled_traffic(profile: str, family: str):
     return int(m_t.group(1))
 
 
-def cpu_baseline(cfg, args):
-    """The oracle timed on a bounded sample of the same workload (one core)."""
+CPU_THREADS = 16  # the host cores one GPU's box share has
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, args, full=None):
+    """The oracle timed on bounded samples of the same workload: build and
+    updates on one core over a sample of the points, then (given the full
+    point set, its queries and boxes) brute-force kNN and range counts over
+    all n points for a seeded sample of queries and boxes on CPU_THREADS
+    threads, reported per query (no extrapolation in n)."""
     import numpy as np
 
     import oracle
@@ -133,13 +153,35 @@ def cpu_baseline(cfg, args):
     ref.batch_insert(ins)
     ref.batch_delete(dels)
     dt = time.perf_counter() - t0
-    return {"value": round((n + 2 * m) / dt / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"build {n} + insert {m} + delete {m} {dim}D {args.dist} {args.curve} points, "
-                      f"single-threaded std::sort/std::merge oracle, {dt:.2f} s"}
+    del ref, data, ins, dels
+    out = {"value": round((n + 2 * m) / dt / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+           "sample": f"build {n} + insert {m} + delete {m} {dim}D {args.dist} {args.curve} points, "
+                     f"single-threaded std::sort/std::merge oracle, {dt:.2f} s",
+           "host_cores": os.cpu_count(), "cpu_model": cpu_model()}
+    if full is not None:
+        pts, q, boxes, k = full
+        rows = synth.sample_rows(len(q), args.cpu_queries, args.seed + 11)
+        t0 = time.perf_counter()
+        oracle.knn_points(pts, q[rows], k, threads=CPU_THREADS)
+        tk = time.perf_counter() - t0
+        brows = synth.sample_rows(len(boxes), args.cpu_queries, args.seed + 12)
+        t0 = time.perf_counter()
+        oracle.range_count_points(pts, boxes[brows], threads=CPU_THREADS)
+        tr = time.perf_counter() - t0
+        out["knn"] = {"value": round(len(rows) / tk, 3), "unit": "queries/s", "cores": CPU_THREADS,
+                      "ms_per_query": round(tk * 1e3 / len(rows), 3),
+                      "sample": f"{len(rows)} seeded {k}-NN queries, brute force over all {len(pts)} points, "
+                                f"{tk:.2f} s"}
+        out["range_count"] = {"value": round(len(brows) / tr, 3), "unit": "boxes/s", "cores": CPU_THREADS,
+                              "ms_per_box": round(tr * 1e3 / len(brows), 3),
+                              "sample": f"{len(brows)} seeded boxes, scan of all {len(pts)} points, {tr:.2f} s"}
+    return out
 
 
-def bench_serve(args):
-    """Serving configuration: plain per-request path vs continuous batching."""
+def serve_runs(n0, n_requests, rhos, seed, leaf, fanout, paths=("plain", "batched", "library"), probe_n=400):
+    """Serving: a resident 3D SPaC-H index of n0 uniform points and a Poisson
+    stream of mixed requests at rho times the plain path's capacity, served
+    by each path on a fresh index; p50/p99 per request type and throughput."""
     import numpy as np
     import torch
 
@@ -147,49 +189,65 @@ def bench_serve(args):
     import synth
     from paper_2601_05347_amd import serve
     cfg = WORKLOADS["serve"]
-    dim, bits, n0 = cfg["dim"], cfg["bits"], args.n or cfg["n"]
+    dim, bits = cfg["dim"], cfg["bits"]
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    base = synth.uniform(n0, dim, bits, args.seed)
-    reqs = synth.request_stream(args.requests, n0, dim, bits, args.seed + 7, rate_per_s=1.0)
+    base = synth.uniform(n0, dim, bits, seed)
+    reqs = synth.request_stream(n_requests, n0, dim, bits, seed + 7, rate_per_s=1.0)
     log(f"serve: {len(reqs)} requests generated in {time.perf_counter() - t:.1f} s")
     d_base = torch.from_numpy(base.view(np.int32)).to(dev)
 
     def fresh():
-        ix = psi.Index(dim, psi.HILBERT, args.leaf, args.fanout, device=dev)
+        ix = psi.Index(dim, psi.HILBERT, leaf, fanout, device=dev)
         psi.psi_build(ix._h, d_base, n0)
         ix.sync()
         return ix
 
     # capacity of the plain path: back-to-back service of a prefix of the stream
-    probe = [dict(r) for r in reqs[:400]]
+    probe = [dict(r) for r in reqs[:probe_n]]
     ix = fresh()
     serve.PlainServer(ix).run(probe, realtime=False)
     lam_plain = len(probe) / probe[-1]["done_s"]  # back-to-back service from t = 0
     log(f"serve: plain path capacity {lam_plain:.1f} requests/s")
-    del ix
+    ix.close()
+    classes = {"plain": serve.PlainServer, "batched": serve.BatchServer, "library": serve.DeviceServer}
     runs = {}
-    for rho in [float(x) for x in args.rho.split(",")]:
+    for rho in rhos:
         lam = rho * lam_plain
         stream_r = [dict(r, arrival=r["arrival"] / lam) for r in reqs]
         res = {}
-        for name, cls in (("plain", serve.PlainServer), ("batched", serve.BatchServer)):
+        for name in paths:
             ix = fresh()
             rs = [dict(r) for r in stream_r]
-            cls(ix).run(rs, realtime=True)
+            if name == "library":
+                classes[name](ix).run(rs, realtime=True, n_live=n0, bits=bits)
+            else:
+                classes[name](ix).run(rs, realtime=True)
             ix.sync()
             res[name] = serve.summarize(rs)
-            log(f"serve rho={rho} {name}: p99 {res[name]['all']['p99_ms']:.1f} ms, "
-                f"{res[name]['throughput_req_s']:.1f} req/s")
-            del ix, rs
+            log(f"serve rho={rho} {name}: p50 {res[name]['all']['p50_ms']:.1f} ms, p99 {res[name]['all']['p99_ms']:.1f} "
+                f"ms, {res[name]['throughput_req_s']:.1f} req/s")
+            ix.close()
+            del rs
         runs[f"rho={rho}"] = res
-    b = runs[max(runs)]["batched"]
+    return lam_plain, runs
+
+
+def bench_serve(args):
+    """Serving configuration: plain per-request path vs continuous batching
+    (the Python scheduler and the library's server)."""
+    cfg = WORKLOADS["serve"]
+    n0 = args.n or cfg["n"]
+    lam_plain, runs = serve_runs(n0, args.requests, [float(x) for x in args.rho.split(",")], args.seed, args.leaf,
+                                 args.fanout)
+    b = runs[max(runs)]["library"]
     out = {"metric": "p99 latency (ms) of mixed requests, continuous batching, 1 GPU", "value": round(b["all"]["p99_ms"], 3),
            "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64",
            "data": "synthetic",
-           "config": {"workload": "serve: resident 3D SPaC-H, uniform", "n0": n0, "requests": args.requests,
-                      "mix": "40/20/30/10 insert/delete/knn/range", "plain_capacity_req_s": round(lam_plain, 2)},
+           "config": {"workload": "serve: resident 3D SPaC-H, uniform, library server", "n0": n0,
+                      "requests": args.requests, "mix": "40/20/30/10 insert/delete/knn/range",
+                      "plain_capacity_req_s": round(lam_plain, 2)},
            "runs": runs}
     print(json.dumps(out), flush=True)
 
@@ -568,7 +626,7 @@ def main():
     d_dels = torch.from_numpy(dels.view(np.int32)).to(dev)
     d_q = torch.from_numpy(q.view(np.int32)).to(dev)
     d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
-    del data, ins, q
+    del ins  # the points, queries and boxes stay on the host for the CPU baseline
     stream = torch.cuda.current_stream(dev)
     ix = psi.Index(dim, curve, args.leaf, args.fanout, device=dev, stream=stream,
                    flags=psi.FLAG_SORTED_LEAVES if args.sorted_leaves else 0)
@@ -701,9 +759,23 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "roofline": roof,
     }
+    ix.close()
+    del d_data, d_ins, d_dels, d_q, d_boxes, k_ids, k_d2, r_ids
+    torch.cuda.empty_cache()
+    if not args.no_serve and args.workload == "3d-1e8":
+        scfg = WORKLOADS["serve"]
+        log("serving block ...")
+        lam_plain, runs = serve_runs(scfg["n"], args.serve_requests, [1.2], args.seed, args.leaf, args.fanout,
+                                     paths=("plain", "library"))
+        r = runs["rho=1.2"]
+        out["serve"] = {"workload": f"resident 3D SPaC-H, {scfg['n']} uniform points, {args.serve_requests} "
+                                    "Poisson requests 40/20/30/10 insert/delete/knn/range at 1.2x plain capacity",
+                        "plain_capacity_req_s": round(lam_plain, 2),
+                        **{name: {"p50_ms": round(r[name]["all"]["p50_ms"], 2), "p99_ms": round(r[name]["all"]["p99_ms"], 2),
+                                  "throughput_req_s": round(r[name]["throughput_req_s"], 2)} for name in r}}
     if not args.no_cpu:
         log("timing the oracle on a CPU sample ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args)
+        out["cpu_baseline"] = cpu_baseline(cfg, args, full=(data, q, boxes, k) if "knn" in ops else None)
     print(json.dumps(out), flush=True)
 
 
