@@ -238,6 +238,82 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     }
 }
 
+// The same search with a stack of child masks. Expanding a node reads the
+// boxes of all its children in one batch of independent loads and keeps the
+// ones within the current k-th distance as a bit mask, one per level, in LDS
+// (`stk`, this lane's words `blockDim.x` apart); the walk then takes the set
+// bits in order, checking each node again against the (by then smaller) k-th
+// distance before expanding or scanning it. A node costs one round trip to
+// memory instead of one per sibling. Needs h() <= the stack depth; the
+// caller takes the other walk beyond it.
+template <int D, int K, class T>
+__device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv, const uint32_t* q, uint64_t key,
+                                                 uint64_t (&bd)[K], uint32_t (&bi)[K], uint32_t* __restrict__ stk,
+                                                 uint32_t stride) {
+    const uint32_t L = tr.L();
+    if (L == 0) return;
+    uint32_t lo = 0, hi = L;  // first pivot key above the query's key
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tr.pkey(mid) <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t j = lo ? lo - 1 : 0u;
+    const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
+    for (uint32_t x = ja; x <= jb; ++x) {
+        const uint2 sc = tr.leaf_sc(x);  // (count, slot)
+        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, false);
+    }
+    const uint32_t B = tr.B(), h = tr.h();
+    if (h == 0) return;  // a single leaf, scanned as a seed
+    // children of node `node` on level l + 1 within the k-th distance (the
+    // seed leaves left out)
+    auto expand = [&](uint32_t l, uint32_t node) -> uint32_t {
+        const uint32_t c0 = node * B, nc = min(B, tr.levn(l + 1) - c0);
+        const uint64_t kth = bd[K - 1];
+        const bool leaves = l + 1 == h;
+        uint32_t m = 0;
+#pragma unroll 8
+        for (uint32_t x = 0; x < nc; ++x) {
+            const uint32_t c = c0 + x;
+            const uint64_t d = tr.dist(l + 1, c, q);
+            const bool keep = d != PAD_D2 && d <= kth && !(leaves && c >= ja && c <= jb);
+            m |= keep ? 1u << x : 0u;
+        }
+        return m;
+    };
+    {
+        const uint64_t d = tr.dist(0, 0, q);
+        if (d == PAD_D2 || d > bd[K - 1]) return;
+    }
+    uint32_t l = 0, base = 0;  // the mask of level l covers the children base .. base + B - 1 (level l + 1)
+    stk[0] = expand(0, 0);
+    for (;;) {
+        const uint32_t m = stk[l * stride];
+        if (m == 0) {
+            if (l == 0) break;
+            --l;
+            base = base / B / B * B;
+            continue;
+        }
+        const uint32_t b = (uint32_t)__builtin_ctz(m);
+        stk[l * stride] = m & (m - 1);
+        const uint32_t c = base + b;
+        if (l + 1 == h) {
+            const uint64_t d = tr.dist(h, c, q);
+            const uint2 sc = tr.leaf_sc(c);
+            if (d <= bd[K - 1]) scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, true);
+            continue;
+        }
+        const uint64_t d = tr.dist(l + 1, c, q);
+        const uint32_t cm = expand(l + 1, c);
+        if (d > bd[K - 1] || cm == 0) continue;
+        ++l;
+        stk[l * stride] = cm;
+        base = c * B;
+    }
+}
+
 // Squared distance from q to a packed box (PAD_D2 for an empty node).
 template <int D>
 __device__ __forceinline__ uint64_t packed_dist(const uint32_t* q, uint4 v) {
@@ -272,12 +348,18 @@ struct SingleTree {
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
 };
 
-template <int D, int K>
-__global__ __launch_bounds__(256) void k_knn_seed(TreeView tv, const uint32_t* __restrict__ qp,
+// MASKS: the walk with a stack of child masks, s_stk, hcap levels of one
+// word per lane (dynamic LDS); a taller tree (never met: hcap bounds the
+// height of every tree the buffers can hold) leaves its queries unanswered
+// and flags ERR_STACK.
+template <int D, int K, bool MASKS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((K <= 8 || K == 10) ? 5 : 1))) void k_knn_seed(TreeView tv, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
-                                                  const uint32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ order, uint32_t hcap,
+                                                  uint32_t* __restrict__ err,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
+    extern __shared__ uint32_t s_stk[];
     const TreeView t = resolve_tree(tv);
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
@@ -295,7 +377,9 @@ __global__ __launch_bounds__(256) void k_knn_seed(TreeView tv, const uint32_t* _
         bi[j] = PAD_ID;
     }
     const SingleTree<D> tr{t, s_lv};
-    knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
+    if (!MASKS) knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
+    else if (t.h <= hcap) knn_seeded_masks<D, K>(tr, t, q, qkeys[qi], bd, bi, s_stk + threadIdx.x, blockDim.x);
+    else if (tq == 0) atomicOr(err, ERR_STACK);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         out_ids[qi * K + j] = bi[j];
@@ -852,14 +936,18 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
 }  // namespace
 
 void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
-                const uint32_t* order, uint32_t k, int variant, uint32_t* ids, uint64_t* d2) {
+                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err, uint32_t* ids,
+                uint64_t* d2) {
     if (nq == 0) return;
+    const bool masks = hcap <= KNN_STACK_MAX;
+    const size_t lds = masks ? (size_t)max(hcap, 1u) * 256 * 4 : 0;
     const unsigned gl = blocks_for(nq, 256);
     const unsigned gw = blocks_for(nq, KW_WAVES);
 #define PSI_KL(D, K)                                                                                             \
     do {                                                                                                         \
         if (variant == 1) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, order, ids, d2); \
-        else hipLaunchKernelGGL((k_knn_seed<D, K>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, ids, d2); \
+        else if (masks) hipLaunchKernelGGL((k_knn_seed<D, K, true>), dim3(gl), dim3(256), lds, st, t, q, qkeys, nq, order, hcap, err, ids, d2); \
+        else hipLaunchKernelGGL((k_knn_seed<D, K, false>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, hcap, err, ids, d2); \
     } while (0)
 #define PSI_KL_ALL(D)                                                                                    \
     switch (k) {                                                                                         \

@@ -737,9 +737,12 @@ psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, u
         launch_pack_tree(ix->st, ix->D, ix->dt(), dirs_of(ix), false, ix->inner.as<NodeRec>(), ix->cinner.as<uint4>(), ni);
         if (!cap) ix->boxes_fresh = true;
     }
+    // the tree is never taller than one over the leaves the node buffers hold
+    uint32_t hcap = 0;
+    for (uint64_t n = ix->L_cap; n > 1; ++hcap) n = (n + ix->B - 1) / ix->B;
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
     launch_knn(ix->st, ix->D, ix->view(), d_q, ix->qkeys.as<uint64_t>(), nq, order, k,
-               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, d_ids, d_d2);
+               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, hcap, ix->err.as<uint32_t>(), d_ids, d_d2);
     return last_launch();
 }
 

@@ -15,6 +15,7 @@ enum : uint32_t {
     ERR_DELETE = 4u,    // a routed delete did not find its id in the leaf
     ERR_CAPACITY = 8u,  // a leaf slot overflowed (internal check)
     ERR_ORTH = 16u,     // a consistency check of the P-Orth build failed
+    ERR_STACK = 32u,    // a kNN walk met a tree taller than its stack (internal check)
 };
 
 constexpr uint32_t PAD_ID = 0xFFFFFFFFu;
@@ -207,19 +208,21 @@ __device__ __forceinline__ uint64_t pt_dist(const uint32_t* q, const uint32_t* p
     return s;
 }
 
-// Insert (d, id) into an ascending list of K pairs held in registers.
+// Insert (d, id) into an ascending list of K pairs held in registers: the
+// new pair is carried down the list, swapping places with every larger
+// entry, so the largest falls off the end. Every step updates its entry in
+// place (no second copy of the list is live).
 template <int K>
 __device__ __forceinline__ void topk_insert(uint64_t (&bd)[K], uint32_t (&bi)[K], uint64_t d, uint32_t id) {
 #pragma unroll
-    for (int j = K - 1; j > 0; --j) {
-        const bool shift = pair_less(d, id, bd[j - 1], bi[j - 1]);
-        const bool here = !shift && pair_less(d, id, bd[j], bi[j]);
-        bd[j] = shift ? bd[j - 1] : (here ? d : bd[j]);
-        bi[j] = shift ? bi[j - 1] : (here ? id : bi[j]);
-    }
-    if (pair_less(d, id, bd[0], bi[0])) {
-        bd[0] = d;
-        bi[0] = id;
+    for (int j = 0; j < K; ++j) {
+        const bool lt = pair_less(d, id, bd[j], bi[j]);
+        const uint64_t od = bd[j];
+        const uint32_t oi = bi[j];
+        bd[j] = lt ? d : od;
+        bi[j] = lt ? id : oi;
+        d = lt ? od : d;
+        id = lt ? oi : id;
     }
 }
 
