@@ -419,12 +419,15 @@ __global__ void k_chunk_counts(const uint64_t* __restrict__ q_off, uint32_t num,
 
 // Persistent: every wave takes (index, 64-query chunk) items from an atomic
 // counter until none are left, so uneven batches spread over the whole GPU.
+// s_stk: the walk's stacks of child masks, hcap (the tallest index's
+// height) levels of one word per lane.
 template <int D, int CURVE, int K>
-__global__ __launch_bounds__(256) void k_multi_knn(TreeView tv, const IdxMeta* __restrict__ meta, uint32_t num,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 ? K <= 8 : K <= 2) ? 5 : 1))) void k_multi_knn(TreeView tv, const IdxMeta* __restrict__ meta, uint32_t num,
                                                    const uint64_t* __restrict__ q_off, const uint32_t* __restrict__ qp,
                                                    const uint32_t* __restrict__ pref, uint32_t* __restrict__ work_ctr,
-                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2,
-                                                   uint32_t* __restrict__ err) {
+                                                   uint32_t hcap, uint32_t* __restrict__ out_ids,
+                                                   uint64_t* __restrict__ out_d2, uint32_t* __restrict__ err) {
+    extern __shared__ uint32_t s_stk[];
     const uint32_t lane = lane_id();
     const uint32_t W = pref[num];
     for (;;) {
@@ -455,7 +458,8 @@ __global__ __launch_bounds__(256) void k_multi_knn(TreeView tv, const IdxMeta* _
                 bi[j] = PAD_ID;
             }
             const MultiTree<D> tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
-            knn_seeded<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi);
+            if (tr.h() <= hcap) knn_seeded_masks<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi, s_stk + threadIdx.x, blockDim.x);
+            else atomicOr(err, ERR_STACK);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 out_ids[qi * K + j] = bi[j];
@@ -969,7 +973,7 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, c
 
 void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, const IdxMeta* meta, uint32_t num,
                       const uint64_t* q_off, const uint32_t* q, uint32_t* chunk_pref, uint32_t* work_ctr, uint32_t k,
-                      uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err) {
+                      uint32_t hcap, uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err) {
     if (num == 0) return;
     hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(num, 256)), dim3(256), 0, st, q_off, num, chunk_pref);
     launch_scan_u32(st, chunk_pref, chunk_pref, num, chunk_pref + num, tmp);
@@ -977,7 +981,8 @@ void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, co
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const dim3 g((unsigned)(cus * 8));
-#define PSI_MK(D, CV, K) hipLaunchKernelGGL((k_multi_knn<D, CV, K>), g, dim3(256), 0, st, tv, meta, num, q_off, q, chunk_pref, work_ctr, ids, d2, err)
+    const size_t lds = (size_t)max(hcap, 1u) * 256 * 4;
+#define PSI_MK(D, CV, K) hipLaunchKernelGGL((k_multi_knn<D, CV, K>), g, dim3(256), lds, st, tv, meta, num, q_off, q, chunk_pref, work_ctr, hcap, ids, d2, err)
 #define PSI_MK_K(D, CV)                                                                                  \
     switch (k) {                                                                                         \
         case 1: PSI_MK(D, CV, 1); break;  case 2: PSI_MK(D, CV, 2); break;  case 4: PSI_MK(D, CV, 4); break; \

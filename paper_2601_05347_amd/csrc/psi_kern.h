@@ -416,8 +416,9 @@ void launch_node_step_seg(hipStream_t st, int dim, uint32_t num, uint64_t nparen
                           const IdxMeta* meta, const NodeRec* leafrec, NodeRec* inner, uint32_t B);
 // kNN over many indexes in one persistent launch; work items are (index,
 // chunk of 64 queries) taken from an atomic counter (zeroed before launch).
+// hcap: the tallest index's height (sizes the walk's stack in LDS).
 void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, const IdxMeta* meta, uint32_t num,
                       const uint64_t* q_off, const uint32_t* q, uint32_t* chunk_pref, uint32_t* work_ctr, uint32_t k,
-                      uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err);
+                      uint32_t hcap, uint32_t* ids, uint64_t* d2, uint32_t* tmp, uint32_t* err);
 
 }  // namespace psi

@@ -14,6 +14,7 @@ struct psi_multi_s {
     uint32_t phi = 32, C = 64, B = 8;
     hipStream_t st = nullptr;
     uint32_t num = 0;
+    uint32_t max_h = 0;  // the tallest index's height
     uint64_t n_total = 0, total_leaves = 0, total_inner = 0, total_tiles = 0;
     std::vector<uint64_t> pt_off;   // host copy of the point offsets
     std::vector<IdxMeta> meta_h;    // host copy of the per-index metadata
@@ -104,6 +105,7 @@ psi_status multi_build(psi_multi mx, const uint64_t* d_pt_off, const uint32_t* d
         inner_total += o;
         max_h = std::max(max_h, m.h);
     }
+    mx->max_h = max_h;
     mx->total_tiles = tile_seg.size();
     mx->total_leaves = leaf_off[num];
     mx->total_inner = inner_total;
@@ -247,7 +249,7 @@ psi_status psi_multi_knn(psi_multi mx, const uint64_t* d_q_off, const uint32_t* 
     uint32_t* work = pref + mx->num + 1;
     uint32_t* tmp = work + 16;
     launch_multi_knn(mx->st, mx->D, mx->curve, mx->view(), mx->meta.as<IdxMeta>(), mx->num, d_q_off, d_q, pref, work, k,
-                     d_ids, d_d2, tmp, mx->err.as<uint32_t>());
+                     mx->max_h, d_ids, d_d2, tmp, mx->err.as<uint32_t>());
     return hip_ok(hipGetLastError());
 }
 
