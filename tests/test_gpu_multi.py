@@ -107,3 +107,48 @@ def test_multi_rejects_bad_input(psi):
     with pytest.raises(psi.PsiError):
         M.knn(np.array([0, 1, 2], np.uint64), pts[:2], 3)  # k = 3 unsupported here
     torch.cuda.synchronize()
+
+
+def test_multi_full_size(psi):
+    """The batched-index configuration at its real size: 4096 2D SPaC-Z
+    indexes with sizes log-uniform in 1e3..1e6 (about 5.8e8 points) and
+    1..1e4 queries each, k = 8. Every row is checked for what holds at any
+    size (d2 equal to the squared distance to the returned point of its own
+    index, rows ascending in (d2, id)); a seeded sample of indexes is
+    brute-forced by the oracle."""
+    import torch
+    say("multi full size")
+    num = 4096
+    r = synth.unit(synth.draws(synth.stream_key(0, 77), 0, 2 * num))
+    sizes = np.floor(10 ** (3 + 3 * r[:num])).astype(np.int64)
+    qsizes = np.floor(10 ** (4 * r[num:])).astype(np.int64).clip(1, 10_000)
+    allp = np.concatenate([synth.uniform(int(n), 2, 30, 1000 + i) for i, n in enumerate(sizes)])
+    allq = np.concatenate([synth.uniform(int(n), 2, 30, 1000 + i, synth.P_QUERY) for i, n in enumerate(qsizes)])
+    off = np.concatenate(([0], np.cumsum(sizes))).astype(np.uint64)
+    qoff = np.concatenate(([0], np.cumsum(qsizes))).astype(np.uint64)
+    say(f"  {len(allp)} points, {len(allq)} queries")
+    M = psi.MultiIndex(2, 0, off, allp, 32, 8)
+    ids, d2 = M.knn(qoff, allq, 8)
+    M.sync()
+    dev = ids.device
+    owner = torch.repeat_interleave(torch.arange(num, device=dev), torch.from_numpy(qsizes).to(dev))
+    base = torch.from_numpy(off[:-1].astype(np.int64)).to(dev)[owner]
+    loc = ids.long()
+    assert bool((loc >= 0).all()) and bool((loc < torch.from_numpy(sizes).to(dev)[owner].unsqueeze(1)).all())
+    pts_d = torch.from_numpy(allp.astype(np.int64)).to(dev)
+    q_d = torch.from_numpy(allq.astype(np.int64)).to(dev)
+    for a in range(0, len(allq), 1_000_000):
+        g = loc[a:a + 1_000_000] + base[a:a + 1_000_000].unsqueeze(1)
+        dd = ((pts_d[g] - q_d[a:a + 1_000_000].unsqueeze(1)) ** 2).sum(-1)
+        assert torch.equal(dd, d2[a:a + 1_000_000])
+        l, d = loc[a:a + 1_000_000], d2[a:a + 1_000_000]
+        assert bool(((d[:, :-1] < d[:, 1:]) | ((d[:, :-1] == d[:, 1:]) & (l[:, :-1] < l[:, 1:]))).all())
+    del pts_d, q_d
+    h_ids, h_d2 = psi.to_u32(ids), psi.to_u64(d2)
+    for s in synth.sample_rows(num, 8, seed=78):
+        a, b = int(qoff[s]), int(qoff[s + 1])
+        rows = np.arange(a, b)[: 256]
+        p = allp[int(off[s]):int(off[s + 1])]
+        eids, ed2 = oracle.knn_points(p, allq[rows], 8, threads=16)
+        np.testing.assert_array_equal(h_d2[rows], ed2, err_msg=f"index {s}")
+        np.testing.assert_array_equal(h_ids[rows], eids, err_msg=f"index {s}")
