@@ -470,31 +470,103 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 ? K
 }
 
 // ------------------------------------------------------- kNN, wave per query
-// The k best pairs live in LDS, ascending. A leaf is scanned one entry per
-// lane; the entries that beat the current k-th pair are ranked among
-// themselves, and both lists are merged by rank (merge by binary search).
+// For k > 16. The k best pairs live in LDS, ascending, in two copies (a merge
+// writes the other one). A leaf is merged in one entry per lane: the entries
+// that beat the current k-th pair are ranked among themselves, and every
+// list entry and candidate finds its new place by binary search in the other
+// sequence. The search is seeded with the leaves around the query's curve
+// position until they hold at least max(2k, 64) points; the tree is then
+// walked as in the lane-per-query search, with the wave testing a node's
+// children one per lane and the stack of child masks in LDS.
 constexpr int KW_WAVES = 4;
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint64_t x = shfl_u64(v, (int)(lane_id() ^ o));
-        v = x < v ? x : v;
+template <int KMAX>
+struct KList {
+    uint64_t (*d)[KMAX];  // [2][KMAX]
+    uint32_t (*i)[KMAX];
+    uint64_t* cd;         // [64] candidates
+    uint32_t* ci;
+};
+
+// Merges entries e0 .. min(cnt, e0 + 64) - 1 of the leaf stored at `s`.
+template <int D, int KMAX>
+__device__ __forceinline__ void kw_merge64(const KList<KMAX>& Ls, int& cur, uint32_t k, const uint32_t* s,
+                                           uint32_t C, uint32_t e0, uint32_t cnt, const uint32_t* q) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = e0 + lane;
+    uint64_t dd = PAD_D2;
+    uint32_t id = PAD_ID;
+    bool cand = false;
+    if (e < cnt) {
+        uint32_t p[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+        dd = pt_dist<D>(q, p);
+        if (dd <= Ls.d[cur][k - 1]) {
+            id = s[D * C + e];
+            cand = pair_less(dd, id, Ls.d[cur][k - 1], Ls.i[cur][k - 1]);
+        }
     }
-    return v;
+    const uint64_t cm = ballot(cand);
+    if (cm == 0) return;
+    const uint32_t nc = (uint32_t)__popcll(cm);
+    if (cand) {
+        const uint32_t slot_c = count_below(cm);
+        Ls.cd[slot_c] = dd;
+        Ls.ci[slot_c] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t cpos = 0, rank = 0;
+    if (cand) {
+        for (uint32_t x = 0; x < nc; ++x) rank += pair_less(Ls.cd[x], Ls.ci[x], dd, id) ? 1u : 0u;
+        uint32_t lo = 0, hi = k;  // list entries below the candidate
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pair_less(Ls.d[cur][mid], Ls.i[cur][mid], dd, id)) lo = mid + 1;
+            else hi = mid;
+        }
+        cpos = rank + lo;
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane has read the unsorted candidates
+    if (cand) {
+        Ls.cd[rank] = dd;
+        Ls.ci[rank] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int nxt = cur ^ 1;
+    for (uint32_t x = lane; x < k; x += 64) {
+        const uint64_t ld = Ls.d[cur][x];
+        const uint32_t li = Ls.i[cur][x];
+        uint32_t lo = 0, hi = nc;  // candidates below list entry x
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pair_less(Ls.cd[mid], Ls.ci[mid], ld, li)) lo = mid + 1;
+            else hi = mid;
+        }
+        if (x + lo < k) {
+            Ls.d[nxt][x + lo] = ld;
+            Ls.i[nxt][x + lo] = li;
+        }
+    }
+    if (cand && cpos < k) {
+        Ls.d[nxt][cpos] = dd;
+        Ls.i[nxt][cpos] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    cur = nxt;
 }
 
-// Among lanes with `on`, the pair (d, idx) that is smallest; returns false if none.
-__device__ __forceinline__ bool wave_argmin(bool on, uint64_t d, uint64_t& best_d, uint32_t& best_lane) {
-    const uint64_t m = wave_min_u64(on ? d : PAD_D2);
-    const uint64_t who = ballot(on && d == m);
-    if (who == 0) return false;
-    best_d = m;
-    best_lane = (uint32_t)__builtin_ctzll(who);
-    return true;
+// Merges the leaf with the given slot and count, 64 entries at a time.
+template <int D, int KMAX>
+__device__ __forceinline__ void kw_merge_leaf(const KList<KMAX>& Ls, int& cur, uint32_t k, const TreeView& t,
+                                              uint32_t slot, uint32_t cnt, const uint32_t* q) {
+    const uint32_t* s = t.slots + (uint64_t)slot * (D + 1) * t.C;
+    for (uint32_t e0 = 0; e0 < cnt; e0 += 64) kw_merge64<D, KMAX>(Ls, cur, k, s, t.C, e0, cnt, q);
 }
 
 template <int D, int KMAX>
-__global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* __restrict__ qp, uint64_t nq,
+__global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* __restrict__ qp,
+                                                  const uint64_t* __restrict__ qkeys, uint64_t nq,
                                                   const uint32_t* __restrict__ order, uint32_t k,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
@@ -502,10 +574,11 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
     __shared__ uint32_t s_i[KW_WAVES][2][KMAX];
     __shared__ uint64_t s_cd[KW_WAVES][64];
     __shared__ uint32_t s_ci[KW_WAVES][64];
+    __shared__ uint32_t s_mask[KW_WAVES][MAX_LEVELS];
     const TreeView t = resolve_tree(tv);
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = lane_id();
     const uint64_t tq = (uint64_t)blockIdx.x * KW_WAVES + w;
     if (tq >= nq) return;
@@ -513,125 +586,81 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
     uint32_t q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
-    int cur = 0;
     for (uint32_t x = lane; x < KMAX; x += 64) {
         s_d[w][0][x] = PAD_D2;
         s_i[w][0][x] = PAD_ID;
     }
-    const uint32_t C = t.C;
-    if (t.L > 0) {
-        uint32_t l = 0;
-        uint64_t i = 0;
-        bool down = true;
-        for (;;) {
-            const uint64_t kth_d = s_d[w][cur][k - 1];
-            if (down) {
-                if (l == t.h) {
-                    const NodeRec r = t.leaf[i];
-                    const uint32_t* s = t.slots + (uint64_t)r.slot * (D + 1) * C;
-                    const uint32_t kth_i = s_i[w][cur][k - 1];
-                    for (uint32_t e0 = 0; e0 < r.cnt; e0 += 64) {
-                        const uint32_t e = e0 + lane;
-                        uint64_t dd = PAD_D2;
-                        uint32_t id = PAD_ID;
-                        bool cand = false;
-                        if (e < r.cnt) {
-                            uint32_t p[D];
-#pragma unroll
-                            for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
-                            id = s[D * C + e];
-                            dd = pt_dist<D>(q, p);
-                            cand = pair_less(dd, id, s_d[w][cur][k - 1], s_i[w][cur][k - 1]);
-                        }
-                        (void)kth_i;
-                        const uint64_t cm = ballot(cand);
-                        if (cm == 0) continue;
-                        const uint32_t nc = (uint32_t)__popcll(cm);
-                        const uint32_t slot = count_below(cm);
-                        if (cand) {
-                            s_cd[w][slot] = dd;
-                            s_ci[w][slot] = id;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        // rank of each candidate among the candidates
-                        uint32_t rank = 0;
-                        if (cand) {
-                            for (uint32_t x = 0; x < nc; ++x) rank += pair_less(s_cd[w][x], s_ci[w][x], dd, id) ? 1u : 0u;
-                        }
-                        // position of each candidate in the merged list
-                        uint32_t cpos = 0;
-                        if (cand) {
-                            uint32_t lo = 0, hi = k;  // count list entries < (dd, id)
-                            while (lo < hi) {
-                                const uint32_t mid = (lo + hi) >> 1;
-                                if (pair_less(s_d[w][cur][mid], s_i[w][cur][mid], dd, id)) lo = mid + 1;
-                                else hi = mid;
-                            }
-                            cpos = rank + lo;
-                        }
-                        // sorted candidates, for the list side of the merge
-                        // (written after every lane has read the unsorted copy)
-                        __builtin_amdgcn_wave_barrier();
-                        if (cand) {
-                            s_cd[w][rank] = dd;
-                            s_ci[w][rank] = id;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        const int nxt = cur ^ 1;
-                        for (uint32_t x = lane; x < k; x += 64) {
-                            const uint64_t ld = s_d[w][cur][x];
-                            const uint32_t li = s_i[w][cur][x];
-                            uint32_t lo = 0, hi = nc;  // candidates smaller than list entry x
-                            while (lo < hi) {
-                                const uint32_t mid = (lo + hi) >> 1;
-                                if (pair_less(s_cd[w][mid], s_ci[w][mid], ld, li)) lo = mid + 1;
-                                else hi = mid;
-                            }
-                            const uint32_t pos = x + lo;
-                            if (pos < k) {
-                                s_d[w][nxt][pos] = ld;
-                                s_i[w][nxt][pos] = li;
-                            }
-                        }
-                        if (cand && cpos < k) {
-                            s_d[w][nxt][cpos] = dd;
-                            s_i[w][nxt][cpos] = id;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        cur = nxt;
-                    }
-                    down = false;
+    __builtin_amdgcn_wave_barrier();
+    const KList<KMAX> Ls{s_d[w], s_i[w], s_cd[w], s_ci[w]};
+    int cur = 0;
+    const SingleTree<D> tr{t, s_lv};
+    const uint32_t L = (uint32_t)t.L;
+    if (L > 0) {
+        // seed leaves: outward from the leaf holding the query's key
+        const uint64_t key = qkeys[qi];
+        uint32_t lo = 0, hi = L;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tr.pkey(mid) <= key) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t j = lo ? lo - 1 : 0u;
+        const uint32_t want = max(2 * k, 64u);
+        uint32_t ja = j, jb = j, have = tr.leaf_sc(j).x;
+        while (have < want && (ja > 0 || jb + 1 < L)) {
+            if (ja > 0) have += tr.leaf_sc(--ja).x;
+            if (jb + 1 < L) have += tr.leaf_sc(++jb).x;
+        }
+        for (uint32_t x = ja; x <= jb; ++x) {
+            const uint2 sc = tr.leaf_sc(x);
+            kw_merge_leaf<D, KMAX>(Ls, cur, k, t, sc.y, sc.x, q);
+        }
+        const uint32_t B = t.B, h = t.h;
+        // children of `node` (level l) within the k-th distance, seeds left out
+        auto expand = [&](uint32_t l, uint32_t node) -> uint32_t {
+            const uint32_t c0 = node * B, nc = min(B, tr.levn(l + 1) - c0);
+            const uint64_t kth = s_d[w][cur][k - 1];
+            const uint32_t c = c0 + lane;
+            bool keep = false;
+            if (lane < nc) {
+                const uint64_t d = tr.dist(l + 1, c, q);
+                keep = d != PAD_D2 && d <= kth && !(l + 1 == h && c >= ja && c <= jb);
+            }
+            return (uint32_t)ballot(keep);
+        };
+        const uint64_t droot = tr.dist(0, 0, q);
+        if (h > 0 && droot != PAD_D2 && droot <= s_d[w][cur][k - 1]) {
+            uint32_t l = 0, base = 0;
+            uint32_t m0 = expand(0, 0);
+            if (lane == 0) s_mask[w][0] = m0;
+            __builtin_amdgcn_wave_barrier();
+            for (;;) {
+                const uint32_t m = s_mask[w][l];
+                if (m == 0) {
+                    if (l == 0) break;
+                    --l;
+                    base = base / B / B * B;
                     continue;
                 }
-                const uint64_t c0 = i * t.B, c1 = min<uint64_t>(c0 + t.B, s_lv[l + 1].n);
-                const uint64_t c = c0 + lane;
-                const bool on = c < c1;
-                const uint64_t dd = on ? box_dist<D>(q, fetch(t, s_lv, l + 1, c)) : PAD_D2;
-                uint64_t best;
-                uint32_t bl;
-                if (wave_argmin(on && dd != PAD_D2, dd, best, bl) && best <= kth_d) {
-                    ++l;
-                    i = c0 + bl;
-                } else {
-                    down = false;
+                const uint32_t b = (uint32_t)__builtin_ctz(m);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) s_mask[w][l] = m & (m - 1);
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t c = base + b;
+                const uint64_t d = tr.dist(l + 1, c, q);
+                if (d > s_d[w][cur][k - 1]) continue;
+                if (l + 1 == h) {
+                    const uint2 sc = tr.leaf_sc(c);
+                    kw_merge_leaf<D, KMAX>(Ls, cur, k, t, sc.y, sc.x, q);
+                    continue;
                 }
-            } else {
-                if (l == 0) break;
-                const uint64_t p = i / t.B, s0 = p * t.B, s1 = min<uint64_t>(s0 + t.B, s_lv[l].n);
-                const uint64_t s = s0 + lane;
-                const bool on = s < s1;
-                const uint64_t dd = on ? box_dist<D>(q, fetch(t, s_lv, l, s)) : PAD_D2;
-                const uint64_t dcur = shfl_u64(dd, (int)(i - s0));
-                const bool after = on && dd != PAD_D2 && (dd > dcur || (dd == dcur && s > i));
-                uint64_t best;
-                uint32_t bl;
-                if (wave_argmin(after, dd, best, bl) && best <= kth_d) {
-                    i = s0 + bl;
-                    down = true;
-                } else {
-                    --l;
-                    i = p;
-                }
+                const uint32_t cm = expand(l + 1, c);
+                if (cm == 0) continue;
+                ++l;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) s_mask[w][l] = cm;
+                __builtin_amdgcn_wave_barrier();
+                base = c * B;
             }
         }
     }
@@ -962,9 +991,9 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, c
         case 13: PSI_KL(D, 13); break; case 14: PSI_KL(D, 14); break; case 15: PSI_KL(D, 15); break;     \
         case 16: PSI_KL(D, 16); break;                                                                   \
         default:                                                                                         \
-            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
-            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
-            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, nq, order, k, ids, d2); \
+            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
     }
     if (dim == 2) { PSI_KL_ALL(2) } else { PSI_KL_ALL(3) }
 #undef PSI_KL_ALL
