@@ -759,6 +759,15 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "roofline": roof,
     }
+    if "knn" in ops:  # one more, untimed kNN pass with the walk counted
+        psi.psi_query_stats(h, True)
+        psi.psi_knn(h, d_q, nq, k, k_ids, k_d2)
+        wc = psi.psi_query_stats(h, False).astype(np.float64)
+        if wc[0] > 0:
+            out["knn_walk"] = {"box_tests_per_query": round(wc[1] / wc[0], 2),
+                               "leaves_per_query": round(wc[2] / wc[0], 2),
+                               "points_per_query": round(wc[3] / wc[0], 2),
+                               "touched_bytes_per_query": round((16 * wc[1] + 8 * wc[2] + 4 * (dim + 1) * wc[3]) / wc[0], 1)}
     ix.close()
     del d_data, d_ins, d_dels, d_q, d_boxes, k_ids, k_d2, r_ids
     torch.cuda.empty_cache()

@@ -426,6 +426,18 @@ psi_status psi_prof_reset(psi_index ix);
 psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches,
                         uint64_t* h_bytes);
 
+/* Work counts of the kNN searches (App. C's visiting rule made measurable).
+ * While enabled, every psi_knn of the index with the seeded traversal (the
+ * default; not PSI_FLAG_KNN_NEAREST_FIRST) adds to four device counters:
+ * queries answered, box tests (a node's bounding box read and compared with
+ * the current k-th distance), leaves scanned and points scanned, seed leaves
+ * included. enable: 1 starts counting from zero (when off before; allocates
+ * 32 bytes, so not under graph capture: PSI_E_STATE), 0 stops. h_counts
+ * (nullable, host, 4 entries): the counts so far, read after waiting for the
+ * stream; all zero when counting was off. Counting adds a few atomic adds
+ * per wave; timed runs leave it off. */
+psi_status psi_query_stats(psi_index ix, int enable, uint64_t* h_counts);
+
 #ifdef __cplusplus
 }
 #endif

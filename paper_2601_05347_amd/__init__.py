@@ -86,6 +86,7 @@ SIGNATURES = {
     "psi_orth_prof_reset": (_i, [_P]),
     "psi_orth_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
     "psi_prof_enable": (_i, [_P, _i]),
+    "psi_query_stats": (_i, [_P, _i, _P]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
 }
@@ -378,6 +379,15 @@ def psi_graph_launch(g, stream=None):
 
 def psi_graph_destroy(g):
     _check(lib().psi_graph_destroy(g), "psi_graph_destroy")
+
+
+def psi_query_stats(h, enable: bool):
+    """kNN walk counts so far [queries, box tests, leaves, points] (numpy
+    u64), then counting switched on or off."""
+    out = np.zeros(4, np.uint64)
+    _check(lib().psi_query_stats(h, 1 if enable else 0, out.ctypes.data),
+           "psi_query_stats")
+    return out
 
 
 def psi_prof_enable(h, on: bool):

@@ -146,36 +146,45 @@ __global__ __launch_bounds__(256) void k_knn_lane(TreeView tv, const uint32_t* _
 // current k-th distance and the seed leaves already scanned. A good seed
 // radius makes this visit little more than the leaves the final k-th
 // distance ball touches, without re-scoring siblings.
-// Four distances at a time; the candidates among them go through one
-// insertion site (not unrolled: the k-best list is the register budget).
-// lazy: an entry's id is read only when its distance could place it among
-// the k best (after the first leaves fill the list that is rare); otherwise
-// the ids are loaded four at a time with the coordinates.
+//
+// A leaf is scanned in two passes, 64 entries at a time: the distances of
+// all entries (four at a time, coordinates only) against the k-th distance
+// at the start give a bit mask of candidates; the candidates are then
+// inserted one after another (their coordinates and ids read again). The
+// lanes of a wave go through the insertion code as often as the lane with
+// the most candidates, not once for every entry that any lane inserts.
 template <int D, int K>
 __device__ __forceinline__ void scan_leaf(const TreeView& t, uint32_t slot, uint32_t cnt, const uint32_t* q,
-                                          uint64_t (&bd)[K], uint32_t (&bi)[K], bool lazy) {
+                                          uint64_t (&bd)[K], uint32_t (&bi)[K]) {
     const uint32_t C = t.C;
     const uint32_t* s = t.slots + (uint64_t)slot * (D + 1) * C;
-    for (uint32_t e = 0; e < cnt; e += 4) {
-        uint4 X[D];
+    for (uint32_t e0 = 0; e0 < cnt; e0 += 64) {
+        const uint32_t ce = min(cnt - e0, 64u);
+        const uint64_t kth = bd[K - 1];
+        uint64_t cm = 0;
+        for (uint32_t e = 0; e < ce; e += 4) {
+            uint4 X[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e);
-        uint4 I = make_uint4(0u, 0u, 0u, 0u);
-        if (!lazy) I = *reinterpret_cast<const uint4*>(s + D * C + e);
-        const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
-                                   {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
-                                   {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
-                                   {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
-        uint64_t dd[4];
+            for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e0 + e);
+            const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
+                                       {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
+                                       {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
+                                       {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dd[u] = pt_dist<D>(q, xs[u]);
-        const uint32_t nu = min(cnt - e, 4u);
-#pragma unroll 1
-        for (uint32_t u = 0; u < nu; ++u) {
-            const uint64_t d = u == 0 ? dd[0] : (u == 1 ? dd[1] : (u == 2 ? dd[2] : dd[3]));
-            if (d > bd[K - 1]) continue;
-            const uint32_t id = lazy ? s[D * C + e + u] : (u == 0 ? I.x : (u == 1 ? I.y : (u == 2 ? I.z : I.w)));
-            if (pair_less(d, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, d, id);
+            for (int u = 0; u < 4; ++u) {
+                const bool c = e + u < ce && pt_dist<D>(q, xs[u]) <= kth;
+                cm |= c ? 1ull << (e + u) : 0ull;
+            }
+        }
+        while (cm) {
+            const uint32_t e = e0 + (uint32_t)__builtin_ctzll(cm);
+            cm &= cm - 1;
+            uint32_t p[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+            const uint32_t id = s[D * C + e];
+            const uint64_t dd = pt_dist<D>(q, p);
+            if (pair_less(dd, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, id);
         }
     }
 }
@@ -199,7 +208,7 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
     for (uint32_t x = ja; x <= jb; ++x) {
         const uint2 sc = tr.leaf_sc(x);  // (count, slot)
-        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, false);
+        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
     }
     const uint32_t B = tr.B(), h = tr.h();
     uint32_t l = 0, i = 0;
@@ -210,7 +219,7 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
             if (l == h) {
                 if (i < ja || i > jb) {
                     const uint2 sc = tr.leaf_sc(i);
-                    scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, true);
+                    scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
                 }
             } else {
                 descend = true;
@@ -238,18 +247,47 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     }
 }
 
-// The same search with a stack of child masks. Expanding a node reads the
-// boxes of all its children in one batch of independent loads and keeps the
-// ones within the current k-th distance as a bit mask, one per level, in LDS
-// (`stk`, this lane's words `blockDim.x` apart); the walk then takes the set
-// bits in order, checking each node again against the (by then smaller) k-th
-// distance before expanding or scanning it. A node costs one round trip to
-// memory instead of one per sibling. Needs h() <= the stack depth; the
-// caller takes the other walk beyond it.
+// What one search touched: box tests (a node's box read and compared),
+// leaves scanned and points scanned (seed leaves included).
+struct WalkCount {
+    uint32_t boxes = 0, leaves = 0, points = 0;
+};
+
+// Sum over the wave (every lane takes part).
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o >= 1; o >>= 1) v += shfl_u32(v, (int)(lane_id() ^ (uint32_t)o));
+    return v;
+}
+
+// Adds a wave's query count and walk counts to stats[0..3] (lane 0).
+__device__ __forceinline__ void add_walk_stats(unsigned long long* stats, uint32_t queries, const WalkCount& wc) {
+    const uint32_t a = wave_sum_u32(queries), b = wave_sum_u32(wc.boxes), c = wave_sum_u32(wc.leaves),
+                   d = wave_sum_u32(wc.points);
+    if (lane_id() == 0) {
+        atomicAdd(stats + 0, (unsigned long long)a);
+        atomicAdd(stats + 1, (unsigned long long)b);
+        atomicAdd(stats + 2, (unsigned long long)c);
+        atomicAdd(stats + 3, (unsigned long long)d);
+    }
+}
+
+// The same search in three phases, so that the lanes of a wave run the same
+// code at the same time (the search is bound by instruction issue, and a
+// wave whose lanes split between expanding nodes and scanning leaves pays
+// for both): (1) the seed leaves are scanned; (2) the tree is walked with a
+// stack of child masks, one per level, in LDS (`stk`): expanding a node
+// reads the boxes of all its children in one batch of independent loads and
+// keeps those within the current k-th distance; children that are leaves go
+// to a list of candidate leaves in LDS (`cand`, KNN_CAND entries) instead of
+// being scanned; (3) the candidates are scanned, each checked again against
+// the k-th distance of the moment. A full list is scanned (and emptied)
+// before more leaves go in, so any number of candidates is handled. Both LDS
+// arrays hold one word per lane per entry, `stride` words apart. Needs
+// h() <= the stack depth; the caller takes the other walk beyond it.
 template <int D, int K, class T>
 __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv, const uint32_t* q, uint64_t key,
                                                  uint64_t (&bd)[K], uint32_t (&bi)[K], uint32_t* __restrict__ stk,
-                                                 uint32_t stride) {
+                                                 uint32_t* __restrict__ cand, uint32_t stride, WalkCount& wc) {
     const uint32_t L = tr.L();
     if (L == 0) return;
     uint32_t lo = 0, hi = L;  // first pivot key above the query's key
@@ -262,12 +300,14 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
     const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
     for (uint32_t x = ja; x <= jb; ++x) {
         const uint2 sc = tr.leaf_sc(x);  // (count, slot)
-        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, false);
+        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
+        wc.leaves += 1;
+        wc.points += sc.x;
     }
     const uint32_t B = tr.B(), h = tr.h();
     if (h == 0) return;  // a single leaf, scanned as a seed
-    // children of node `node` on level l + 1 within the k-th distance (the
-    // seed leaves left out)
+    // children of `node` on level l + 1 within the k-th distance (the seed
+    // leaves left out)
     auto expand = [&](uint32_t l, uint32_t node) -> uint32_t {
         const uint32_t c0 = node * B, nc = min(B, tr.levn(l + 1) - c0);
         const uint64_t kth = bd[K - 1];
@@ -280,37 +320,73 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
             const bool keep = d != PAD_D2 && d <= kth && !(leaves && c >= ja && c <= jb);
             m |= keep ? 1u << x : 0u;
         }
+        wc.boxes += nc;
         return m;
     };
     {
         const uint64_t d = tr.dist(0, 0, q);
+        wc.boxes += 1;
         if (d == PAD_D2 || d > bd[K - 1]) return;
     }
-    uint32_t l = 0, base = 0;  // the mask of level l covers the children base .. base + B - 1 (level l + 1)
-    stk[0] = expand(0, 0);
+    // walk state: the masks on the stack cover inner nodes only (level l's
+    // mask covers the children base .. base + B - 1 on level l + 1 < h);
+    // pend: leaf children (from pbase) not yet on the candidate list
+    uint32_t l = 0, base = 0, pend = 0, pbase = 0, ncand = 0;
+    bool walking = h > 1;
+    const uint32_t m0 = expand(0, 0);
+    if (walking) stk[0] = m0;
+    else pend = m0;
     for (;;) {
-        const uint32_t m = stk[l * stride];
-        if (m == 0) {
-            if (l == 0) break;
-            --l;
-            base = base / B / B * B;
-            continue;
+        // (2) fill the candidate list
+        while (ncand < KNN_CAND) {
+            if (pend) {
+                const uint32_t b = (uint32_t)__builtin_ctz(pend);
+                pend &= pend - 1;
+                cand[ncand * stride] = pbase + b;
+                ++ncand;
+                continue;
+            }
+            if (!walking) break;
+            const uint32_t m = stk[l * stride];
+            if (m == 0) {
+                if (l == 0) {
+                    walking = false;
+                } else {
+                    --l;
+                    base = base / B / B * B;
+                }
+                continue;
+            }
+            const uint32_t b = (uint32_t)__builtin_ctz(m);
+            stk[l * stride] = m & (m - 1);
+            const uint32_t c = base + b;
+            const uint64_t d = tr.dist(l + 1, c, q);
+            const uint32_t cm = expand(l + 1, c);
+            wc.boxes += 1;  // the recheck
+            if (d > bd[K - 1] || cm == 0) continue;
+            if (l + 2 == h) {  // c's children are leaves
+                pend = cm;
+                pbase = c * B;
+                continue;
+            }
+            ++l;
+            stk[l * stride] = cm;
+            base = c * B;
         }
-        const uint32_t b = (uint32_t)__builtin_ctz(m);
-        stk[l * stride] = m & (m - 1);
-        const uint32_t c = base + b;
-        if (l + 1 == h) {
+        // (3) scan the candidates
+        for (uint32_t x = 0; x < ncand; ++x) {
+            const uint32_t c = cand[x * stride];
             const uint64_t d = tr.dist(h, c, q);
             const uint2 sc = tr.leaf_sc(c);
-            if (d <= bd[K - 1]) scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi, true);
-            continue;
+            wc.boxes += 1;
+            if (d <= bd[K - 1]) {
+                scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
+                wc.leaves += 1;
+                wc.points += sc.x;
+            }
         }
-        const uint64_t d = tr.dist(l + 1, c, q);
-        const uint32_t cm = expand(l + 1, c);
-        if (d > bd[K - 1] || cm == 0) continue;
-        ++l;
-        stk[l * stride] = cm;
-        base = c * B;
+        ncand = 0;
+        if (!walking && pend == 0) break;
     }
 }
 
@@ -348,15 +424,17 @@ struct SingleTree {
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
 };
 
-// MASKS: the walk with a stack of child masks, s_stk, hcap levels of one
-// word per lane (dynamic LDS); a taller tree (never met: hcap bounds the
+// MASKS: the three-phase walk; s_stk (dynamic LDS) holds its stack of child
+// masks, hcap levels of one word per lane, then KNN_CAND candidate-leaf
+// words per lane; a taller tree (never met: hcap bounds the
 // height of every tree the buffers can hold) leaves its queries unanswered
-// and flags ERR_STACK.
+// and flags ERR_STACK. stats (nullable, MASKS only): the walk counts are
+// added to stats[0..3] (queries, box tests, leaves, points).
 template <int D, int K, bool MASKS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((K <= 8 || K == 10) ? 5 : 1))) void k_knn_seed(TreeView tv, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
                                                   const uint32_t* __restrict__ order, uint32_t hcap,
-                                                  uint32_t* __restrict__ err,
+                                                  uint32_t* __restrict__ err, unsigned long long* __restrict__ stats,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
     extern __shared__ uint32_t s_stk[];
@@ -364,27 +442,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((K <= 8 || 
     if (threadIdx.x <= t.h) s_lv[threadIdx.x] = tv.dt->lv[threadIdx.x];
     __syncthreads();
     const uint64_t tq = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tq >= nq) return;
-    const uint64_t qi = order ? order[tq] : tq;
-    uint32_t q[D];
+    WalkCount wc;
+    if (tq < nq) {
+        const uint64_t qi = order ? order[tq] : tq;
+        uint32_t q[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
-    uint64_t bd[K];
-    uint32_t bi[K];
+        for (int d = 0; d < D; ++d) q[d] = qp[qi * D + d];
+        uint64_t bd[K];
+        uint32_t bi[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        bd[j] = PAD_D2;
-        bi[j] = PAD_ID;
+        for (int j = 0; j < K; ++j) {
+            bd[j] = PAD_D2;
+            bi[j] = PAD_ID;
+        }
+        const SingleTree<D> tr{t, s_lv};
+        if (!MASKS) knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
+        else if (t.h <= hcap)
+            knn_seeded_masks<D, K>(tr, t, q, qkeys[qi], bd, bi, s_stk + threadIdx.x,
+                                   s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, wc);
+        else if (tq == 0) atomicOr(err, ERR_STACK);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            out_ids[qi * K + j] = bi[j];
+            out_d2[qi * K + j] = bd[j];
+        }
     }
-    const SingleTree<D> tr{t, s_lv};
-    if (!MASKS) knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
-    else if (t.h <= hcap) knn_seeded_masks<D, K>(tr, t, q, qkeys[qi], bd, bi, s_stk + threadIdx.x, blockDim.x);
-    else if (tq == 0) atomicOr(err, ERR_STACK);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        out_ids[qi * K + j] = bi[j];
-        out_d2[qi * K + j] = bd[j];
-    }
+    if (MASKS && stats) add_walk_stats(stats, tq < nq ? 1u : 0u, wc);
 }
 
 // ---------------------------------------------- kNN over many small indexes
@@ -420,9 +503,10 @@ __global__ void k_chunk_counts(const uint64_t* __restrict__ q_off, uint32_t num,
 // Persistent: every wave takes (index, 64-query chunk) items from an atomic
 // counter until none are left, so uneven batches spread over the whole GPU.
 // s_stk: the walk's stacks of child masks, hcap (the tallest index's
-// height) levels of one word per lane.
+// height) levels of one word per lane, then KNN_CAND candidate-leaf words
+// per lane.
 template <int D, int CURVE, int K>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 ? K <= 8 : K <= 2) ? 5 : 1))) void k_multi_knn(TreeView tv, const IdxMeta* __restrict__ meta, uint32_t num,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 && K <= 4) ? 5 : 1))) void k_multi_knn(TreeView tv, const IdxMeta* __restrict__ meta, uint32_t num,
                                                    const uint64_t* __restrict__ q_off, const uint32_t* __restrict__ qp,
                                                    const uint32_t* __restrict__ pref, uint32_t* __restrict__ work_ctr,
                                                    uint32_t hcap, uint32_t* __restrict__ out_ids,
@@ -458,7 +542,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 ? K
                 bi[j] = PAD_ID;
             }
             const MultiTree<D> tr{meta + s, tv.inner, tv.leaf, tv.pkey, tv.B};
-            if (tr.h() <= hcap) knn_seeded_masks<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi, s_stk + threadIdx.x, blockDim.x);
+            WalkCount wc;
+            if (tr.h() <= hcap)
+                knn_seeded_masks<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi, s_stk + threadIdx.x,
+                                       s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, wc);
             else atomicOr(err, ERR_STACK);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -564,10 +651,12 @@ __device__ __forceinline__ void kw_merge_leaf(const KList<KMAX>& Ls, int& cur, u
     for (uint32_t e0 = 0; e0 < cnt; e0 += 64) kw_merge64<D, KMAX>(Ls, cur, k, s, t.C, e0, cnt, q);
 }
 
+// stats (nullable): as for k_knn_seed.
 template <int D, int KMAX>
 __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
                                                   const uint32_t* __restrict__ order, uint32_t k,
+                                                  unsigned long long* __restrict__ stats,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
     __shared__ uint64_t s_d[KW_WAVES][2][KMAX];
@@ -595,6 +684,7 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
     int cur = 0;
     const SingleTree<D> tr{t, s_lv};
     const uint32_t L = (uint32_t)t.L;
+    uint32_t n_box = 0, n_leaf = 0, n_pts = 0;  // wave-uniform walk counts
     if (L > 0) {
         // seed leaves: outward from the leaf holding the query's key
         const uint64_t key = qkeys[qi];
@@ -614,6 +704,8 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
         for (uint32_t x = ja; x <= jb; ++x) {
             const uint2 sc = tr.leaf_sc(x);
             kw_merge_leaf<D, KMAX>(Ls, cur, k, t, sc.y, sc.x, q);
+            n_leaf += 1;
+            n_pts += sc.x;
         }
         const uint32_t B = t.B, h = t.h;
         // children of `node` (level l) within the k-th distance, seeds left out
@@ -626,9 +718,11 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
                 const uint64_t d = tr.dist(l + 1, c, q);
                 keep = d != PAD_D2 && d <= kth && !(l + 1 == h && c >= ja && c <= jb);
             }
+            n_box += nc;
             return (uint32_t)ballot(keep);
         };
         const uint64_t droot = tr.dist(0, 0, q);
+        n_box += 1;
         if (h > 0 && droot != PAD_D2 && droot <= s_d[w][cur][k - 1]) {
             uint32_t l = 0, base = 0;
             uint32_t m0 = expand(0, 0);
@@ -648,10 +742,13 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
                 __builtin_amdgcn_wave_barrier();
                 const uint32_t c = base + b;
                 const uint64_t d = tr.dist(l + 1, c, q);
+                n_box += 1;
                 if (d > s_d[w][cur][k - 1]) continue;
                 if (l + 1 == h) {
                     const uint2 sc = tr.leaf_sc(c);
                     kw_merge_leaf<D, KMAX>(Ls, cur, k, t, sc.y, sc.x, q);
+                    n_leaf += 1;
+                    n_pts += sc.x;
                     continue;
                 }
                 const uint32_t cm = expand(l + 1, c);
@@ -667,6 +764,12 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
     for (uint32_t x = lane; x < k; x += 64) {
         out_ids[qi * k + x] = s_i[w][cur][x];
         out_d2[qi * k + x] = s_d[w][cur][x];
+    }
+    if (stats && lane == 0) {
+        atomicAdd(stats + 0, 1ull);
+        atomicAdd(stats + 1, (unsigned long long)n_box);
+        atomicAdd(stats + 2, (unsigned long long)n_leaf);
+        atomicAdd(stats + 3, (unsigned long long)n_pts);
     }
 }
 
@@ -969,18 +1072,18 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
 }  // namespace
 
 void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
-                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err, uint32_t* ids,
-                uint64_t* d2) {
+                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err,
+                unsigned long long* stats, uint32_t* ids, uint64_t* d2) {
     if (nq == 0) return;
     const bool masks = hcap <= KNN_STACK_MAX;
-    const size_t lds = masks ? (size_t)max(hcap, 1u) * 256 * 4 : 0;
+    const size_t lds = masks ? (size_t)(hcap + KNN_CAND) * 256 * 4 : 0;
     const unsigned gl = blocks_for(nq, 256);
     const unsigned gw = blocks_for(nq, KW_WAVES);
 #define PSI_KL(D, K)                                                                                             \
     do {                                                                                                         \
         if (variant == 1) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, order, ids, d2); \
-        else if (masks) hipLaunchKernelGGL((k_knn_seed<D, K, true>), dim3(gl), dim3(256), lds, st, t, q, qkeys, nq, order, hcap, err, ids, d2); \
-        else hipLaunchKernelGGL((k_knn_seed<D, K, false>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, hcap, err, ids, d2); \
+        else if (masks) hipLaunchKernelGGL((k_knn_seed<D, K, true>), dim3(gl), dim3(256), lds, st, t, q, qkeys, nq, order, hcap, err, stats, ids, d2); \
+        else hipLaunchKernelGGL((k_knn_seed<D, K, false>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, hcap, err, nullptr, ids, d2); \
     } while (0)
 #define PSI_KL_ALL(D)                                                                                    \
     switch (k) {                                                                                         \
@@ -991,9 +1094,9 @@ void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, c
         case 13: PSI_KL(D, 13); break; case 14: PSI_KL(D, 14); break; case 15: PSI_KL(D, 15); break;     \
         case 16: PSI_KL(D, 16); break;                                                                   \
         default:                                                                                         \
-            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
-            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
-            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, ids, d2); \
+            if (k <= 32) hipLaunchKernelGGL((k_knn_wave<D, 32>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, stats, ids, d2); \
+            else if (k <= 64) hipLaunchKernelGGL((k_knn_wave<D, 64>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, stats, ids, d2); \
+            else hipLaunchKernelGGL((k_knn_wave<D, 128>), dim3(gw), dim3(256), 0, st, t, q, qkeys, nq, order, k, stats, ids, d2); \
     }
     if (dim == 2) { PSI_KL_ALL(2) } else { PSI_KL_ALL(3) }
 #undef PSI_KL_ALL
@@ -1010,7 +1113,7 @@ void launch_multi_knn(hipStream_t st, int dim, int curve, const TreeView& tv, co
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const dim3 g((unsigned)(cus * 8));
-    const size_t lds = (size_t)max(hcap, 1u) * 256 * 4;
+    const size_t lds = (size_t)(hcap + KNN_CAND) * 256 * 4;
 #define PSI_MK(D, CV, K) hipLaunchKernelGGL((k_multi_knn<D, CV, K>), g, dim3(256), lds, st, tv, meta, num, q_off, q, chunk_pref, work_ctr, hcap, ids, d2, err)
 #define PSI_MK_K(D, CV)                                                                                  \
     switch (k) {                                                                                         \

@@ -742,7 +742,8 @@ psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, u
     for (uint64_t n = ix->L_cap; n > 1; ++hcap) n = (n + ix->B - 1) / ix->B;
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
     launch_knn(ix->st, ix->D, ix->view(), d_q, ix->qkeys.as<uint64_t>(), nq, order, k,
-               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, hcap, ix->err.as<uint32_t>(), d_ids, d_d2);
+               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, hcap, ix->err.as<uint32_t>(),
+               ix->qstats_on ? ix->qstats.as<unsigned long long>() : nullptr, d_ids, d_d2);
     return last_launch();
 }
 
@@ -963,6 +964,27 @@ psi_status psi_graph_destroy(psi_graph g) {
     if (g->e) (void)hipGraphExecDestroy(g->e);
     if (g->g) (void)hipGraphDestroy(g->g);
     delete g;
+    return PSI_OK;
+}
+
+psi_status psi_query_stats(psi_index ix, int enable, uint64_t* h_counts) {
+    if (!ix) return PSI_E_ARG;
+    psi_status s;
+    if (h_counts) {
+        if (ix->qstats_on) {
+            if ((s = hip_ok(hipStreamSynchronize(ix->st))) != PSI_OK) return s;
+            if ((s = hip_ok(hipMemcpy(h_counts, ix->qstats.p, 32, hipMemcpyDeviceToHost))) != PSI_OK) return s;
+        } else {
+            for (int x = 0; x < 4; ++x) h_counts[x] = 0;
+        }
+    }
+    if (enable && !ix->qstats_on) {
+        if (capturing(ix->st)) return PSI_E_STATE;  // allocates
+        if ((s = ix->qstats.ensure(32)) != PSI_OK) return s;
+        launch_fill_u32(ix->st, ix->qstats.as<uint32_t>(), 8, 0u);
+        if ((s = last_launch()) != PSI_OK) return s;
+    }
+    ix->qstats_on = enable != 0;
     return PSI_OK;
 }
 

@@ -240,6 +240,8 @@ struct psi_index_s {
     psi::Scratch scr;
     hipStream_t aux_st = nullptr;  // a second stream the index's queries run on (a server's)
     psi::Prof prof;
+    psi::Buf qstats;           // kNN walk counts (psi_query_stats)
+    bool qstats_on = false;
 
     uint64_t slot_words() const { return (uint64_t)(D + 1) * C; }
     psi::DevTree* dt() const { return dev.as<psi::DevTree>(); }

@@ -276,11 +276,14 @@ __device__ __forceinline__ TreeView resolve_tree(const TreeView& tv) {
 // fixed-order traversal; 1: nearest-child-first traversal. hcap: an upper
 // bound of the tree's height that sizes the seeded walk's stack of child
 // masks in LDS (up to KNN_STACK_MAX levels; a taller tree walks without
-// it). err: flags word (ERR_STACK if the tree outgrew hcap).
+// it). err: flags word (ERR_STACK if the tree outgrew hcap). stats
+// (nullable): queries, box tests, leaves and points scanned are added to
+// stats[0..3] (the seeded walks only).
 constexpr uint32_t KNN_STACK_MAX = 24;
+constexpr uint32_t KNN_CAND = 16;  // candidate leaves a seeded walk collects before scanning them
 void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
-                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err, uint32_t* ids,
-                uint64_t* d2);
+                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err,
+                unsigned long long* stats, uint32_t* ids, uint64_t* d2);
 // Boxes are processed in the order `order` gives (nullptr: input order);
 // results always land at the box's own index.
 void launch_range_count(hipStream_t st, int dim, const TreeView& t, const uint32_t* boxes, uint64_t nb,

@@ -202,6 +202,29 @@ def test_knn_k_exceeds_n(psi, n):
         np.testing.assert_array_equal(psi.to_u32(ids), eids)
 
 
+@pytest.mark.parametrize("k", [10, 50])
+def test_knn_walk_counts(psi, k):
+    """The kNN walk counters: counting leaves the results unchanged; every
+    query is counted once; a search reads at least the root's box, scans at
+    least one leaf and at least k points (n > k), and never more points than
+    its leaves hold (2 phi each) or than the index holds."""
+    say(f"knn walk counts k={k}")
+    n = 200_000
+    data, _, q = synth.workload("uniform", 3, 21, seed=5, n=n, n_query=3000)
+    ix = psi.Index(3, 1, 32, 8).build(data)
+    ids0, d0 = ix.knn(q, k)
+    assert not psi.psi_query_stats(ix._h, True).any()  # was off: zeros
+    ids1, d1 = ix.knn(q, k)
+    c = psi.psi_query_stats(ix._h, False).astype(np.int64)
+    np.testing.assert_array_equal(psi.to_u32(ids0), psi.to_u32(ids1))
+    np.testing.assert_array_equal(psi.to_u64(d0), psi.to_u64(d1))
+    nq = len(q)
+    assert c[0] == nq
+    assert c[1] >= nq and c[2] >= nq
+    assert k * nq <= c[3] <= min(64 * c[2], n * nq)
+    say(f"  per query: {c[1] / nq:.1f} box tests, {c[2] / nq:.2f} leaves, {c[3] / nq:.1f} points")
+
+
 # ------------------------------------------------------------------- range
 @pytest.mark.parametrize("dim,curve", CURVES)
 def test_range_parity(psi, dim, curve):
