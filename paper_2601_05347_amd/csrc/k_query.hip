@@ -359,11 +359,11 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
             }
             const uint32_t b = (uint32_t)__builtin_ctz(m);
             stk[l * stride] = m & (m - 1);
+            // (a node farther than the k-th distance has all its children
+            // farther too: expanding it finds none, no separate check)
             const uint32_t c = base + b;
-            const uint64_t d = tr.dist(l + 1, c, q);
             const uint32_t cm = expand(l + 1, c);
-            wc.boxes += 1;  // the recheck
-            if (d > bd[K - 1] || cm == 0) continue;
+            if (cm == 0) continue;
             if (l + 2 == h) {  // c's children are leaves
                 pend = cm;
                 pbase = c * B;
@@ -422,6 +422,16 @@ struct SingleTree {
     }
     __device__ uint2 leaf_sc(uint32_t i) const { return *reinterpret_cast<const uint2*>(&t.leaf[i].cnt); }
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
+};
+
+// The same over the node records themselves (boxes unpacked: more bytes,
+// less arithmetic per box test; the wave-per-query search, where one box
+// test serves a whole wave's lane, gains from it).
+template <int D>
+struct SingleTreeRec : SingleTree<D> {
+    __device__ uint64_t dist(uint32_t l, uint32_t i, const uint32_t* q) const {
+        return box_dist<D>(q, l == this->t.h ? this->t.leaf[i] : this->t.inner[this->lv[l].off + i]);
+    }
 };
 
 // MASKS: the three-phase walk; s_stk (dynamic LDS) holds its stack of child
@@ -682,7 +692,7 @@ __global__ __launch_bounds__(256) void k_knn_wave(TreeView tv, const uint32_t* _
     __builtin_amdgcn_wave_barrier();
     const KList<KMAX> Ls{s_d[w], s_i[w], s_cd[w], s_ci[w]};
     int cur = 0;
-    const SingleTree<D> tr{t, s_lv};
+    const SingleTreeRec<D> tr{{t, s_lv}};
     const uint32_t L = (uint32_t)t.L;
     uint32_t n_box = 0, n_leaf = 0, n_pts = 0;  // wave-uniform walk counts
     if (L > 0) {
