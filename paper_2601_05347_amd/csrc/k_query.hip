@@ -147,12 +147,44 @@ __global__ __launch_bounds__(256) void k_knn_lane(TreeView tv, const uint32_t* _
 // radius makes this visit little more than the leaves the final k-th
 // distance ball touches, without re-scoring siblings.
 //
-// A leaf is scanned in two passes, 64 entries at a time: the distances of
-// all entries (four at a time, coordinates only) against the k-th distance
-// at the start give a bit mask of candidates; the candidates are then
-// inserted one after another (their coordinates and ids read again). The
-// lanes of a wave go through the insertion code as often as the lane with
-// the most candidates, not once for every entry that any lane inserts.
+// Seed leaves, where most entries enter the k best, are scanned in one
+// pass: four entries at a time (coordinates and ids together), each one
+// inserted straight from registers when it beats the current k-th pair.
+//
+// Leaves met by the walk, where few entries do, are scanned in two passes,
+// 64 entries at a time: the distances of all entries (coordinates only)
+// against the k-th distance at the start give a bit mask of candidates; the
+// candidates, two at a time, are read again (both loads in flight together)
+// and inserted. The lanes of a wave then go through the insertion code about
+// as often as the lane with the most candidates, not once for every entry
+// that any lane inserts.
+template <int D, int K>
+__device__ __forceinline__ void scan_seed_leaf(const TreeView& t, uint32_t slot, uint32_t cnt, const uint32_t* q,
+                                               uint64_t (&bd)[K], uint32_t (&bi)[K]) {
+    const uint32_t C = t.C;
+    const uint32_t* s = t.slots + (uint64_t)slot * (D + 1) * C;
+    for (uint32_t e = 0; e < cnt; e += 4) {
+        uint4 X[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = *reinterpret_cast<const uint4*>(s + d * C + e);
+        const uint4 I = *reinterpret_cast<const uint4*>(s + D * C + e);
+        const uint32_t xs[4][3] = {{X[0].x, X[1].x, D == 3 ? X[D - 1].x : 0u},
+                                   {X[0].y, X[1].y, D == 3 ? X[D - 1].y : 0u},
+                                   {X[0].z, X[1].z, D == 3 ? X[D - 1].z : 0u},
+                                   {X[0].w, X[1].w, D == 3 ? X[D - 1].w : 0u}};
+        uint64_t dd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dd[u] = pt_dist<D>(q, xs[u]);
+        const uint32_t nu = min(cnt - e, 4u);
+#pragma unroll 1
+        for (uint32_t u = 0; u < nu; ++u) {
+            const uint64_t d = u == 0 ? dd[0] : (u == 1 ? dd[1] : (u == 2 ? dd[2] : dd[3]));
+            const uint32_t id = u == 0 ? I.x : (u == 1 ? I.y : (u == 2 ? I.z : I.w));
+            if (pair_less(d, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, d, id);
+        }
+    }
+}
+
 template <int D, int K>
 __device__ __forceinline__ void scan_leaf(const TreeView& t, uint32_t slot, uint32_t cnt, const uint32_t* q,
                                           uint64_t (&bd)[K], uint32_t (&bi)[K]) {
@@ -177,14 +209,22 @@ __device__ __forceinline__ void scan_leaf(const TreeView& t, uint32_t slot, uint
             }
         }
         while (cm) {
-            const uint32_t e = e0 + (uint32_t)__builtin_ctzll(cm);
+            const uint32_t ea = e0 + (uint32_t)__builtin_ctzll(cm);
             cm &= cm - 1;
-            uint32_t p[D];
+            const bool two = cm != 0;
+            const uint32_t eb = two ? e0 + (uint32_t)__builtin_ctzll(cm) : ea;
+            if (two) cm &= cm - 1;
+            uint32_t pa[D], pb[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
-            const uint32_t id = s[D * C + e];
-            const uint64_t dd = pt_dist<D>(q, p);
-            if (pair_less(dd, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, id);
+            for (int d = 0; d < D; ++d) {
+                pa[d] = s[d * C + ea];
+                pb[d] = s[d * C + eb];
+            }
+            const uint32_t ia = s[D * C + ea], ib = s[D * C + eb];
+            const uint64_t da = pt_dist<D>(q, pa);
+            if (pair_less(da, ia, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, da, ia);
+            const uint64_t db = pt_dist<D>(q, pb);
+            if (two && pair_less(db, ib, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, db, ib);
         }
     }
 }
@@ -208,7 +248,7 @@ __device__ __forceinline__ void knn_seeded(const T& tr, const TreeView& tv, cons
     const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
     for (uint32_t x = ja; x <= jb; ++x) {
         const uint2 sc = tr.leaf_sc(x);  // (count, slot)
-        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
+        scan_seed_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
     }
     const uint32_t B = tr.B(), h = tr.h();
     uint32_t l = 0, i = 0;
@@ -300,7 +340,7 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
     const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
     for (uint32_t x = ja; x <= jb; ++x) {
         const uint2 sc = tr.leaf_sc(x);  // (count, slot)
-        scan_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
+        scan_seed_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
         wc.leaves += 1;
         wc.points += sc.x;
     }
