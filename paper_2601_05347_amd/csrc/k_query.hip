@@ -353,12 +353,15 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
         const uint64_t kth = bd[K - 1];
         const bool leaves = l + 1 == h;
         uint32_t m = 0;
-#pragma unroll 8
-        for (uint32_t x = 0; x < nc; ++x) {
-            const uint32_t c = c0 + x;
-            const uint64_t d = tr.dist(l + 1, c, q);
-            const bool keep = d != PAD_D2 && d <= kth && !(leaves && c >= ja && c <= jb);
-            m |= keep ? 1u << x : 0u;
+        for (uint32_t x0 = 0; x0 < nc; x0 += 8) {
+            uint64_t d[8];
+            tr.dist8(l + 1, c0 + x0, min(nc - x0, 8u), q, d);
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                const uint32_t c = c0 + x0 + u;
+                const bool keep = x0 + u < nc && d[u] != PAD_D2 && d[u] <= kth && !(leaves && c >= ja && c <= jb);
+                m |= keep ? 1u << (x0 + u) : 0u;
+            }
         }
         wc.boxes += nc;
         return m;
@@ -430,11 +433,12 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
     }
 }
 
-// Squared distance from q to a packed box (PAD_D2 for an empty node).
+// Squared distance from q to a packed box (PAD_D2 for an empty node). No
+// branch: the box is decoded whether or not it is empty, so a caller's
+// loads of several boxes stay independent and go out together.
 template <int D>
 __device__ __forceinline__ uint64_t packed_dist(const uint32_t* q, uint4 v) {
     const uint64_t a = ((uint64_t)v.y << 32) | v.x, b = ((uint64_t)v.w << 32) | v.z;
-    if (a >> 63) return PAD_D2;
     constexpr int W = BoxBits<D>::W;
     constexpr uint64_t M = (1ull << W) - 1;
     uint64_t s = 0;
@@ -444,7 +448,7 @@ __device__ __forceinline__ uint64_t packed_dist(const uint32_t* q, uint4 v) {
         const uint32_t x = q[d] < lo ? lo - q[d] : (q[d] > hi ? q[d] - hi : 0u);
         s += (uint64_t)x * x;
     }
-    return s;
+    return (a >> 63) ? PAD_D2 : s;
 }
 
 // Accessor of a single index whose level table sits in LDS: box tests read
@@ -459,6 +463,17 @@ struct SingleTree {
     __device__ uint32_t levn(uint32_t l) const { return (uint32_t)lv[l].n; }
     __device__ uint64_t dist(uint32_t l, uint32_t i, const uint32_t* q) const {
         return packed_dist<D>(q, l == t.h ? t.cleaf[i] : t.cinner[lv[l].off + i]);
+    }
+    // distances of nodes c .. c + n - 1 (1 <= n <= 8) of level l into d[0..n);
+    // the eight loads are unconditional (clamped to the last node) and go
+    // out together
+    __device__ void dist8(uint32_t l, uint32_t c, uint32_t n, const uint32_t* q, uint64_t (&d)[8]) const {
+        const uint4* p = (l == t.h ? t.cleaf : t.cinner + lv[l].off) + c;
+        uint4 v[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) v[u] = p[min(u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = packed_dist<D>(q, v[u]);
     }
     __device__ uint2 leaf_sc(uint32_t i) const { return *reinterpret_cast<const uint2*>(&t.leaf[i].cnt); }
     __device__ uint64_t pkey(uint32_t i) const { return t.pkey[i]; }
@@ -537,6 +552,18 @@ struct MultiTree {
     __device__ NodeRec leaf(uint32_t i) const { return leafs[m->leaf_base + i]; }
     __device__ uint64_t dist(uint32_t l, uint32_t i, const uint32_t* q) const {
         return box_dist<D>(q, l == m->h ? leaf(i) : node(l, i));
+    }
+    // as SingleTree::dist8, over the node records, four loads at a time
+    __device__ void dist8(uint32_t l, uint32_t c, uint32_t n, const uint32_t* q, uint64_t (&d)[8]) const {
+        const NodeRec* p = (l == m->h ? leafs + m->leaf_base : inner + m->inner_base + m->lvl_off[l]) + c;
+#pragma unroll
+        for (uint32_t h4 = 0; h4 < 8; h4 += 4) {
+            NodeRec r[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) r[u] = p[min(h4 + u, n - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[h4 + u] = box_dist<D>(q, r[u]);
+        }
     }
     __device__ uint2 leaf_sc(uint32_t i) const {
         const NodeRec r = leaf(i);
