@@ -118,41 +118,30 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
     }
 }
 
-// One node level: parent i = union of children [B i, B i + B) one level down.
-// G = B rounded up to a power of two lanes per parent: every lane loads one
-// child record (a parent's children are one contiguous run of records) and the
-// group reduces counts and boxes by xor shuffles. The level is the u-th above
-// the leaves in the layout the device state holds (nothing to do if the tree
-// is lower than that).
-template <int D, int G>
-__global__ __launch_bounds__(256) void k_node_level(const DevTree* __restrict__ dt, uint32_t u,
-                                                    NodeRec* __restrict__ inner, uint32_t B, Dirs dirs) {
-    const uint32_t h = dt->h;
-    if (u > h || dt->L == 0) return;
-    const uint32_t l = h - u;  // parent level
-    const uint64_t n_parent = dt->lv[l].n, n_child = dt->lv[l + 1].n;
-    const NodeRec* child = u == 1 ? dirs.leaf[dt->cur] : inner + dt->lv[l + 1].off;
-    NodeRec* parent = inner + dt->lv[l].off;
-    const uint32_t g = threadIdx.x % G;
-    // a group of G lanes per parent, striding over the level (the grid is
-    // sized by a bound of the level's size); the loop bound is uniform per
-    // group, so all of a group's lanes stay for the shuffles
-    const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) / G;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n_parent; i += stride) {
-    const uint64_t c = i * B + g;
-    const bool on = i < n_parent && g < B && c < n_child;  // all lanes stay for the shuffles
-    NodeRec x = {};
-    if (on) x = child[c];
-    uint32_t cnt = on ? x.cnt : 0u;
-    uint32_t lo[D], hi[D];
+// Node levels u0 + 1 .. u0 + k above the leaves (fewer where the tree is
+// lower), one subtree per workgroup: the first level's parents are formed
+// from the B^k children read straight from memory (level u0 above the
+// leaves: the current directory for u0 = 0; one child per lane, coalesced),
+// each further level from the one below held in LDS (count = sum, box =
+// per-axis min/max of the non-empty children); every level is written out.
+// B^k <= KN_CHILD. s_dyn holds B^(k-1) + B^(k-2) records. Grid-stride over
+// the subtrees (the grid is sized from a bound of the leaf count; the
+// device state holds the layout).
+constexpr uint32_t KN_CHILD = 1024;
+
+// Parent of a group of G lanes (G a power of two >= B): lane g of the group
+// brings child g (`on`: it exists) and the group reduces by xor shuffles;
+// every lane of the group must take part.
+template <int D>
+__device__ __forceinline__ NodeRec reduce_group(const NodeRec& x, bool on, uint32_t G) {
+    uint32_t cnt = on ? x.cnt : 0u, lo[D], hi[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         lo[d] = cnt ? x.lo[d] : 0xFFFFFFFFu;
         hi[d] = cnt ? x.hi[d] : 0u;
     }
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) {
-        const int src = (int)(lane_id() ^ (uint32_t)o);
+    for (uint32_t o = G / 2; o >= 1; o >>= 1) {
+        const int src = (int)(lane_id() ^ o);
         cnt += shfl_u32(cnt, src);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -160,17 +149,66 @@ __global__ __launch_bounds__(256) void k_node_level(const DevTree* __restrict__ 
             hi[d] = max(hi[d], shfl_u32(hi[d], src));
         }
     }
-    if (g == 0 && i < n_parent) {
-        NodeRec r;
+    NodeRec p;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            r.lo[d] = d < D ? lo[d % D] : (cnt ? 0u : 0xFFFFFFFFu);
-            r.hi[d] = d < D ? hi[d % D] : 0u;
-        }
-        r.cnt = cnt;
-        r.slot = 0xFFFFFFFFu;
-        parent[i] = r;
+    for (int d = 0; d < 3; ++d) {
+        p.lo[d] = d < D ? lo[d % D] : (cnt ? 0u : 0xFFFFFFFFu);
+        p.hi[d] = d < D ? hi[d % D] : 0u;
     }
+    p.cnt = cnt;
+    p.slot = 0xFFFFFFFFu;
+    return p;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_node_levels(const DevTree* __restrict__ dt, uint32_t u0, uint32_t k,
+                                                     NodeRec* __restrict__ inner, uint32_t B, Dirs dirs) {
+    extern __shared__ NodeRec s_dyn[];
+    const uint32_t h = dt->h;
+    if (dt->L == 0 || u0 >= h) return;
+    const uint32_t kk = min(k, h - u0);
+    uint32_t span = 1;  // B^kk: children of one subtree
+    for (uint32_t j = 0; j < kk; ++j) span *= B;
+    uint32_t G = 2;
+    while (G < B) G <<= 1;
+    const uint32_t lc = h - u0;  // the children's level
+    const uint64_t n_child = dt->lv[lc].n;
+    const NodeRec* child = u0 == 0 ? dirs.leaf[dt->cur] : inner + dt->lv[lc].off;
+    const uint64_t roots = (n_child + span - 1) / span;
+    for (uint64_t w = blockIdx.x; w < roots; w += gridDim.x) {
+        const uint64_t c0 = w * span;
+        uint32_t cc = (uint32_t)min<uint64_t>(span, n_child - c0);
+        const NodeRec* in = child + c0;
+        NodeRec* out = s_dyn;
+        NodeRec* spare = s_dyn + span / B;
+        uint32_t per = span;  // children per subtree at the current child level
+        for (uint32_t j = 1; j <= kk; ++j) {
+            per /= B;
+            const uint32_t l = lc - j;  // parent level
+            const uint64_t p0 = w * per;
+            const uint32_t pc = (uint32_t)((cc + B - 1) / B);  // parents in this subtree (one per B children)
+            NodeRec* gp = inner + dt->lv[l].off + p0;
+            // G lanes per parent (G divides the block, so a group never
+            // straddles two passes and the pass count is the block's)
+            for (uint32_t b0 = 0; b0 < pc * G; b0 += blockDim.x) {
+                const uint32_t idx = b0 + threadIdx.x, x = idx / G, g = idx % G;
+                const uint32_t c = x * B + g;
+                const bool on = x < pc && g < B && c < cc;
+                NodeRec r = {};
+                if (on) r = in[c];
+                r = reduce_group<D>(r, on, G);
+                if (g == 0 && x < pc) {
+                    out[x] = r;
+                    gp[x] = r;
+                }
+            }
+            __syncthreads();
+            NodeRec* t = spare;
+            spare = out;
+            in = out;
+            out = t;
+            cc = pc;
+        }
     }
 }
 
@@ -322,28 +360,23 @@ void launch_pack_tree(hipStream_t st, int dim, const DevTree* dt, const Dirs& di
     else hipLaunchKernelGGL(k_pack_tree<3>, dim3(g), dim3(256), 0, st, dt, leaves, inner, out, dirs);
 }
 
-void launch_node_level(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint32_t u,
-                       uint64_t n_parent_cap, NodeRec* inner, uint32_t B) {
-    if (n_parent_cap == 0) return;
-    uint32_t G = 2;
-    while (G < B) G <<= 1;
-    unsigned g = blocks_for(n_parent_cap * G, 256);
-    if (g > 4096) g = 4096;
-#define PSI_NL(D, GG) hipLaunchKernelGGL((k_node_level<D, GG>), dim3(g), dim3(256), 0, st, dt, u, inner, B, dirs)
-#define PSI_NL2(GG)              \
-    do {                         \
-        if (dim == 2) PSI_NL(2, GG); \
-        else PSI_NL(3, GG);      \
-    } while (0)
-    switch (G) {
-        case 2: PSI_NL2(2); break;
-        case 4: PSI_NL2(4); break;
-        case 8: PSI_NL2(8); break;
-        case 16: PSI_NL2(16); break;
-        default: PSI_NL2(32); break;
+void launch_node_levels(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint64_t L_bound,
+                        NodeRec* inner, uint32_t B) {
+    uint32_t hb = 0;  // height for L_bound leaves: the device's is at most this
+    for (uint64_t n = L_bound; n > 1; ++hb) n = (n + B - 1) / B;
+    uint32_t k = 1;  // levels per launch: B^k <= KN_CHILD children staged per workgroup
+    for (uint64_t p = (uint64_t)B * B; p <= KN_CHILD; p *= B) ++k;
+    for (uint32_t u0 = 0; u0 < hb; u0 += k) {
+        const uint32_t kk = std::min(k, hb - u0);
+        uint64_t n = L_bound;  // bound of the level u0 + kk node count: the subtrees
+        for (uint32_t j = 0; j < u0 + kk; ++j) n = (n + B - 1) / B;
+        unsigned g = (unsigned)std::min<uint64_t>(std::max<uint64_t>(n, 1), 8192);
+        uint64_t span = 1;
+        for (uint32_t j = 0; j < k; ++j) span *= B;
+        const size_t lds = (span / B + std::max<uint64_t>(span / B / B, 1)) * sizeof(NodeRec);
+        if (dim == 2) hipLaunchKernelGGL(k_node_levels<2>, dim3(g), dim3(256), lds, st, dt, u0, k, inner, B, dirs);
+        else hipLaunchKernelGGL(k_node_levels<3>, dim3(g), dim3(256), lds, st, dt, u0, k, inner, B, dirs);
     }
-#undef PSI_NL2
-#undef PSI_NL
 }
 
 void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp) {

@@ -192,10 +192,12 @@ __global__ void k_del_check(const DevTree* __restrict__ dt, uint32_t* __restrict
     }
 }
 
+// Rejects the whole delete (ctr[9] = 1: no id is claimed) when the tree has
+// more leaves than the launches cover.
 __global__ void k_del_precheck(const DevTree* __restrict__ dt, uint32_t* __restrict__ ctr, Caps cap) {
     if (threadIdx.x | blockIdx.x) return;
     if (dt->L > cap.lgrid) {
-        ctr[0] = 0;
+        ctr[9] = 1;
         atomicOr(cap.err, ERR_CAPACITY);
     }
 }

@@ -403,40 +403,54 @@ __global__ void k_ins_free(const uint32_t* __restrict__ run_leaf, const uint32_t
 }
 
 // ------------------------------------------------------------------ delete
-__global__ void k_del_gather(const uint32_t* __restrict__ ids, uint64_t m, const uint64_t* __restrict__ idkey,
-                             const DevTree* __restrict__ dt, uint64_t* __restrict__ dk, uint32_t* __restrict__ di) {
+// Takes the batch: every id below next_id is claimed by swapping its key in
+// the id table for the dead mark, so an id already deleted, and every repeat
+// of an id after the first, finds the mark and is dropped. A claimed
+// (key, id) is routed to its leaf by the current pivots; the sort key is the
+// leaf index, or `marker` (above every leaf index) for a dropped entry, so
+// that sorting on the leaf bits alone puts the claimed entries first,
+// grouped by leaf. The number claimed is added to ctr[0]. Nothing is claimed
+// when ctr[9] holds a rejection.
+__global__ void k_del_take(const uint32_t* __restrict__ ids, uint64_t m, uint64_t* __restrict__ idkey,
+                           const DevTree* __restrict__ dt, Dirs dirs, uint32_t* __restrict__ ctr, uint64_t marker,
+                           uint64_t* __restrict__ lk, uint32_t* __restrict__ li) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const uint32_t next_id = dt->next_id;
-    const uint32_t id = ids[e];
-    const uint64_t key = id < next_id ? idkey[id] : DEAD_KEY;
-    dk[e] = key;
-    di[e] = key == DEAD_KEY ? PAD_ID : id;
+    uint32_t id = PAD_ID;
+    uint64_t key = DEAD_KEY;
+    if (e < m && ctr[9] == 0) {
+        id = ids[e];
+        if (id < dt->next_id)
+            key = atomicExch(reinterpret_cast<unsigned long long*>(idkey + id), (unsigned long long)DEAD_KEY);
+    }
+    const bool ok = key != DEAD_KEY;
+    uint64_t leaf = marker;
+    if (ok) {
+        const uint32_t c = dt->cur;
+        const uint64_t* pk = dirs.pkey[c];
+        const uint32_t* pi = dirs.pid[c];
+        uint64_t lo = 0, hi = dt->L;  // first pivot greater than (key, id)
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (!pair_less(key, id, pk[mid], pi[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        leaf = lo == 0 ? 0u : lo - 1;
+    }
+    if (e < m) {
+        lk[e] = leaf;
+        li[e] = id;
+    }
+    const uint64_t b = ballot(ok);
+    if (lane_id() == 0 && b) atomicAdd(ctr, (uint32_t)__popcll(b));
 }
 
-__global__ void k_del_valid(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ si, uint64_t m,
-                            uint32_t* __restrict__ flag) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const bool dup = e > 0 && sk[e] == sk[e - 1] && si[e] == si[e - 1];
-    flag[e] = sk[e] != DEAD_KEY && !dup ? 1u : 0u;
-}
-
-__global__ void k_del_compact(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ si,
-                              const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, uint64_t m,
-                              uint64_t* __restrict__ ck, uint32_t* __restrict__ ci) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m || !flag[e]) return;
-    ck[pos[e]] = sk[e];
-    ci[pos[e]] = si[e];
-}
-
-__global__ void k_del_kill(const uint32_t* __restrict__ ci, const uint32_t* __restrict__ ctr, uint64_t m,
-                           uint64_t* __restrict__ idkey, uint64_t* __restrict__ ndel) {
+// Leaf index of every sorted entry (the low word of its sort key), and the
+// number deleted to *ndel.
+__global__ void k_del_leaf_of(const uint64_t* __restrict__ sk, uint64_t m, const uint32_t* __restrict__ ctr,
+                              uint32_t* __restrict__ leaf_of, uint64_t* __restrict__ ndel) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0 && ndel) *ndel = ctr[0];
-    if (e >= m || e >= ctr[0]) return;
-    idkey[ci[e]] = DEAD_KEY;
+    if (e < m) leaf_of[e] = (uint32_t)sk[e];
 }
 
 // One wave per run: lane e holds leaf entry e; entries whose id is in the
@@ -934,19 +948,13 @@ void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr,
     hipLaunchKernelGGL(k_ins_free, dim3(blocks_for(m, 256)), dim3(256), 0, st, run_leaf, ctr, m, rsplit, free_off, dt, free_stack, cap);
 }
 
-void upd_del_gather(hipStream_t st, const uint32_t* ids, uint64_t m, const uint64_t* idkey, const DevTree* dt,
-                    uint64_t* dk, uint32_t* di) {
-    hipLaunchKernelGGL(k_del_gather, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, dt, dk, di);
+void upd_del_take(hipStream_t st, const uint32_t* ids, uint64_t m, uint64_t* idkey, const DevTree* dt, const Dirs& dirs,
+                  uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li) {
+    hipLaunchKernelGGL(k_del_take, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, dt, dirs, ctr, marker, lk, li);
 }
-void upd_del_compact(hipStream_t st, const uint64_t* sk, const uint32_t* si, uint64_t m, uint32_t* flag,
-                     uint32_t* pos, uint32_t* V_dev, uint64_t* ck, uint32_t* ci, uint32_t* tmp) {
-    hipLaunchKernelGGL(k_del_valid, dim3(blocks_for(m, 256)), dim3(256), 0, st, sk, si, m, flag);
-    launch_scan_u32(st, flag, pos, m, V_dev, tmp);
-    hipLaunchKernelGGL(k_del_compact, dim3(blocks_for(m, 256)), dim3(256), 0, st, sk, si, flag, pos, m, ck, ci);
-}
-void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint64_t m, uint64_t* idkey,
-                  uint64_t* ndel) {
-    hipLaunchKernelGGL(k_del_kill, dim3(blocks_for(m, 256)), dim3(256), 0, st, ci, ctr, m, idkey, ndel);
+void upd_del_leaf_of(hipStream_t st, const uint64_t* sk, uint64_t m, const uint32_t* ctr, uint32_t* leaf_of,
+                     uint64_t* ndel) {
+    hipLaunchKernelGGL(k_del_leaf_of, dim3(blocks_for(m, 256)), dim3(256), 0, st, sk, m, ctr, leaf_of, ndel);
 }
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,
                     const uint32_t* ctr, uint64_t m, const DevTree* dt, uint32_t* slots, uint32_t C, uint32_t phi,

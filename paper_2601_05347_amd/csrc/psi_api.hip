@@ -391,11 +391,7 @@ psi_status build_nodes(psi_index ix, uint64_t L_bound) {
     if ((s = ensure_q(ix, ix->cleaf, std::max<uint64_t>(L_bound, 1) * 16)) != PSI_OK) return s;
     ix->L_cap = std::max(ix->L_cap, L_bound);
     ProfScope ps(ix, "nodes", inner_n * 32 + L_bound * 32);
-    uint64_t np = L_bound;
-    for (uint32_t u = 1; u <= h; ++u) {
-        np = (np + ix->B - 1) / ix->B;
-        launch_node_level(ix->st, ix->D, ix->dt(), dirs_of(ix), u, np, ix->inner.as<NodeRec>(), ix->B);
-    }
+    launch_node_levels(ix->st, ix->D, ix->dt(), dirs_of(ix), L_bound, ix->inner.as<NodeRec>(), ix->B);
     return last_launch();
 }
 

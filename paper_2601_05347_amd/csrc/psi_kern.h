@@ -220,11 +220,12 @@ void launch_scan_multi(hipStream_t st, const ScanSet& s, int k, uint32_t* tmp);
 void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk, const uint32_t* sid,
                          uint64_t n, uint64_t L, uint32_t C, uint32_t* slots, uint64_t* piv_key,
                          uint32_t* piv_id, NodeRec* leafrec, const uint64_t* skip = nullptr);
-// Node level u (1 = the parents of the leaves) of the layout in dt: parent i
-// = union of children [B i, B i + B). n_parent_cap bounds the level's size
-// (the grid); a level above the tree's height does nothing.
-void launch_node_level(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint32_t u,
-                       uint64_t n_parent_cap, NodeRec* inner, uint32_t B);
+// Every node level of the layout in dt, bottom up (parent i = union and sum
+// of children [B i, B i + B)), several levels per launch. L_bound bounds the
+// leaf count (the grids and the number of launches); levels above the
+// tree's height do nothing.
+void launch_node_levels(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint64_t L_bound,
+                        NodeRec* inner, uint32_t B);
 // Packed boxes of the current leaves (leaves = true) or inner nodes of dt;
 // cap bounds their number.
 void launch_pack_tree(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, bool leaves,

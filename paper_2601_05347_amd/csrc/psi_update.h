@@ -55,12 +55,14 @@ void upd_piece_meta(hipStream_t st, int dim, const uint32_t* piece_pos, uint64_t
 void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr, uint64_t m, const uint32_t* rsplit,
                   const uint32_t* free_off, const DevTree* dt, uint32_t* free_stack, Caps cap);
 
-void upd_del_gather(hipStream_t st, const uint32_t* ids, uint64_t m, const uint64_t* idkey, const DevTree* dt,
-                    uint64_t* dk, uint32_t* di);
-void upd_del_compact(hipStream_t st, const uint64_t* sk, const uint32_t* si, uint64_t m, uint32_t* flag,
-                     uint32_t* pos, uint32_t* V_dev, uint64_t* ck, uint32_t* ci, uint32_t* tmp);
-void upd_del_kill(hipStream_t st, const uint32_t* ci, const uint32_t* ctr, uint64_t m, uint64_t* idkey,
-                  uint64_t* ndel);
+// Claims the batch's live ids (their keys in idkey become the dead mark),
+// routes them to their leaves and writes the sort keys (leaf index, or
+// `marker` for a dropped id) and ids; ctr[0] += the number claimed.
+void upd_del_take(hipStream_t st, const uint32_t* ids, uint64_t m, uint64_t* idkey, const DevTree* dt, const Dirs& dirs,
+                  uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li);
+// leaf_of[e] = low word of the sorted key e; *ndel (nullable) = ctr[0].
+void upd_del_leaf_of(hipStream_t st, const uint64_t* sk, uint64_t m, const uint32_t* ctr, uint32_t* leaf_of,
+                     uint64_t* ndel);
 // Removes the runs' ids from their leaves; *under |= 1 if a leaf ends below
 // ceil(phi / 2) entries.
 void upd_del_remove(hipStream_t st, int dim, const uint32_t* ci, const uint32_t* run_leaf, const uint32_t* run_beg,

@@ -136,8 +136,8 @@ InsArrays carve_ins(Carver& c, uint64_t m, uint64_t L, uint64_t A_max) {
 
 struct DelArrays {
     uint32_t* ctr;
-    uint64_t *dk, *ck;
-    uint32_t *di, *flag, *pos, *ci, *leaf_of, *ridx, *run_leaf, *run_beg;
+    uint64_t* dk;
+    uint32_t *di, *flag, *ci, *leaf_of, *ridx, *run_leaf, *run_beg;
     uint32_t *cnt, *cum, *start, *gidx, *grp_first, *gpieces, *gchunks, *galloc, *gfree, *gchanged, *gpos, *chunk_off,
         *alloc_off, *free_off, *tmp, *slot_alloc, *piece_pos;
 };
@@ -147,11 +147,9 @@ DelArrays carve_del(Carver& c, uint64_t m, uint64_t L, uint64_t A_max) {
     DelArrays a;
     a.ctr = c.take<uint32_t>(16);
     a.dk = c.take<uint64_t>(m);
-    a.ck = c.take<uint64_t>(m);
     a.di = c.take<uint32_t>(m);
     a.flag = c.take<uint32_t>(m);
-    a.pos = c.take<uint32_t>(m);
-    a.ci = c.take<uint32_t>(m);
+    a.ci = nullptr;  // the sorted ids (the sorter's buffer)
     a.leaf_of = c.take<uint32_t>(m);
     a.ridx = c.take<uint32_t>(m);
     a.run_leaf = c.take<uint32_t>(m);
@@ -323,20 +321,23 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
     if ((s = grid_leaves(ix, Lb, L_cap, need, &Lg, &Lc)) != PSI_OK) return s;
     Carver real;
     real.base = static_cast<char*>(ix->scr.a.p);
-    const DelArrays a = carve_del(real, m, Lg, A_max);
+    DelArrays a = carve_del(real, m, Lg, A_max);
     const Caps cap = caps_of(ix, A_max, Lg, Lc);
     DevTree* dt = ix->dt();
     uint32_t* slots = ix->slots.as<uint32_t>();
 
     launch_fill_u32(st, a.ctr, 16, 0u);
-    upd_del_gather(st, d_ids, m, ix->idkey.as<uint64_t>(), dt, a.dk, a.di);
-    int w = 0;
-    if ((s = sort_pairs(ix, a.dk, a.di, 0, m, true, false, &w, "radix_update")) != PSI_OK) return s;
-    upd_del_compact(st, ix->sorter.k[w].as<uint64_t>(), ix->sorter.i[w].as<uint32_t>(), m, a.flag, a.pos, a.ctr + 0,
-                    a.ck, a.ci, a.tmp);
     st_del_precheck(st, dt, a.ctr, cap);
-    upd_del_kill(st, a.ci, a.ctr, m, ix->idkey.as<uint64_t>(), d_ndeleted);
-    upd_route(st, a.ck, a.ci, m, a.ctr + 0, dt, cap.dirs, a.leaf_of);
+    // the batch claimed and routed, then grouped by leaf: a sort on the
+    // bits of the leaf index only (entries within a leaf need no order)
+    int P = 1;
+    while (P < 4 && ((1ull << (8 * P)) - 1) < Lg) ++P;
+    const uint64_t marker = (1ull << (8 * P)) - 1;  // above every leaf index (< L <= Lg)
+    upd_del_take(st, d_ids, m, ix->idkey.as<uint64_t>(), dt, cap.dirs, a.ctr, marker, a.dk, a.di);
+    int w = 0;
+    if ((s = sort_pairs(ix, a.dk, a.di, 0, m, false, false, &w, "radix_update", 0, P)) != PSI_OK) return s;
+    a.ci = ix->sorter.i[w].as<uint32_t>();
+    upd_del_leaf_of(st, ix->sorter.k[w].as<uint64_t>(), m, a.ctr, a.leaf_of, d_ndeleted);
     upd_runs(st, a.leaf_of, m, a.ctr + 0, a.flag, a.ridx, a.run_leaf, a.run_beg, a.ctr + 1, a.tmp);
     if (before_apply && (s = hip_ok(hipStreamWaitEvent(st, before_apply, 0))) != PSI_OK) return s;
     upd_del_remove(st, ix->D, a.ci, a.run_leaf, a.run_beg, a.ctr, m, dt, slots, ix->C, phi, a.ctr + 8,
