@@ -212,6 +212,20 @@ __global__ __launch_bounds__(256) void k_node_levels(const DevTree* __restrict__
     }
 }
 
+// Every PSAMPLE-th pivot (key, id) of the current directory as one 16-byte
+// record {key low, key high, id, 0}: a table small enough to stay in cache
+// for the first steps of routing a key to its leaf.
+__global__ void k_pivot_sample(const DevTree* __restrict__ dt, Dirs dirs, uint4* __restrict__ out, uint64_t cap) {
+    const uint64_t L = dt->L, ns = min<uint64_t>((L + PSAMPLE - 1) / PSAMPLE, cap);
+    const uint32_t c = dt->cur;
+    const uint64_t* pk = dirs.pkey[c];
+    const uint32_t* pi = dirs.pid[c];
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = pk[j * PSAMPLE];
+        out[j] = make_uint4((uint32_t)k, (uint32_t)(k >> 32), pi[j * PSAMPLE], 0u);
+    }
+}
+
 // Packed boxes of the current leaves (leaves = true) or of the inner nodes,
 // as many as the device state holds; grid-stride over at most `cap` records.
 template <int D>
@@ -377,6 +391,12 @@ void launch_node_levels(hipStream_t st, int dim, const DevTree* dt, const Dirs& 
         if (dim == 2) hipLaunchKernelGGL(k_node_levels<2>, dim3(g), dim3(256), lds, st, dt, u0, k, inner, B, dirs);
         else hipLaunchKernelGGL(k_node_levels<3>, dim3(g), dim3(256), lds, st, dt, u0, k, inner, B, dirs);
     }
+}
+
+void launch_pivot_sample(hipStream_t st, const DevTree* dt, const Dirs& dirs, uint4* out, uint64_t cap) {
+    if (!cap) return;
+    const unsigned g = (unsigned)std::min<uint64_t>((cap + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pivot_sample, dim3(g), dim3(256), 0, st, dt, dirs, out, cap);
 }
 
 void launch_leaf_offsets(hipStream_t st, const NodeRec* leaf, uint64_t L, uint64_t* off, uint64_t* tmp) {

@@ -411,9 +411,12 @@ __global__ void k_ins_free(const uint32_t* __restrict__ run_leaf, const uint32_t
 // that sorting on the leaf bits alone puts the claimed entries first,
 // grouped by leaf. The number claimed is added to ctr[0]. Nothing is claimed
 // when ctr[9] holds a rejection.
+// The route searches the pivot sample (every PSAMPLE-th pivot, `samp`) first,
+// then the PSAMPLE pivots it narrows the leaf to.
 __global__ void k_del_take(const uint32_t* __restrict__ ids, uint64_t m, uint64_t* __restrict__ idkey,
-                           const DevTree* __restrict__ dt, Dirs dirs, uint32_t* __restrict__ ctr, uint64_t marker,
-                           uint64_t* __restrict__ lk, uint32_t* __restrict__ li) {
+                           const DevTree* __restrict__ dt, Dirs dirs, const uint4* __restrict__ samp,
+                           uint32_t* __restrict__ ctr, uint64_t marker, uint64_t* __restrict__ lk,
+                           uint32_t* __restrict__ li) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t id = PAD_ID;
     uint64_t key = DEAD_KEY;
@@ -428,13 +431,22 @@ __global__ void k_del_take(const uint32_t* __restrict__ ids, uint64_t m, uint64_
         const uint32_t c = dt->cur;
         const uint64_t* pk = dirs.pkey[c];
         const uint32_t* pi = dirs.pid[c];
-        uint64_t lo = 0, hi = dt->L;  // first pivot greater than (key, id)
+        const uint64_t L = dt->L, ns = (L + PSAMPLE - 1) / PSAMPLE;
+        uint64_t lo = 0, hi = ns;  // first sampled pivot greater than (key, id)
         while (lo < hi) {
             const uint64_t mid = (lo + hi) >> 1;
-            if (!pair_less(key, id, pk[mid], pi[mid])) lo = mid + 1;
+            const uint4 sv = samp[mid];
+            if (!pair_less(key, id, ((uint64_t)sv.y << 32) | sv.x, sv.z)) lo = mid + 1;
             else hi = mid;
         }
-        leaf = lo == 0 ? 0u : lo - 1;
+        // the first pivot greater than (key, id) is in (PSAMPLE (lo - 1), PSAMPLE lo]
+        uint64_t a = lo ? (lo - 1) * PSAMPLE : 0, b = min<uint64_t>(lo ? lo * PSAMPLE : PSAMPLE, L);
+        while (a < b) {
+            const uint64_t mid = (a + b) >> 1;
+            if (!pair_less(key, id, pk[mid], pi[mid])) a = mid + 1;
+            else b = mid;
+        }
+        leaf = a == 0 ? 0u : a - 1;
     }
     if (e < m) {
         lk[e] = leaf;
@@ -949,8 +961,8 @@ void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr,
 }
 
 void upd_del_take(hipStream_t st, const uint32_t* ids, uint64_t m, uint64_t* idkey, const DevTree* dt, const Dirs& dirs,
-                  uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li) {
-    hipLaunchKernelGGL(k_del_take, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, dt, dirs, ctr, marker, lk, li);
+                  const uint4* samp, uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li) {
+    hipLaunchKernelGGL(k_del_take, dim3(blocks_for(m, 256)), dim3(256), 0, st, ids, m, idkey, dt, dirs, samp, ctr, marker, lk, li);
 }
 void upd_del_leaf_of(hipStream_t st, const uint64_t* sk, uint64_t m, const uint32_t* ctr, uint32_t* leaf_of,
                      uint64_t* ndel) {

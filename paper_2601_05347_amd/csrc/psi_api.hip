@@ -392,6 +392,9 @@ psi_status build_nodes(psi_index ix, uint64_t L_bound) {
     ix->L_cap = std::max(ix->L_cap, L_bound);
     ProfScope ps(ix, "nodes", inner_n * 32 + L_bound * 32);
     launch_node_levels(ix->st, ix->D, ix->dt(), dirs_of(ix), L_bound, ix->inner.as<NodeRec>(), ix->B);
+    const uint64_t ns = (L_bound + PSAMPLE - 1) / PSAMPLE + 1;
+    if ((s = ensure_q(ix, ix->psample, ns * 16)) != PSI_OK) return s;
+    launch_pivot_sample(ix->st, ix->dt(), dirs_of(ix), ix->psample.as<uint4>(), ns);
     return last_launch();
 }
 

@@ -227,6 +227,7 @@ struct psi_index_s {
     // node levels 0..h-1, level-major from the root
     psi::Buf inner;
     psi::Buf cinner, cleaf;  // packed boxes of the inner nodes and of the leaves
+    psi::Buf psample;        // every PSAMPLE-th pivot (routing's first steps)
     bool boxes_fresh = false;  // packed boxes match the current tree
     uint64_t L_cap = 0;        // leaves the node buffers and packed boxes are sized for
 

@@ -226,6 +226,10 @@ void launch_build_leaves(hipStream_t st, int dim, int curve, const uint64_t* sk,
 // tree's height do nothing.
 void launch_node_levels(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, uint64_t L_bound,
                         NodeRec* inner, uint32_t B);
+// Every PSAMPLE-th pivot of the current directory, {key lo, key hi, id, 0}
+// per record, at most cap records (ceil(L / PSAMPLE) are written).
+constexpr uint32_t PSAMPLE = 32;
+void launch_pivot_sample(hipStream_t st, const DevTree* dt, const Dirs& dirs, uint4* out, uint64_t cap);
 // Packed boxes of the current leaves (leaves = true) or inner nodes of dt;
 // cap bounds their number.
 void launch_pack_tree(hipStream_t st, int dim, const DevTree* dt, const Dirs& dirs, bool leaves,

@@ -58,8 +58,9 @@ void upd_ins_free(hipStream_t st, const uint32_t* run_leaf, const uint32_t* ctr,
 // Claims the batch's live ids (their keys in idkey become the dead mark),
 // routes them to their leaves and writes the sort keys (leaf index, or
 // `marker` for a dropped id) and ids; ctr[0] += the number claimed.
+// samp: the pivot sample of the current directory (first routing steps).
 void upd_del_take(hipStream_t st, const uint32_t* ids, uint64_t m, uint64_t* idkey, const DevTree* dt, const Dirs& dirs,
-                  uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li);
+                  const uint4* samp, uint32_t* ctr, uint64_t marker, uint64_t* lk, uint32_t* li);
 // leaf_of[e] = low word of the sorted key e; *ndel (nullable) = ctr[0].
 void upd_del_leaf_of(hipStream_t st, const uint64_t* sk, uint64_t m, const uint32_t* ctr, uint32_t* leaf_of,
                      uint64_t* ndel);

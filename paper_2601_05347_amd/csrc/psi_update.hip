@@ -333,7 +333,8 @@ psi_status do_delete(psi_index ix, const uint32_t* d_ids, uint64_t m, uint64_t* 
     int P = 1;
     while (P < 4 && ((1ull << (8 * P)) - 1) < Lg) ++P;
     const uint64_t marker = (1ull << (8 * P)) - 1;  // above every leaf index (< L <= Lg)
-    upd_del_take(st, d_ids, m, ix->idkey.as<uint64_t>(), dt, cap.dirs, a.ctr, marker, a.dk, a.di);
+    upd_del_take(st, d_ids, m, ix->idkey.as<uint64_t>(), dt, cap.dirs, ix->psample.as<uint4>(), a.ctr, marker, a.dk,
+                 a.di);
     int w = 0;
     if ((s = sort_pairs(ix, a.dk, a.di, 0, m, false, false, &w, "radix_update", 0, P)) != PSI_OK) return s;
     a.ci = ix->sorter.i[w].as<uint32_t>();
