@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=600, help="requests in the default line's serving block")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests per stream")
     ap.add_argument("--rho", default="0.5,0.8,1.2", help="serve: loads relative to the plain path's capacity")
+    ap.add_argument("--serve-paths", default="plain,batched,library", help="serve: the paths to run")
     ap.add_argument("--indexes", type=int, default=4096, help="multi: number of indexes")
     ap.add_argument("--batch-frac", default="0.1,0.01,0.001,0.0001", help="incr: batch sizes as fractions of n")
     ap.add_argument("--tree", default="spac", choices=["spac", "orth"],
@@ -86,37 +87,47 @@ def parse():
     return ap.parse_args()
 
 
-def csrc_hash() -> str:
-    """SHA-256 over the library's kernel sources (names and code, sorted),
-    with comments and blank space left out: counters taken on the code stay
-    valid across comment edits."""
+# The source files whose code decides each kernel family's memory traffic
+# (its own file and the device helpers it includes).
+FAMILY_SOURCES = {
+    "radix_first": ["k_sort.hip"], "radix_pass": ["k_sort.hip"], "encode_hist": ["k_sort.hip"],
+    "local_sort": ["k_bucket.hip"], "local_sort_wide": ["k_bucket.hip"], "bucket_starts": ["k_bucket.hip"],
+    "radix_big": ["k_bucket.hip"], "leaf_fill": ["k_build.hip"], "nodes": ["k_build.hip"],
+    "knn": ["k_query.hip"], "range_count": ["k_query.hip"], "range_report": ["k_query.hip"],
+}
+DEVICE_HELPERS = ["psi_dev.h", "psi_hilbert.h"]
+
+
+def src_hash(family: str) -> str:
+    """SHA-256 over the sources of a kernel family, with comments and blank
+    space left out: counters taken on the code stay valid across comment
+    edits and across changes to other kernels."""
     import hashlib
     import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2601_05347_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            code = open(os.path.join(d, f)).read()
-            code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
-            code = re.sub(r"//[^\n]*", " ", code)
-            h.update(f.encode())
-            h.update(" ".join(code.split()).encode())
+    for f in FAMILY_SOURCES[family] + DEVICE_HELPERS:
+        code = open(os.path.join(d, f)).read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(f.encode())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 
 def profiled_traffic(profile: str, family: str):
     """HBM bytes per launch of a kernel family recorded by rocprofv3 counter
-    runs, if no kernel source changed since (the profile carries the hash)."""
+    runs, if none of its sources changed since (the profile carries their
+    hash on the family's line: `traffic[family]: bytes sha256`)."""
     import re
     try:
         txt = open(os.path.join(ROOT, "profiles", profile)).read()
     except OSError:
         return None
-    m_t = re.search(r"traffic\[%s\]:\s*(\d+)" % re.escape(family), txt)
-    m_h = re.search(r"csrc_sha256:\s*([0-9a-f]{64})", txt)
-    if not (m_t and m_h) or m_h.group(1) != csrc_hash():
+    m = re.search(r"traffic\[%s\]:\s*(\d+)\s+([0-9a-f]{64})" % re.escape(family), txt)
+    if not m or family not in FAMILY_SOURCES or m.group(2) != src_hash(family):
         return None
-    return int(m_t.group(1))
+    return int(m.group(1))
 
 
 CPU_THREADS = 16  # the host cores one GPU's box share has
@@ -238,9 +249,10 @@ def bench_serve(args):
     (the Python scheduler and the library's server)."""
     cfg = WORKLOADS["serve"]
     n0 = args.n or cfg["n"]
+    paths = tuple(args.serve_paths.split(","))
     lam_plain, runs = serve_runs(n0, args.requests, [float(x) for x in args.rho.split(",")], args.seed, args.leaf,
-                                 args.fanout)
-    b = runs[max(runs)]["library"]
+                                 args.fanout, paths=paths)
+    b = runs[max(runs)][paths[-1]]
     out = {"metric": "p99 latency (ms) of mixed requests, continuous batching, 1 GPU", "value": round(b["all"]["p99_ms"], 3),
            "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64",

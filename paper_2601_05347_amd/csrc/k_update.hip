@@ -59,10 +59,12 @@ __global__ void k_route(const uint64_t* __restrict__ bk, const uint32_t* __restr
     const uint64_t L = dt->L;
     const uint64_t k = bk[e];
     const uint32_t i = bi[e];
-    uint64_t lo = 0, hi = L;  // first pivot greater than (k, i)
+    uint64_t lo = 0, hi = L;  // first pivot greater than (k, i); ids read on key ties only
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (!pair_less(k, i, pk[mid], pi[mid])) lo = mid + 1;
+        const uint64_t km = pk[mid];
+        const bool below = k < km || (k == km && i < pi[mid]);
+        if (!below) lo = mid + 1;
         else hi = mid;
     }
     leaf_of[e] = lo == 0 ? 0u : (uint32_t)(lo - 1);
@@ -441,9 +443,11 @@ __global__ void k_del_take(const uint32_t* __restrict__ ids, uint64_t m, uint64_
         }
         // the first pivot greater than (key, id) is in (PSAMPLE (lo - 1), PSAMPLE lo]
         uint64_t a = lo ? (lo - 1) * PSAMPLE : 0, b = min<uint64_t>(lo ? lo * PSAMPLE : PSAMPLE, L);
-        while (a < b) {
+        while (a < b) {  // a pivot's id is read only when its key ties
             const uint64_t mid = (a + b) >> 1;
-            if (!pair_less(key, id, pk[mid], pi[mid])) a = mid + 1;
+            const uint64_t km = pk[mid];
+            const bool below = key < km || (key == km && id < pi[mid]);
+            if (!below) a = mid + 1;
             else b = mid;
         }
         leaf = a == 0 ? 0u : a - 1;
