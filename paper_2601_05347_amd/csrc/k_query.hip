@@ -380,25 +380,28 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
     if (walking) stk[0] = m0;
     else pend = m0;
     for (;;) {
-        // (2) fill the candidate list
+        // (2) fill the candidate list. Every pass of the loop ends in one
+        // expansion (the costly step, run by the whole wave at once); the
+        // cheap steps before it (moving pending leaves to the list, popping
+        // exhausted levels) run in loops of their own, so a lane busy with
+        // them does not hold the others' expansions back a pass each.
         while (ncand < KNN_CAND) {
-            if (pend) {
+            while (pend && ncand < KNN_CAND) {
                 const uint32_t b = (uint32_t)__builtin_ctz(pend);
                 pend &= pend - 1;
                 cand[ncand * stride] = pbase + b;
                 ++ncand;
-                continue;
             }
-            if (!walking) break;
-            const uint32_t m = stk[l * stride];
+            if (pend || !walking) break;
+            uint32_t m = stk[l * stride];
+            while (m == 0 && l > 0) {
+                --l;
+                base = base / B / B * B;
+                m = stk[l * stride];
+            }
             if (m == 0) {
-                if (l == 0) {
-                    walking = false;
-                } else {
-                    --l;
-                    base = base / B / B * B;
-                }
-                continue;
+                walking = false;
+                break;
             }
             const uint32_t b = (uint32_t)__builtin_ctz(m);
             stk[l * stride] = m & (m - 1);
