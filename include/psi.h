@@ -426,6 +426,26 @@ psi_status psi_prof_reset(psi_index ix);
 psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches,
                         uint64_t* h_bytes);
 
+/* --- runtime knobs (for a tuner) ---------------------------------------- */
+
+/* Knobs that change speed, never results. knn_seed_leaves: leaves scanned
+ * before the walk of the lane-per-query kNN (k <= 16, the default
+ * traversal): the query's own leaf (the last whose pivot key is not above
+ * the query's curve key, App. C's nearby start) and (knn_seed_leaves - 1) / 2
+ * on each side in curve order; odd, 1..9, default 3. knn_cand: candidate
+ * leaves that walk collects before scanning them, 1..32, default 16.
+ * order_bits: top curve-key bits the ordering of query and box batches sorts
+ * on (8, 16, 24 or 32; default 24), when batches are ordered at all (not
+ * with PSI_FLAG_INPUT_ORDER). psi_set_tuning returns PSI_E_ARG for values
+ * out of range and changes nothing then; it applies to later calls. */
+typedef struct psi_tuning {
+    uint32_t knn_seed_leaves;
+    uint32_t knn_cand;
+    uint32_t order_bits;
+} psi_tuning;
+psi_status psi_set_tuning(psi_index ix, const psi_tuning* t);
+psi_status psi_get_tuning(psi_index ix, psi_tuning* t);
+
 /* Work counts of the kNN searches (App. C's visiting rule made measurable).
  * While enabled, every psi_knn of the index with the seeded traversal (the
  * default; not PSI_FLAG_KNN_NEAREST_FIRST) adds to four device counters:

@@ -87,6 +87,8 @@ SIGNATURES = {
     "psi_orth_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
     "psi_prof_enable": (_i, [_P, _i]),
     "psi_query_stats": (_i, [_P, _i, _P]),
+    "psi_set_tuning": (_i, [_P, _P]),
+    "psi_get_tuning": (_i, [_P, _P]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
 }
@@ -379,6 +381,21 @@ def psi_graph_launch(g, stream=None):
 
 def psi_graph_destroy(g):
     _check(lib().psi_graph_destroy(g), "psi_graph_destroy")
+
+
+class psi_tuning(C.Structure):
+    _fields_ = [("knn_seed_leaves", C.c_uint32), ("knn_cand", C.c_uint32), ("order_bits", C.c_uint32)]
+
+
+def psi_set_tuning(h, knn_seed_leaves: int = 3, knn_cand: int = 16, order_bits: int = 24):
+    t = psi_tuning(knn_seed_leaves, knn_cand, order_bits)
+    _check(lib().psi_set_tuning(h, C.byref(t)), "psi_set_tuning")
+
+
+def psi_get_tuning(h) -> dict:
+    t = psi_tuning()
+    _check(lib().psi_get_tuning(h, C.byref(t)), "psi_get_tuning")
+    return {"knn_seed_leaves": t.knn_seed_leaves, "knn_cand": t.knn_cand, "order_bits": t.order_bits}
 
 
 def psi_query_stats(h, enable: bool):

@@ -318,16 +318,20 @@ __device__ __forceinline__ void add_walk_stats(unsigned long long* stats, uint32
 // stack of child masks, one per level, in LDS (`stk`): expanding a node
 // reads the boxes of all its children in one batch of independent loads and
 // keeps those within the current k-th distance; children that are leaves go
-// to a list of candidate leaves in LDS (`cand`, KNN_CAND entries) instead of
+// to a list of candidate leaves in LDS (`cand`, ncap entries) instead of
 // being scanned; (3) the candidates are scanned, each checked again against
 // the k-th distance of the moment. A full list is scanned (and emptied)
 // before more leaves go in, so any number of candidates is handled. Both LDS
 // arrays hold one word per lane per entry, `stride` words apart. Needs
 // h() <= the stack depth; the caller takes the other walk beyond it.
+// sr: seed radius (the leaves j - sr .. j + sr around the query's own leaf j
+// seed the search); ncap: candidate leaves collected before a scan
+// (<= the LDS list's length).
 template <int D, int K, class T>
 __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv, const uint32_t* q, uint64_t key,
                                                  uint64_t (&bd)[K], uint32_t (&bi)[K], uint32_t* __restrict__ stk,
-                                                 uint32_t* __restrict__ cand, uint32_t stride, WalkCount& wc) {
+                                                 uint32_t* __restrict__ cand, uint32_t stride, uint32_t sr,
+                                                 uint32_t ncap, WalkCount& wc) {
     const uint32_t L = tr.L();
     if (L == 0) return;
     uint32_t lo = 0, hi = L;  // first pivot key above the query's key
@@ -337,7 +341,7 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
         else hi = mid;
     }
     const uint32_t j = lo ? lo - 1 : 0u;
-    const uint32_t ja = j ? j - 1 : 0u, jb = min(j + 1, L - 1);
+    const uint32_t ja = j > sr ? j - sr : 0u, jb = min(j + sr, L - 1);
     for (uint32_t x = ja; x <= jb; ++x) {
         const uint2 sc = tr.leaf_sc(x);  // (count, slot)
         scan_seed_leaf<D, K>(tv, sc.y, sc.x, q, bd, bi);
@@ -385,8 +389,8 @@ __device__ __forceinline__ void knn_seeded_masks(const T& tr, const TreeView& tv
         // cheap steps before it (moving pending leaves to the list, popping
         // exhausted levels) run in loops of their own, so a lane busy with
         // them does not hold the others' expansions back a pass each.
-        while (ncand < KNN_CAND) {
-            while (pend && ncand < KNN_CAND) {
+        while (ncand < ncap) {
+            while (pend && ncand < ncap) {
                 const uint32_t b = (uint32_t)__builtin_ctz(pend);
                 pend &= pend - 1;
                 cand[ncand * stride] = pbase + b;
@@ -493,7 +497,7 @@ struct SingleTreeRec : SingleTree<D> {
 };
 
 // MASKS: the three-phase walk; s_stk (dynamic LDS) holds its stack of child
-// masks, hcap levels of one word per lane, then KNN_CAND candidate-leaf
+// masks, hcap levels of one word per lane, then ncap candidate-leaf
 // words per lane; a taller tree (never met: hcap bounds the
 // height of every tree the buffers can hold) leaves its queries unanswered
 // and flags ERR_STACK. stats (nullable, MASKS only): the walk counts are
@@ -502,6 +506,7 @@ template <int D, int K, bool MASKS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((K <= 8 || K == 10) ? 5 : 1))) void k_knn_seed(TreeView tv, const uint32_t* __restrict__ qp,
                                                   const uint64_t* __restrict__ qkeys, uint64_t nq,
                                                   const uint32_t* __restrict__ order, uint32_t hcap,
+                                                  uint32_t sr, uint32_t ncap,
                                                   uint32_t* __restrict__ err, unsigned long long* __restrict__ stats,
                                                   uint32_t* __restrict__ out_ids, uint64_t* __restrict__ out_d2) {
     __shared__ LevelInfo s_lv[MAX_LEVELS];
@@ -527,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((K <= 8 || 
         if (!MASKS) knn_seeded<D, K>(tr, t, q, qkeys[qi], bd, bi);
         else if (t.h <= hcap)
             knn_seeded_masks<D, K>(tr, t, q, qkeys[qi], bd, bi, s_stk + threadIdx.x,
-                                   s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, wc);
+                                   s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, sr, ncap, wc);
         else if (tq == 0) atomicOr(err, ERR_STACK);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -625,7 +630,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D == 2 && 
             WalkCount wc;
             if (tr.h() <= hcap)
                 knn_seeded_masks<D, K>(tr, tv, q, sfc_key_tab<D, CURVE>(q), bd, bi, s_stk + threadIdx.x,
-                                       s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, wc);
+                                       s_stk + (size_t)hcap * blockDim.x + threadIdx.x, blockDim.x, 1u,
+                                       KNN_CAND, wc);
             else atomicOr(err, ERR_STACK);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -1152,18 +1158,19 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
 }  // namespace
 
 void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
-                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err,
-                unsigned long long* stats, uint32_t* ids, uint64_t* d2) {
+                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, const KnnTuning& tune,
+                uint32_t* err, unsigned long long* stats, uint32_t* ids, uint64_t* d2) {
     if (nq == 0) return;
     const bool masks = hcap <= KNN_STACK_MAX;
-    const size_t lds = masks ? (size_t)(hcap + KNN_CAND) * 256 * 4 : 0;
+    const uint32_t sr = tune.seed_leaves / 2, ncap = max(1u, min(tune.cand, KNN_CAND_MAX));
+    const size_t lds = masks ? (size_t)(hcap + ncap) * 256 * 4 : 0;
     const unsigned gl = blocks_for(nq, 256);
     const unsigned gw = blocks_for(nq, KW_WAVES);
 #define PSI_KL(D, K)                                                                                             \
     do {                                                                                                         \
         if (variant == 1) hipLaunchKernelGGL((k_knn_lane<D, K>), dim3(gl), dim3(256), 0, st, t, q, nq, order, ids, d2); \
-        else if (masks) hipLaunchKernelGGL((k_knn_seed<D, K, true>), dim3(gl), dim3(256), lds, st, t, q, qkeys, nq, order, hcap, err, stats, ids, d2); \
-        else hipLaunchKernelGGL((k_knn_seed<D, K, false>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, hcap, err, nullptr, ids, d2); \
+        else if (masks) hipLaunchKernelGGL((k_knn_seed<D, K, true>), dim3(gl), dim3(256), lds, st, t, q, qkeys, nq, order, hcap, sr, ncap, err, stats, ids, d2); \
+        else hipLaunchKernelGGL((k_knn_seed<D, K, false>), dim3(gl), dim3(256), 0, st, t, q, qkeys, nq, order, hcap, sr, ncap, err, nullptr, ids, d2); \
     } while (0)
 #define PSI_KL_ALL(D)                                                                                    \
     switch (k) {                                                                                         \

@@ -527,7 +527,9 @@ psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool b
     // passes instead of all 64 bits in eight.
     int w = 0;
     const uint32_t kb = ix->D == 2 ? 62u : 63u;
-    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order", kb - 24, 3, &ix->qsorter)) !=
+    const uint32_t ob = ix->order_bits;
+    if ((s = sort_pairs(ix, keys, nullptr, 0, n, false, false, &w, "radix_order", kb - ob, (int)(ob / 8),
+                        &ix->qsorter)) !=
         PSI_OK)
         return s;
     *order = ix->qsorter.i[w].as<uint32_t>();
@@ -741,7 +743,7 @@ psi_status psi_knn(psi_index ix, const uint32_t* d_q, uint64_t nq, uint32_t k, u
     for (uint64_t n = ix->L_cap; n > 1; ++hcap) n = (n + ix->B - 1) / ix->B;
     ProfScope ps(ix, "knn", nq * (4ull * ix->D + 12ull * k));
     launch_knn(ix->st, ix->D, ix->view(), d_q, ix->qkeys.as<uint64_t>(), nq, order, k,
-               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, hcap, ix->err.as<uint32_t>(),
+               (ix->flags & PSI_FLAG_KNN_NEAREST_FIRST) ? 1 : 0, hcap, ix->knn_tune, ix->err.as<uint32_t>(),
                ix->qstats_on ? ix->qstats.as<unsigned long long>() : nullptr, d_ids, d_d2);
     return last_launch();
 }
@@ -963,6 +965,25 @@ psi_status psi_graph_destroy(psi_graph g) {
     if (g->e) (void)hipGraphExecDestroy(g->e);
     if (g->g) (void)hipGraphDestroy(g->g);
     delete g;
+    return PSI_OK;
+}
+
+psi_status psi_set_tuning(psi_index ix, const psi_tuning* t) {
+    if (!ix || !t) return PSI_E_ARG;
+    if (t->knn_seed_leaves < 1 || t->knn_seed_leaves > 9 || !(t->knn_seed_leaves & 1) || t->knn_cand < 1 ||
+        t->knn_cand > KNN_CAND_MAX || t->order_bits < 8 || t->order_bits > 32 || t->order_bits % 8)
+        return PSI_E_ARG;
+    ix->knn_tune.seed_leaves = t->knn_seed_leaves;
+    ix->knn_tune.cand = t->knn_cand;
+    ix->order_bits = t->order_bits;
+    return PSI_OK;
+}
+
+psi_status psi_get_tuning(psi_index ix, psi_tuning* t) {
+    if (!ix || !t) return PSI_E_ARG;
+    t->knn_seed_leaves = ix->knn_tune.seed_leaves;
+    t->knn_cand = ix->knn_tune.cand;
+    t->order_bits = ix->order_bits;
     return PSI_OK;
 }
 

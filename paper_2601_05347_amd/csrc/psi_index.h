@@ -242,6 +242,8 @@ struct psi_index_s {
     hipStream_t aux_st = nullptr;  // a second stream the index's queries run on (a server's)
     psi::Prof prof;
     psi::Buf qstats;           // kNN walk counts (psi_query_stats)
+    psi::KnnTuning knn_tune;   // psi_set_tuning
+    uint32_t order_bits = 24;  // top key bits the query order sorts on
     bool qstats_on = false;
 
     uint64_t slot_words() const { return (uint64_t)(D + 1) * C; }

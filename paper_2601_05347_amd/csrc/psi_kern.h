@@ -285,9 +285,17 @@ __device__ __forceinline__ TreeView resolve_tree(const TreeView& tv) {
 // (nullable): queries, box tests, leaves and points scanned are added to
 // stats[0..3] (the seeded walks only).
 constexpr uint32_t KNN_STACK_MAX = 24;
-constexpr uint32_t KNN_CAND = 16;  // candidate leaves a seeded walk collects before scanning them
+constexpr uint32_t KNN_CAND = 16;      // default: candidate leaves a seeded walk collects before scanning them
+constexpr uint32_t KNN_CAND_MAX = 32;
+// Runtime knobs of the lane-per-query seeded search (no effect on results):
+// seed leaves (odd: the query's own leaf and (seed_leaves - 1) / 2 on each
+// side in curve order) and the candidate list's length.
+struct KnnTuning {
+    uint32_t seed_leaves = 3;
+    uint32_t cand = KNN_CAND;
+};
 void launch_knn(hipStream_t st, int dim, const TreeView& t, const uint32_t* q, const uint64_t* qkeys, uint64_t nq,
-                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, uint32_t* err,
+                const uint32_t* order, uint32_t k, int variant, uint32_t hcap, const KnnTuning& tune, uint32_t* err,
                 unsigned long long* stats, uint32_t* ids, uint64_t* d2);
 // Boxes are processed in the order `order` gives (nullptr: input order);
 // results always land at the box's own index.
