@@ -426,6 +426,37 @@ psi_status psi_prof_reset(psi_index ix);
 psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches,
                         uint64_t* h_bytes);
 
+/* --- the SPaC-tree in the paper's own shape (Sec. 4) ---------------------
+ * A binary search tree on (curve key, id) built by Alg. 3's BuildSorted: a
+ * subtree of at most leaf_wrap points is one leaf; an interior node over
+ * sorted entries [a, b) holds entry m = a + (b - a) / 2 as its pivot, its
+ * left child covers [a, m) and its right child [m + 1, b). Boxes are tight
+ * (an interior node's covers its pivot). The paper sets leaf_wrap = 40
+ * (App. C). Batch updates (Alg. 4) leave the tree BuildSorted would make for
+ * the new point set (the points stay sorted; the shape is laid out again),
+ * where the paper's join-based updates only keep it weight-balanced.
+ * Queries, ids and errors behave as for psi_index (ids 0..n-1 at build, new
+ * ids from next_id on insert; kNN k <= 16). Every update waits for its work
+ * (it reads the new size back). */
+typedef struct psi_bst_s* psi_bst;
+psi_status psi_bst_create(uint32_t dim, uint32_t curve, uint32_t leaf_wrap, void* hip_stream, psi_bst* out);
+psi_status psi_bst_destroy(psi_bst t);
+psi_status psi_bst_build(psi_bst t, const uint32_t* d_pts, uint64_t n);
+psi_status psi_bst_batch_insert(psi_bst t, const uint32_t* d_pts, uint64_t m, uint32_t* d_new_ids);
+psi_status psi_bst_batch_delete(psi_bst t, const uint32_t* d_ids, uint64_t m, uint64_t* d_ndeleted);
+psi_status psi_bst_knn(psi_bst t, const uint32_t* d_q, uint64_t nq, uint32_t k, uint32_t* d_ids, uint64_t* d_d2);
+psi_status psi_bst_range_count(psi_bst t, const uint32_t* d_boxes, uint64_t nb, uint64_t* d_counts);
+psi_status psi_bst_range_report(psi_bst t, const uint32_t* d_boxes, uint64_t nb, const uint64_t* d_offsets,
+                                uint32_t* d_ids);
+psi_status psi_bst_sync(psi_bst t);
+/* Points n, heap depth and heap size H = 2^(depth + 1) - 1 (node v has
+ * children 2v + 1 and 2v + 2). */
+psi_status psi_bst_shape(psi_bst t, uint64_t* h_n, uint32_t* h_depth, uint64_t* h_heap);
+/* Device copies: d_nodes H records of 8 words (lo[3], hi[3], count, kind:
+ * 1 leaf, 0 interior; count 0 = absent, with lo = 0xFFFFFFFF, hi = 0), d_ranges H (a, b) pairs, d_ids and
+ * d_pts the n entries in (key, id) order (D words per point). */
+psi_status psi_bst_export(psi_bst t, uint32_t* d_nodes, uint32_t* d_ranges, uint32_t* d_ids, uint32_t* d_pts);
+
 /* --- runtime knobs (for a tuner) ---------------------------------------- */
 
 /* Knobs that change speed, never results. knn_seed_leaves: leaves scanned

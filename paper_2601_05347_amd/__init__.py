@@ -87,6 +87,17 @@ SIGNATURES = {
     "psi_orth_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
     "psi_prof_enable": (_i, [_P, _i]),
     "psi_query_stats": (_i, [_P, _i, _P]),
+    "psi_bst_create": (_i, [_u32, _u32, _u32, _P, _P]),
+    "psi_bst_destroy": (_i, [_P]),
+    "psi_bst_build": (_i, [_P, _P, _u64]),
+    "psi_bst_batch_insert": (_i, [_P, _P, _u64, _P]),
+    "psi_bst_batch_delete": (_i, [_P, _P, _u64, _P]),
+    "psi_bst_knn": (_i, [_P, _P, _u64, _u32, _P, _P]),
+    "psi_bst_range_count": (_i, [_P, _P, _u64, _P]),
+    "psi_bst_range_report": (_i, [_P, _P, _u64, _P, _P]),
+    "psi_bst_sync": (_i, [_P]),
+    "psi_bst_shape": (_i, [_P, _P, _P, _P]),
+    "psi_bst_export": (_i, [_P, _P, _P, _P, _P]),
     "psi_set_tuning": (_i, [_P, _P]),
     "psi_get_tuning": (_i, [_P, _P]),
     "psi_prof_reset": (_i, [_P]),
@@ -751,6 +762,105 @@ class Orth:
 
     def prof_get(self, family: str):
         return psi_orth_prof_get(self._h, family)
+
+
+class Bst:
+    """The SPaC-tree in the paper's own shape (BuildSorted, Sec. 4) on the
+    current ROCm device, bound to one stream."""
+
+    def __init__(self, dim: int, curve: int, leaf_wrap: int = 40, device="cuda", stream=None):
+        torch = _torch()
+        self.dim, self.curve, self.leaf_wrap = dim, curve, leaf_wrap
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().psi_bst_create(dim, curve, leaf_wrap, _stream_ptr(self.stream), C.byref(h)), "psi_bst_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psi_bst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pts(self, pts):
+        return _as_u32(pts, self.device).reshape(-1, self.dim).contiguous()
+
+    def build(self, pts):
+        t = self._pts(pts)
+        _check(lib().psi_bst_build(self._h, _dev_ptr(t), t.shape[0]), "psi_bst_build")
+        return self
+
+    def batch_insert(self, pts):
+        torch = _torch()
+        t = self._pts(pts)
+        ids = torch.empty(max(t.shape[0], 1), dtype=torch.int32, device=self.device)
+        _check(lib().psi_bst_batch_insert(self._h, _dev_ptr(t), t.shape[0], _dev_ptr(ids)), "psi_bst_batch_insert")
+        return ids[:t.shape[0]]
+
+    def batch_delete(self, ids):
+        torch = _torch()
+        t = _as_u32(ids, self.device).reshape(-1)
+        nd = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().psi_bst_batch_delete(self._h, _dev_ptr(t), t.numel(), _dev_ptr(nd)), "psi_bst_batch_delete")
+        return nd
+
+    def knn(self, q, k: int):
+        torch = _torch()
+        t = self._pts(q)
+        nq = t.shape[0]
+        ids = torch.empty((max(nq, 1), k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((max(nq, 1), k), dtype=torch.int64, device=self.device)
+        _check(lib().psi_bst_knn(self._h, _dev_ptr(t), nq, k, _dev_ptr(ids), _dev_ptr(d2)), "psi_bst_knn")
+        return ids[:nq], d2[:nq]
+
+    def range_count(self, boxes):
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = torch.empty(max(b.shape[0], 1), dtype=torch.int64, device=self.device)
+        _check(lib().psi_bst_range_count(self._h, _dev_ptr(b), b.shape[0], _dev_ptr(cnt)), "psi_bst_range_count")
+        return cnt[:b.shape[0]]
+
+    def range_report(self, boxes, counts=None):
+        torch = _torch()
+        b = _as_u32(boxes, self.device).reshape(-1, 2, self.dim).contiguous()
+        cnt = self.range_count(b) if counts is None else counts
+        off = torch.zeros(b.shape[0] + 1, dtype=torch.int64, device=self.device)
+        torch.cumsum(cnt, 0, out=off[1:])
+        total = int(off[-1].item())
+        ids = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
+        _check(lib().psi_bst_range_report(self._h, _dev_ptr(b), b.shape[0], _dev_ptr(off), _dev_ptr(ids)),
+               "psi_bst_range_report")
+        return off, ids[:total]
+
+    def sync(self):
+        _check(lib().psi_bst_sync(self._h), "psi_bst_sync")
+
+    def shape(self):
+        n, d, h = C.c_uint64(), C.c_uint32(), C.c_uint64()
+        _check(lib().psi_bst_shape(self._h, C.byref(n), C.byref(d), C.byref(h)), "psi_bst_shape")
+        return n.value, d.value, h.value
+
+    def export(self) -> dict:
+        """Heap records (lo, hi, count, kind) and ranges, and the sorted ids
+        and points, as numpy arrays."""
+        torch = _torch()
+        n, depth, H = self.shape()
+        nodes = torch.empty(max(H, 1) * 8, dtype=torch.int32, device=self.device)
+        rng = torch.empty(max(H, 1) * 2, dtype=torch.int32, device=self.device)
+        ids = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        pts = torch.empty(max(n, 1) * self.dim, dtype=torch.int32, device=self.device)
+        _check(lib().psi_bst_export(self._h, _dev_ptr(nodes), _dev_ptr(rng), _dev_ptr(ids), _dev_ptr(pts)),
+               "psi_bst_export")
+        nd = to_u32(nodes)[:H * 8].reshape(H, 8)
+        return {"n": n, "depth": depth, "lo": nd[:, 0:3], "hi": nd[:, 3:6], "cnt": nd[:, 6], "kind": nd[:, 7],
+                "range": to_u32(rng)[:H * 2].reshape(H, 2), "ids": to_u32(ids)[:n],
+                "pts": to_u32(pts)[:n * self.dim].reshape(n, self.dim)}
 
 
 class MultiIndex:
