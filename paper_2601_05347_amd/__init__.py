@@ -764,6 +764,31 @@ class Orth:
         return psi_orth_prof_get(self._h, family)
 
 
+def psi_bst_build(h, pts, n: int):
+    _check(lib().psi_bst_build(h, _dev_ptr(pts), n), "psi_bst_build")
+
+
+def psi_bst_batch_insert(h, pts, m: int, new_ids):
+    _check(lib().psi_bst_batch_insert(h, _dev_ptr(pts), m, _dev_ptr(new_ids)), "psi_bst_batch_insert")
+
+
+def psi_bst_batch_delete(h, ids, m: int, ndeleted=None):
+    _check(lib().psi_bst_batch_delete(h, _dev_ptr(ids), m, _dev_ptr(ndeleted)), "psi_bst_batch_delete")
+
+
+def psi_bst_knn(h, q, nq: int, k: int, ids, d2):
+    _check(lib().psi_bst_knn(h, _dev_ptr(q), nq, k, _dev_ptr(ids), _dev_ptr(d2)), "psi_bst_knn")
+
+
+def psi_bst_range_count(h, boxes, nb: int, counts):
+    _check(lib().psi_bst_range_count(h, _dev_ptr(boxes), nb, _dev_ptr(counts)), "psi_bst_range_count")
+
+
+def psi_bst_range_report(h, boxes, nb: int, offsets, ids):
+    _check(lib().psi_bst_range_report(h, _dev_ptr(boxes), nb, _dev_ptr(offsets), _dev_ptr(ids)),
+           "psi_bst_range_report")
+
+
 class Bst:
     """The SPaC-tree in the paper's own shape (BuildSorted, Sec. 4) on the
     current ROCm device, bound to one stream."""
