@@ -304,7 +304,7 @@ psi_status psi_server_poll(psi_server s, uint64_t ticket, int* h_done, double* h
 psi_status psi_server_wait(psi_server s, uint64_t ticket, double* h_done_ms);
 psi_status psi_server_flush(psi_server s);
 
-/* --- graph capture of query steps ----------------------------------------- */
+/* --- graph capture of index steps ----------------------------------------- */
 
 /* Capture the calls (psi_build, psi_batch_insert, psi_batch_delete,
  * psi_knn, psi_range_count, psi_range_report, psi_multi_knn) issued on

@@ -3,10 +3,13 @@
 // query to their boxes and prune a box farther than the current k-th
 // neighbour; leaves are scanned in full because their order is relaxed).
 //
-// Traversals keep no stack. The tree is implicit (node i of a level has
-// children B i .. B i + B - 1), so after finishing a node the next node is
-// found again from the parent: kNN re-scores the siblings and moves to the
-// nearest one not yet visited, range queries walk siblings in index order.
+// The tree is implicit (node i of a level has children B i .. B i + B - 1).
+// The seeded kNN walks (lane per query and wave per query) and the range
+// walk keep a stack of child masks in LDS, one word per level: expanding a
+// node tests all its children at once and remembers the ones still to
+// visit. The nearest-child-first kNN (lane per query) keeps no stack: after
+// finishing a node it re-scores the siblings from the parent and moves to the
+// nearest one not yet visited.
 //
 // Exactness: a subtree is skipped only when its box distance is strictly
 // greater than the k-th distance, so an equal-distance point with a smaller

@@ -21,6 +21,7 @@ struct psi_multi_s {
     Buf keys, k[2], i[2], hist, off, status, ctr, tiles, seg, slots, leaf, pkey, pid, inner, meta, pref, err, qtmp;
     uint32_t epoch = 0;
     void* pinned = nullptr;
+    void* stage = nullptr;  // pinned staging of the build's tables
     TreeView view() const {
         TreeView t{};
         t.inner = inner.as<NodeRec>();
@@ -150,18 +151,37 @@ psi_status multi_build(psi_multi mx, const uint64_t* d_pt_off, const uint32_t* d
     uint32_t* d_seg_end = d_seg_first + num;
     uint32_t* d_leaf_off = d_seg_end + num;
     uint64_t* d_seg_begin = reinterpret_cast<uint64_t*>(mx->seg.as<char>() + (((uint64_t)num * 3 + 1) * 4 + 7) / 8 * 8);
-    // synchronous uploads of the host-built tables (the build waits anyway)
-    if ((s = ok(hipMemcpy(d_tile_seg, tile_seg.data(), tile_seg.size() * 4, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(d_tile_beg, tile_beg.data(), tile_beg.size() * 4, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(d_seg_first, seg_first.data(), num * 4, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(d_seg_end, seg_end.data(), num * 4, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(d_leaf_off, leaf_off.data(), (num + 1) * 4, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(d_seg_begin, po.data(), num * 8, hipMemcpyHostToDevice))) != PSI_OK) return s;
-    if ((s = ok(hipMemcpy(mx->meta.p, mx->meta_h.data(), num * sizeof(IdxMeta), hipMemcpyHostToDevice))) != PSI_OK)
+    // The host-built tables go through one pinned staging block, copied on the
+    // stream without waiting; the block lives until the index is destroyed
+    // (which waits for the stream).
+    struct Piece {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    const Piece pieces[] = {{d_tile_seg, tile_seg.data(), tile_seg.size() * 4},
+                            {d_tile_beg, tile_beg.data(), tile_beg.size() * 4},
+                            {d_seg_first, seg_first.data(), (size_t)num * 4},
+                            {d_seg_end, seg_end.data(), (size_t)num * 4},
+                            {d_leaf_off, leaf_off.data(), (size_t)(num + 1) * 4},
+                            {d_seg_begin, po.data(), (size_t)num * 8},
+                            {mx->meta.p, mx->meta_h.data(), (size_t)num * sizeof(IdxMeta)},
+                            {mx->pref.p, pref.data(), pref.size() * 4}};
+    size_t stage_bytes = 0;
+    for (const Piece& pc : pieces) stage_bytes += (pc.bytes + 255) / 256 * 256;
+    if (mx->stage) (void)hipHostFree(mx->stage);
+    mx->stage = nullptr;
+    if ((s = ok(hipHostMalloc(&mx->stage, std::max<size_t>(stage_bytes, 256), hipHostMallocDefault))) != PSI_OK) {
+        mx->stage = nullptr;
         return s;
-    if (!pref.empty() &&
-        (s = ok(hipMemcpy(mx->pref.p, pref.data(), pref.size() * 4, hipMemcpyHostToDevice))) != PSI_OK)
-        return s;
+    }
+    char* h = static_cast<char*>(mx->stage);
+    for (const Piece& pc : pieces) {
+        if (pc.bytes == 0) continue;
+        std::memcpy(h, pc.src, pc.bytes);
+        if ((s = ok(hipMemcpyAsync(pc.dst, h, pc.bytes, hipMemcpyHostToDevice, st))) != PSI_OK) return s;
+        h += (pc.bytes + 255) / 256 * 256;
+    }
     if (N == 0) return PSI_OK;
 
     SegTiles sg{d_tile_seg, d_tile_beg, d_seg_first, d_seg_end, 8 * RADIX};
@@ -220,6 +240,7 @@ psi_status psi_multi_build(const psi_params* prm, void* hip_stream, uint32_t num
     if (s != PSI_OK) {
         (void)hipStreamSynchronize(mx->st);
         if (mx->pinned) (void)hipHostFree(mx->pinned);
+        if (mx->stage) (void)hipHostFree(mx->stage);
         delete mx;
         return s;
     }
@@ -231,6 +252,7 @@ psi_status psi_multi_destroy(psi_multi mx) {
     if (!mx) return PSI_E_ARG;
     (void)hipStreamSynchronize(mx->st);
     if (mx->pinned) (void)hipHostFree(mx->pinned);
+    if (mx->stage) (void)hipHostFree(mx->stage);
     delete mx;
     return PSI_OK;
 }

@@ -430,9 +430,11 @@ class DeviceServer:
                         r["ticket"] = psi_server_submit(srv, REQ_RANGE_REPORT, n, r["dev"], d_ids=r["out"][1],
                                                         d_out=r["out"][0], ids_cap=cap, ready_event=r["ready"])
                     outstanding.append(r)
-                # completions (each poll also dispatches what is queued)
-                still = deque()
-                for r in outstanding:
+                # completions, oldest first, up to the first ticket still running
+                # (each poll also dispatches what is queued; the completion time is
+                # the server's event time, so a ticket collected late is timed right)
+                while outstanding:
+                    r = outstanding[0]
                     try:
                         done, ms = psi_server_poll(srv, r["ticket"])
                     except PsiError as e:
@@ -440,12 +442,12 @@ class DeviceServer:
                             raise
                         r["rejected"] = True
                         r.pop("out", None)
+                        outstanding.popleft()
                         continue
-                    if done:
-                        self._finish(r, ms)
-                    else:
-                        still.append(r)
-                outstanding = still
+                    if not done:
+                        break
+                    self._finish(r, ms)
+                    outstanding.popleft()
                 if outstanding or i < len(reqs):
                     nxt = reqs[i]["arrival"] if i < len(reqs) and realtime else None
                     if not outstanding and nxt is not None:
