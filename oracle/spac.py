@@ -86,7 +86,9 @@ def flatten(t):
         return s.keys, s.ids, s.pts
     lk, li, lp = flatten(t.left)
     rk, ri, rp = flatten(t.right)
-    return (np.concatenate([lk, [t.key], rk]).astype(np.uint64), np.concatenate([li, [t.id], ri]).astype(np.uint32),
+    # the keys stay 64-bit integers (a Python int beside a uint64 array would
+    # promote the concatenation to floating point and round keys above 2^53)
+    return (np.concatenate([lk, np.array([t.key], np.uint64), rk]), np.concatenate([li, [t.id], ri]).astype(np.uint32),
             np.concatenate([lp, t.pt[None, :], rp]).astype(np.uint32))
 
 
@@ -136,7 +138,7 @@ class SpacTree:
             m = n // 2
             return Node(Leaf(k[:m], i[:m], p[:m]), int(k[m]), int(i[m]), p[m], Leaf(k[m + 1:], i[m + 1:], p[m + 1:]))
         if isinstance(left, Leaf) and isinstance(right, Leaf):  # left < key < right: concatenation in place
-            return Leaf(np.concatenate([left.keys, [key], right.keys]).astype(np.uint64),
+            return Leaf(np.concatenate([left.keys, np.array([key], np.uint64), right.keys]),
                         np.concatenate([left.ids, [id_], right.ids]).astype(np.uint32),
                         np.concatenate([left.pts, pt[None, :], right.pts]).astype(np.uint32), both_leaves_sorted)
         k, i, p = flatten(Node(left, key, id_, pt, right))

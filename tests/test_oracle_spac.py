@@ -150,8 +150,26 @@ def test_updates_keep_invariants(phi, curve, seed):
             model -= gone
         t.check()
         assert set(int(x) for x in t.live()[0]) == model
+        assert t.size() == len(model)
         in_order_matches(t)
     check_boxes(t, 2)
+
+
+@pytest.mark.parametrize("dim,bits", [(2, 30), (3, 21)])
+def test_full_width_keys_survive_updates(dim, bits):
+    # keys above 2^53 (30-bit 2D and 21-bit 3D coordinates) stay exact
+    # through flattening, Node()'s concatenation and deletes of pivots
+    rng = np.random.default_rng(dim)
+    t = spac.SpacTree(dim, oracle.HILBERT, phi=6).build(synth.uniform(300, dim, bits, 5))
+    for step in range(8):
+        if step % 2 == 0:
+            t.batch_insert(synth.uniform(int(rng.integers(1, 200)), dim, bits, 50 + step))
+        else:
+            live = t.live()[0]
+            t.batch_delete(rng.choice(live, len(live) // 2, replace=False))
+        t.check()
+        assert t.size() == len(t.live()[0])
+        in_order_matches(t)
 
 
 def test_expose_path_of_a_large_batch():
