@@ -427,17 +427,30 @@ psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t
                         uint64_t* h_bytes);
 
 /* --- the SPaC-tree in the paper's own shape (Sec. 4) ---------------------
- * A binary search tree on (curve key, id) built by Alg. 3's BuildSorted: a
- * subtree of at most leaf_wrap points is one leaf; an interior node over
- * sorted entries [a, b) holds entry m = a + (b - a) / 2 as its pivot, its
- * left child covers [a, m) and its right child [m + 1, b). Boxes are tight
- * (an interior node's covers its pivot). The paper sets leaf_wrap = 40
- * (App. C). Batch updates (Alg. 4) leave the tree BuildSorted would make for
- * the new point set (the points stay sorted; the shape is laid out again),
- * where the paper's join-based updates only keep it weight-balanced.
- * Queries, ids and errors behave as for psi_index (ids 0..n-1 at build, new
- * ids from next_id on insert; kNN k <= 16). Every update waits for its work
- * (it reads the new size back). */
+ * A binary search tree on (curve key, id): a subtree of at most leaf_wrap
+ * points is one leaf (its entries in no particular order once appended to),
+ * every interior node holds one point, its pivot, and has two children.
+ * Boxes are tight (an interior node's covers its pivot). The paper sets
+ * leaf_wrap = 40 (App. C); 2 <= leaf_wrap <= 64 here.
+ *   - psi_bst_build: Alg. 3's BuildSorted over the points sorted by (key, id):
+ *     a leaf when n <= leaf_wrap, else entry m = n / 2 is the pivot, [0, m)
+ *     the left subtree and [m + 1, n) the right one.
+ *   - psi_bst_batch_insert / psi_bst_batch_delete: Alg. 4's join-based
+ *     recursion over the batch sorted by (key, id): a leaf takes its share
+ *     unsorted while it fits leaf_wrap, is rebuilt by BuildSorted with it
+ *     below 4 leaf_wrap points (App. C), else is exposed and the share goes
+ *     on down; every node on the way joins its updated sides with Join
+ *     (weight balance with alpha = 0.2: the lighter side weighs at least a
+ *     fifth of both, weight = size + 1; single and double rotations; Node()
+ *     turns a subtree of at most 2 leaf_wrap points into one or two leaves),
+ *     or with Join2 when its pivot is deleted.
+ *   - Queries, ids and errors behave as for psi_index (ids 0..n-1 at build,
+ *     new ids from next_id on insert; unknown, dead and repeated ids are
+ *     ignored on delete; kNN k <= 16).
+ *   - Builds and updates wait for their work (they read counts back). An
+ *     update is functional: a pool that runs out mid-way is grown and the
+ *     update run again from the same root. Insert before any build:
+ *     PSI_E_STATE. */
 typedef struct psi_bst_s* psi_bst;
 psi_status psi_bst_create(uint32_t dim, uint32_t curve, uint32_t leaf_wrap, void* hip_stream, psi_bst* out);
 psi_status psi_bst_destroy(psi_bst t);
@@ -449,13 +462,17 @@ psi_status psi_bst_range_count(psi_bst t, const uint32_t* d_boxes, uint64_t nb, 
 psi_status psi_bst_range_report(psi_bst t, const uint32_t* d_boxes, uint64_t nb, const uint64_t* d_offsets,
                                 uint32_t* d_ids);
 psi_status psi_bst_sync(psi_bst t);
-/* Points n, heap depth and heap size H = 2^(depth + 1) - 1 (node v has
- * children 2v + 1 and 2v + 2). */
-psi_status psi_bst_shape(psi_bst t, uint64_t* h_n, uint32_t* h_depth, uint64_t* h_heap);
-/* Device copies: d_nodes H records of 8 words (lo[3], hi[3], count, kind:
- * 1 leaf, 0 interior; count 0 = absent, with lo = 0xFFFFFFFF, hi = 0), d_ranges H (a, b) pairs, d_ids and
- * d_pts the n entries in (key, id) order (D words per point). */
-psi_status psi_bst_export(psi_bst t, uint32_t* d_nodes, uint32_t* d_ranges, uint32_t* d_ids, uint32_t* d_pts);
+/* Points n, the root reference (a node index, or a leaf index with bit 31
+ * set) and the pool slots in use (node_slots interior-node records,
+ * leaf_slots leaf records; freed slots among them are unreachable). */
+psi_status psi_bst_shape(psi_bst t, uint64_t* h_n, uint32_t* h_root, uint64_t* h_node_slots, uint64_t* h_leaf_slots);
+/* Device copies of the pools: d_nodes node_slots records of 16 words (lo[3],
+ * size, hi[3], pivot id, pivot key (2 words, low first), left, right,
+ * pivot point[3], 0), d_leaves leaf_slots records of 8 words (lo[3], count,
+ * hi[3], sorted), d_ids leaf_slots x leaf_wrap ids and d_pts leaf_slots x
+ * leaf_wrap points (D words each); a leaf's entries are the first count of
+ * its slot. Unused coordinate words (2D) are 0. */
+psi_status psi_bst_export(psi_bst t, uint32_t* d_nodes, uint32_t* d_leaves, uint32_t* d_ids, uint32_t* d_pts);
 
 /* --- runtime knobs (for a tuner) ---------------------------------------- */
 

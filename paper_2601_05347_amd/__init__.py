@@ -96,7 +96,7 @@ SIGNATURES = {
     "psi_bst_range_count": (_i, [_P, _P, _u64, _P]),
     "psi_bst_range_report": (_i, [_P, _P, _u64, _P, _P]),
     "psi_bst_sync": (_i, [_P]),
-    "psi_bst_shape": (_i, [_P, _P, _P, _P]),
+    "psi_bst_shape": (_i, [_P, _P, _P, _P, _P]),
     "psi_bst_export": (_i, [_P, _P, _P, _P, _P]),
     "psi_set_tuning": (_i, [_P, _P]),
     "psi_get_tuning": (_i, [_P, _P]),
@@ -764,6 +764,31 @@ class Orth:
         return psi_orth_prof_get(self._h, family)
 
 
+def psi_bst_create(dim: int, curve: int, leaf_wrap: int, stream=None):
+    h = C.c_void_p()
+    _check(lib().psi_bst_create(dim, curve, leaf_wrap, _stream_ptr(stream) if stream is not None else None,
+                                C.byref(h)), "psi_bst_create")
+    return h
+
+
+def psi_bst_destroy(h):
+    _check(lib().psi_bst_destroy(h), "psi_bst_destroy")
+
+
+def psi_bst_sync(h):
+    _check(lib().psi_bst_sync(h), "psi_bst_sync")
+
+
+def psi_bst_shape(h):
+    n, root, ns, ls = C.c_uint64(), C.c_uint32(), C.c_uint64(), C.c_uint64()
+    _check(lib().psi_bst_shape(h, C.byref(n), C.byref(root), C.byref(ns), C.byref(ls)), "psi_bst_shape")
+    return n.value, root.value, ns.value, ls.value
+
+
+def psi_bst_export(h, nodes, leaves, ids, pts):
+    _check(lib().psi_bst_export(h, _dev_ptr(nodes), _dev_ptr(leaves), _dev_ptr(ids), _dev_ptr(pts)), "psi_bst_export")
+
+
 def psi_bst_build(h, pts, n: int):
     _check(lib().psi_bst_build(h, _dev_ptr(pts), n), "psi_bst_build")
 
@@ -867,25 +892,23 @@ class Bst:
         _check(lib().psi_bst_sync(self._h), "psi_bst_sync")
 
     def shape(self):
-        n, d, h = C.c_uint64(), C.c_uint32(), C.c_uint64()
-        _check(lib().psi_bst_shape(self._h, C.byref(n), C.byref(d), C.byref(h)), "psi_bst_shape")
-        return n.value, d.value, h.value
+        """(points, root reference, node slots, leaf slots)."""
+        return psi_bst_shape(self._h)
 
     def export(self) -> dict:
-        """Heap records (lo, hi, count, kind) and ranges, and the sorted ids
-        and points, as numpy arrays."""
+        """The pools as numpy arrays: node records (16 words), leaf records
+        (8 words), each leaf slot's ids and points, and the root."""
         torch = _torch()
-        n, depth, H = self.shape()
-        nodes = torch.empty(max(H, 1) * 8, dtype=torch.int32, device=self.device)
-        rng = torch.empty(max(H, 1) * 2, dtype=torch.int32, device=self.device)
-        ids = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
-        pts = torch.empty(max(n, 1) * self.dim, dtype=torch.int32, device=self.device)
-        _check(lib().psi_bst_export(self._h, _dev_ptr(nodes), _dev_ptr(rng), _dev_ptr(ids), _dev_ptr(pts)),
-               "psi_bst_export")
-        nd = to_u32(nodes)[:H * 8].reshape(H, 8)
-        return {"n": n, "depth": depth, "lo": nd[:, 0:3], "hi": nd[:, 3:6], "cnt": nd[:, 6], "kind": nd[:, 7],
-                "range": to_u32(rng)[:H * 2].reshape(H, 2), "ids": to_u32(ids)[:n],
-                "pts": to_u32(pts)[:n * self.dim].reshape(n, self.dim)}
+        n, root, ns, ls = self.shape()
+        w = self.leaf_wrap
+        nodes = torch.empty(max(ns, 1) * 16, dtype=torch.int32, device=self.device)
+        leaves = torch.empty(max(ls, 1) * 8, dtype=torch.int32, device=self.device)
+        ids = torch.empty(max(ls, 1) * w, dtype=torch.int32, device=self.device)
+        pts = torch.empty(max(ls, 1) * w * self.dim, dtype=torch.int32, device=self.device)
+        psi_bst_export(self._h, nodes, leaves, ids, pts)
+        return {"n": n, "root": root, "nodes": to_u32(nodes)[:ns * 16].reshape(ns, 16),
+                "leaves": to_u32(leaves)[:ls * 8].reshape(ls, 8), "ids": to_u32(ids)[:ls * w].reshape(ls, w),
+                "pts": to_u32(pts)[:ls * w * self.dim].reshape(ls, w, self.dim), "leaf_wrap": w}
 
 
 class MultiIndex:

@@ -1,9 +1,10 @@
-"""The SPaC-tree in the paper's own shape on the GPU (psi_bst_*): the
-structure after a build is bit-equal to the oracle's BuildSorted (Alg. 3)
-tree, node by node in preorder (kind, pivot id or leaf id set, size, box);
-after batch updates it equals BuildSorted over the live set (what the GPU
-path keeps, see include/psi.h); kNN and range answers equal the oracle's
-brute force."""
+"""The SPaC-tree in the paper's own shape on the GPU (psi_bst_*): after a
+build the tree equals the oracle's BuildSorted (Alg. 3) node by node in
+preorder (kind, pivot id or leaf id set, size, box); after every batch
+insertion and deletion it equals the oracle's join-based update (Alg. 4:
+Join's rotations with alpha = 0.2, Node()'s leaf wrap, App. C's 4 phi local
+rebuild, Join2 for deleted pivots) run on the same batches; kNN and range
+answers equal the oracle's brute force."""
 import sys
 
 import numpy as np
@@ -30,27 +31,36 @@ def psi():
     return psi
 
 
-def gpu_preorder(ex, dim):
+LEAF = 0x80000000
+
+
+def gpu_preorder(ex, dim, pts_of=None):
+    """The exported pools walked from the root, in the oracle's preorder
+    format; pts_of (id -> point) checks every stored point on the way."""
     out = []
-    ids = ex["ids"]
-
-    def rec(v):
-        cnt, kind = int(ex["cnt"][v]), int(ex["kind"][v])
-        lo = tuple(int(x) for x in ex["lo"][v][:dim])
-        hi = tuple(int(x) for x in ex["hi"][v][:dim])
-        a, b = (int(x) for x in ex["range"][v])
-        if cnt == 0:
-            out.append((1, (), 0, (0xFFFFFFFF,) * dim, (0,) * dim))
-            return
-        if kind == 1:
-            out.append((1, tuple(sorted(int(i) for i in ids[a:b])), cnt, lo, hi))
-            return
-        m = a + (b - a) // 2
-        out.append((0, int(ids[m]), cnt, lo, hi))
-        rec(2 * v + 1)
-        rec(2 * v + 2)
-
-    rec(0)
+    nodes, leaves, ids, pts = ex["nodes"], ex["leaves"], ex["ids"], ex["pts"]
+    stack = [ex["root"]]
+    while stack:
+        r = stack.pop()
+        if r & LEAF:
+            l = r & ~LEAF
+            c = int(leaves[l][3])
+            if c == 0:
+                out.append((1, (), 0, (0xFFFFFFFF,) * dim, (0,) * dim))
+                continue
+            lid = [int(i) for i in ids[l][:c]]
+            if pts_of is not None:
+                for i, p in zip(lid, pts[l][:c]):
+                    assert tuple(int(x) for x in p) == tuple(int(x) for x in pts_of[i])
+            out.append((1, tuple(sorted(lid)), c, tuple(int(x) for x in leaves[l][0:dim]),
+                        tuple(int(x) for x in leaves[l][4:4 + dim])))
+            continue
+        nd = nodes[r]
+        if pts_of is not None:
+            assert tuple(int(x) for x in nd[12:12 + dim]) == tuple(int(x) for x in pts_of[int(nd[7])])
+        out.append((0, int(nd[7]), int(nd[3]), tuple(int(x) for x in nd[0:dim]), tuple(int(x) for x in nd[4:4 + dim])))
+        stack.append(int(nd[11]))
+        stack.append(int(nd[10]))
     return out
 
 
@@ -75,10 +85,15 @@ def test_build_equals_buildsorted(psi, dim, curve, n, phi):
     assert ex["n"] == n
     ids = np.arange(n, dtype=np.uint32)
     ref = oracle_sorted_tree(pts, ids, dim, curve, phi)
-    assert gpu_preorder(ex, dim) == ref.preorder()
-    keys = oracle.encode(pts, dim, curve) if n else np.zeros(0, np.uint64)
-    np.testing.assert_array_equal(ex["ids"], ids[np.lexsort((ids, keys))])
-    np.testing.assert_array_equal(ex["pts"], pts[ex["ids"]])
+    assert gpu_preorder(ex, dim, pts) == ref.preorder()
+
+
+def test_fig1_shape(psi):
+    # Fig. 1: 15 points with a leaf wrap of 3: four leaves of three, three pivots
+    pts = synth.uniform(15, 2, 10, seed=1)
+    pre = gpu_preorder(psi.Bst(2, oracle.HILBERT, 3).build(pts).export(), 2)
+    assert [k for k, *_ in pre] == [0, 0, 1, 1, 0, 1, 1]
+    assert [s for _, _, s, *_ in pre] == [15, 7, 3, 3, 7, 3, 3]
 
 
 @pytest.mark.parametrize("dim,curve", [(2, 1), (3, 1), (3, 0)])
@@ -99,51 +114,69 @@ def test_queries_match_brute_force(psi, dim, curve):
     off, rid = psi.to_u64(off), psi.to_u32(rid)
     for s in range(0, len(bx), 97):
         got = np.sort(rid[off[s]:off[s + 1]])
-        p = data
-        inside = np.all((p >= bx[s, 0]) & (p <= bx[s, 1]), axis=1)
+        inside = np.all((data >= bx[s, 0]) & (data <= bx[s, 1]), axis=1)
         np.testing.assert_array_equal(got, np.nonzero(inside)[0].astype(np.uint32))
 
 
-@pytest.mark.parametrize("dim,curve,phi", [(2, 1, 40), (3, 0, 8)])
-def test_updates_equal_buildsorted_of_live_set(psi, dim, curve, phi):
-    say(f"bst updates dim={dim} curve={curve} phi={phi}")
-    bits = 30 if dim == 2 else 21
-    rng = np.random.default_rng(dim * 10 + phi)
-    n0 = 20_000
-    allp = [synth.uniform(n0, dim, bits, seed=1)]
-    t = psi.Bst(dim, curve, phi).build(allp[0])
-    live = set(range(n0))
-    for step in range(6):
-        if step % 3 != 2:
-            m = int(rng.choice([1, 777, 9000]))
-            p = synth.uniform(m, dim, bits, seed=100 + step)
-            new = psi.to_u32(t.batch_insert(p))
-            base = sum(len(a) for a in allp)
-            np.testing.assert_array_equal(new, np.arange(base, base + m, dtype=np.uint32))
-            allp.append(p)
-            live |= set(range(base, base + m))
-        else:
-            lv = np.array(sorted(live), np.uint32)
-            dels = rng.choice(lv, len(lv) // 3, replace=False)
-            ask = np.concatenate([dels, dels[:5], [10**9, lv.max() + 1000]]).astype(np.uint32)
-            nd = int(psi.to_u64(t.batch_delete(ask))[0])
-            assert nd == len(dels)
-            live -= set(int(x) for x in dels)
-        pts_all = np.concatenate(allp)
-        ids = np.array(sorted(live), np.uint32)
-        ex = t.export()
-        assert ex["n"] == len(ids)
-        ref = oracle_sorted_tree(pts_all[ids], ids, dim, curve, phi)
-        assert gpu_preorder(ex, dim) == ref.preorder()
-        q = synth.uniform(500, dim, bits, seed=200 + step, purpose=synth.P_QUERY)
-        gid, gd2 = t.knn(q, 10)
-        eid, ed2 = oracle.knn_points(pts_all[ids], q, 10, threads=16)
+def _check_against(psi, t, ref, pts_all, dim, bits, step):
+    ids, pts = ref.live()
+    ex = t.export()
+    assert ex["n"] == len(ids)
+    assert gpu_preorder(ex, dim, pts_all) == ref.preorder()
+    if len(ids):
+        q = synth.uniform(400, dim, bits, seed=300 + step, purpose=synth.P_QUERY)
+        k = min(10, len(ids))
+        gid, gd2 = t.knn(q, k)
+        eid, ed2 = oracle.knn_points(pts, q, k, threads=16)
         np.testing.assert_array_equal(psi.to_u64(gd2), ed2)
         np.testing.assert_array_equal(psi.to_u32(gid), ids[eid])
-    # delete everything, then insert into the empty tree
-    t.batch_delete(np.array(sorted(live), np.uint32))
-    assert t.export()["n"] == 0
-    p = synth.uniform(100, dim, bits, seed=999)
-    t.batch_insert(p)
-    ex = t.export()
-    assert ex["n"] == 100
+        bx = synth.boxes(q[:200], bits, seed=7 + step, side_lo=max(bits - 8, 1), side_hi=bits - 2)
+        np.testing.assert_array_equal(psi.to_u64(t.range_count(bx)), oracle.range_count_points(pts, bx, threads=16))
+
+
+@pytest.mark.parametrize("dim,curve,phi,n0", [(2, 1, 40, 20_000), (3, 0, 8, 6000), (2, 0, 3, 1500),
+                                              (3, 1, 40, 0), (3, 1, 5, 3000)])
+def test_updates_equal_join_based_oracle(psi, dim, curve, phi, n0):
+    """Inserts of 1 .. 12000 points (appends, local rebuilds, exposed leaves,
+    rebuilds of empty leaves) and deletes of live, dead, unknown and repeated
+    ids and of pivots; the GPU tree equals the oracle's after every batch."""
+    say(f"bst updates dim={dim} curve={curve} phi={phi} n0={n0}")
+    bits = 30 if dim == 2 else 21
+    rng = np.random.default_rng(dim * 100 + phi + n0)
+    base = synth.uniform(n0, dim, bits, seed=11)
+    t = psi.Bst(dim, curve, phi).build(base)
+    ref = spac.SpacTree(dim, curve, phi=phi).build(base)
+    pts_all = [base]
+    plan = ["ins", "ins", "del", "ins", "del_piv", "ins", "del", "ins", "del_all", "ins", "ins"]
+    sizes = [1, 777, None, 12_000, None, 3, None, 4 * phi, None, 5000, 2 * phi]
+    for step, (op, m) in enumerate(zip(plan, sizes)):
+        if op == "ins":
+            p = synth.uniform(m, dim, bits, seed=100 + step)
+            new = psi.to_u32(t.batch_insert(p))
+            want = ref.batch_insert(p)
+            np.testing.assert_array_equal(new, want)
+            pts_all.append(p)
+        else:
+            live = ref.live()[0]
+            if op == "del":
+                dels = rng.choice(live, len(live) // 3, replace=False) if len(live) else np.zeros(0, np.uint32)
+            elif op == "del_piv":
+                piv = np.array([v for k, v, *_ in ref.preorder() if k == 0], np.uint32)
+                dels = piv[: max(1, len(piv) // 2)]
+            else:
+                dels = live
+            ask = np.concatenate([dels, dels[:5], [10**9, ref.next_id + 7]]).astype(np.uint32)
+            nd = int(psi.to_u64(t.batch_delete(ask))[0])
+            assert nd == ref.batch_delete(ask)
+        say(f"  step {step} {op}: n = {ref.size()}")
+        _check_against(psi, t, ref, np.concatenate(pts_all), dim, bits, step)
+    t.sync()
+
+
+def test_insert_before_build_is_refused(psi):
+    t = psi.Bst(2, 0, 40)
+    with pytest.raises(psi.PsiError) as e:
+        t.batch_insert(synth.uniform(10, 2, 30, seed=1))
+    assert e.value.code == 6
+    with pytest.raises(psi.PsiError):
+        psi.Bst(2, 0, 65)
