@@ -44,6 +44,8 @@ WORKLOADS = {
     # P-Orth tree (Sec. 3) beside the SPaC-H tree on the 3d-1e8 inputs: build,
     # insert 1e6, delete 1e6, 1e7 10-NN queries, 1e6 range counts and reports
     "orth": dict(dim=3, bits=21, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
+    # the SPaC tree in the paper's shape beside the directory SPaC-H tree (3D)
+    "bst": dict(dim=3, bits=21, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
     # the same in 2D, coordinates in [0, 2^30)^2
     "orth2d": dict(dim=2, bits=30, n=100_000_000, m=1_000_000, nq=10_000_000, k=10, nb=1_000_000),
     # incremental workload: 3D, 1e8 points inserted into an empty index in n/b
@@ -505,6 +507,110 @@ def bench_orth(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_bst(args):
+    """The SPaC tree in the paper's shape (BuildSorted builds, join-based batch
+    updates, leaf wrap 40) beside the SPaC-H directory tree on the same inputs
+    (those of the 3d-1e8 workload): per step, a build of each, a batch insert
+    and a batch delete, then kNN, range count and range report on each. Every
+    phase is timed with HIP events on the stream; the paper-shape tree's
+    calls include their readbacks."""
+    import numpy as np
+    import torch
+
+    import paper_2601_05347_amd as psi
+    import synth
+    cfg = dict(WORKLOADS["3d-1e8"])
+    if args.n:
+        cfg["n"] = args.n
+    dim, bits, n, nq, k, nb, m = (cfg[x] for x in ("dim", "bits", "n", "nq", "k", "nb", "m"))
+    k = min(args.k or k, 16)
+    nq = min(nq, max(1000, n // 10))
+    nb = min(nb, max(1000, n // 100))
+    m = min(m, max(1000, n // 100))
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    data, ins, q = synth.workload(args.dist, dim, bits, args.seed, n=n, n_insert=m, n_query=nq)
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, args.seed)
+    boxes = synth.boxes(q[:nb], bits, args.seed)
+    log(f"bst: inputs generated in {time.perf_counter() - t:.1f} s")
+    d_data = torch.from_numpy(data.view(np.int32)).to(dev)
+    d_ins = torch.from_numpy(ins.view(np.int32)).to(dev)
+    d_dels = torch.from_numpy(dels.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(q.view(np.int32)).to(dev)
+    d_boxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
+    del data, q, ins
+    stream = torch.cuda.current_stream(dev)
+    trees = {"paper_shape": psi.Bst(dim, psi.HILBERT, 40, device=dev, stream=stream),
+             "spac_h": psi.Index(dim, psi.HILBERT, args.leaf, args.fanout, device=dev, stream=stream)}
+    api = {"paper_shape": (psi.psi_bst_build, psi.psi_bst_batch_insert, psi.psi_bst_batch_delete, psi.psi_bst_knn,
+                           psi.psi_bst_range_count, psi.psi_bst_range_report),
+           "spac_h": (psi.psi_build, psi.psi_batch_insert, psi.psi_batch_delete, psi.psi_knn, psi.psi_range_count,
+                      psi.psi_range_report)}
+    new_ids = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    k_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    k_d2 = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    cnt = torch.empty(nb, dtype=torch.int64, device=dev)
+    off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+    rids, res, outs = {}, {}, {}
+    for name, tr in trees.items():
+        build, insert, delete, knn, rcount, rreport = api[name]
+        h = tr._h
+        ms = {p: [] for p in ("build", "insert", "delete", "knn", "range_count", "range_report")}
+        for it in range(args.warmup + args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            log(f"bst: {name} step {it}")
+            ev[0].record(stream)
+            build(h, d_data, n)
+            ev[1].record(stream)
+            insert(h, d_ins, m, new_ids)
+            ev[2].record(stream)
+            delete(h, d_dels, m, nd)
+            ev[3].record(stream)
+            knn(h, d_q, nq, k, k_ids, k_d2)
+            ev[4].record(stream)
+            rcount(h, d_boxes, nb, cnt)
+            ev[5].record(stream)
+            if name not in rids:
+                torch.cumsum(cnt, 0, out=off[1:])
+                rids[name] = torch.empty(max(int(off[-1].item()), 1), dtype=torch.int32, device=dev)
+                ev[5].record(stream)
+            rreport(h, d_boxes, nb, off, rids[name])
+            ev[6].record(stream)
+            ev[6].synchronize()
+            if it >= args.warmup:
+                for j, p in enumerate(ms):
+                    ms[p].append(ev[j].elapsed_time(ev[j + 1]))
+        tr.sync()
+        outs[name] = (k_ids.clone(), k_d2.clone(), cnt.clone())
+        med = {p: round(float(np.median(v)), 3) for p, v in ms.items()}
+        res[name] = {"ms": med, "build_mpts_s": round(n / med["build"] / 1e3, 1),
+                     "insert_mpts_s": round(m / med["insert"] / 1e3, 1),
+                     "delete_mpts_s": round(m / med["delete"] / 1e3, 1),
+                     "knn_mq_s": round(nq / med["knn"] / 1e3, 1),
+                     "range_count_mbox_s": round(nb / med["range_count"] / 1e3, 2),
+                     "range_report_mbox_s": round(nb / med["range_report"] / 1e3, 2)}
+        if name == "paper_shape":
+            pn, root, ns, ls = tr.shape()
+            res[name]["shape"] = {"points": pn, "node_slots": ns, "leaf_slots": ls}
+        log(f"{name}: {res[name]}")
+    a, b = outs["paper_shape"], outs["spac_h"]
+    identical = all(bool(torch.equal(x, y)) for x, y in zip(a, b))
+    ps, sp = res["paper_shape"], res["spac_h"]
+    out = {"metric": "paper-shape SPaC-H build Mpoints/s (3D); join-based updates, kNN and range beside the "
+                     "directory SPaC-H", "value": ps["build_mpts_s"],
+           "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(sum(ps["ms"].values()), 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+           "config": {"workload": f"bst: {dim}D {args.dist} paper shape (leaf wrap 40) vs directory SPaC-H",
+                      "n": n, "insert": m, "delete": m, "queries": nq, "k": k, "boxes": nb,
+                      "leaf_size": args.leaf},
+           "paper_shape": ps, "spac_h": sp,
+           "spac_h_over_paper_shape": {p: round(ps["ms"][p] / sp["ms"][p], 3) for p in ps["ms"]},
+           "knn_and_counts_identical": identical}
+    print(json.dumps(out), flush=True)
+
+
 def bench_multi(args):
     """Batched small indexes: one segmented build + one persistent kNN launch
     vs per-index builds and launches (and those launches replayed as a graph)."""
@@ -611,6 +717,8 @@ def main():
         return bench_incr(args)
     if args.workload in ("orth", "orth2d"):
         return bench_orth(args)
+    if args.workload == "bst":
+        return bench_bst(args)
     import numpy as np
     import torch
 

@@ -1402,7 +1402,7 @@ psi_status jb_update(psi_bst t, bool del, const uint64_t* bk, const uint32_t* bi
                     PSI_OK)
                 return s;
             h[C_TASKS] = 0;
-            if ((s = jb_set_counters(t, h)) != PSI_OK) return s;
+            launch_fill_u32(st, t->ctr.as<uint32_t>() + C_TASKS, 1, 0u);
             const Pools P = jb_pools(t, bk, bi, bp, m);
             const unsigned g = blocks_of(nt, 64);
             const uint32_t tcap = 2 * nt;
