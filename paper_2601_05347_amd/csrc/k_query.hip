@@ -977,6 +977,7 @@ __global__ __launch_bounds__(256) void k_range(TreeView tv, const uint32_t* __re
 // entry per lane; whole subtrees inside the box add their counts, or, for
 // reports, have their leaves' ids copied two leaves at a time.
 constexpr int RW_WAVES = 4;
+constexpr int RW_PAIRS = 4;  // straddling leaf pairs whose first rows are loaded together
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
     const uint32_t lane = lane_id();
@@ -1051,9 +1052,10 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
     }
     const uint32_t C = t.C, B = t.B, h = t.h;
 
-    // Visit nc children starting at c0 on level l (lane c owns child c0 + c).
-    auto visit = [&](uint32_t l, uint64_t c0, uint32_t nc) {
-        const bool on = lane < nc;
+    // Visit nc children starting at c0 on level l (lane c owns child c0 + c);
+    // lane c takes part when bit c / B of pm is set (its parent is expanded).
+    auto visit = [&](uint32_t l, uint64_t c0, uint32_t nc, uint64_t pm) {
+        const bool on = lane < nc && ((pm >> (lane / B)) & 1ull);
         NodeRec r = {};
         int rel = 0;
         if (on) {
@@ -1098,47 +1100,81 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
             if (REPORT) o += tot;
             else cnt += tot;
         }
-        // straddling leaves two at a time, one per half-wave (entry e of a
-        // leaf on lane e mod 32 of its half)
+        // straddling leaves: up to RW_PAIRS pairs at a time, a leaf per
+        // half-wave (entry e of a leaf on lane e mod 32 of its half); the
+        // first 32 entries of every leaf of the batch are loaded together,
+        // the rest (leaves grown past 32 by inserts) leaf pair by pair
         uint64_t m = partial;
         const uint32_t hl = lane & 31u;
         while (m) {
-            const uint32_t ca = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1;
-            uint32_t cb = 64u;  // no second leaf
-            if (m) {
-                cb = (uint32_t)__builtin_ctzll(m);
-                m &= m - 1;
-            }
-            const uint32_t mine = lane < 32u ? ca : cb;
-            const uint32_t sc = shfl_u32(r.cnt, (int)(mine & 63u)), ss = shfl_u32(r.slot, (int)(mine & 63u));
-            const uint32_t rc = mine < 64u ? sc : 0u;
-            const uint32_t rs = mine < 64u ? ss : 0u;
-            const uint32_t rmax = max((uint32_t)__builtin_amdgcn_readlane((int)rc, 0),
-                                      (uint32_t)__builtin_amdgcn_readlane((int)rc, 32));
-            const uint32_t* s = t.slots + (uint64_t)rs * (D + 1) * C;
-            for (uint32_t e0 = 0; e0 < rmax; e0 += 32) {
-                const uint32_t e = e0 + hl;
-                bool in = false;
-                if (e < rc) {
-                    uint32_t p[D];
+            uint32_t rc[RW_PAIRS], rs[RW_PAIRS];
 #pragma unroll
-                    for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
-                    in = in_box<D>(p, lo, hi);
+            for (int q = 0; q < RW_PAIRS; ++q) {
+                uint32_t ca = 64u, cb = 64u;  // 64: no leaf
+                if (m) {
+                    ca = (uint32_t)__builtin_ctzll(m);
+                    m &= m - 1;
                 }
+                if (m) {
+                    cb = (uint32_t)__builtin_ctzll(m);
+                    m &= m - 1;
+                }
+                const uint32_t mine = lane < 32u ? ca : cb;
+                const uint32_t sc = shfl_u32(r.cnt, (int)(mine & 63u)), ss = shfl_u32(r.slot, (int)(mine & 63u));
+                rc[q] = mine < 64u ? sc : 0u;
+                rs[q] = mine < 64u ? ss : 0u;
+            }
+            uint32_t pc[RW_PAIRS][D];
+#pragma unroll
+            for (int q = 0; q < RW_PAIRS; ++q) {
+                const uint32_t* s = t.slots + (uint64_t)rs[q] * (D + 1) * C;
+                const bool on = hl < rc[q];
+#pragma unroll
+                for (int d = 0; d < D; ++d) pc[q][d] = on ? s[d * C + hl] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < RW_PAIRS; ++q) {
+                const bool in = hl < rc[q] && in_box<D>(pc[q], lo, hi);
                 const uint64_t hit = ballot(in);
                 if (REPORT && in) {
                     const uint64_t dst = o + count_below(hit);
-                    if (dst < lim) out[dst] = s[D * C + e];
+                    if (dst < lim) out[dst] = t.slots[(uint64_t)rs[q] * (D + 1) * C + D * C + hl];
                 }
                 if (REPORT) o += (uint32_t)__popcll(hit);
                 else cnt += (uint32_t)__popcll(hit);
+            }
+#pragma unroll
+            for (int q = 0; q < RW_PAIRS; ++q) {
+                const uint32_t rmax = max((uint32_t)__builtin_amdgcn_readlane((int)rc[q], 0),
+                                          (uint32_t)__builtin_amdgcn_readlane((int)rc[q], 32));
+                const uint32_t* s = t.slots + (uint64_t)rs[q] * (D + 1) * C;
+                for (uint32_t e0 = 32; e0 < rmax; e0 += 32) {
+                    const uint32_t e = e0 + hl;
+                    bool in = false;
+                    if (e < rc[q]) {
+                        uint32_t p[D];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) p[d] = s[d * C + e];
+                        in = in_box<D>(p, lo, hi);
+                    }
+                    const uint64_t hit = ballot(in);
+                    if (REPORT && in) {
+                        const uint64_t dst = o + count_below(hit);
+                        if (dst < lim) out[dst] = s[D * C + e];
+                    }
+                    if (REPORT) o += (uint32_t)__popcll(hit);
+                    else cnt += (uint32_t)__popcll(hit);
+                }
             }
         }
     };
 
     if (!empty && t.L > 0) {
-        visit(0, 0, 1);
+        visit(0, 0, 1, 1ull);
+        // the straddling nodes of one group of G = 64 / B siblings are
+        // expanded together: their children fill one wave of lanes
+        const uint32_t G = 64u / B;
+        const uint64_t gsel = G >= 64u ? ~0ull : (1ull << G) - 1;
         int d = 0;
         while (h > 0 && d >= 0) {
             const uint64_t m = s_mask[w][d];
@@ -1147,11 +1183,12 @@ __global__ __launch_bounds__(256) void k_range_wave(TreeView tv, const uint32_t*
                 continue;
             }
             const uint32_t bit = (uint32_t)__builtin_ctzll(m);
-            s_mask[w][d] = m & (m - 1);
-            const uint64_t node = s_base[w][d] + bit;
-            const uint64_t c0 = node * B;
-            const uint32_t nc = (uint32_t)min<uint64_t>(B, s_lv[d + 1].n - c0);
-            visit((uint32_t)d + 1, c0, nc);
+            const uint32_t g0 = bit - bit % G;
+            const uint64_t gm = (m >> g0) & gsel;
+            s_mask[w][d] = m & ~(gm << g0);
+            const uint64_t c0 = (s_base[w][d] + g0) * B;
+            const uint32_t nc = (uint32_t)min<uint64_t>((uint64_t)G * B, s_lv[d + 1].n - c0);
+            visit((uint32_t)d + 1, c0, nc, gm);
             if ((uint32_t)d + 1 < h) ++d;
         }
     }
