@@ -330,7 +330,7 @@ psi_status ensure_dirs(psi_index ix, uint64_t leaves);
 // The directory buffers as kernel arguments take them.
 psi::Dirs dirs_of(psi_index ix);
 // Processing order of a query batch (curve keys of the points or box centres
-// in scr.c, input order; *order null or the positions sorted by key); latches
+// in qkeys, input order; *order null or the positions sorted by key); latches
 // ERR_RANGE for out-of-range query points.
 psi_status query_order(psi_index ix, const uint32_t* d_items, uint64_t n, bool boxes, const uint32_t** order);
 

@@ -329,7 +329,7 @@ psi_status psi_orth_knn(psi_orth o, const uint32_t* d_q, uint64_t nq, uint32_t k
     psi_status s = query_order(ix, d_q, nq, false, &order);
     if (s != PSI_OK) return s;
     ProfScope ps(ix, "orth_knn", nq * (4ull * ix->D + 12ull * k));
-    launch_orth_knn(ix->st, ix->D, o->view(), d_q, ix->scr.c.as<uint64_t>(), nq, order, k, d_ids, d_d2);
+    launch_orth_knn(ix->st, ix->D, o->view(), d_q, ix->qkeys.as<uint64_t>(), nq, order, k, d_ids, d_d2);
     return last_launch();
 }
 
