@@ -22,7 +22,10 @@
  *     grids by upper bounds (an update's worst case for its batch size), which
  *     it tightens from a copy of the device state taken after each update
  *     without waiting for it. A call may still wait when more than 64 updates
- *     are queued, or when a replayed graph left the sizes unknown. Growing a
+ *     are queued, when two or more queued updates could together have grown
+ *     the tree past 1.5 times its last known size (their worst cases add up;
+ *     the oldest is waited for), or when a replayed graph left the sizes
+ *     unknown. Growing a
  *     buffer never waits either (the replaced block is freed once the stream
  *     is idle). The inspection calls (psi_sync, psi_size, psi_next_id,
  *     psi_shape, the exports) wait for the stream.

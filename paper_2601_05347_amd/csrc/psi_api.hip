@@ -75,7 +75,9 @@ void poll(psi_index ix) {
         ix->ev_pool.push_back(f.ev);
         ix->inflight.pop_front();
     }
-    if (!ix->grave.empty() && ix->inflight.empty() && hipStreamQuery(ix->st) == hipSuccess &&
+    // replaced blocks are freed in bunches (a free of device memory is a
+    // synchronous call): when eight have gathered and the streams are idle
+    if (ix->grave.size() >= 8 && ix->inflight.empty() && hipStreamQuery(ix->st) == hipSuccess &&
         (!ix->aux_st || hipStreamQuery(ix->aux_st) == hipSuccess)) {
         for (void* p : ix->grave) (void)hipFree(p);
         ix->grave.clear();
@@ -105,11 +107,24 @@ psi_status bounds(psi_index ix, Bounds* out) {
         if (s != PSI_OK) return s;
     }
     poll(ix);
-    Bounds b = ix->base;
-    for (const Inflight& f : ix->inflight)
-        if (!f.stale) add(b, f.delta);
-    *out = b;
-    return PSI_OK;
+    for (;;) {
+        Bounds b = ix->base;
+        for (const Inflight& f : ix->inflight)
+            if (!f.stale) add(b, f.delta);
+        // Worst cases add up when large updates are queued back to back, and
+        // grids, scans and buffers follow the bound: with two or more updates
+        // queued and the bound past 1.5 times the last known size, the oldest
+        // is waited for (the device still has the others to run).
+        const bool loose = b.L > ix->base.L + ix->base.L / 2 + (1u << 16) ||
+                           b.slot_top > ix->base.slot_top + ix->base.slot_top / 2 + (1u << 16);
+        if (!loose || ix->inflight.size() < 2 || capturing(ix->st)) {
+            *out = b;
+            return PSI_OK;
+        }
+        psi_status s = hip_ok(hipEventSynchronize(ix->inflight.front().ev));
+        if (s != PSI_OK) return s;
+        poll(ix);
+    }
 }
 
 psi_status track_update(psi_index ix, const Bounds& delta) {

@@ -63,13 +63,15 @@ struct Buf {
         return PSI_OK;
     }
     // Stream-ordered variants for the index's hot paths: the new block is
-    // allocated at once, the old one (its contents copied on `st` first by
-    // grow_keep_q) goes to `grave` and is freed once the stream is idle, so
-    // neither call waits for queued work. need <= bytes does nothing.
+    // allocated at once (twice the size asked for, so that a stream of
+    // growing updates reallocates rarely), the old one (its contents copied
+    // on `st` first by grow_keep_q) goes to `grave` and is freed once the
+    // stream is idle, so neither call waits for queued work. need <= bytes
+    // does nothing.
     psi_status ensure_q(size_t need, std::vector<void*>& grave) {
         if (need <= bytes) return PSI_OK;
         void* q = nullptr;
-        size_t want = need + need / 4 + 256;
+        size_t want = 2 * need + 256;
         if (hipMalloc(&q, want) != hipSuccess) {
             (void)hipGetLastError();
             want = need;
@@ -86,7 +88,7 @@ struct Buf {
     psi_status grow_keep_q(size_t need, hipStream_t st, std::vector<void*>& grave) {
         if (need <= bytes) return PSI_OK;
         void* q = nullptr;
-        size_t want = need + need / 2 + 256;
+        size_t want = 2 * need + 256;
         if (hipMalloc(&q, want) != hipSuccess) {
             (void)hipGetLastError();
             want = need;
