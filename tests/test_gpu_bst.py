@@ -180,3 +180,80 @@ def test_insert_before_build_is_refused(psi):
     assert e.value.code == 6
     with pytest.raises(psi.PsiError):
         psi.Bst(2, 0, 65)
+
+
+def test_large_tree_invariants_and_answers(psi):
+    """2e6 points, an insert and a delete of 2e5: the exported tree keeps the
+    paper's invariants (in-order (key, id) sequence equal to the live set
+    sorted, weight balance with alpha = 0.2, leaves of at most 40 points and
+    interior nodes of more, sizes and tight boxes), and its kNN and range
+    answers equal the directory tree's on the same points (itself checked
+    against the oracle)."""
+    import torch
+    say("bst large tree")
+    dim, curve, phi, bits = 3, 1, 40, 21
+    n, m = 2_000_000, 200_000
+    pts = synth.uniform(n, dim, bits, seed=41)
+    ins = synth.uniform(m, dim, bits, seed=42)
+    dels = synth.delete_ids(np.arange(n + m, dtype=np.uint32), m, seed=43)
+    t = psi.Bst(dim, curve, phi).build(pts)
+    t.batch_insert(ins)
+    t.batch_delete(dels)
+    ix = psi.Index(dim, curve, 32, 8).build(pts)
+    ix.batch_insert(ins)
+    ix.batch_delete(dels)
+    allp = np.concatenate([pts, ins])
+    keys = oracle.encode(allp, dim, curve)
+    live = np.setdiff1d(np.arange(n + m, dtype=np.uint32), dels)
+    ex = t.export()
+    assert ex["n"] == len(live)
+    nodes, leaves, lids, lpts = ex["nodes"], ex["leaves"], ex["ids"], ex["pts"]
+    seq = []
+
+    def walk(r):  # returns (size, lo, hi) and appends the in-order ids
+        stack, out = [(r, 0)], {}
+        while stack:
+            x, state = stack.pop()
+            if x & LEAF:
+                l = x & ~LEAF
+                c = int(leaves[l][3])
+                assert c <= phi
+                ids_l = lids[l][:c].astype(np.int64)
+                seq.extend(sorted(ids_l.tolist(), key=lambda i: (int(keys[i]), i)))
+                p = lpts[l][:c]
+                if c:
+                    np.testing.assert_array_equal(p.min(0), leaves[l][0:dim])
+                    np.testing.assert_array_equal(p.max(0), leaves[l][4:4 + dim])
+                out[x] = (c, p.min(0) if c else None, p.max(0) if c else None)
+                continue
+            nd = nodes[x]
+            lc, rc = int(nd[10]), int(nd[11])
+            if state == 0:
+                stack.append((x, 1))
+                stack.append((lc, 0))
+            elif state == 1:
+                seq.append(int(nd[7]))
+                stack.append((x, 2))
+                stack.append((rc, 0))
+            else:
+                (sl, llo, lhi), (sr, rlo, rhi) = out[lc], out[rc]
+                size = sl + 1 + sr
+                assert int(nd[3]) == size and size > phi
+                assert (sl + sr + 2) <= 5 * min(sl + 1, sr + 1)  # weight balance, alpha = 1/5
+                pp = nd[12:12 + dim].astype(np.int64)
+                lo = np.minimum.reduce([a for a in (llo, rlo, pp) if a is not None])
+                hi = np.maximum.reduce([a for a in (lhi, rhi, pp) if a is not None])
+                np.testing.assert_array_equal(lo, nd[0:dim])
+                np.testing.assert_array_equal(hi, nd[4:4 + dim])
+                out[x] = (size, lo, hi)
+    walk(ex["root"])
+    order = live[np.lexsort((live, keys[live]))]
+    np.testing.assert_array_equal(np.array(seq, np.uint32), order)
+    q = synth.uniform(20_000, dim, bits, seed=44, purpose=synth.P_QUERY)
+    a_ids, a_d2 = t.knn(q, 10)
+    b_ids, b_d2 = ix.knn(q, 10)
+    assert bool(torch.equal(a_d2, b_d2)) and bool(torch.equal(a_ids, b_ids))
+    bx = synth.boxes(q[:5000], bits, seed=45)
+    assert bool(torch.equal(t.range_count(bx), ix.range_count(bx)))
+    t.sync()
+    ix.sync()
