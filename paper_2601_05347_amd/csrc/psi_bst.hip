@@ -51,7 +51,7 @@ constexpr uint32_t JB_NIL = 0xFFFFFFFFu;
 constexpr uint32_t JB_IN = 0x40000000u;    // range walk: a subtree inside the box
 constexpr uint32_t JB_PHI_MAX = 64;        // leaf wrap limit (sizes of the per-thread arrays)
 constexpr int JB_STACK = 96;               // spine stacks of Join and the largest-entry split
-constexpr int JB_QSTACK = 96;              // query stacks (a weight-balanced tree of 2^31 points is shallower)
+constexpr int JB_QSTACK = 64;              // query stacks: one entry per level at most (deeper trees flag ERR_STACK)
 constexpr int JB_QT = 64;                  // query threads per block
 
 struct JNode {
@@ -1069,36 +1069,48 @@ __global__ __launch_bounds__(JB_QT) void k_jb_knn(JView t, const uint32_t* __res
         const uint64_t dd = pt_dist<D>(q, p);
         if (pair_less(dd, id, bd[K - 1], bi[K - 1])) topk_insert<K>(bd, bi, dd, id);
     };
+    // depth first: the nearer child next, the farther one on the stack (its
+    // box distance tested again when it is taken off)
     uint32_t* stk = &s_stk[0][threadIdx.x];
     int sp = 0;
-    if (t.root != JB_NIL) stk[(sp++) * JB_QT] = t.root;
-    for (uint32_t guard = 0; sp > 0; ++guard) {
+    uint32_t v = t.root;
+    uint64_t dv = v != JB_NIL ? jv_dist<D>(t, q, v) : PAD_D2;
+    for (uint32_t guard = 0;; ++guard) {
         if (guard >= (1u << 26)) {  // more steps than any tree of 2^31 points takes
             atomicOr(err, ERR_STACK);
             break;
         }
-        const uint32_t v = stk[(--sp) * JB_QT];
-        if (jv_dist<D>(t, q, v) > bd[K - 1]) continue;
-        if (v & JB_LEAF) {
-            const uint32_t l = v & ~JB_LEAF;
-            if (l >= t.lcap) continue;
-            const uint32_t c = min(t.leaf[l].cnt, t.phi);
-            const uint64_t base = (uint64_t)l * t.phi;
-            for (uint32_t e = 0; e < c; ++e) take(t.lpt + (base + e) * D, t.lid[base + e]);
-            continue;
+        bool next = false;
+        if (v != JB_NIL && dv <= bd[K - 1]) {
+            if (v & JB_LEAF) {
+                const uint32_t l = v & ~JB_LEAF;
+                if (l < t.lcap) {
+                    const uint32_t c = min(t.leaf[l].cnt, t.phi);
+                    const uint64_t base = (uint64_t)l * t.phi;
+                    for (uint32_t e = 0; e < c; ++e) take(t.lpt + (base + e) * D, t.lid[base + e]);
+                }
+            } else if (v < t.ncap) {
+                const JNode N = t.node[v];
+                take(N.ppt, N.pid);
+                const uint64_t d0 = jv_dist<D>(t, q, N.left), d1 = jv_dist<D>(t, q, N.right);
+                const uint32_t fa = d0 <= d1 ? N.right : N.left, ne = d0 <= d1 ? N.left : N.right;
+                const uint64_t dfa = d0 <= d1 ? d1 : d0, dne = d0 <= d1 ? d0 : d1;
+                if (dfa <= bd[K - 1]) {
+                    if (sp >= JB_QSTACK) {
+                        atomicOr(err, ERR_STACK);
+                        break;
+                    }
+                    stk[(sp++) * JB_QT] = fa;
+                }
+                v = ne;
+                dv = dne;
+                next = true;
+            }
         }
-        if (v >= t.ncap) continue;
-        const JNode N = t.node[v];
-        take(N.ppt, N.pid);
-        const uint64_t d0 = jv_dist<D>(t, q, N.left), d1 = jv_dist<D>(t, q, N.right);
-        const uint32_t fa = d0 <= d1 ? N.right : N.left, ne = d0 <= d1 ? N.left : N.right;
-        const uint64_t dfa = d0 <= d1 ? d1 : d0, dne = d0 <= d1 ? d0 : d1;
-        if (sp + 2 > JB_QSTACK) {
-            atomicOr(err, ERR_STACK);
-            break;
-        }
-        if (dfa <= bd[K - 1]) stk[(sp++) * JB_QT] = fa;
-        if (dne <= bd[K - 1]) stk[(sp++) * JB_QT] = ne;
+        if (next) continue;
+        if (sp == 0) break;
+        v = stk[(--sp) * JB_QT];
+        dv = jv_dist<D>(t, q, v);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
