@@ -93,7 +93,8 @@ def parse():
 # (its own file and the device helpers it includes).
 FAMILY_SOURCES = {
     "radix_first": ["k_sort.hip"], "radix_pass": ["k_sort.hip"], "encode_hist": ["k_sort.hip"],
-    "local_sort": ["k_bucket.hip"], "local_sort_wide": ["k_bucket.hip"], "bucket_starts": ["k_bucket.hip"],
+    "local_sort": ["k_bucket.hip"], "local_sort_wide": ["k_bucket.hip"], "local_sort_huge": ["k_bucket.hip"],
+    "bucket_starts": ["k_bucket.hip"],
     "radix_big": ["k_bucket.hip"], "leaf_fill": ["k_build.hip"], "nodes": ["k_build.hip"],
     "knn": ["k_query.hip"], "range_count": ["k_query.hip"], "range_report": ["k_query.hip"],
 }
@@ -485,7 +486,7 @@ def bench_orth(args):
             knn(h, d_q, nq, k, k_ids, k_d2)
             fam = {}
             for f in ("encode_hist", "radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide",
-                      "orth_marks", "orth_nodes", "orth_boxes", "orth_merge", "orth_knn", "order", "radix_order"):
+                      "local_sort_huge", "radix_big", "orth_marks", "orth_nodes", "orth_boxes", "orth_merge", "orth_knn", "order", "radix_order"):
                 fms, nl_, _ = tr.prof_get(f)
                 if nl_:
                     fam[f] = round(fms, 3)
@@ -828,13 +829,14 @@ def main():
     value = upd_pts / (upd_ms / 1e3) / 1e6 if upd_ms > 0 else 0.0
 
     # dominant kernel family and its roofline
-    fams = ["radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide", "radix_big", "encode_hist",
+    fams = ["radix_first", "radix_pass", "bucket_starts", "local_sort", "local_sort_wide", "local_sort_huge", "radix_big",
+            "encode_hist",
             "leaf_fill", "nodes", "hist",
             "radix_update", "radix_order", "order", "knn", "range_count", "range_report", "update"]
     prof = {f: ix.prof_get(f) for f in fams}
     # the dominant streaming kernel of the build & update path
     mem_fams = [f for f in ("radix_first", "radix_pass", "local_sort", "radix_big", "encode_hist", "leaf_fill", "nodes")
-                if prof[f][1] > 0]
+                if prof[f][1] > 0 and prof[f][2] > 0]
     dom = max(mem_fams, key=lambda f: prof[f][0]) if mem_fams else None
     roof = None
     if dom:

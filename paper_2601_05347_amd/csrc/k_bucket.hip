@@ -6,8 +6,9 @@
 // global LSD passes order the pairs by their top 16 key bits (65536
 // buckets), then every bucket of at most BUCKET_MAX pairs is sorted entirely
 // inside one workgroup's LDS, in place: one counting pass into 256
-// sub-buckets, then one thread sorts each sub-bucket in registers. Larger
-// buckets (clustered data) are sorted by six segmented global passes
+// sub-buckets, then one thread sorts each sub-bucket in registers. Buckets
+// of up to BUCKET_HUGE pairs take a 1024-thread variant of the same scheme;
+// larger ones (clustered data) are sorted by six segmented global passes
 // instead. Traffic for uniform data: two global passes plus one read and one
 // write of every pair, instead of eight global passes.
 #include "psi_kern.h"
@@ -304,6 +305,136 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
     }
 }
 
+// Buckets of BUCKET_MAX + 1 .. BUCKET_HUGE pairs (clustered data, or about
+// 7600 pairs per bucket at 5e8 points): the light variant's scheme with four
+// times the threads, one sub-bucket per thread (the 10 key bits below the
+// highest bit in which the bucket's keys differ) and the bucket staged in
+// 96 KB of LDS. One workgroup per CU: workgroup g owns buckets g, g + grid,
+// g + 2 grid, ... (at most HUGE_THREADS of them), finds those in range with
+// one load per thread, then sorts them one after the other. A bucket with a
+// sub-bucket of more than RUN_WAVE pairs is left as it is, flagged, for the
+// segmented passes.
+constexpr int HUGE_THREADS = 1024;
+constexpr int HUGE_WAVES = HUGE_THREADS / 64;
+constexpr uint32_t HUGE_SUB = HUGE_THREADS;  // sub-buckets
+static_assert(BUCKET_HUGE % HUGE_THREADS == 0, "items per thread");
+
+__global__ __launch_bounds__(HUGE_THREADS) void k_local_sort_huge(uint64_t* __restrict__ keys,
+                                                                  uint32_t* __restrict__ ids,
+                                                                  const uint32_t* __restrict__ bstart,
+                                                                  uint32_t nb, uint32_t* __restrict__ big) {
+    constexpr int IPT = BUCKET_HUGE / HUGE_THREADS;
+    __shared__ uint64_t s_k[BUCKET_HUGE];
+    __shared__ uint32_t s_i[BUCKET_HUGE];
+    __shared__ uint32_t s_cnt[HUGE_SUB];
+    __shared__ uint32_t s_off[HUGE_SUB];
+    __shared__ uint32_t s_wsum[HUGE_WAVES];
+    __shared__ uint32_t s_wmax[HUGE_WAVES];
+    __shared__ uint64_t s_red[2 * HUGE_WAVES];
+    __shared__ uint32_t s_list[HUGE_THREADS];
+    __shared__ uint32_t s_nl;
+    const int w = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    if (threadIdx.x == 0) s_nl = 0;
+    __syncthreads();
+    {
+        const uint64_t t = blockIdx.x + (uint64_t)gridDim.x * threadIdx.x;
+        if (t < nb) {
+            const uint32_t b = bstart[t], e = bstart[t + 1];
+            if (e >= b && e - b > (uint32_t)BUCKET_MAX && e - b <= (uint32_t)BUCKET_HUGE)
+                s_list[atomicAdd(&s_nl, 1u)] = (uint32_t)t;
+        }
+    }
+    __syncthreads();
+    const uint32_t total = s_nl;
+    for (uint32_t j = 0; j < total; ++j) {
+        __syncthreads();  // the previous bucket's LDS reads are done
+        const uint32_t t = s_list[j];
+        const uint32_t b = bstart[t], size = bstart[t + 1] - b;
+        // wave w owns positions [w*chunk, (w+1)*chunk): item order (wave,
+        // item, lane) is position order
+        const uint32_t chunk = ((size + HUGE_WAVES - 1) / HUGE_WAVES + 63) & ~63u;
+        const uint32_t nit = chunk / 64;
+        uint64_t k[IPT];
+        uint32_t id[IPT];
+        uint32_t rk[IPT];
+        uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            const bool ok = (uint32_t)i < nit && pos < size;
+            k[i] = ok ? keys[b + pos] : 0ull;
+            id[i] = ok ? ids[b + pos] : 0u;
+            if (ok) {
+                mn = min(mn, k[i]);
+                mx = max(mx, k[i]);
+            }
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            mn = min(mn, shfl_u64(mn, (int)(lane ^ o)));
+            mx = max(mx, shfl_u64(mx, (int)(lane ^ o)));
+        }
+        s_cnt[threadIdx.x] = 0;
+        if (lane == 0) {
+            s_red[w] = mn;
+            s_red[HUGE_WAVES + w] = mx;
+        }
+        __syncthreads();
+        mn = s_red[0];
+        mx = s_red[HUGE_WAVES];
+#pragma unroll
+        for (int x = 1; x < HUGE_WAVES; ++x) {
+            mn = min(mn, s_red[x]);
+            mx = max(mx, s_red[HUGE_WAVES + x]);
+        }
+        if (mn == mx) {  // one key: already in id order
+            if (threadIdx.x == 0) big[t] = 0u;
+            continue;
+        }
+        const int hb = 63 - __clzll(mn ^ mx);
+        const uint32_t sh = hb >= 9 ? (uint32_t)hb - 9 : 0u;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            if (pos < size) rk[i] = atomicAdd(&s_cnt[(uint32_t)(k[i] >> sh) & (HUGE_SUB - 1)], 1u);
+        }
+        __syncthreads();
+        const uint32_t c = s_cnt[threadIdx.x];
+        const uint32_t s0 = block_incl_scan256(c, s_wsum) - c;
+        const uint32_t wm = wave_max_u32(c);
+        s_off[threadIdx.x] = s0;
+        if (lane == 0) s_wmax[w] = wm;
+        __syncthreads();
+        uint32_t bm = s_wmax[0];
+#pragma unroll
+        for (int x = 1; x < HUGE_WAVES; ++x) bm = max(bm, s_wmax[x]);
+        if (bm > RUN_WAVE) continue;  // skewed: the segmented passes take it
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if ((uint32_t)i >= nit) break;
+            const uint32_t pos = w * chunk + i * 64 + lane;
+            if (pos < size) {
+                const uint32_t lp = s_off[(uint32_t)(k[i] >> sh) & (HUGE_SUB - 1)] + rk[i];
+                s_k[lp] = k[i];
+                s_i[lp] = id[i];
+            }
+        }
+        __syncthreads();
+        const uint32_t cn = c <= RUN_NET ? c : 0u;
+        const uint32_t wn = wave_max_u32(cn);  // uniform over the wave
+        if (wn <= 8) sort_run<8>(s_k, s_i, s0, cn);
+        else sort_run<16>(s_k, s_i, s0, cn);
+        rank_runs(s_k, s_i, s0, c);
+        __syncthreads();
+        for (uint32_t pos = threadIdx.x; pos < size; pos += HUGE_THREADS) {
+            keys[b + pos] = s_k[pos];
+            ids[b + pos] = s_i[pos];
+        }
+        if (threadIdx.x == 0) big[t] = 0u;
+    }
+}
+
 // Histograms of the two bucket digits (bits [s0, s0 + 8) and [s1, s1 + 8))
 // of every key; eight loads in flight per thread.
 __global__ __launch_bounds__(256) void k_hist_keys2(const uint64_t* __restrict__ keys, uint64_t n, uint32_t s0,
@@ -523,6 +654,14 @@ void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint
                        const uint32_t* top, uint32_t* big, uint32_t* err, bool wide) {
     if (wide) hipLaunchKernelGGL(k_local_sort<BUCKET_MAX>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, top, big, err);
     else hipLaunchKernelGGL(k_local_sort<BUCKET_SMALL>, dim3(nb), dim3(256), 0, st, keys, ids, bstart, top, big, err);
+}
+
+void launch_local_sort_huge(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
+                            uint32_t* big) {
+    // 256 workgroups (one per CU), more if a workgroup would own more
+    // buckets than it has threads
+    const uint32_t grid = std::max<uint32_t>(256u, (nb + HUGE_THREADS - 1) / HUGE_THREADS);
+    hipLaunchKernelGGL(k_local_sort_huge, dim3(grid), dim3(HUGE_THREADS), 0, st, keys, ids, bstart, nb, big);
 }
 
 void launch_fix_top(hipStream_t st, const uint64_t* kmax, uint32_t guess, uint32_t* top, uint32_t* redo) {

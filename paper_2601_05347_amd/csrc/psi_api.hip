@@ -353,6 +353,12 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
         ProfScope ps(ix, "local_sort_wide", 0);
         launch_local_sort(st, K, I, bstart, nb, top, big, ix->err.as<uint32_t>(), true);
     }
+    if (n > (uint64_t)BUCKET_MAX) {
+        // one workgroup per CU (none of its buckets in range for uniform data
+        // below about 2.5e8 points)
+        ProfScope ps(ix, "local_sort_huge", 0);
+        launch_local_sort_huge(st, K, I, bstart, nb, big);
+    }
     launch_big_tables(st, bstart, big, nb, ntiles, tile_off, big_idx, totals, tmp);
     *which = 1;
     // big buckets: segmented passes over their tiles only (k/i[1] -> [0] ->

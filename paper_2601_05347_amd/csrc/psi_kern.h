@@ -142,6 +142,7 @@ void launch_iota_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t base);
 // leading bit.
 constexpr int BUCKET_MAX = 4096;
 constexpr int BUCKET_SMALL = 2048;  // lighter variant (half the LDS) for the common bucket sizes
+constexpr int BUCKET_HUGE = 8192;   // 1024-thread variant (112 KB of LDS) for BUCKET_MAX + 1 .. BUCKET_HUGE
 constexpr uint32_t BUCKET_COUNT = 1u << 16;
 // Histograms of two 8-bit key digits (rows at bits s0 and s1; hist [2][256],
 // zeroed).
@@ -177,6 +178,12 @@ void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, cons
 // and clears their flag. Decreasing bucket starts latch ERR_SPIN.
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
                        const uint32_t* top, uint32_t* big, uint32_t* err, bool wide);
+// Then the buckets of BUCKET_MAX + 1 .. BUCKET_HUGE pairs: each is sorted in
+// LDS and its flag cleared, unless one of its sub-buckets holds more than the
+// in-LDS scheme takes (then it is left untouched, flagged, for the segmented
+// passes).
+void launch_local_sort_huge(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
+                            uint32_t* big);
 // Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
 // bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
 // big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).

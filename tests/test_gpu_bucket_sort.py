@@ -6,7 +6,8 @@ Bucket = the 16 key bits below the largest key's leading bit. With 2D Morton
 keys and a largest coordinate of 2^31 - 1 those are bits 23..30 of both
 coordinates, which lets the tests place exact bucket sizes: 2048 (the largest
 the light LDS variant sorts), 2049 (the smallest the wide variant takes), 4096
-(the largest the wide variant sorts) and 4097 (the smallest that takes the
+(the largest the wide variant sorts), 4097 and 8192 (the smallest and largest
+the 1024-thread variant takes) and 8193 (the smallest that takes the
 segmented global passes).
 """
 import sys
@@ -72,7 +73,8 @@ def test_bucket_size_boundaries(psi):
     between them, a bucket of 1 and a uniform remainder (2D Morton: bucket
     bit j is bit 23 + j // 2 of axis j % 2)."""
     say("two-level bucket boundaries")
-    sizes = [(2048, (1, 0)), (2049, (0, 1)), (4096, (1, 1)), (4097, (2, 0)), (1, (0, 3))]
+    sizes = [(2048, (1, 0)), (2049, (0, 1)), (4096, (1, 1)), (4097, (2, 0)), (1, (0, 3)), (8192, (3, 0)),
+             (8193, (0, 2))]
     rest = 50_000
     r = synth.uniform(sum(c for c, _ in sizes) + rest, 2, 23, seed=3)  # low 23 bits of each coordinate
     hi = np.zeros((len(r), 2), np.uint32)
@@ -83,7 +85,7 @@ def test_bucket_size_boundaries(psi):
         o += c
     hi[o:, 0] = synth.uniform(rest, 1, 8, seed=4)[:, 0]
     hi[o:, 1] = synth.uniform(rest, 1, 8, seed=5)[:, 0] | 4  # bucket bit 5 set: never one of the above
-    hi[-1] = (255, 255)  # the largest coordinates: key bit length 62
+    hi[-1] = (255, 255)  # the largest coordinates: key bit length 62 (buckets 5 and 8 above)
     pts = (r | (hi << np.uint32(23))).astype(np.uint32)
     perm = np.argsort(synth.draws(synth.stream_key(9, synth.P_AUX), 0, len(pts)), kind="stable")
     check(psi, 2, 0, pts[perm])
@@ -147,9 +149,9 @@ def _bucket0(n_spread, n_cluster, cluster_bits, seed):
 
 
 def test_skewed_buckets(psi):
-    """Sub-buckets of 17..32 pairs (the 32-wide register network), a bucket
-    whose pairs crowd into one sub-bucket (the LDS LSD fallback), and a
-    bucket of equal keys, among uniform buckets."""
+    """Sub-buckets of 17..32 pairs (ranked by a wave), a bucket whose pairs
+    crowd into one sub-bucket (the LDS LSD fallback), and a bucket of equal
+    keys, among uniform buckets."""
     say("two-level skewed buckets")
     rest = synth.uniform(200_000, 2, 31, seed=40)
     rest = rest[(rest[:, 0] >> 23) + (rest[:, 1] >> 23) > 1]  # keep buckets 0..3 for the parts below
@@ -158,6 +160,46 @@ def test_skewed_buckets(psi):
     same = np.tile(np.array([[77, 1 << 23]], np.uint32), (2500, 1))            # bucket 2
     pts = np.concatenate([rest, net32, crowd, same]).astype(np.uint32)
     pts = pts[np.argsort(synth.draws(synth.stream_key(44, synth.P_AUX), 0, len(pts)), kind="stable")]
+    check(psi, 2, 0, pts)
+
+
+def _axes_of_bucket(t):
+    """(x >> 23, y >> 23) of the 2D Morton points in bucket t (bucket bit j
+    is bit 23 + j // 2 of axis j % 2)."""
+    hx = sum(((t >> (2 * i)) & 1) << i for i in range(8))
+    hy = sum(((t >> (2 * i + 1)) & 1) << i for i in range(8))
+    return hx, hy
+
+
+def test_huge_buckets(psi):
+    """Buckets of 4097..8192 pairs (the 1024-thread LDS variant): the two
+    ends, more of them than that launch has workgroups (each loops over the
+    list), a bucket of equal keys, a bucket whose pairs crowd into one
+    sub-bucket (left to the segmented passes), one of 8193 pairs (the
+    segmented passes), among small uniform buckets."""
+    say("two-level huge buckets")
+    draws = synth.draws(synth.stream_key(61, synth.P_AUX), 0, 300)
+    sizes = [4097, 8192, 8193] + [4097 + int(d % 4096) for d in draws]
+    parts, t = [], 0
+    for i, c in enumerate(sizes):  # buckets 0 .. len(sizes) - 1
+        low = synth.uniform(c, 2, 23, seed=100 + i)
+        hx, hy = _axes_of_bucket(t)
+        parts.append(low | np.array([hx << 23, hy << 23], np.uint32))
+        t += 1
+    hx, hy = _axes_of_bucket(t)  # equal keys
+    parts.append(np.tile(np.array([[5 | (hx << 23), 9 | (hy << 23)]], np.uint32), (6000, 1)))
+    t += 1
+    hx, hy = _axes_of_bucket(t)  # 6900 pairs in 64 grid points, 100 spread: one sub-bucket of > 64
+    crowd = np.concatenate([synth.uniform(6900, 2, 3, seed=70), synth.uniform(100, 2, 23, seed=71)])
+    parts.append(crowd | np.array([hx << 23, hy << 23], np.uint32))
+    t += 1
+    rest = synth.uniform(50_000, 2, 23, seed=72)
+    hb = 60_000 + synth.draws(synth.stream_key(73, synth.P_AUX), 0, len(rest)) % 5535
+    hxy = np.array([_axes_of_bucket(int(b)) for b in hb], np.uint32)
+    parts.append(rest | (hxy << np.uint32(23)))
+    parts.append(np.array([[0x7FFFFFFF, 0x7FFFFFFF]], np.uint32))  # key bit length 62
+    pts = np.concatenate(parts).astype(np.uint32)
+    pts = pts[np.argsort(synth.draws(synth.stream_key(74, synth.P_AUX), 0, len(pts)), kind="stable")]
     check(psi, 2, 0, pts)
 
 
