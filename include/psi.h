@@ -425,6 +425,11 @@ psi_status psi_orth_prof_get(psi_orth o, const char* family, double* h_ms, uint6
  * "update", ...), the summed device time in ms, the launch count, and
  * the algorithmic bytes those launches move. psi_prof_reset clears them. */
 psi_status psi_prof_enable(psi_index ix, int on);
+/* Restricts the bracketing to one family (family: a NUL-terminated name,
+ * copied), or lifts the restriction (family NULL): fewer events on the
+ * stream while one kernel is timed. Other families then accumulate nothing.
+ * PSI_E_ARG if ix is NULL. */
+psi_status psi_prof_only(psi_index ix, const char* family);
 psi_status psi_prof_reset(psi_index ix);
 psi_status psi_prof_get(psi_index ix, const char* family, double* h_ms, uint64_t* h_launches,
                         uint64_t* h_bytes);

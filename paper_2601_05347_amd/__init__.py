@@ -100,6 +100,7 @@ SIGNATURES = {
     "psi_bst_export": (_i, [_P, _P, _P, _P, _P]),
     "psi_set_tuning": (_i, [_P, _P]),
     "psi_get_tuning": (_i, [_P, _P]),
+    "psi_prof_only": (_i, [_P, C.c_char_p]),
     "psi_prof_reset": (_i, [_P]),
     "psi_prof_get": (_i, [_P, C.c_char_p, _P, _P, _P]),
 }
@@ -422,6 +423,10 @@ def psi_prof_enable(h, on: bool):
     _check(lib().psi_prof_enable(h, 1 if on else 0), "psi_prof_enable")
 
 
+def psi_prof_only(h, family):
+    _check(lib().psi_prof_only(h, family.encode() if family else None), "psi_prof_only")
+
+
 def psi_prof_reset(h):
     _check(lib().psi_prof_reset(h), "psi_prof_reset")
 
@@ -642,6 +647,9 @@ class Index:
     # timing
     def prof_enable(self, on=True):
         psi_prof_enable(self._h, on)
+
+    def prof_only(self, family=None):
+        psi_prof_only(self._h, family)
 
     def prof_reset(self):
         psi_prof_reset(self._h)

@@ -1035,6 +1035,12 @@ psi_status psi_prof_enable(psi_index ix, int on) {
     return PSI_OK;
 }
 
+psi_status psi_prof_only(psi_index ix, const char* family) {
+    if (!ix) return PSI_E_ARG;
+    ix->prof.only = family ? family : "";
+    return PSI_OK;
+}
+
 psi_status psi_prof_reset(psi_index ix) {
     if (!ix) return PSI_E_ARG;
     (void)hipStreamSynchronize(ix->st);

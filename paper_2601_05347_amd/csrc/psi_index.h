@@ -136,6 +136,7 @@ struct ProfFamily {
 };
 struct Prof {
     bool on = false;
+    std::string only;  // when not empty: the one family bracketed
     std::map<std::string, ProfFamily> fam;
     std::vector<hipEvent_t> pool;
     hipEvent_t take() {
@@ -262,14 +263,16 @@ struct ProfScope {
     const char* fam;
     uint64_t bytes;
     hipEvent_t a = nullptr;
-    ProfScope(psi_index x, const char* f, uint64_t b) : ix(x), fam(f), bytes(b) {
-        if (ix->prof.on) {
+    bool on;
+    ProfScope(psi_index x, const char* f, uint64_t b)
+        : ix(x), fam(f), bytes(b), on(x->prof.on && (x->prof.only.empty() || x->prof.only == f)) {
+        if (on) {
             a = ix->prof.take();
             (void)hipEventRecord(a, ix->st);
         }
     }
     ~ProfScope() {
-        if (ix->prof.on) {
+        if (on) {
             hipEvent_t e = ix->prof.take();
             (void)hipEventRecord(e, ix->st);
             ProfFamily& f = ix->prof.fam[fam];
