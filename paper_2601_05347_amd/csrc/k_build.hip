@@ -70,7 +70,9 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
         q = x / L;
         r = (uint32_t)(x % L);
     }
-    for (uint64_t j = j_first; j < L; j += step) {
+    // first position and count of the half-wave's next leaf (every lane of
+    // the half-wave calls it)
+    auto next_leaf = [&](uint32_t& b, uint32_t& cnt) {
         const uint32_t bt = (uint32_t)min<uint64_t>(q, n);
         q += sq;
         r += sr;  // below 2 L: a wrap past 2^32 shows as r < sr
@@ -78,14 +80,36 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
             r -= Lw;
             ++q;
         }
-        const uint32_t b = shfl_u32(bt, hb), cnt = shfl_u32(bt, hb + 1) - b;
-        const bool on = t < cnt;
-        uint32_t p[D];
-        uint64_t key = 0;
-        uint32_t id = 0;
-        if (on) {
+        b = shfl_u32(bt, hb);
+        cnt = shfl_u32(bt, hb + 1) - b;
+    };
+    // the pairs of leaf j + step are loaded while leaf j is decoded and
+    // written (one stride ahead)
+    uint32_t cnt = 0;
+    uint64_t key = 0;
+    uint32_t id = 0;
+    if (j_first < L) {
+        uint32_t b = 0;
+        next_leaf(b, cnt);
+        if (t < cnt) {
             key = sk[(uint64_t)b + t];
             id = sid[(uint64_t)b + t];
+        }
+    }
+    for (uint64_t j = j_first; j < L; j += step) {
+        uint32_t b1 = 0, cnt1 = 0;
+        uint64_t key1 = 0;
+        uint32_t id1 = 0;
+        if (j + step < L) {  // uniform over the half-wave
+            next_leaf(b1, cnt1);
+            if (t < cnt1) {
+                key1 = sk[(uint64_t)b1 + t];
+                id1 = sid[(uint64_t)b1 + t];
+            }
+        }
+        const bool on = t < cnt;
+        uint32_t p[D];
+        if (on) {
             if (CURVE) hilbert_point_fsm<D>(key, p, s_h);
             else morton_point<D>(key, p);
             uint32_t* s = slots + j * (uint64_t)(D + 1) * C;
@@ -115,6 +139,9 @@ __global__ __launch_bounds__(256) void k_build_leaves(const uint64_t* __restrict
             piv_key[j] = key;
             piv_id[j] = id;
         }
+        cnt = cnt1;
+        key = key1;
+        id = id1;
     }
 }
 
