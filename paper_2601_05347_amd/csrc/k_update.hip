@@ -443,6 +443,27 @@ __global__ void k_del_take(const uint32_t* __restrict__ ids, uint64_t m, uint64_
         }
         // the first pivot greater than (key, id) is in (PSAMPLE (lo - 1), PSAMPLE lo]
         uint64_t a = lo ? (lo - 1) * PSAMPLE : 0, b = min<uint64_t>(lo ? lo * PSAMPLE : PSAMPLE, L);
+        if (b - a == PSAMPLE) {
+            // a whole stretch: its PSAMPLE keys in one round of loads (16-byte
+            // aligned: a is a multiple of PSAMPLE), counting those below the
+            // key; a key equal to a pivot's takes the search below (ids)
+            const uint4* pv = reinterpret_cast<const uint4*>(pk + a);
+            uint4 v[PSAMPLE / 2];
+#pragma unroll
+            for (uint32_t u = 0; u < PSAMPLE / 2; ++u) v[u] = pv[u];
+            uint32_t nb = 0;
+            bool tie = false;
+#pragma unroll
+            for (uint32_t u = 0; u < PSAMPLE / 2; ++u) {
+                const uint64_t k0 = ((uint64_t)v[u].y << 32) | v[u].x, k1 = ((uint64_t)v[u].w << 32) | v[u].z;
+                nb += (k0 < key ? 1u : 0u) + (k1 < key ? 1u : 0u);
+                tie |= k0 == key || k1 == key;
+            }
+            if (!tie) {
+                a += nb;
+                b = a;
+            }
+        }
         while (a < b) {  // a pivot's id is read only when its key ties
             const uint64_t mid = (a + b) >> 1;
             const uint64_t km = pk[mid];
