@@ -172,11 +172,21 @@ __global__ void k_dir_copy(const DevTree* __restrict__ dt, const uint32_t* __res
 }
 
 template <int D, int CURVE>
-__global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi,
-                             const uint32_t* __restrict__ run_leaf, const uint32_t* __restrict__ run_beg,
-                             const uint32_t* __restrict__ ctr, uint64_t m, const uint32_t* __restrict__ rsplit,
-                             const uint32_t* __restrict__ newpos, const DevTree* __restrict__ dt,
-                             uint32_t* __restrict__ slots, uint32_t C, uint32_t* __restrict__ err, Caps cap) {
+__global__ __launch_bounds__(256) void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bi,
+                                                    const uint32_t* __restrict__ run_leaf,
+                                                    const uint32_t* __restrict__ run_beg,
+                                                    const uint32_t* __restrict__ ctr, uint64_t m,
+                                                    const uint32_t* __restrict__ rsplit,
+                                                    const uint32_t* __restrict__ newpos, const DevTree* __restrict__ dt,
+                                                    uint32_t* __restrict__ slots, uint32_t C,
+                                                    uint32_t* __restrict__ err, Caps cap) {
+    // Hilbert keys decode through the curve's table staged in LDS (a lookup
+    // per two planes: eleven dependent reads per point)
+    __shared__ uint16_t s_h[CURVE ? HilbertFsm<D>::ENTRIES : 1];
+    if (CURVE) {
+        stage_hilbert<D>(s_h, false);
+        __syncthreads();
+    }
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t R = ctr[1];
     if (r >= R || rsplit[r]) return;
@@ -200,7 +210,8 @@ __global__ void k_ins_append(const uint64_t* __restrict__ bk, const uint32_t* __
     uint32_t* s = slots + (uint64_t)rec.slot * (D + 1) * C;
     for (uint32_t e = beg; e < end; ++e) {
         uint32_t p[D];
-        sfc_point_tab<D, CURVE>(bk[e], p);
+        if (CURVE) hilbert_point_fsm<D>(bk[e], p, s_h);
+        else morton_point<D>(bk[e], p);
         const uint32_t o = rec.cnt + (e - beg);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
