@@ -117,15 +117,17 @@ __device__ __forceinline__ void rank_runs(uint64_t* s_k, uint32_t* s_i, uint32_t
 // One workgroup per bucket of at most BMAX pairs, sorted in place by (key,
 // id). The BUCKET_SMALL variant runs first over all buckets and flags the
 // larger ones; the BUCKET_MAX variant then takes those of at most BUCKET_MAX
-// pairs (half the occupancy, for the rare large buckets). The pairs arrive in id order (the global passes are stable).
+// pairs (half the occupancy, for the rare large buckets). The pairs arrive in
+// id order (the global passes are stable).
 // Sub-buckets: the 8 key bits just below the highest bit in which the
 // bucket's keys differ (so that clustered buckets still spread); a thread
 // sorts its sub-bucket in registers (at most RUN_NET pairs), a wave ranks the
-// larger ones (at most RUN_WAVE). A bucket with a larger sub-bucket is sorted
-// instead by stable 8-bit LSD passes over the bits [0, lo_bits) in LDS.
-// Larger buckets are only flagged (big[t] = 1). Decreasing bucket starts
-// (pairs not ordered by their top bits) latch ERR_SPIN and the bucket is left
-// alone.
+// larger ones (at most RUN_WAVE). A bucket with a larger sub-bucket (skewed)
+// is sorted by the BUCKET_MAX variant instead, by stable 8-bit LSD passes
+// over the bits [0, lo_bits) in LDS: the BUCKET_SMALL variant flags it
+// (big[t] = 2) and leaves its pairs alone. Buckets above BMAX are only
+// flagged (big[t] = 1). Decreasing bucket starts (pairs not ordered by their
+// top bits) latch ERR_SPIN and the bucket is left alone.
 template <int BMAX>
 __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
                                                     const uint32_t* __restrict__ bstart,
@@ -133,13 +135,16 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ err) {
     const uint32_t lo_bits = *top;
     constexpr int IPT = BMAX / 256;  // items per thread at the largest bucket
+    // the light variant has no LSD path (it leaves skewed buckets to the wide
+    // one): fewer registers and less LDS, six workgroups per CU
+    constexpr bool LSD = BMAX != BUCKET_SMALL;
     __shared__ uint64_t s_k[BMAX];
     __shared__ uint32_t s_i[BMAX];
-    __shared__ uint32_t s_cnt[4][RADIX];
+    __shared__ uint32_t s_cnt[LSD ? 4 : 2][RADIX];
     __shared__ uint32_t s_wsum[4];
     __shared__ uint64_t s_red[8];
     __shared__ uint32_t s_wmax[4];
-    __shared__ uint32_t s_skip[8];  // one flag per LSD pass: no reset races between passes
+    __shared__ uint32_t s_skip[LSD ? 8 : 1];  // one flag per LSD pass: no reset races between passes
     const uint32_t t = blockIdx.x;
     const uint32_t b = bstart[t], e = bstart[t + 1];
     if (e < b) {
@@ -153,8 +158,9 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
     if (BMAX == BUCKET_SMALL) {  // first launch: every bucket gets its flag
         if (threadIdx.x == 0) big[t] = size > (uint32_t)BMAX ? 1u : 0u;
         if (size <= 1 || size > (uint32_t)BMAX) return;
-    } else {  // second launch: only the buckets the first one left
-        if (size <= (uint32_t)BUCKET_SMALL || size > (uint32_t)BMAX) return;
+    } else {  // second launch: only the buckets the first one left (larger, or skewed)
+        if (size > (uint32_t)BMAX || (size <= (uint32_t)BUCKET_SMALL && big[t] != 2u)) return;
+        __syncthreads();  // every thread has read the flag
         if (threadIdx.x == 0) big[t] = 0u;
     }
     const int w = threadIdx.x >> 6;
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         mx = max(mx, shfl_u64(mx, (int)(lane ^ o)));
     }
     for (int x = threadIdx.x; x < RADIX; x += 256) s_cnt[0][x] = 0;
-    if (threadIdx.x < 8) s_skip[threadIdx.x] = 0;
+    if (LSD && threadIdx.x < 8) s_skip[threadIdx.x] = 0;
     if (lane == 0) {
         s_red[w] = mn;
         s_red[4 + w] = mx;
@@ -234,6 +240,10 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
         }
         return;
     }
+    if constexpr (!LSD) {  // skewed: flagged for the wide variant, pairs untouched
+        if (threadIdx.x == 0) big[t] = 2u;
+        return;
+    } else {
     // skewed bucket: stable LSD passes in LDS
     for (uint32_t shift = 0, pass = 0; shift < lo_bits; shift += RADIX_BITS, ++pass) {
         for (int x = threadIdx.x; x < 4 * RADIX; x += 256) (&s_cnt[0][0])[x] = 0;
@@ -302,6 +312,7 @@ __global__ __launch_bounds__(256) void k_local_sort(uint64_t* __restrict__ keys,
             keys[b + pos] = k[i];
             ids[b + pos] = id[i];
         }
+    }
     }
 }
 

@@ -174,8 +174,9 @@ void launch_bucket_starts(hipStream_t st, const uint64_t* keys, uint64_t n, cons
                           uint32_t nb);
 // Sorts buckets by (key, id) in place, in two launches: wide = false takes
 // every bucket of at most BUCKET_SMALL pairs and sets big[t] = 1 for the
-// larger ones (else 0); wide = true then takes those of at most BUCKET_MAX
-// and clears their flag. Decreasing bucket starts latch ERR_SPIN.
+// larger ones (2 for a skewed one it leaves alone, else 0); wide = true then
+// takes those of at most BUCKET_MAX and the skewed ones and clears their
+// flag. Decreasing bucket starts latch ERR_SPIN.
 void launch_local_sort(hipStream_t st, uint64_t* keys, uint32_t* ids, const uint32_t* bstart, uint32_t nb,
                        const uint32_t* top, uint32_t* big, uint32_t* err, bool wide);
 // Then the buckets of BUCKET_MAX + 1 .. BUCKET_HUGE pairs: each is sorted in

@@ -149,16 +149,18 @@ def _bucket0(n_spread, n_cluster, cluster_bits, seed):
 
 
 def test_skewed_buckets(psi):
-    """Sub-buckets of 17..32 pairs (ranked by a wave), a bucket whose pairs
-    crowd into one sub-bucket (the LDS LSD fallback), and a bucket of equal
-    keys, among uniform buckets."""
+    """Sub-buckets of 17..32 pairs (ranked by a wave), buckets whose pairs
+    crowd into one sub-bucket (the LDS LSD fallback of the wide variant: one
+    above 2048 pairs, one below that the light variant hands over), and a
+    bucket of equal keys, among uniform buckets."""
     say("two-level skewed buckets")
     rest = synth.uniform(200_000, 2, 31, seed=40)
-    rest = rest[(rest[:, 0] >> 23) + (rest[:, 1] >> 23) > 1]  # keep buckets 0..3 for the parts below
+    rest = rest[((rest[:, 0] >> 23) > 1) | ((rest[:, 1] >> 23) > 1)]  # keep buckets 0..3 for the parts below
     net32 = _bucket0(900, 20, 10, seed=41)                     # bucket 0
     crowd = _bucket0(12, 3000, 4, seed=43) | np.array([1 << 23, 0], np.uint32)   # bucket 1
     same = np.tile(np.array([[77, 1 << 23]], np.uint32), (2500, 1))            # bucket 2
-    pts = np.concatenate([rest, net32, crowd, same]).astype(np.uint32)
+    crowd_small = _bucket0(10, 1490, 4, seed=45) | np.array([1 << 23, 1 << 23], np.uint32)  # bucket 3
+    pts = np.concatenate([rest, net32, crowd, same, crowd_small]).astype(np.uint32)
     pts = pts[np.argsort(synth.draws(synth.stream_key(44, synth.P_AUX), 0, len(pts)), kind="stable")]
     check(psi, 2, 0, pts)
 
