@@ -690,8 +690,16 @@ void launch_zero_counted(hipStream_t st, uint32_t* p, uint64_t words_per, const 
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,
                        uint32_t* tile_off, uint32_t* big_idx, uint32_t* totals, uint32_t* tmp) {
     hipLaunchKernelGGL(k_big_count, dim3(blocks_for(nb, 256)), dim3(256), 0, st, bstart, big, nb, ntiles);
-    launch_scan_u32(st, ntiles, tile_off, nb, totals, tmp);
-    launch_scan_u32(st, big, big_idx, nb, totals + 1, tmp);
+    ScanSet ss{};  // both scans in one set of launches
+    ss.in[0] = ntiles;
+    ss.out[0] = tile_off;
+    ss.total[0] = totals;
+    ss.n[0] = nb;
+    ss.in[1] = big;
+    ss.out[1] = big_idx;
+    ss.total[1] = totals + 1;
+    ss.n[1] = nb;
+    launch_scan_multi(st, ss, 2, tmp);
 }
 
 void launch_big_fill(hipStream_t st, const uint32_t* bstart, const uint32_t* big, const uint32_t* big_idx,

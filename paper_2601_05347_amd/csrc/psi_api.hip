@@ -284,7 +284,7 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
         return S.epoch;
     };
     const uint64_t tmpw = scan_tmp_words(nb);
-    if ((s = ensure_q(ix, S.bk, ((uint64_t)nb * 5 + 1 + 2 + 2 + tmpw) * 4)) != PSI_OK) return s;
+    if ((s = ensure_q(ix, S.bk, ((uint64_t)nb * 5 + 1 + 2 + 2 + 2 * tmpw) * 4)) != PSI_OK) return s;
     uint32_t* bstart = S.bk.as<uint32_t>();  // nb + 1
     uint32_t* big = bstart + nb + 1;
     uint32_t* ntiles = big + nb;
@@ -292,7 +292,7 @@ psi_status bucket_sort(psi_index ix, const uint64_t* keys, uint32_t id_base, uin
     uint32_t* big_idx = tile_off + nb;
     uint32_t* totals = big_idx + nb;  // 2: tiles of the big buckets, big buckets
     uint32_t* redo = totals + 2;      // 1
-    uint32_t* tmp = redo + 2;
+    uint32_t* tmp = redo + 2;  // 2 tmpw: the two scans of the big-bucket tables
     uint32_t* top = &ix->dt()->sort_top;
     if ((s = ensure_status(btiles_max + XCD_CHUNKS)) != PSI_OK) return s;
     if ((s = ensure_q(ix, S.xt, XT_WORDS * 4)) != PSI_OK) return s;

@@ -187,7 +187,7 @@ void launch_local_sort_huge(hipStream_t st, uint64_t* keys, uint32_t* ids, const
                             uint32_t* big);
 // Tile counts of the big buckets: tile_off = exclusive scan of the tiles per
 // bucket, big_idx = exclusive scan of big[]; totals[0] = tiles, totals[1] =
-// big buckets. ntiles, tile_off, big_idx hold nb words; tmp scan_tmp_words(nb).
+// big buckets. ntiles, tile_off, big_idx hold nb words; tmp 2 scan_tmp_words(nb).
 void launch_big_tables(hipStream_t st, const uint32_t* bstart, const uint32_t* big, uint32_t nb, uint32_t* ntiles,
                        uint32_t* tile_off, uint32_t* big_idx, uint32_t* totals, uint32_t* tmp);
 // Segment tables (segment = big bucket) for the segmented passes.
