@@ -63,12 +63,22 @@ def _all_ids(nd):
     return np.concatenate([_all_ids(c) for c in nd.children])
 
 
-def build(pts, dim: int, phi: int, lam: int | None = None):
-    """The P-Orth tree of `pts` (ids = row numbers); None when empty."""
+def build(pts, dim: int, phi: int, lam: int | None = None, ids=None):
+    """The P-Orth tree of `pts` (ids = row numbers), or of the rows `ids`
+    alone when given; None when empty."""
     pts = np.asarray(pts, dtype=np.int64).reshape(-1, dim)
+    ids = np.arange(len(pts), dtype=np.int64) if ids is None else np.asarray(ids, dtype=np.int64)
+    if len(ids) == 0:
+        return None
+    return _build_region(pts, ids, tuple([0] * dim), 0, dim, phi, lam)
+
+
+def _build_region(pts, ids, corner, level, dim: int, phi: int, lam: int | None = None):
+    """Alg. 1 on the points `ids` (rows of pts) of the region with low corner
+    `corner` at `level`; None when there are none."""
     W = domain_bits(dim)
     lam = lam if lam is not None else (3 if dim == 2 else 2)
-    if len(pts) == 0:
+    if len(ids) == 0:
         return None
 
     def build_orth(ids, corner, level):
@@ -131,7 +141,122 @@ def build(pts, dim: int, phi: int, lam: int | None = None):
 
         return assemble(0, 0, tuple(corner))
 
-    return build_orth(np.arange(len(pts), dtype=np.int64), tuple([0] * dim), 0)
+    return build_orth(np.asarray(ids, dtype=np.int64), tuple(corner), level)
+
+
+def _interior(level, corner, kids):
+    nd = Node(level, corner)
+    nd.children = kids
+    nd.count = sum(k.count for k in kids)
+    nd.lo = np.min([k.lo for k in kids], axis=0)
+    nd.hi = np.max([k.hi for k in kids], axis=0)
+    return nd
+
+
+def _sieve_children(pts, ids, node, corner, level, dim):
+    """Sec. 3.2's sieve one level down: for each sub-region of the region
+    (index sum_d [upper half on axis d] << d), its low corner, the existing
+    child there (None when empty) and the slice of `ids` that falls in it,
+    order kept."""
+    W = domain_bits(dim)
+    half = 1 << (W - level - 1)
+    p = pts[ids]
+    child = np.zeros(len(ids), dtype=np.int64)
+    for d in range(dim):
+        child |= (p[:, d] >= corner[d] + half).astype(np.int64) << d
+    existing = {}
+    if node is not None:
+        for c in node.children:
+            idx = sum(((c.corner[d] - corner[d]) // half) << d for d in range(dim))
+            existing[idx] = c
+    for ch in range(1 << dim):
+        sc = tuple(corner[d] + (half if (ch >> d) & 1 else 0) for d in range(dim))
+        yield sc, existing.get(ch), ids[child == ch]
+
+
+def batch_insert(root, pts, new_ids, dim: int, phi: int, lam: int | None = None):
+    """Alg. 2 (batch insertion): the points `new_ids` (rows of pts, not in the
+    tree) added to the tree `root` of other rows of pts. An empty batch leaves
+    a subtree as it is; a leaf takes Alg. 1 again on its points and the
+    batch's; an interior node's skeleton (lambda levels of its subtree) sieves
+    the batch to its external nodes, each of which takes its share the same
+    way (an empty sub-region gets Alg. 1 on its share); the boxes of the
+    skeleton's nodes are then updated. `root` is not modified (the subtrees
+    the batch does not reach are shared with the tree returned)."""
+    pts = np.asarray(pts, dtype=np.int64).reshape(-1, dim)
+    W = domain_bits(dim)
+    lam = lam if lam is not None else (3 if dim == 2 else 2)
+    new_ids = np.asarray(new_ids, dtype=np.int64)
+
+    def insert(node, ids, corner, level):
+        if len(ids) == 0:
+            return node
+        if node is None:
+            return _build_region(pts, ids, corner, level, dim, phi, lam)
+        if node.leaf:
+            return _build_region(pts, np.concatenate([node.ids, ids]), corner, level, dim, phi, lam)
+        return skeleton(node, ids, corner, level, min(lam, W - level))
+
+    def skeleton(node, ids, corner, level, h):
+        # the skeleton's nodes down to h levels below; its external nodes
+        # (leaves, empty sub-regions, nodes h levels down) take their shares
+        if len(ids) == 0:  # nothing below changes
+            return node
+        if h == 0 or node is None or node.leaf:
+            return insert(node, ids, corner, level)
+        kids = []
+        for sc, c, share in _sieve_children(pts, ids, node, corner, level, dim):
+            t = skeleton(c, share, sc, level + 1, h - 1)
+            if t is not None:
+                kids.append(t)
+        return _interior(level, corner, kids)
+
+    if root is None:
+        return build(pts, dim, phi, lam, ids=new_ids)
+    return insert(root, new_ids, tuple([0] * dim), 0)
+
+
+def batch_delete(root, pts, del_ids, dim: int, phi: int, lam: int | None = None):
+    """Alg. 2's deletion (symmetric to insertion, Sec. 3.2): the rows
+    `del_ids` (coordinates from pts) are sieved down the skeletons to the
+    leaves that hold them and removed there (ids the tree does not hold are
+    ignored); a node left without points disappears, and every affected
+    ancestor whose subtree holds at most phi points is flattened into one
+    leaf. `root` is not modified (the subtrees the batch does not reach are
+    shared with the tree returned)."""
+    pts = np.asarray(pts, dtype=np.int64).reshape(-1, dim)
+    W = domain_bits(dim)
+    lam = lam if lam is not None else (3 if dim == 2 else 2)
+    del_ids = np.unique(np.asarray(del_ids, dtype=np.int64))
+
+    def delete(node, ids, corner, level):
+        if node is None or len(ids) == 0:
+            return node
+        if node.leaf:
+            keep = node.ids[~np.isin(node.ids, ids)]
+            if len(keep) == len(node.ids):
+                return node
+            return _leaf(pts, keep, level, corner) if len(keep) else None
+        return skeleton(node, ids, corner, level, min(lam, W - level))
+
+    def skeleton(node, ids, corner, level, h):
+        if len(ids) == 0:  # nothing below changes
+            return node
+        if h == 0 or node is None or node.leaf:
+            return delete(node, ids, corner, level)
+        kids = []
+        for sc, c, share in _sieve_children(pts, ids, node, corner, level, dim):
+            t = skeleton(c, share, sc, level + 1, h - 1) if c is not None else None
+            if t is not None:
+                kids.append(t)
+        if not kids:
+            return None
+        nd = _interior(level, corner, kids)
+        if nd.count <= phi:  # flatten a subtree the deletions brought down to phi points
+            return _leaf(pts, _all_ids(nd), level, corner)
+        return nd
+
+    return skeleton(root, del_ids, tuple([0] * dim), 0, min(lam, W)) if root is not None else None
 
 
 def preorder(root, dim: int, ids=None) -> dict:

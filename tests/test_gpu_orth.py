@@ -42,11 +42,16 @@ def segment_sort(ids, first, count):
     return v[np.lexsort((v, seg))]
 
 
-def check_structure(o, pts, dim, phi, live=None):
-    """live: the ids of the rows of pts (ascending; default 0 .. n-1)."""
+def check_structure(o, pts, dim, phi, live=None, ref_root=None):
+    """live: the ids of the rows of pts (ascending; default 0 .. n-1).
+    ref_root: the oracle's tree to compare with, its leaves holding ids
+    (default: Alg. 1 on pts)."""
     live = np.arange(len(pts), dtype=np.int64) if live is None else np.asarray(live, dtype=np.int64)
     nodes, gp = o.export()
-    ref = orth.preorder(orth.build(pts, dim, phi), dim, ids=live)
+    if ref_root is not None:
+        ref = orth.preorder(ref_root, dim)
+    else:
+        ref = orth.preorder(orth.build(pts, dim, phi), dim, ids=live)
     N = len(ref["level"])
     nn, nl, h = o.shape()
     assert nn == N and nl == int(ref["leaf"].sum())
@@ -291,8 +296,10 @@ def test_out_of_range_points_and_bad_arguments(psi):
 def test_batch_updates_match_the_oracle(psi, dim, phi):
     """build -> insert (with points equal to live ones) -> delete (live, dead,
     unknown and repeated ids) -> insert -> delete nearly all -> delete all ->
-    insert into the empty tree; after each step the tree equals the oracle's
-    tree of the live set, and queries match brute force."""
+    insert into the empty tree; after each step the tree equals the tree the
+    oracle's Alg. 2 reaches by the same updates (insertions and deletions
+    applied to its own tree, ids = rows of allp), and queries match brute
+    force."""
     bits = bits_of(dim) if dim == 3 else 20
     rng = synth.draws(synth.stream_key(41 + dim + phi, synth.P_AUX), 0, 10_000)
     pts = synth.uniform(3000, dim, bits, 42)
@@ -300,42 +307,54 @@ def test_batch_updates_match_the_oracle(psi, dim, phi):
     allp = np.concatenate([pts, extra])
     o = psi.Orth(dim, phi).build(pts)
     live = np.arange(3000)
+    ref = orth.build(allp, dim, phi, ids=live)  # the oracle's tree, updated by Alg. 2 below
     q = queries(dim, 200, 44, pts, bits)
     bx = synth.boxes(q[:150], bits, 45, side_lo=bits - 8, side_hi=bits - 3)
 
     def check(step):
         say(f"orth updates dim={dim} phi={phi}: {step}, {len(live)} live")
         assert o.size()[0] == len(live)
-        check_structure(o, allp[live], dim, phi, live)
+        if len(live):
+            check_structure(o, allp[live], dim, phi, live, ref_root=ref)
+        else:
+            assert ref is None
+            check_structure(o, allp[live], dim, phi, live)
         check_queries(psi, o, allp[live], dim, phi, q, bx, ks=(1, 10), live=live)
 
     check("build")
     new = psi.to_u32(o.batch_insert(extra))
     np.testing.assert_array_equal(new, np.arange(3000, 5000))
+    ref = orth.batch_insert(ref, allp, np.arange(3000, 5000), dim, phi)
     live = np.arange(5000)
     check("insert")
     dels = live[rng[:5000] % 3 == 0]
     batch = np.concatenate([dels, dels[:50], [6000, 7000, 0xFFFFFFF0]]).astype(np.uint32)
     assert o.batch_delete(batch) == len(dels)
+    ref = orth.batch_delete(ref, allp, batch[batch < len(allp)], dim, phi)  # ids never handed out have no point
     live = np.setdiff1d(live, dels)
     assert o.batch_delete(dels[:10]) == 0  # already deleted
+    ref = orth.batch_delete(ref, allp, dels[:10], dim, phi)
     check("delete")
     more = synth.uniform(500, dim, bits, 46, synth.P_INSERT)
     allp = np.concatenate([allp, more])
     np.testing.assert_array_equal(psi.to_u32(o.batch_insert(more)), np.arange(5000, 5500))
+    ref = orth.batch_insert(ref, allp, np.arange(5000, 5500), dim, phi)
     live = np.concatenate([live, np.arange(5000, 5500)])
     check("insert 2")
     keep = live[:: max(1, len(live) // 10)][:10]
     assert o.batch_delete(np.setdiff1d(live, keep).astype(np.uint32)) == len(live) - len(keep)
+    ref = orth.batch_delete(ref, allp, np.setdiff1d(live, keep), dim, phi)
     live = keep
     check("delete nearly all")
     assert o.batch_delete(live.astype(np.uint32)) == len(live)
+    ref = orth.batch_delete(ref, allp, live, dim, phi)
     live = live[:0]
     check("delete all")
     assert o.shape() == (0, 0, 0)
     last = synth.uniform(40, dim, bits, 47, synth.P_INSERT)
     allp = np.concatenate([allp, last])
     np.testing.assert_array_equal(psi.to_u32(o.batch_insert(last)), np.arange(5500, 5540))
+    ref = orth.batch_insert(ref, allp, np.arange(5500, 5540), dim, phi)
     live = np.arange(5500, 5540)
     check("insert into the empty tree")
 

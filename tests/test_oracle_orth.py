@@ -200,3 +200,137 @@ def test_pins_catch_a_planted_mistake(what, old, new):
         if caught:
             break
     assert caught, what
+
+
+# ------------------------------------------------ batch updates (Alg. 2)
+def check_canonical(root, rows, allp, dim, phi):
+    """root is the orth-tree of the points allp[rows] by the definition (the
+    brute-force cells), its leaves hold exactly those rows, and every node's
+    box is the bounding box of its subtree's points."""
+    p = allp[rows]
+    assert tree_nodes(root) == brute_force_nodes(p, dim, phi)
+    pre = orth.preorder(root, dim)
+    got = np.sort(np.concatenate(pre["leaf_ids"])) if pre["leaf_ids"] else np.zeros(0, np.int64)
+    np.testing.assert_array_equal(got, np.sort(np.asarray(rows, dtype=np.int64)))
+    li = 0
+    for v in range(len(pre["level"])):
+        nl = int(pre["leaf"][v:pre["end"][v]].sum())
+        ids = np.concatenate(pre["leaf_ids"][li:li + nl])
+        np.testing.assert_array_equal(pre["lo"][v], allp[ids].min(axis=0))
+        np.testing.assert_array_equal(pre["hi"][v], allp[ids].max(axis=0))
+        assert pre["count"][v] == len(ids)
+        if pre["leaf"][v]:
+            li += 1
+
+
+def update_script(dim, n, seed):
+    """Seeded rows for a build, three insert batches (one of a single point)
+    and three delete batches (one with repeats and rows never in the tree
+    or already deleted)."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    base, rest = perm[: n * 6 // 10], perm[n * 6 // 10:]
+    ins = [rest[:1], rest[1:len(rest) // 2], rest[len(rest) // 2:]]
+    live = np.sort(perm)
+    d1 = rng.choice(live, n // 3, replace=False)
+    left = np.setdiff1d(live, d1)
+    d2 = np.concatenate([rng.choice(left, n // 5, replace=False), d1[:50], d1[:50], rng.choice(left, 20)])
+    return base, ins, [d1, d2]
+
+
+def run_updates(mod, name, dim, pts, phi):
+    allp = np.asarray(pts, dtype=np.int64)
+    base, ins, dels = update_script(dim, len(allp), seed=len(allp) + phi)
+    root = mod.build(allp, dim, phi, ids=base)
+    rows = np.asarray(base)
+    yield root, rows
+    for b in ins:
+        root = mod.batch_insert(root, allp, b, dim, phi)
+        rows = np.concatenate([rows, b])
+        yield root, rows
+    for d in dels:
+        root = mod.batch_delete(root, allp, d, dim, phi)
+        rows = np.setdiff1d(rows, d)
+        yield root, rows
+    root = mod.batch_delete(root, allp, rows, dim, phi)  # everything
+    yield root, rows[:0]
+
+
+@pytest.mark.parametrize("name,dim,pts", list(inputs()), ids=[x[0] for x in inputs()])
+@pytest.mark.parametrize("phi", [2, 8, 32])
+def test_alg2_updates_give_the_canonical_tree(name, dim, pts, phi):
+    """Alg. 2's insertions (a leaf rebuilt by Alg. 1, skeletons sieving the
+    batch) and deletions (removal at the leaves, ancestors of at most phi
+    points flattened) reach the orth-tree of the new point set: the tree is
+    canonical, which is what lets the GPU path cut the tree again from the
+    merged order instead of updating it in place."""
+    allp = np.asarray(pts, dtype=np.int64)
+    for root, rows in run_updates(orth, name, dim, pts, phi):
+        if len(rows) == 0:
+            assert root is None
+        else:
+            check_canonical(root, rows, allp, dim, phi)
+
+
+def test_alg2_skeleton_height_and_sharing():
+    """Updates do not depend on the skeleton height, and leave their input
+    tree unchanged."""
+    dim, phi = 3, 8
+    allp = np.asarray(points("varden", 3000, 3, bits=21, seed=3), dtype=np.int64)
+    base, ins, dels = update_script(dim, len(allp), seed=77)
+    t0 = orth.build(allp, dim, phi, ids=base)
+    before = orth.preorder(t0, dim)
+    ref = orth.preorder(orth.batch_delete(orth.batch_insert(t0, allp, ins[2], dim, phi, lam=1), allp, dels[0],
+                                          dim, phi, lam=1), dim)
+    for lam in (2, 4):
+        got = orth.preorder(orth.batch_delete(orth.batch_insert(t0, allp, ins[2], dim, phi, lam=lam), allp, dels[0],
+                                              dim, phi, lam=lam), dim)
+        for k in ("level", "corner", "leaf", "count", "lo", "hi", "end", "first"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"lam={lam} {k}")
+    after = orth.preorder(t0, dim)
+    for k in ("level", "corner", "leaf", "count", "lo", "hi", "end", "first"):
+        np.testing.assert_array_equal(after[k], before[k])
+
+
+UPDATE_MUTANTS = [
+    ("deletions never flatten", "if nd.count <= phi:  # flatten", "if nd.count < 0:  # flatten"),
+    ("a leaf takes its share without Alg. 1",
+     "return _build_region(pts, np.concatenate([node.ids, ids]), corner, level, dim, phi, lam)",
+     "return _leaf(pts, np.concatenate([node.ids, ids]), level, corner)"),
+    ("skeleton boxes not updated", "nd.lo = np.min([k.lo for k in kids], axis=0)", "nd.lo = kids[0].lo"),
+    ("an emptied leaf kept", "return _leaf(pts, keep, level, corner) if len(keep) else None",
+     "return _leaf(pts, keep if len(keep) else node.ids, level, corner)"),
+    ("a point on the midpoint sieved low",
+     "child |= (p[:, d] >= corner[d] + half).astype(np.int64) << d",
+     "child |= (p[:, d] > corner[d] + half).astype(np.int64) << d"),
+]
+
+
+@pytest.mark.parametrize("what,old,new", UPDATE_MUTANTS, ids=[m[0] for m in UPDATE_MUTANTS])
+def test_update_pins_catch_a_planted_mistake(what, old, new):
+    """Each plausible slip in Alg. 2's oracle, planted in a copy, fails the
+    update pins."""
+    import types
+    src = open(orth.__file__).read()
+    assert old in src
+    mod = types.ModuleType("orth_update_mutant")
+    exec(compile(src.replace(old, new), "orth_update_mutant", "exec"), mod.__dict__)
+    caught = False
+    for name, dim, pts in inputs():
+        allp = np.asarray(pts, dtype=np.int64)
+        for phi in (2, 8):
+            try:
+                for root, rows in run_updates(mod, name, dim, pts, phi):
+                    if len(rows) == 0:
+                        assert root is None
+                    else:
+                        check_canonical(root, rows, allp, dim, phi)
+            except AssertionError:
+                caught = True
+            except Exception:
+                caught = True
+            if caught:
+                break
+        if caught:
+            break
+    assert caught, what
